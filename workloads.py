@@ -1,0 +1,91 @@
+"""Seeded synthetic inputs for the variable-coefficient 7-point problem.
+
+This module only draws random numbers: coefficient fields a(x), b(x) and
+right-hand sides f, each in natural grid order (flat index x1 + n*x2 + n^2*x3,
+x1 fastest).  It holds none of the factorization's arithmetic, so both the
+CPU oracle and the GPU path can consume the same arrays.
+
+The paper's experiments use formula-defined coefficient fields, not a dataset
+(Section 4, Examples 1-3); the workloads below are the synthetic stand-ins
+the measurements are quoted on.  Every draw uses numpy's PCG64 generator with
+an explicit seed.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def _gen(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def log_uniform_field(n: int, lo: float, hi: float, seed: int) -> np.ndarray:
+    """a_j = 10**U(lo, hi), one independent draw per grid node (x1 fastest)."""
+    return 10.0 ** _gen(seed).uniform(lo, hi, n ** 3)
+
+
+def uniform_field(n: int, lo: float, hi: float, seed: int) -> np.ndarray:
+    """b_j = U(lo, hi) per grid node."""
+    return _gen(seed).uniform(lo, hi, n ** 3)
+
+
+def const_field(n: int, value: float) -> np.ndarray:
+    return np.full(n ** 3, float(value))
+
+
+def normal_rhs(n: int, seed: int, nrhs: int = 1) -> np.ndarray:
+    """f ~ i.i.d. N(0,1); shape (N,) for one RHS, else (nrhs, N) row per RHS
+    (each row is one column of the column-major N x nrhs block)."""
+    g = _gen(seed)
+    if nrhs == 1:
+        return g.standard_normal(n ** 3)
+    return g.standard_normal((nrhs, n ** 3))
+
+
+@dataclass
+class Workload:
+    """One synthetic problem: grid n^3, leaf width m, coefficient recipe, ID tolerance."""
+    name: str
+    n: int
+    leaf: int
+    eps: float
+    a_kind: str            # "const" | "logu"
+    a_args: tuple
+    b_kind: str            # "const" | "unif"
+    b_args: tuple
+    f_seed: int
+    precision: str = "fp64"  # "fp64" | "mixed"
+    extra: dict = field(default_factory=dict)
+
+    def a(self) -> np.ndarray:
+        if self.a_kind == "const":
+            return const_field(self.n, *self.a_args)
+        return log_uniform_field(self.n, *self.a_args)
+
+    def b(self) -> np.ndarray:
+        if self.b_kind == "const":
+            return const_field(self.n, *self.b_args)
+        return uniform_field(self.n, *self.b_args)
+
+    def f(self, nrhs: int = 1) -> np.ndarray:
+        return normal_rhs(self.n, self.f_seed, nrhs)
+
+
+# Named workloads.  "logu" args are (lo, hi, seed) of log10 a ~ U(lo, hi).
+WORKLOADS = {
+    # 16^3, a = 1, b = 0, leaf 4^3, eps 1e-6: the small case the oracle runs in seconds.
+    "c16_const": Workload("c16_const", 16, 4, 1e-6, "const", (1.0,), "const", (0.0,), 101),
+    # 64^3 high-contrast field, FP64, leaf 8^3, eps 1e-6.
+    "c64_contrast": Workload("c64_contrast", 64, 8, 1e-6, "logu", (-2.0, 2.0, 201),
+                             "const", (0.0,), 202),
+    # 128^3 high-contrast field: the headline problem, mixed eps 1e-4 and FP64 eps 1e-6.
+    "c128_mixed": Workload("c128_mixed", 128, 8, 1e-4, "logu", (-2.0, 2.0, 301),
+                           "const", (0.0,), 302, precision="mixed"),
+    "c128_fp64": Workload("c128_fp64", 128, 8, 1e-6, "logu", (-2.0, 2.0, 301),
+                          "const", (0.0,), 302, precision="fp64"),
+    # 32^3 high-contrast field used for mid-size parity and the CPU baseline sample.
+    "c32_contrast": Workload("c32_contrast", 32, 8, 1e-6, "logu", (-2.0, 2.0, 211),
+                             "const", (0.0,), 212),
+}
