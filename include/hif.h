@@ -1,0 +1,141 @@
+/*
+ * hif.h — C ABI of the MI355X hierarchical interpolative factorization (HIF)
+ * of the 3-D variable-coefficient elliptic operator
+ *
+ *     -div(a(x) grad u(x)) + b(x) u(x) = f(x)          (paper, eq. 1.1)
+ *
+ * discretized by the 7-point stencil on an n x n x n interior grid
+ * (paper, Section 2.4, "seven-point stencil") with zero Dirichlet values
+ * outside, grid spacing h = 1/(n+1) and harmonic-mean edge coefficients.
+ *
+ * The factorization follows the paper's sequential HIF (Section 2.4) with
+ * the distributed version's face snapshot (Section 3.2): for each level
+ * l = 0..L-1 of the cell tree (cells of width leaf*2^l, Section 2.1) every
+ * cell interior is eliminated (Section 2.2) and every face is skeletonized
+ * by an interpolative decomposition to relative precision eps (Section
+ * 2.3); level L is a dense factorization.  A ~= F and
+ * F^{-1} = W^0 ... W^L D^{-1} W^L^T ... W^0^T (Section 2.4).
+ *
+ * Conventions shared by every call:
+ *   - Grid vectors are in natural order: index x1 + n*x2 + n^2*x3 (x1
+ *     fastest).  A block of nrhs vectors is column-major N x nrhs, N = n^3.
+ *   - Array arguments named a, b, f, u, x, y are DEVICE pointers to doubles
+ *     owned by the caller; the library copies what it keeps.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   - Every call returns a status; nothing throws or aborts across the ABI.
+ *     On error an output handle is set to NULL and nothing leaks;
+ *     hif_last_error() gives a thread-local description.
+ */
+#ifndef HIF_H
+#define HIF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hif_problem_s* hif_problem_t; /* operator A (library-owned)          */
+typedef struct hif_factor_s* hif_factor_t;   /* factorization F (device arenas)     */
+
+typedef enum {
+  HIF_OK = 0,
+  HIF_EINVAL = -1,   /* bad sizes/options, non-positive or non-finite a, non-finite b */
+  HIF_ENOMEM = -2,   /* device allocation failed                                   */
+  HIF_ENOTSPD = -3,  /* a Cholesky pivot was not positive (level/front in message) */
+  HIF_ENOCONV = -4,  /* PCG reached maxit; u holds the last iterate                */
+  HIF_EDEVICE = -5   /* any other HIP runtime error                                */
+} hif_status;
+
+enum { HIF_FP64 = 0, HIF_MIXED = 1 };  /* factor precision                        */
+enum { HIF_DIRICHLET = 0 };            /* boundary condition                      */
+
+#define HIF_MAX_LEVELS 16
+
+typedef struct {
+  int32_t n;         /* grid points per dimension; n = leaf * 2^L, L >= 0         */
+  int32_t leaf;      /* leaf cell width m >= 2 (paper: m, Section 2.1)             */
+  double eps;        /* ID relative precision; 0 = no ID (exact nested dissection) */
+  int32_t precision; /* HIF_FP64: all front work in FP64.  HIF_MIXED: fronts,
+                        Schur updates and skeleton algebra in FP32; ID pivot
+                        decisions (Gram + pivoted Cholesky) in FP64.             */
+  int32_t bc;        /* HIF_DIRICHLET (the only one implemented)                  */
+} hif_options;
+
+typedef struct {
+  int32_t iters;     /* PCG iterations taken                                      */
+  int32_t converged; /* 1 if the true relative residual reached tol               */
+  double relres;     /* ||f - A u||_2 / ||f||_2 recomputed in FP64 at exit         */
+} hif_pcg_info;
+
+typedef struct {
+  int32_t levels;                          /* L                                    */
+  int32_t precision;
+  int64_t n_dof;                           /* N = n^3                              */
+  int64_t root_size;                       /* |Sigma_L|, active DOFs at level L    */
+  int64_t cells[HIF_MAX_LEVELS + 1];       /* cells per level (level L: 1 root)    */
+  int64_t faces[HIF_MAX_LEVELS];           /* faces per level                      */
+  int64_t eliminated[HIF_MAX_LEVELS + 1];  /* interior DOFs eliminated per level   */
+  int64_t face_dofs[HIF_MAX_LEVELS];       /* active face DOFs entering the ID     */
+  int64_t redundant[HIF_MAX_LEVELS];       /* face DOFs removed as redundant       */
+  int64_t max_front[HIF_MAX_LEVELS + 1];   /* largest |I| + |S| per level          */
+  double level_seconds[HIF_MAX_LEVELS + 1];/* wall time per level of hif_build     */
+  double factor_flops;                     /* algorithmic flops counted per front  */
+  int64_t factor_bytes;                    /* bytes of stored factor blocks        */
+  int64_t peak_bytes;                      /* device high-water mark of the library */
+  double build_seconds;                    /* wall time of hif_build               */
+} hif_stats;
+
+/* Create the operator A from coefficient fields a (> 0, finite) and b
+ * (finite), both device arrays of N doubles.  Builds the 7-point stencil
+ * (paper, Section 2.4).  Returns HIF_EINVAL for bad options or values. */
+hif_status hif_problem_create(const hif_options* opts, const double* a, const double* b,
+                              void* stream, hif_problem_t* out);
+
+/* Factor A ~= F (paper, Sections 2.2-2.4 and 3.2).  Blocks the calling
+ * thread: ranks of each level are read back before the next level is
+ * planned.  The factor keeps no reference to caller memory. */
+hif_status hif_build(hif_problem_t A, const hif_options* opts, void* stream,
+                     hif_factor_t* out);
+
+/* u = F^{-1} f for nrhs column-major vectors (paper, Section 2.4: the
+ * product W^0..W^L D^{-1} W^L^T..W^0^T).  FP64 in and out (the mixed factor
+ * is read in FP32, accumulated in FP64).  u may alias f.  Asynchronous on
+ * `stream`.  nrhs = 0 is a no-op. */
+hif_status hif_apply(hif_factor_t F, const double* f, double* u, int32_t nrhs, void* stream);
+
+/* y = A x for nrhs column-major vectors, FP64.  Asynchronous. */
+hif_status hif_matvec(hif_problem_t A, const double* x, double* y, int32_t nrhs, void* stream);
+
+/* Solve A u = f by preconditioned CG with F^{-1} as the preconditioner,
+ * FP64 residuals, matvecs and inner products, from u = 0; stops when the
+ * true relative residual is <= tol.  info has nrhs entries (host memory).
+ * Returns HIF_ENOCONV if any column hit maxit.  Blocks the calling thread. */
+hif_status hif_pcg(hif_problem_t A, hif_factor_t F, const double* f, double* u, int32_t nrhs,
+                   double tol, int32_t maxit, hif_pcg_info* info, void* stream);
+
+/* Sizes, ranks, flops, bytes and times of a factor (host struct). */
+hif_status hif_factor_stats(hif_factor_t F, hif_stats* out);
+
+/* Rank k of every face of `level` in face order (faces enumerated by
+ * (normal d, plane j_d >= 1, then the other two cell indices, slowest
+ * first)), and the face sizes |F| (host arrays of `cap` entries; either
+ * may be NULL).  *count receives the number of faces. */
+hif_status hif_factor_ranks(hif_factor_t F, int32_t level, int32_t* ranks, int32_t* sizes,
+                            int32_t cap, int32_t* count);
+
+/* Active-DOF mask after `level` (0..L-1): mask[p] = 1 if grid point p is
+ * still active in A^{level+1} (host array of N bytes). */
+hif_status hif_factor_active(hif_factor_t F, int32_t level, uint8_t* mask);
+
+void hif_factor_destroy(hif_factor_t F);
+void hif_problem_destroy(hif_problem_t A);
+
+const char* hif_status_string(hif_status s);
+const char* hif_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIF_H */

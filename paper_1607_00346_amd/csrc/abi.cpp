@@ -1,0 +1,198 @@
+// extern "C" entry points of the HIF library: argument checks, status codes,
+// thread-local error text.  No exception crosses this boundary.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "hif_impl.hpp"
+
+namespace hif {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+MemStats& mem_stats() {
+  static MemStats ms;
+  return ms;
+}
+
+}  // namespace hif
+
+namespace {
+
+template <typename Fn>
+hif_status guarded(Fn&& fn) {
+  try {
+    hif::set_last_error("");
+    fn();
+    return HIF_OK;
+  } catch (const hif::Error& e) {
+    hif::set_last_error(e.what());
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    hif::set_last_error("host allocation failed");
+    return HIF_ENOMEM;
+  } catch (const std::exception& e) {
+    hif::set_last_error(e.what());
+    return HIF_EDEVICE;
+  } catch (...) {
+    hif::set_last_error("unknown error");
+    return HIF_EDEVICE;
+  }
+}
+
+void check_options(const hif_options* o) {
+  HIF_REQUIRE(o != nullptr, HIF_EINVAL, "options must not be NULL");
+  HIF_REQUIRE(o->n >= 2 && o->n <= 1024, HIF_EINVAL, "n must be in [2, 1024]");
+  HIF_REQUIRE(hif::levels_for(o->n, o->leaf) >= 0, HIF_EINVAL,
+              "n must equal leaf * 2^L with leaf >= 2");
+  HIF_REQUIRE(std::isfinite(o->eps) && o->eps >= 0.0 && o->eps < 1.0, HIF_EINVAL,
+              "eps must be in [0, 1)");
+  HIF_REQUIRE(o->precision == HIF_FP64 || o->precision == HIF_MIXED, HIF_EINVAL,
+              "precision must be HIF_FP64 or HIF_MIXED");
+  HIF_REQUIRE(o->bc == HIF_DIRICHLET, HIF_EINVAL, "only HIF_DIRICHLET is implemented");
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+hif_status hif_problem_create(const hif_options* opts, const double* a, const double* b,
+                              void* stream, hif_problem_t* out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    HIF_REQUIRE(out != nullptr, HIF_EINVAL, "out must not be NULL");
+    check_options(opts);
+    HIF_REQUIRE(a != nullptr && b != nullptr, HIF_EINVAL, "a and b must not be NULL");
+    auto* A = new hif_problem_s();
+    try {
+      A->opts = *opts;
+      A->n = opts->n;
+      A->N = (int64_t)opts->n * opts->n * opts->n;
+      hif::problem_assemble(A, a, b, as_stream(stream));
+    } catch (...) {
+      delete A;
+      throw;
+    }
+    *out = A;
+  });
+}
+
+hif_status hif_build(hif_problem_t A, const hif_options* opts, void* stream, hif_factor_t* out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    HIF_REQUIRE(out != nullptr && A != nullptr, HIF_EINVAL, "NULL handle");
+    check_options(opts);
+    HIF_REQUIRE(opts->n == A->n, HIF_EINVAL, "options describe another grid than the problem");
+    auto* F = new hif_factor_s();
+    try {
+      F->opts = *opts;
+      if (opts->precision == HIF_MIXED)
+        hif::build_factor<float>(A, *opts, as_stream(stream), F);
+      else
+        hif::build_factor<double>(A, *opts, as_stream(stream), F);
+    } catch (...) {
+      (void)hipStreamSynchronize(as_stream(stream));
+      delete F;
+      throw;
+    }
+    *out = F;
+  });
+}
+
+hif_status hif_apply(hif_factor_t F, const double* f, double* u, int32_t nrhs, void* stream) {
+  return guarded([&] {
+    HIF_REQUIRE(F != nullptr && F->impl, HIF_EINVAL, "NULL factor");
+    HIF_REQUIRE(nrhs >= 0, HIF_EINVAL, "nrhs must be >= 0");
+    if (nrhs == 0) return;
+    HIF_REQUIRE(f != nullptr && u != nullptr, HIF_EINVAL, "NULL vector");
+    const int64_t N = F->stats.n_dof;
+    for (int c = 0; c < nrhs; ++c) F->impl->apply(f + c * N, u + c * N, as_stream(stream));
+  });
+}
+
+hif_status hif_matvec(hif_problem_t A, const double* x, double* y, int32_t nrhs, void* stream) {
+  return guarded([&] {
+    HIF_REQUIRE(A != nullptr, HIF_EINVAL, "NULL problem");
+    HIF_REQUIRE(nrhs >= 0, HIF_EINVAL, "nrhs must be >= 0");
+    if (nrhs == 0) return;
+    HIF_REQUIRE(x != nullptr && y != nullptr && x != y, HIF_EINVAL, "bad vectors");
+    for (int c = 0; c < nrhs; ++c)
+      hif::stencil_matvec(A->stencil(), x + c * A->N, y + c * A->N, as_stream(stream));
+  });
+}
+
+hif_status hif_pcg(hif_problem_t A, hif_factor_t F, const double* f, double* u, int32_t nrhs,
+                   double tol, int32_t maxit, hif_pcg_info* info, void* stream) {
+  return guarded([&] {
+    HIF_REQUIRE(A != nullptr && F != nullptr && F->impl, HIF_EINVAL, "NULL handle");
+    HIF_REQUIRE(F->stats.n_dof == A->N, HIF_EINVAL, "factor and problem sizes differ");
+    HIF_REQUIRE(nrhs >= 0 && maxit >= 1 && std::isfinite(tol) && tol > 0.0, HIF_EINVAL,
+                "need nrhs >= 0, maxit >= 1, tol > 0");
+    if (nrhs == 0) return;
+    HIF_REQUIRE(f != nullptr && u != nullptr && info != nullptr && f != u, HIF_EINVAL,
+                "bad vectors");
+    bool all = true;
+    for (int c = 0; c < nrhs; ++c) {
+      hif::pcg_solve(A, F, f + c * A->N, u + c * A->N, tol, maxit, &info[c], as_stream(stream));
+      all = all && info[c].converged;
+    }
+    if (!all) throw hif::Error(HIF_ENOCONV, "PCG did not reach tol within maxit");
+  });
+}
+
+hif_status hif_factor_stats(hif_factor_t F, hif_stats* out) {
+  return guarded([&] {
+    HIF_REQUIRE(F != nullptr && out != nullptr, HIF_EINVAL, "NULL argument");
+    *out = F->stats;
+  });
+}
+
+hif_status hif_factor_ranks(hif_factor_t F, int32_t level, int32_t* ranks, int32_t* sizes,
+                            int32_t cap, int32_t* count) {
+  return guarded([&] {
+    HIF_REQUIRE(F != nullptr && count != nullptr, HIF_EINVAL, "NULL argument");
+    HIF_REQUIRE(level >= 0 && level < (int)F->ranks.size(), HIF_EINVAL, "level out of range");
+    const auto& rk = F->ranks[level];
+    const auto& sz = F->sizes[level];
+    *count = (int32_t)rk.size();
+    const int m = std::min<int>(cap, (int)rk.size());
+    if (ranks) std::memcpy(ranks, rk.data(), sizeof(int32_t) * std::max(m, 0));
+    if (sizes) std::memcpy(sizes, sz.data(), sizeof(int32_t) * std::max(m, 0));
+  });
+}
+
+hif_status hif_factor_active(hif_factor_t F, int32_t level, uint8_t* mask) {
+  return guarded([&] {
+    HIF_REQUIRE(F != nullptr && mask != nullptr, HIF_EINVAL, "NULL argument");
+    HIF_REQUIRE(level >= 0 && level < (int)F->active_after.size(), HIF_EINVAL,
+                "level out of range");
+    const auto& a = F->active_after[level];
+    std::memcpy(mask, a.data(), a.size());
+  });
+}
+
+void hif_factor_destroy(hif_factor_t F) { delete F; }
+void hif_problem_destroy(hif_problem_t A) { delete A; }
+
+const char* hif_status_string(hif_status s) {
+  switch (s) {
+    case HIF_OK: return "HIF_OK";
+    case HIF_EINVAL: return "HIF_EINVAL: invalid argument";
+    case HIF_ENOMEM: return "HIF_ENOMEM: out of device memory";
+    case HIF_ENOTSPD: return "HIF_ENOTSPD: matrix not positive definite";
+    case HIF_ENOCONV: return "HIF_ENOCONV: PCG did not converge";
+    case HIF_EDEVICE: return "HIF_EDEVICE: device runtime error";
+  }
+  return "unknown hif_status";
+}
+
+const char* hif_last_error(void) { return hif::g_last_error.c_str(); }
+
+}  // extern "C"

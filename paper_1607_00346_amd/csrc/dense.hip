@@ -1,0 +1,531 @@
+// Batched dense kernels for the HIF fronts on gfx950 (CDNA4, wave64).
+#include <climits>
+#include <cfloat>
+
+#include "dense.hpp"
+
+namespace hif {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// 16x16x4 MFMA.  Lane l supplies A(l%16, l/16) and B(l/16, l%16); result
+// element v of lane l is C(4*(l/16)+v, l%16).
+template <typename TC>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef d4 acc_t;
+  static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<float> {
+  typedef f4 acc_t;
+  static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int BM = 64, BN = 64, KC = 16, NTHR = 256;
+
+// One 64x64 tile of C = alpha op(A) op(B) + beta C, four waves in a 2x2
+// arrangement of 32x32 sub-tiles, K staged through LDS in chunks of 16 with
+// a register prefetch of the next chunk.
+template <typename TIn, typename TC>
+__device__ void gemm_tile(int opa, int opb, int flags, const TIn* __restrict__ A, int lda,
+                          const TIn* __restrict__ B, int ldb, TC* __restrict__ C, int ldc, int m,
+                          int n, int k, int m0, int n0, TC alpha, TC beta,
+                          TC (*As)[KC][BM], TC (*Bs)[KC][BN]) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  int kb = 0, ke = k;
+  if (flags & GF_A_LOWER) ke = min(ke, m0 + BM);
+  if (flags & GF_A_UPPER) kb = max(kb, m0);
+  if (flags & GF_B_LOWER) kb = max(kb, n0);
+  if (flags & GF_B_UPPER) ke = min(ke, n0 + BN);
+  const int nchunk = ke > kb ? (ke - kb + KC - 1) / KC : 0;
+
+  typename Mfma<TC>::acc_t acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[x][y][v] = TC(0);
+
+  TC ra[4], rb[4];
+  auto load = [&](int c) {
+    const int t0 = kb + c * KC;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int i, t;
+      if (opa == OP_N) { i = tid & 63; t = (tid >> 6) + 4 * r; }
+      else { t = tid & 15; i = (tid >> 4) + 16 * r; }
+      const int gi = m0 + i, gt = t0 + t;
+      bool ok = gi < m && gt < ke;
+      if (flags & GF_A_LOWER) ok = ok && gt <= gi;
+      if (flags & GF_A_UPPER) ok = ok && gt >= gi;
+      TC v = TC(0);
+      if (ok) v = (TC)(opa == OP_N ? A[gi + (int64_t)lda * gt] : A[gt + (int64_t)lda * gi]);
+      ra[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int j, t;
+      if (opb == OP_N) { t = tid & 15; j = (tid >> 4) + 16 * r; }
+      else { j = tid & 63; t = (tid >> 6) + 4 * r; }
+      const int gj = n0 + j, gt = t0 + t;
+      bool ok = gj < n && gt < ke;
+      if (flags & GF_B_LOWER) ok = ok && gt >= gj;
+      if (flags & GF_B_UPPER) ok = ok && gt <= gj;
+      TC v = TC(0);
+      if (ok) v = (TC)(opb == OP_N ? B[gt + (int64_t)ldb * gj] : B[gj + (int64_t)ldb * gt]);
+      rb[r] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (opa == OP_N) As[buf][(tid >> 6) + 4 * r][tid & 63] = ra[r];
+      else As[buf][tid & 15][(tid >> 4) + 16 * r] = ra[r];
+      if (opb == OP_N) Bs[buf][tid & 15][(tid >> 4) + 16 * r] = rb[r];
+      else Bs[buf][(tid >> 6) + 4 * r][tid & 63] = rb[r];
+    }
+  };
+
+  if (nchunk > 0) {
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int c = 0; c < nchunk; ++c) {
+      const int buf = c & 1;
+      if (c + 1 < nchunk) load(c + 1);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kk = 4 * s + (lane >> 4);
+        const TC a0 = As[buf][kk][wm * 32 + (lane & 15)];
+        const TC a1 = As[buf][kk][wm * 32 + 16 + (lane & 15)];
+        const TC b0 = Bs[buf][kk][wn * 32 + (lane & 15)];
+        const TC b1 = Bs[buf][kk][wn * 32 + 16 + (lane & 15)];
+        acc[0][0] = Mfma<TC>::run(a0, b0, acc[0][0]);
+        acc[0][1] = Mfma<TC>::run(a0, b1, acc[0][1]);
+        acc[1][0] = Mfma<TC>::run(a1, b0, acc[1][0]);
+        acc[1][1] = Mfma<TC>::run(a1, b1, acc[1][1]);
+      }
+      if (c + 1 < nchunk) store(buf ^ 1);
+      __syncthreads();
+    }
+  }
+
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = m0 + wm * 32 + x * 16 + 4 * (lane >> 4) + v;
+        const int gj = n0 + wn * 32 + y * 16 + (lane & 15);
+        if (gi < m && gj < n && (!(flags & GF_C_LOWER) || gi >= gj)) {
+          const int64_t idx = gi + (int64_t)ldc * gj;
+          TC val = alpha * acc[x][y][v];
+          if (beta != TC(0)) val += beta * C[idx];
+          C[idx] = val;
+        }
+      }
+}
+
+template <typename TIn, typename TC>
+__global__ __launch_bounds__(NTHR) void k_gemm_desc(int opa, int opb, int flags,
+                                                    const GemmDesc* __restrict__ desc, TC alpha,
+                                                    TC beta) {
+  __shared__ TC As[2][KC][BM];
+  __shared__ TC Bs[2][KC][BN];
+  const GemmDesc d = desc[blockIdx.z];
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  if (m0 >= d.m || n0 >= d.n) return;
+  if ((flags & GF_C_LOWER) && m0 + BM - 1 < n0) return;
+  gemm_tile<TIn, TC>(opa, opb, flags, (const TIn*)d.A, d.lda, (const TIn*)d.B, d.ldb, (TC*)d.C,
+                     d.ldc, d.m, d.n, d.k, m0, n0, alpha, beta, As, Bs);
+}
+
+// Trailing update of the blocked front Cholesky at block column j0:
+// Phi[j1:nR, j1:nI] -= P[j1:nR] P[j1:nI]^T (lower part), P = Phi[:, j0:j1].
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_front_trailing(T* arena, const FrontDesc* __restrict__ fd,
+                                                         int j0) {
+  __shared__ T As[2][KC][BM];
+  __shared__ T Bs[2][KC][BN];
+  const FrontDesc f = fd[blockIdx.z];
+  if (j0 >= f.nI) return;
+  const int nb = min(kPanel, f.nI - j0);
+  const int j1 = j0 + nb;
+  const int m = f.nR - j1, n = f.nI - j1;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  if (m0 >= m || n0 >= n) return;
+  if (m0 + BM - 1 < n0) return;
+  T* base = arena + f.off;
+  const T* P = base + j1 + (int64_t)f.ld * j0;
+  gemm_tile<T, T>(OP_N, OP_T, GF_C_LOWER, P, f.ld, P, f.ld, base + j1 + (int64_t)f.ld * j1, f.ld,
+                  m, n, nb, m0, n0, T(-1), T(1), As, Bs);
+}
+
+// Cholesky of the diagonal block Phi[j0:j1, j0:j1] in LDS, written back in
+// place (one workgroup per front).
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_front_diag(T* arena, const FrontDesc* __restrict__ fd,
+                                                     int j0, int* err) {
+  __shared__ T D[kPanel][kPanel + 1];
+  __shared__ int bad;
+  const FrontDesc f = fd[blockIdx.x];
+  if (j0 >= f.nI) return;
+  const int nb = min(kPanel, f.nI - j0);
+  const int tid = threadIdx.x;
+  T* base = arena + f.off;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < nb * nb; e += NTHR) {
+    const int i = e / nb, t = e % nb;
+    if (t <= i) D[i][t] = base[(j0 + i) + (int64_t)f.ld * (j0 + t)];
+  }
+  __syncthreads();
+  for (int t = 0; t < nb; ++t) {
+    if (tid == 0) {
+      T piv = D[t][t];
+      if (!(piv > T(0))) { bad = 1; piv = T(1); }
+      D[t][t] = sqrt(piv);
+    }
+    __syncthreads();
+    if (tid > t && tid < nb) D[tid][t] /= D[t][t];
+    __syncthreads();
+    for (int e = tid; e < nb * nb; e += NTHR) {
+      const int i = e / nb, j = e % nb;
+      if (j > t && j <= i) D[i][j] -= D[i][t] * D[j][t];
+    }
+    __syncthreads();
+  }
+  if (bad && tid == 0) atomicMin(err, (int)blockIdx.x);
+  for (int e = tid; e < nb * nb; e += NTHR) {
+    const int i = e / nb, t = e % nb;
+    if (t <= i) base[(j0 + i) + (int64_t)f.ld * (j0 + t)] = D[i][t];
+  }
+}
+
+// Panel rows below the factored diagonal block:
+// Phi[r, j0:j1] <- Phi[r, j0:j1] L_jj^{-T}, by substitution (thread per row).
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_front_panel(T* arena, const FrontDesc* __restrict__ fd,
+                                                      int j0) {
+  __shared__ T D[kPanel][kPanel + 1];
+  const FrontDesc f = fd[blockIdx.y];
+  if (j0 >= f.nI) return;
+  const int nb = min(kPanel, f.nI - j0);
+  const int r0 = j0 + nb + blockIdx.x * NTHR;
+  if (r0 >= f.nR) return;
+  const int tid = threadIdx.x;
+  T* base = arena + f.off;
+  for (int e = tid; e < nb * nb; e += NTHR) {
+    const int i = e / nb, t = e % nb;
+    if (t <= i) D[i][t] = base[(j0 + i) + (int64_t)f.ld * (j0 + t)];
+  }
+  __syncthreads();
+  const int r = r0 + tid;
+  if (r < f.nR) {
+    T z[kPanel];
+#pragma unroll
+    for (int t = 0; t < kPanel; ++t) {
+      if (t < nb) {
+        T s = base[r + (int64_t)f.ld * (j0 + t)];
+#pragma unroll
+        for (int q = 0; q < t; ++q) s -= z[q] * D[t][q];
+        z[t] = s / D[t][t];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kPanel; ++t)
+      if (t < nb) base[r + (int64_t)f.ld * (j0 + t)] = z[t];
+  }
+}
+
+// Block row j0 of the in-place inverse: W = L[j0:j1, 0:j0] Linv[0:j0, 0:j0].
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_trtri_gemm(T* arena, const FrontDesc* __restrict__ fd,
+                                                     int j0, T* work, int64_t wstride) {
+  __shared__ T As[2][KC][BM];
+  __shared__ T Bs[2][KC][BN];
+  const FrontDesc f = fd[blockIdx.z];
+  if (j0 >= f.nI) return;
+  const int nb = min(kPanel, f.nI - j0);
+  const int n0 = blockIdx.x * BN;
+  if (n0 >= j0) return;
+  T* base = arena + f.off;
+  gemm_tile<T, T>(OP_N, OP_N, GF_B_LOWER, base + j0, f.ld, base, f.ld,
+                  work + blockIdx.z * wstride, kPanel, nb, j0, j0, 0, n0, T(1), T(0), As, Bs);
+}
+
+// Linv_jj = L_jj^{-1}, in place on the diagonal block (one workgroup per front).
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_trtri_diag(T* arena, const FrontDesc* __restrict__ fd,
+                                                     int j0) {
+  __shared__ T D[kPanel][kPanel + 1];
+  __shared__ T Di[kPanel][kPanel + 1];
+  const FrontDesc f = fd[blockIdx.x];
+  if (j0 >= f.nI) return;
+  const int nb = min(kPanel, f.nI - j0);
+  const int tid = threadIdx.x;
+  T* base = arena + f.off;
+  for (int e = tid; e < nb * nb; e += NTHR) {
+    const int i = e / nb, t = e % nb;
+    D[i][t] = t <= i ? base[(j0 + i) + (int64_t)f.ld * (j0 + t)] : T(0);
+  }
+  __syncthreads();
+  if (tid < nb) {
+    const int c = tid;
+    for (int i = 0; i < nb; ++i) {
+      T v;
+      if (i < c) v = T(0);
+      else if (i == c) v = T(1) / D[c][c];
+      else {
+        T s = T(0);
+        for (int t = c; t < i; ++t) s += D[i][t] * Di[t][c];
+        v = -s / D[i][i];
+      }
+      Di[i][c] = v;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < nb * nb; e += NTHR) {
+    const int i = e / nb, t = e % nb;
+    if (t <= i) base[(j0 + i) + (int64_t)f.ld * (j0 + t)] = Di[i][t];
+  }
+}
+
+// Linv[j0:j1, 0:j0] = -Linv_jj W (the diagonal block already holds Linv_jj).
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_trtri_apply(T* arena, const FrontDesc* __restrict__ fd,
+                                                      int j0, const T* work, int64_t wstride) {
+  __shared__ T Di[kPanel][kPanel + 1];
+  const FrontDesc f = fd[blockIdx.y];
+  if (j0 >= f.nI) return;
+  const int c0 = blockIdx.x * NTHR;
+  if (c0 >= j0) return;
+  const int nb = min(kPanel, f.nI - j0);
+  const int tid = threadIdx.x;
+  T* base = arena + f.off;
+  for (int e = tid; e < nb * nb; e += NTHR) {
+    const int i = e / nb, t = e % nb;
+    Di[i][t] = t <= i ? base[(j0 + i) + (int64_t)f.ld * (j0 + t)] : T(0);
+  }
+  __syncthreads();
+  const int c = c0 + tid;
+  if (c < j0) {
+    const T* w = work + blockIdx.y * wstride + (int64_t)kPanel * c;
+    T wv[kPanel];
+#pragma unroll
+    for (int t = 0; t < kPanel; ++t) wv[t] = t < nb ? w[t] : T(0);
+#pragma unroll
+    for (int i = 0; i < kPanel; ++i) {
+      if (i < nb) {
+        T s = T(0);
+#pragma unroll
+        for (int t = 0; t <= i; ++t) s += Di[i][t] * wv[t];
+        base[(j0 + i) + (int64_t)f.ld * c] = -s;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(NTHR) void k_pchol(const double* __restrict__ G, double* __restrict__ L,
+                                                const int64_t* __restrict__ goff,
+                                                const int* __restrict__ nFa,
+                                                const int* __restrict__ ldga,
+                                                const int64_t* __restrict__ poff,
+                                                int* __restrict__ perm, int* __restrict__ kout,
+                                                double eps) {
+  __shared__ double d[kPcholMax];
+  __shared__ unsigned char piv[kPcholMax];
+  __shared__ double rv[NTHR / 64];
+  __shared__ int ri[NTHR / 64];
+  __shared__ int s_p, s_stop;
+  __shared__ double s_dp, s_r11;
+  const int b = blockIdx.x;
+  const int nF = nFa[b];
+  const int ld = ldga[b];
+  const double* Gb = G + goff[b];
+  double* Lb = L + goff[b];
+  int* pb = perm + poff[b];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int a = tid; a < nF; a += NTHR) {
+    d[a] = Gb[a + (int64_t)ld * a];
+    piv[a] = 0;
+  }
+  __syncthreads();
+  int k = nF;
+  for (int j = 0; j < nF; ++j) {
+    double bv = -DBL_MAX;
+    int bi = INT_MAX;
+    for (int a = tid; a < nF; a += NTHR) {
+      if (!piv[a]) {
+        const double v = d[a];
+        if (v > bv || (v == bv && a < bi)) { bv = v; bi = a; }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { rv[wave] = bv; ri[wave] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 1; w < NTHR / 64; ++w)
+        if (rv[w] > bv || (rv[w] == bv && ri[w] < bi)) { bv = rv[w]; bi = ri[w]; }
+      if (j == 0) s_r11 = bv;
+      const int stop = (j == 0) ? !(bv > 0.0) : !(bv > eps * eps * s_r11);
+      s_stop = stop;
+      if (!stop) {
+        s_p = bi;
+        s_dp = bv;
+        piv[bi] = 1;
+        pb[j] = bi;
+      }
+    }
+    __syncthreads();
+    if (s_stop) { k = j; break; }
+    const int p = s_p;
+    const double ljj = sqrt(s_dp);
+    for (int a = tid; a < nF; a += NTHR) {
+      double v;
+      if (a == p) v = ljj;
+      else if (piv[a]) v = 0.0;
+      else {
+        double s = Gb[a + (int64_t)ld * p];
+        const double* la = Lb + a;
+        const double* lp = Lb + p;
+        int t = 0;
+        for (; t + 4 <= j; t += 4) {
+          s -= la[(int64_t)ld * t] * lp[(int64_t)ld * t] +
+               la[(int64_t)ld * (t + 1)] * lp[(int64_t)ld * (t + 1)] +
+               la[(int64_t)ld * (t + 2)] * lp[(int64_t)ld * (t + 2)] +
+               la[(int64_t)ld * (t + 3)] * lp[(int64_t)ld * (t + 3)];
+        }
+        for (; t < j; ++t) s -= la[(int64_t)ld * t] * lp[(int64_t)ld * t];
+        v = s / ljj;
+        d[a] -= v * v;
+      }
+      Lb[a + (int64_t)ld * j] = v;
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  if (tid == 0) {
+    kout[b] = k;
+    int pos = k;
+    for (int a = 0; a < nF; ++a)
+      if (!piv[a]) pb[pos++] = a;
+  }
+}
+
+}  // namespace
+
+template <typename TIn, typename TC>
+void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch, int max_m,
+                  int max_n, TC alpha, TC beta, hipStream_t s) {
+  if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
+  for (int b0 = 0; b0 < batch; b0 += 65535) {
+    const int nb = std::min(batch - b0, 65535);
+    dim3 grid((unsigned)ceil_div(max_n, BN), (unsigned)ceil_div(max_m, BM), (unsigned)nb);
+    hipLaunchKernelGGL((k_gemm_desc<TIn, TC>), grid, dim3(NTHR), 0, s, opa, opb, flags,
+                       d_desc + b0, alpha, beta);
+    HIF_LAUNCH_CHECK();
+  }
+}
+
+template <typename T>
+void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
+                  T* work, int* err, hipStream_t s) {
+  const int batch = (int)h_fronts.size();
+  if (batch == 0) return;
+  HIF_REQUIRE(batch <= 65535, HIF_EINVAL, "too many fronts in one launch");
+  int maxI = 0;
+  for (auto& f : h_fronts) maxI = std::max(maxI, f.nI);
+  for (int j0 = 0; j0 < maxI; j0 += kPanel) {
+    int max_m = 0, max_n = 0;
+    for (auto& f : h_fronts) {
+      if (f.nI <= j0) continue;
+      const int nb = std::min(kPanel, f.nI - j0);
+      max_m = std::max(max_m, f.nR - j0 - nb);
+      max_n = std::max(max_n, f.nI - j0 - nb);
+    }
+    hipLaunchKernelGGL((k_front_diag<T>), dim3((unsigned)batch), dim3(NTHR), 0, s, arena,
+                       d_fronts, j0, err);
+    HIF_LAUNCH_CHECK();
+    if (max_m > 0) {
+      dim3 gp((unsigned)ceil_div(max_m, NTHR), (unsigned)batch);
+      hipLaunchKernelGGL((k_front_panel<T>), gp, dim3(NTHR), 0, s, arena, d_fronts, j0);
+      HIF_LAUNCH_CHECK();
+    }
+    if (max_m > 0 && max_n > 0) {
+      dim3 gt((unsigned)ceil_div(max_n, BN), (unsigned)ceil_div(max_m, BM), (unsigned)batch);
+      hipLaunchKernelGGL((k_front_trailing<T>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0);
+      HIF_LAUNCH_CHECK();
+    }
+  }
+  front_invert<T>(arena, d_fronts, h_fronts, work, s);
+}
+
+template <typename T>
+void front_invert(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
+                  T* work, hipStream_t s) {
+  const int batch = (int)h_fronts.size();
+  if (batch == 0) return;
+  HIF_REQUIRE(batch <= 65535, HIF_EINVAL, "too many fronts in one launch");
+  int maxI = 0;
+  for (auto& f : h_fronts) maxI = std::max(maxI, f.nI);
+  const int64_t wstride = (int64_t)kPanel * std::max(maxI, 1);
+  for (int j0 = 0; j0 < maxI; j0 += kPanel) {
+    hipLaunchKernelGGL((k_trtri_diag<T>), dim3((unsigned)batch), dim3(NTHR), 0, s, arena,
+                       d_fronts, j0);
+    HIF_LAUNCH_CHECK();
+    if (j0 > 0) {
+      dim3 g((unsigned)ceil_div(j0, BN), 1, (unsigned)batch);
+      hipLaunchKernelGGL((k_trtri_gemm<T>), g, dim3(NTHR), 0, s, arena, d_fronts, j0, work,
+                         wstride);
+      HIF_LAUNCH_CHECK();
+      dim3 g2((unsigned)ceil_div(j0, NTHR), (unsigned)batch);
+      hipLaunchKernelGGL((k_trtri_apply<T>), g2, dim3(NTHR), 0, s, arena, d_fronts, j0,
+                         (const T*)work, wstride);
+      HIF_LAUNCH_CHECK();
+    }
+  }
+}
+
+void pivoted_cholesky(const double* G, double* L, const int64_t* goff, const int* nF,
+                      const int* ldg, const int64_t* poff, int* perm, int* k, int batch,
+                      double eps, hipStream_t s) {
+  if (batch <= 0) return;
+  hipLaunchKernelGGL(k_pchol, dim3((unsigned)batch), dim3(NTHR), 0, s, G, L, goff, nF, ldg, poff,
+                     perm, k, eps);
+  HIF_LAUNCH_CHECK();
+}
+
+template void gemm_batched<double, double>(int, int, int, const GemmDesc*, int, int, int, double,
+                                           double, hipStream_t);
+template void gemm_batched<float, float>(int, int, int, const GemmDesc*, int, int, int, float,
+                                         float, hipStream_t);
+template void gemm_batched<float, double>(int, int, int, const GemmDesc*, int, int, int, double,
+                                          double, hipStream_t);
+template void front_factor<double>(double*, const FrontDesc*, const std::vector<FrontDesc>&,
+                                   double*, int*, hipStream_t);
+template void front_factor<float>(float*, const FrontDesc*, const std::vector<FrontDesc>&, float*,
+                                  int*, hipStream_t);
+template void front_invert<double>(double*, const FrontDesc*, const std::vector<FrontDesc>&,
+                                   double*, hipStream_t);
+template void front_invert<float>(float*, const FrontDesc*, const std::vector<FrontDesc>&, float*,
+                                  hipStream_t);
+
+}  // namespace hif

@@ -1,0 +1,75 @@
+// Batched dense kernels for the HIF fronts (gfx950).
+//
+//   * gemm_batched: C_b = alpha op(A_b) op(B_b) + beta C_b over a batch of
+//     independently sized problems, 64x64 tiles on MFMA (FP64 16x16x4 or FP32
+//     16x16x4), optional triangular masks on the operands and on C.
+//   * front_factor: per front [A_II; A_SI] ((nI+nS) x nI, column-major), a
+//     blocked right-looking Cholesky of the first nI columns (L_I and
+//     L_SI = A_SI L_I^{-T}), then an in-place blocked inverse of L_I.
+//   * pivoted_cholesky: greedy diagonal-pivoted Cholesky of a Gram matrix in
+//     FP64, stopped at relative precision eps (rank-revealing, equivalent to
+//     column-pivoted QR of the Gram's factor).
+#pragma once
+
+#include "common.hpp"
+
+namespace hif {
+
+enum : int { OP_N = 0, OP_T = 1 };
+
+// Triangular structure of the logical operands op(A) (m x k), op(B) (k x n)
+// and of the written part of C.  Masked operand entries read as zero, so the
+// unreferenced triangle of a stored factor may hold anything.
+enum : int {
+  GF_A_LOWER = 1,   // op(A)(i,t) = 0 for t > i
+  GF_A_UPPER = 2,   // op(A)(i,t) = 0 for t < i
+  GF_B_LOWER = 4,   // op(B)(t,j) = 0 for t < j
+  GF_B_UPPER = 8,   // op(B)(t,j) = 0 for t > j
+  GF_C_LOWER = 16,  // only C(i,j) with i >= j is computed and written
+};
+
+struct GemmDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  int m, n, k;
+  int lda, ldb, ldc;
+};
+
+// TIn: element type of A and B; TC: accumulation and C type.
+template <typename TIn, typename TC>
+void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch, int max_m,
+                  int max_n, TC alpha, TC beta, hipStream_t s);
+
+// One front: element offset of its column-major block in the arena, interior
+// count nI, total rows nR = nI + nS, leading dimension ld >= nR.
+struct FrontDesc {
+  int64_t off;
+  int nI, nR, ld;
+  int pad_;
+};
+
+constexpr int kPanel = 32;  // block width of the blocked factorizations
+
+// Partial Cholesky of the first nI columns of every front, then L_I <- L_I^{-1}
+// in place.  work must hold batch * kPanel * max_nI elements.  err[0] receives
+// the smallest batch index with a non-positive pivot (untouched otherwise).
+template <typename T>
+void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
+                  T* work, int* err, hipStream_t s);
+
+// Only the in-place inverse of an already factored lower-triangular L_I.
+template <typename T>
+void front_invert(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
+                  T* work, hipStream_t s);
+
+// Pivoted Cholesky of each symmetric G_b (nF x nF, FP64, offset goff[b], ld ldg[b]).
+// Writes the pivot columns L (same layout as G, column j = j-th pivot, rows in
+// original order), perm (nF entries at poff[b]: pivots then the unpivoted
+// indices ascending) and the rank k[b].  eps > 0.
+constexpr int kPcholMax = 4096;
+void pivoted_cholesky(const double* G, double* L, const int64_t* goff, const int* nF,
+                      const int* ldg, const int64_t* poff, int* perm, int* k, int batch,
+                      double eps, hipStream_t s);
+
+}  // namespace hif

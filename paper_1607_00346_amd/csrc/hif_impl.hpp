@@ -1,0 +1,108 @@
+// Internal data structures of the HIF library: the operator, the per-level
+// factor store and the entry points of the build / apply / solve modules.
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+#include "dense.hpp"
+#include "plan.hpp"
+
+namespace hif {
+
+// 7-point operator: A(p,p) = diag[p]; A(p, p+e_d) = -c_d[p] (c_d = 0 past the
+// last grid line, so the coupling across a wrapped index is always zero).
+struct Stencil {
+  int n;
+  const double* diag;
+  const double* cx;
+  const double* cy;
+  const double* cz;
+};
+
+// Face skeleton of one face with r = |F̌| > 0 (k = |F̂| may be 0).  Offsets are
+// element offsets into the level's skeleton arena (T: k x r, Lc^{-1}: r x r,
+// Y: r x k, all column-major with ld = rows) and into the level's skeleton
+// point list (the face's points in pivot order: F̂ then F̌).
+struct SkelDesc {
+  int face, k, r, pad_;
+  int64_t pts_off;
+  int64_t offT, offL, offY;
+};
+
+template <typename T>
+struct Level {
+  LevelPlan P;
+  // cells
+  DevBuf<int> rows;
+  DevBuf<int64_t> crow_off;
+  std::vector<FrontDesc> hfd;
+  DevBuf<FrontDesc> fd;
+  DevBuf<T> front;  // per cell [L_I^{-1}; L_SI], (nI+nS) x nI column-major
+  DevBuf<int64_t> yoff, zoff;  // per cell offsets into the apply scratch vectors
+  int64_t ysum = 0, zsum = 0;
+  int maxI = 0, maxS = 0;
+  // faces
+  DevBuf<int> fpts, fN, fcellA, fcellB, rb_face, rb_off, rb_sa, rb_sb;
+  DevBuf<int64_t> fpt_off;
+  DevBuf<T> panel;  // per face Ã^l([F; other faces of both cells], F)
+  DevBuf<int64_t> panel_off;
+  DevBuf<int> panel_ld;
+  int maxF = 0;
+  // skeletons
+  std::vector<int> hk;      // rank per face
+  DevBuf<int> skpts;        // face points in pivot order (offsets = fpt_off)
+  std::vector<SkelDesc> hsk;
+  DevBuf<SkelDesc> sk;
+  DevBuf<T> skel;
+  int maxk = 0, maxr = 0;
+  int64_t redundant = 0;
+};
+
+struct FactorBase {
+  virtual ~FactorBase() = default;
+  virtual void apply(const double* f, double* u, hipStream_t s) = 0;
+  virtual int64_t stored_bytes() const = 0;
+};
+
+template <typename T>
+struct FactorImpl : FactorBase {
+  int n = 0, L = 0;
+  int64_t N = 0;
+  std::vector<Level<T>> levels;
+  DevBuf<double> ybuf, zbuf, xs;  // apply scratch
+  void apply(const double* f, double* u, hipStream_t s) override;
+  int64_t stored_bytes() const override;
+};
+
+}  // namespace hif
+
+struct hif_problem_s {
+  hif_options opts;
+  int n = 0;
+  int64_t N = 0;
+  hif::DevBuf<double> diag, cx, cy, cz;
+  hif::Stencil stencil() const { return {n, diag.get(), cx.get(), cy.get(), cz.get()}; }
+};
+
+struct hif_factor_s {
+  hif_options opts;
+  std::unique_ptr<hif::FactorBase> impl;
+  hif_stats stats;
+  std::vector<std::vector<uint8_t>> active_after;  // per level l < L
+  std::vector<std::vector<int>> ranks, sizes;      // per level l < L
+};
+
+namespace hif {
+
+void problem_assemble(hif_problem_s* A, const double* a, const double* b, hipStream_t s);
+void stencil_matvec(const Stencil& st, const double* x, double* y, hipStream_t s);
+
+template <typename T>
+void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, hif_factor_s* F);
+
+void pcg_solve(const hif_problem_s* A, hif_factor_s* F, const double* f, double* u, double tol,
+               int maxit, hif_pcg_info* info, hipStream_t s);
+
+}  // namespace hif

@@ -1,0 +1,198 @@
+"""Thin ctypes binding of the HIF C ABI (include/hif.h).
+
+Argument marshalling only: every step of the factorization, apply and solve
+runs in the HIP kernels of libhif.so.  Device arrays are torch CUDA tensors
+(float64, contiguous); streams are torch streams.  Loading fails loudly if
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhif.so")
+
+HIF_OK, HIF_EINVAL, HIF_ENOMEM, HIF_ENOTSPD, HIF_ENOCONV, HIF_EDEVICE = 0, -1, -2, -3, -4, -5
+HIF_FP64, HIF_MIXED = 0, 1
+HIF_DIRICHLET = 0
+HIF_MAX_LEVELS = 16
+
+EXPORTED = [
+    "hif_problem_create", "hif_build", "hif_apply", "hif_matvec", "hif_pcg",
+    "hif_factor_stats", "hif_factor_ranks", "hif_factor_active", "hif_factor_destroy",
+    "hif_problem_destroy", "hif_status_string", "hif_last_error",
+]
+
+
+class hif_options(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("leaf", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("bc", ctypes.c_int32)]
+
+
+class hif_pcg_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("relres", ctypes.c_double)]
+
+
+_M = HIF_MAX_LEVELS
+
+
+class hif_stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("n_dof", ctypes.c_int64), ("root_size", ctypes.c_int64),
+                ("cells", ctypes.c_int64 * (_M + 1)), ("faces", ctypes.c_int64 * _M),
+                ("eliminated", ctypes.c_int64 * (_M + 1)), ("face_dofs", ctypes.c_int64 * _M),
+                ("redundant", ctypes.c_int64 * _M), ("max_front", ctypes.c_int64 * (_M + 1)),
+                ("level_seconds", ctypes.c_double * (_M + 1)), ("factor_flops", ctypes.c_double),
+                ("factor_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
+                ("build_seconds", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        L = self.levels
+        return {
+            "levels": L, "precision": self.precision, "n_dof": self.n_dof,
+            "root_size": self.root_size,
+            "cells": list(self.cells[:L + 1]), "faces": list(self.faces[:L]),
+            "eliminated": list(self.eliminated[:L + 1]), "face_dofs": list(self.face_dofs[:L]),
+            "redundant": list(self.redundant[:L]), "max_front": list(self.max_front[:L + 1]),
+            "level_seconds": list(self.level_seconds[:L + 1]),
+            "factor_flops": self.factor_flops, "factor_bytes": self.factor_bytes,
+            "peak_bytes": self.peak_bytes, "build_seconds": self.build_seconds,
+        }
+
+
+class HifError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status}: {detail}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libhif.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        L.hif_problem_create.argtypes = [ctypes.POINTER(hif_options), vp, vp, vp,
+                                         ctypes.POINTER(vp)]
+        L.hif_build.argtypes = [vp, ctypes.POINTER(hif_options), vp, ctypes.POINTER(vp)]
+        L.hif_apply.argtypes = [vp, vp, vp, i32, vp]
+        L.hif_matvec.argtypes = [vp, vp, vp, i32, vp]
+        L.hif_pcg.argtypes = [vp, vp, vp, vp, i32, f64, i32, ctypes.POINTER(hif_pcg_info), vp]
+        L.hif_factor_stats.argtypes = [vp, ctypes.POINTER(hif_stats)]
+        L.hif_factor_ranks.argtypes = [vp, i32, vp, vp, i32, ctypes.POINTER(i32)]
+        L.hif_factor_active.argtypes = [vp, i32, vp]
+        L.hif_factor_destroy.argtypes = [vp]
+        L.hif_problem_destroy.argtypes = [vp]
+        L.hif_status_string.argtypes = [i32]
+        L.hif_status_string.restype = ctypes.c_char_p
+        L.hif_last_error.restype = ctypes.c_char_p
+        for name in ("hif_problem_create", "hif_build", "hif_apply", "hif_matvec", "hif_pcg",
+                     "hif_factor_stats", "hif_factor_ranks", "hif_factor_active"):
+            getattr(L, name).restype = ctypes.c_int
+        L.hif_factor_destroy.restype = None
+        L.hif_problem_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str, allow=()) -> int:
+    if status != HIF_OK and status not in allow:
+        raise HifError(status, where, lib().hif_last_error().decode())
+    return status
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+def _dptr(t):
+    import torch
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), "need contiguous CUDA f64"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_options(n: int, leaf: int, eps: float, precision: int = HIF_FP64,
+                 bc: int = HIF_DIRICHLET) -> hif_options:
+    return hif_options(int(n), int(leaf), float(eps), int(precision), int(bc))
+
+
+def hif_problem_create(opts: hif_options, a, b, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().hif_problem_create(ctypes.byref(opts), _dptr(a), _dptr(b), _stream(stream),
+                                    ctypes.byref(h)), "hif_problem_create")
+    return h
+
+
+def hif_build(A, opts: hif_options, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().hif_build(A, ctypes.byref(opts), _stream(stream), ctypes.byref(h)), "hif_build")
+    return h
+
+
+def hif_apply(F, f, u, nrhs: int = 1, stream=None):
+    _check(lib().hif_apply(F, _dptr(f), _dptr(u), int(nrhs), _stream(stream)), "hif_apply")
+
+
+def hif_matvec(A, x, y, nrhs: int = 1, stream=None):
+    _check(lib().hif_matvec(A, _dptr(x), _dptr(y), int(nrhs), _stream(stream)), "hif_matvec")
+
+
+def hif_pcg(A, F, f, u, nrhs: int = 1, tol: float = 1e-10, maxit: int = 500, stream=None):
+    """Returns (status, [hif_pcg_info]); HIF_ENOCONV is reported, not raised."""
+    info = (hif_pcg_info * max(nrhs, 1))()
+    st = _check(lib().hif_pcg(A, F, _dptr(f), _dptr(u), int(nrhs), float(tol), int(maxit),
+                              info, _stream(stream)), "hif_pcg", allow=(HIF_ENOCONV,))
+    return st, [info[i] for i in range(nrhs)]
+
+
+def hif_factor_stats(F) -> hif_stats:
+    s = hif_stats()
+    _check(lib().hif_factor_stats(F, ctypes.byref(s)), "hif_factor_stats")
+    return s
+
+
+def hif_factor_ranks(F, level: int):
+    import numpy as np
+    cnt = ctypes.c_int32()
+    _check(lib().hif_factor_ranks(F, int(level), None, None, 0, ctypes.byref(cnt)),
+           "hif_factor_ranks")
+    ranks = np.zeros(cnt.value, dtype=np.int32)
+    sizes = np.zeros(cnt.value, dtype=np.int32)
+    _check(lib().hif_factor_ranks(F, int(level), ranks.ctypes.data_as(ctypes.c_void_p),
+                                  sizes.ctypes.data_as(ctypes.c_void_p), cnt.value,
+                                  ctypes.byref(cnt)), "hif_factor_ranks")
+    return ranks, sizes
+
+
+def hif_factor_active(F, level: int, n_dof: int):
+    import numpy as np
+    m = np.zeros(n_dof, dtype=np.uint8)
+    _check(lib().hif_factor_active(F, int(level), m.ctypes.data_as(ctypes.c_void_p)),
+           "hif_factor_active")
+    return m
+
+
+def hif_factor_destroy(F):
+    lib().hif_factor_destroy(F)
+
+
+def hif_problem_destroy(A):
+    lib().hif_problem_destroy(A)
+
+
+def hif_status_string(s: int) -> str:
+    return lib().hif_status_string(int(s)).decode()
+
+
+def hif_last_error() -> str:
+    return lib().hif_last_error().decode()

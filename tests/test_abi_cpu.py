@@ -1,0 +1,65 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+that include/hif.h declares, and rejects bad arguments before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1607_00346_amd import hif as H
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "hif.h")).read()
+    return sorted(set(re.findall(r"\b(hif_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(H.LIB_PATH):
+        pytest.skip("library not built")
+    return H.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert "hif_build" in names and "hif_pcg" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(H.EXPORTED) == names
+
+
+def test_status_strings(L):
+    for s in (H.HIF_OK, H.HIF_EINVAL, H.HIF_ENOMEM, H.HIF_ENOTSPD, H.HIF_ENOCONV, H.HIF_EDEVICE):
+        assert H.hif_status_string(s).startswith("HIF_")
+
+
+@pytest.mark.parametrize("n,leaf,eps,prec", [
+    (7, 2, 1e-6, 0),      # 7 is not leaf * 2^L
+    (16, 1, 1e-6, 0),     # leaf < 2
+    (16, 4, -1.0, 0),     # eps < 0
+    (16, 4, float("nan"), 0),
+    (16, 4, 1e-6, 7),     # unknown precision
+    (0, 2, 1e-6, 0),
+])
+def test_bad_options_rejected(L, n, leaf, eps, prec):
+    opts = H.make_options(n, leaf, eps, prec)
+    h = ctypes.c_void_p(123)
+    dummy = ctypes.c_void_p(16)  # never dereferenced: options are checked first
+    st = L.hif_problem_create(ctypes.byref(opts), dummy, dummy, None, ctypes.byref(h))
+    assert st == H.HIF_EINVAL
+    assert h.value is None
+    assert len(H.hif_last_error()) > 0
+
+
+def test_null_arguments_rejected(L):
+    opts = H.make_options(16, 4, 1e-6)
+    h = ctypes.c_void_p()
+    assert L.hif_problem_create(ctypes.byref(opts), None, None, None, ctypes.byref(h)) == H.HIF_EINVAL
+    assert L.hif_problem_create(None, None, None, None, ctypes.byref(h)) == H.HIF_EINVAL
+    assert L.hif_apply(None, None, None, 1, None) == H.HIF_EINVAL
+    assert L.hif_pcg(None, None, None, None, 1, 1e-10, 10, None, None) == H.HIF_EINVAL
+    cnt = ctypes.c_int32()
+    assert L.hif_factor_ranks(None, 0, None, None, 0, ctypes.byref(cnt)) == H.HIF_EINVAL

@@ -1,0 +1,253 @@
+"""GPU path vs the CPU oracle, through the C ABI.
+
+Tolerances:
+  * FP64 at eps = 0 the HIF is exact nested dissection, so F^{-1} f equals
+    A^{-1} f up to rounding: relative error <= 1e-11 (kappa(A) u with
+    kappa <= 1e5 on these grids, u = 1.1e-16).
+  * Mixed precision at eps = 0: the factor is an FP32 Cholesky, error ~
+    kappa(A) * u32 * growth; bound 2e-3 on the small grids used here.
+  * eps > 0: skeleton sets can differ on near ties (several answers are
+    correct), so ranks are compared face by face with a small allowed
+    fraction of mismatches, and the preconditioned solves are compared after
+    PCG to 1e-12 (|u - u_oracle| / |u_oracle| <= 1e-9).
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle as O
+from workloads import const_field, log_uniform_field, normal_rhs, uniform_field
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
+
+
+class GpuHif:
+    def __init__(self, H, n, leaf, eps, a, b, precision=0):
+        import torch
+        self.H = H
+        self.n = n
+        self.opts = H.make_options(n, leaf, eps, precision)
+        self.ta, self.tb = _t(a), _t(b)
+        self.A = H.hif_problem_create(self.opts, self.ta, self.tb)
+        self.F = H.hif_build(self.A, self.opts)
+        torch.cuda.synchronize()
+
+    def apply(self, f):
+        import torch
+        tf = _t(f)
+        tu = torch.empty_like(tf)
+        self.H.hif_apply(self.F, tf, tu)
+        torch.cuda.synchronize()
+        return tu.cpu().numpy()
+
+    def matvec(self, x):
+        import torch
+        tx = _t(x)
+        ty = torch.empty_like(tx)
+        self.H.hif_matvec(self.A, tx, ty)
+        torch.cuda.synchronize()
+        return ty.cpu().numpy()
+
+    def pcg(self, f, tol, maxit=300):
+        import torch
+        tf = _t(f)
+        tu = torch.empty_like(tf)
+        st, info = self.H.hif_pcg(self.A, self.F, tf, tu, tol=tol, maxit=maxit)
+        torch.cuda.synchronize()
+        return st, info[0], tu.cpu().numpy()
+
+    def stats(self):
+        return self.H.hif_factor_stats(self.F).as_dict()
+
+    def close(self):
+        self.H.hif_factor_destroy(self.F)
+        self.H.hif_problem_destroy(self.A)
+
+
+@pytest.mark.parametrize("n", [5, 12])
+def test_matvec_matches_oracle(gpu_lib, n):
+    a = log_uniform_field(n, -2, 2, 81)
+    b = uniform_field(n, 0, 1, 82)
+    x = normal_rhs(n, 83)
+    A = O.assemble(n, a, b)
+    g = GpuHif(gpu_lib, n, n, 0.0, a, b)
+    y = g.matvec(x)
+    ref = A @ x
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    g.close()
+
+
+@pytest.mark.parametrize("n,leaf", [(4, 4), (8, 2), (12, 3), (16, 4), (16, 8), (24, 6), (32, 8)])
+def test_eps0_apply_is_exact(gpu_lib, n, leaf):
+    """eps = 0: GPU F^{-1} f = A^{-1} f (sparse direct solve) and = oracle apply."""
+    a = log_uniform_field(n, -2, 2, 91 + n)
+    b = const_field(n, 0.0)
+    f = normal_rhs(n, 92 + n)
+    A = O.assemble(n, a, b)
+    ref = spla.spsolve(A.tocsc(), f)
+    g = GpuHif(gpu_lib, n, leaf, 0.0, a, b)
+    u = g.apply(f)
+    err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+    assert err <= 1e-11, err
+    st = g.stats()
+    counts, root = O.count_levels(n, leaf)
+    assert st["eliminated"][:len(counts)] == counts
+    assert st["root_size"] == root
+    g.close()
+
+
+@pytest.mark.parametrize("n,leaf", [(16, 4), (32, 8)])
+def test_eps0_mixed_precision(gpu_lib, n, leaf):
+    a = log_uniform_field(n, -1, 1, 101)
+    b = const_field(n, 0.0)
+    f = normal_rhs(n, 102)
+    A = O.assemble(n, a, b)
+    ref = spla.spsolve(A.tocsc(), f)
+    g = GpuHif(gpu_lib, n, leaf, 0.0, a, b, precision=1)
+    u = g.apply(f)
+    err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+    assert err <= 2e-3, err
+    st, info, u2 = g.pcg(f, 1e-10)
+    assert st == 0 and info.converged and info.relres <= 1e-10
+    assert np.linalg.norm(u2 - ref) / np.linalg.norm(ref) <= 1e-8
+    g.close()
+
+
+@pytest.mark.parametrize("n,leaf,eps", [(16, 4, 1e-6), (16, 4, 1e-3), (32, 8, 1e-6)])
+def test_eps_ranks_match_oracle(gpu_lib, n, leaf, eps):
+    a = log_uniform_field(n, -1, 1, 111)
+    b = const_field(n, 0.0)
+    fac = O.build(n, leaf, a, b, eps)
+    g = GpuHif(gpu_lib, n, leaf, eps, a, b)
+    total, bad = 0, 0
+    for level, lev in enumerate(fac.levels):
+        ranks, sizes = gpu_lib.hif_factor_ranks(g.F, level)
+        assert list(sizes) == lev.face_sizes
+        total += len(ranks)
+        bad += int(np.sum(np.abs(np.array(ranks) - np.array(lev.face_ranks)) > 1))
+    assert bad <= max(1, total // 50), (bad, total)
+    st = g.stats()
+    assert abs(st["root_size"] - fac.root_size) <= max(3, fac.root_size // 50)
+    g.close()
+
+
+@pytest.mark.parametrize("n,leaf,eps", [(16, 4, 1e-6), (32, 8, 1e-4)])
+def test_apply_close_to_oracle(gpu_lib, n, leaf, eps):
+    """eps > 0: both F^{-1} approximate A^{-1} to O(eps); they agree far better
+    than that when the skeletons coincide."""
+    a = log_uniform_field(n, -1, 1, 121)
+    b = const_field(n, 0.0)
+    f = normal_rhs(n, 122)
+    fac = O.build(n, leaf, a, b, eps)
+    g = GpuHif(gpu_lib, n, leaf, eps, a, b)
+    u = g.apply(f)
+    uo = O.apply_inverse(fac, f)
+    d = np.linalg.norm(u - uo) / np.linalg.norm(uo)
+    A = O.assemble(n, a, b)
+    x = normal_rhs(n, 123)
+    es_gpu = np.linalg.norm(x - g.apply(A @ x)) / np.linalg.norm(x)
+    es_or = O.relative_solve_error(fac, A, x)
+    assert d <= 50 * eps, d
+    assert es_gpu <= 3 * es_or + 1e-12, (es_gpu, es_or)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_pcg_matches_oracle_solution(gpu_lib, prec):
+    n, leaf, eps = 32, 8, 1e-4
+    a = log_uniform_field(n, -2, 2, 131)
+    b = const_field(n, 0.0)
+    f = normal_rhs(n, 132)
+    A = O.assemble(n, a, b)
+    fac = O.build(n, leaf, a, b, eps)
+    uo, _, rel_o, ok = O.pcg(A, lambda r: O.apply_inverse(fac, r), f, 1e-13, 300)
+    assert ok
+    g = GpuHif(gpu_lib, n, leaf, eps, a, b, precision=prec)
+    st, info, u = g.pcg(f, 1e-13)
+    assert st == 0 and info.converged
+    res = np.linalg.norm(f - A @ u) / np.linalg.norm(f)
+    assert res <= 1e-12
+    assert np.linalg.norm(u - uo) / np.linalg.norm(uo) <= 1e-10
+    g.close()
+
+
+def test_indefinite_reports_not_spd(gpu_lib):
+    n = 8
+    a = const_field(n, 1.0)
+    b = const_field(n, -1e6)   # far below -lambda_min: A is indefinite
+    H = gpu_lib
+    opts = H.make_options(n, 2, 0.0)
+    A = H.hif_problem_create(opts, _t(a), _t(b))
+    with pytest.raises(H.HifError) as ei:
+        H.hif_build(A, opts)
+    assert ei.value.status == H.HIF_ENOTSPD
+    H.hif_problem_destroy(A)
+
+
+def test_bad_coefficients_rejected(gpu_lib):
+    n = 8
+    H = gpu_lib
+    opts = H.make_options(n, 2, 0.0)
+    a = const_field(n, 1.0)
+    a[17] = -1.0
+    with pytest.raises(H.HifError) as ei:
+        H.hif_problem_create(opts, _t(a), _t(const_field(n, 0.0)))
+    assert ei.value.status == H.HIF_EINVAL
+    a[17] = np.nan
+    with pytest.raises(H.HifError):
+        H.hif_problem_create(opts, _t(a), _t(const_field(n, 0.0)))
+
+
+def test_pcg_maxit_reports_noconv(gpu_lib):
+    n, leaf = 16, 4
+    a = log_uniform_field(n, -2, 2, 141)
+    b = const_field(n, 0.0)
+    g = GpuHif(gpu_lib, n, leaf, 1e-2, a, b)
+    st, info, _ = g.pcg(normal_rhs(n, 142), 1e-14, maxit=1)
+    assert st == gpu_lib.HIF_ENOCONV and not info.converged and info.iters == 1
+    g.close()
+
+
+def test_empty_rhs_and_zero_rhs(gpu_lib):
+    import torch
+    n, leaf = 8, 2
+    g = GpuHif(gpu_lib, n, leaf, 1e-6, const_field(n, 1.0), const_field(n, 0.0))
+    tf = torch.zeros(n ** 3, dtype=torch.float64, device="cuda:0")
+    tu = torch.empty_like(tf)
+    gpu_lib.hif_apply(g.F, tf, tu, nrhs=0)
+    st, info, u = g.pcg(np.zeros(n ** 3), 1e-10)
+    assert st == 0 and info.converged and np.all(u == 0)
+    g.close()
+
+
+def test_multi_rhs_apply(gpu_lib):
+    import torch
+    n, leaf = 16, 4
+    a = log_uniform_field(n, -1, 1, 151)
+    g = GpuHif(gpu_lib, n, leaf, 1e-4, a, const_field(n, 0.0))
+    F = normal_rhs(n, 152, nrhs=3)
+    tf = _t(F)
+    tu = torch.empty_like(tf)
+    gpu_lib.hif_apply(g.F, tf, tu, nrhs=3)
+    torch.cuda.synchronize()
+    U = tu.cpu().numpy()
+    for i in range(3):
+        assert np.allclose(U[i], g.apply(F[i]), rtol=0, atol=1e-14 * np.abs(U[i]).max())
+    g.close()
+
+
+def test_deterministic_factor(gpu_lib):
+    n, leaf = 16, 4
+    a = log_uniform_field(n, -2, 2, 161)
+    b = const_field(n, 0.0)
+    f = normal_rhs(n, 162)
+    g1 = GpuHif(gpu_lib, n, leaf, 1e-5, a, b)
+    g2 = GpuHif(gpu_lib, n, leaf, 1e-5, a, b)
+    assert np.array_equal(g1.apply(f), g2.apply(f))
+    g1.close()
+    g2.close()
