@@ -10,8 +10,9 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-// 16x16x4 MFMA.  Lane l supplies A(l%16, l/16) and B(l/16, l%16); result
-// element v of lane l is C(4*(l/16)+v, l%16).
+// 16x16x4 MFMA.  Lane l supplies A(l%16, l/16) and B(l/16, l%16).  Result
+// element v of lane l is C(row(l, v), l%16): row = l/16 + 4v for FP64 and
+// 4(l/16) + v for FP32 (measured on gfx950).
 template <typename TC>
 struct Mfma;
 template <>
@@ -20,6 +21,7 @@ struct Mfma<double> {
   static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 template <>
 struct Mfma<float> {
@@ -27,6 +29,7 @@ struct Mfma<float> {
   static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
 constexpr int BM = 64, BN = 64, KC = 16, NTHR = 256;
@@ -128,7 +131,7 @@ __device__ void gemm_tile(int opa, int opb, int flags, const TIn* __restrict__ A
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gi = m0 + wm * 32 + x * 16 + 4 * (lane >> 4) + v;
+        const int gi = m0 + wm * 32 + x * 16 + Mfma<TC>::row(lane, v);
         const int gj = n0 + wn * 32 + y * 16 + (lane & 15);
         if (gi < m && gj < n && (!(flags & GF_C_LOWER) || gi >= gj)) {
           const int64_t idx = gi + (int64_t)ldc * gj;
