@@ -1,0 +1,223 @@
+"""Benchmark: HIF factor + PCG solve throughput (DOF/s) on one MI355X.
+
+One step = hif_build of the 128^3 high-contrast problem (log10 a ~ U(-2,2)
+per node, b = 0, leaf 8^3) followed by hif_pcg to a true relative residual of
+1e-10.  `value` is the mixed-precision run (FP32 fronts, eps = 1e-4, FP64
+PCG); the plain FP64 GPU HIF (eps = 1e-6) is timed beside it.  Inputs are
+synthetic and already resident in HBM when timing starts.
+
+Prints ONE JSON line (rank 0).  Only one GPU is supported: --gpus > 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from workloads import WORKLOADS  # noqa: E402
+
+PEAK = {"fp64_tflops": 78.6, "fp32_tflops": 157.3, "hbm_gbs": 8000.0}
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_gpu(args):
+    import torch
+    from paper_1607_00346_amd import hif as H
+
+    wl_m = WORKLOADS[args.workload + "_mixed"]
+    wl_d = WORKLOADS[args.workload + "_fp64"]
+    n, leaf = wl_m.n, wl_m.leaf
+    N = n ** 3
+    dev = torch.device("cuda:0")
+    a, b, f = wl_m.a(), wl_m.b(), wl_m.f()
+    ta = torch.tensor(a, dtype=torch.float64, device=dev)
+    tb = torch.tensor(b, dtype=torch.float64, device=dev)
+    tf = torch.tensor(f, dtype=torch.float64, device=dev)
+    tu = torch.zeros_like(tf)
+    opt_m = H.make_options(n, leaf, wl_m.eps, H.HIF_MIXED)
+    opt_d = H.make_options(n, leaf, wl_d.eps, H.HIF_FP64)
+    A = H.hif_problem_create(opt_m, ta, tb)
+    torch.cuda.synchronize()
+
+    def step(opts, keep=False):
+        t0 = time.perf_counter()
+        F = H.hif_build(A, opts)
+        t1 = time.perf_counter()
+        st, info = H.hif_pcg(A, F, tf, tu, tol=args.tol, maxit=args.maxit)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        stats = H.hif_factor_stats(F).as_dict()
+        if keep:
+            return F, st, info[0], stats, t1 - t0, t2 - t1
+        H.hif_factor_destroy(F)
+        return None, st, info[0], stats, t1 - t0, t2 - t1
+
+    def timed(opts, label):
+        for i in range(args.warmup):
+            _, st, info, _, tf_, ts_ = step(opts)
+            log(f"[{label}] warmup {i}: factor {tf_:.3f}s pcg {ts_:.3f}s it={info.iters}")
+        torch.cuda.synchronize()
+        H.hif_profile_begin()
+        t0 = time.perf_counter()
+        rec = []
+        for i in range(args.steps):
+            _, st, info, stats, tf_, ts_ = step(opts)
+            rec.append((st, info.iters, info.relres, info.converged, tf_, ts_))
+            log(f"[{label}] step {i}: factor {tf_:.3f}s pcg {ts_:.3f}s it={info.iters} "
+                f"relres={info.relres:.2e}")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = H.hif_profile_end()
+        return (t1 - t0) / args.steps, rec, stats, prof
+
+    ms_m, rec_m, stats_m, prof_m = timed(opt_m, "mixed")
+    u_m = tu.cpu().numpy().copy()
+    out = {"mixed": {"s_per_step": ms_m, "rec": rec_m, "stats": stats_m, "u": u_m,
+                     "prof": prof_m}}
+    if not args.skip_fp64:
+        ms_d, rec_d, stats_d, prof_d = timed(opt_d, "fp64")
+        out["fp64"] = {"s_per_step": ms_d, "rec": rec_d, "stats": stats_d,
+                       "u": tu.cpu().numpy().copy(), "prof": prof_d}
+    H.hif_problem_destroy(A)
+    out["N"] = N
+    out["a"], out["b"], out["f"] = a, b, f
+    return out
+
+
+def roofline(prof, fp64: bool):
+    """Dominant kernel class of the timed region against its roofline: flops
+    for the matrix-core kernels, bytes for the sweeps."""
+    name, k = max(prof.items(), key=lambda kv: kv[1]["seconds"])
+    avg = k["seconds"] / max(k["launches"], 1)
+    if k["flops"] > 0 and not name.startswith("apply") and name not in ("matvec", "pcg_dot"):
+        peak = PEAK["fp64_tflops"] if (fp64 or name in ("gemm_gram", "gemm_interp")) \
+            else PEAK["fp32_tflops"]
+        ach = k["flops"] / k["seconds"] / 1e12
+        return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": None, "kernel": name,
+                "launches": k["launches"], "avg_launch_us": avg * 1e6,
+                "flops_per_launch": k["flops"] / max(k["launches"], 1)}
+    ach = k["bytes"] / k["seconds"] / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+            "frac": ach / PEAK["hbm_gbs"], "traffic": None, "kernel": name,
+            "launches": k["launches"], "avg_launch_us": avg * 1e6,
+            "bytes_per_launch": k["bytes"] / max(k["launches"], 1)}
+
+
+def kernel_table(prof, steps):
+    tot = sum(v["seconds"] for v in prof.values())
+    rows = []
+    for name, v in sorted(prof.items(), key=lambda kv: -kv[1]["seconds"]):
+        r = {"kernel": name, "ms_per_step": 1e3 * v["seconds"] / steps,
+             "share": v["seconds"] / tot if tot else 0.0, "launches": v["launches"] // steps}
+        if v["flops"] > 0:
+            r["tflops"] = v["flops"] / v["seconds"] / 1e12
+        if v["bytes"] > 0:
+            r["gbs"] = v["bytes"] / v["seconds"] / 1e9
+        rows.append(r)
+    return rows
+
+
+def cpu_baseline(args):
+    """The oracle (plain FP64 CPU HIF) on a bounded sample of the same law."""
+    import oracle as O
+    wl = WORKLOADS["c32_contrast"]
+    n, leaf = wl.n, wl.leaf
+    a, b, f = wl.a(), wl.b(), wl.f()
+    reps = 2
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fac = O.build(n, leaf, a, b, 1e-4)
+        A = O.assemble(n, a, b)
+        _, it, rel, ok = O.pcg(A, lambda r: O.apply_inverse(fac, r), f, args.tol, args.maxit)
+    dt = (time.perf_counter() - t0) / reps
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    return {"value": n ** 3 / dt, "unit": "DOF/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n}^3 log10 a~U(-2,2), leaf {leaf}, eps 1e-4, oracle build + PCG to "
+                      f"{args.tol:g} ({it} it, {dt:.1f} s per solve, {reps} solves)"}
+
+
+def main():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=2)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="c128")
+    p.add_argument("--tol", type=float, default=1e-10)
+    p.add_argument("--maxit", type=int, default=500)
+    p.add_argument("--skip-fp64", action="store_true")
+    p.add_argument("--skip-cpu", action="store_true")
+    args = p.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    r = run_gpu(args)
+    N = r["N"]
+    mixed = r["mixed"]
+    value = N / mixed["s_per_step"]
+    import scipy.sparse  # noqa: F401
+    import oracle as O
+    A = O.assemble(int(round(N ** (1 / 3))), r["a"], r["b"])
+    fn = np.linalg.norm(r["f"])
+    res_m = float(np.linalg.norm(r["f"] - A @ mixed["u"]) / fn)
+    extra = {"mixed_relres_oracle_matvec": res_m,
+             "mixed_pcg_iters": mixed["rec"][-1][1],
+             "mixed_t_factor_s": float(np.mean([x[4] for x in mixed["rec"]])),
+             "mixed_t_pcg_s": float(np.mean([x[5] for x in mixed["rec"]])),
+             "mixed_root_size": mixed["stats"]["root_size"],
+             "mixed_factor_gb": mixed["stats"]["factor_bytes"] / 1e9,
+             "mixed_peak_gb": mixed["stats"]["peak_bytes"] / 1e9}
+    if "fp64" in r:
+        d = r["fp64"]
+        extra.update({
+            "fp64_value": N / d["s_per_step"],
+            "fp64_pcg_iters": d["rec"][-1][1],
+            "fp64_t_factor_s": float(np.mean([x[4] for x in d["rec"]])),
+            "fp64_t_pcg_s": float(np.mean([x[5] for x in d["rec"]])),
+            "fp64_relres_oracle_matvec": float(np.linalg.norm(r["f"] - A @ d["u"]) / fn),
+            "mixed_vs_fp64_solution_diff": float(np.linalg.norm(mixed["u"] - d["u"])
+                                                 / np.linalg.norm(d["u"])),
+            "mixed_over_fp64": d["s_per_step"] / mixed["s_per_step"],
+            "fp64_root_size": d["stats"]["root_size"],
+        })
+    line = {
+        "metric": "HIF factor+solve DOF/s at 128^3 to PCG rel. residual 1e-10, mixed vs FP64",
+        "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": mixed["s_per_step"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: 128^3 7-point, log10 a~U(-2,2), b=0, leaf 8, "
+                               "mixed eps 1e-4 (FP32 fronts) vs FP64 eps 1e-6, PCG 1e-10",
+                   "n": 128, "leaf": 8, "eps_mixed": 1e-4, "eps_fp64": 1e-6},
+        "extra": extra,
+    }
+    line["roofline"] = roofline(mixed["prof"], fp64=False)
+    apply_classes = {k: v for k, v in mixed["prof"].items() if k.startswith("apply_")}
+    if apply_classes:
+        line["extra"]["roofline_apply"] = roofline(apply_classes, fp64=False)
+    line["extra"]["kernels_mixed"] = kernel_table(mixed["prof"], args.steps)
+    if "fp64" in r:
+        line["extra"]["roofline_fp64"] = roofline(r["fp64"]["prof"], fp64=True)
+        line["extra"]["kernels_fp64"] = kernel_table(r["fp64"]["prof"], args.steps)
+    line["extra"]["stats_mixed"] = {k: mixed["stats"][k] for k in (
+        "cells", "faces", "eliminated", "face_dofs", "redundant", "max_front", "level_seconds",
+        "factor_flops")}
+    if not args.skip_cpu:
+        line["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

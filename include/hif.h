@@ -128,6 +128,25 @@ hif_status hif_factor_ranks(hif_factor_t F, int32_t level, int32_t* ranks, int32
  * still active in A^{level+1} (host array of N bytes). */
 hif_status hif_factor_active(hif_factor_t F, int32_t level, uint8_t* mask);
 
+/* Per-kernel-class device timing.  hif_profile_begin() clears and starts
+ * recording: every library kernel launch made afterwards (on any stream)
+ * is bracketed by a pair of HIP events recorded on that launch's stream,
+ * together with the launch's algorithmic flops and bytes.  hif_profile_end()
+ * waits for the recorded events, stops recording and returns one entry per
+ * kernel class (host array of `cap` entries; *count = number of classes).
+ * Process-wide and not thread safe; it exists for benchmarks and
+ * roofline measurements. */
+typedef struct {
+  char name[40];     /* kernel class, e.g. "gemm_syrk", "apply_up_L"           */
+  int64_t launches;  /* timed launches                                        */
+  double seconds;    /* summed event-to-event device time                     */
+  double flops;      /* algorithmic flops of those launches (0: not counted)  */
+  double bytes;      /* algorithmic HBM bytes of those launches (0: not counted) */
+} hif_kernel_stat;
+
+hif_status hif_profile_begin(void);
+hif_status hif_profile_end(hif_kernel_stat* out, int32_t cap, int32_t* count);
+
 void hif_factor_destroy(hif_factor_t F);
 void hif_problem_destroy(hif_problem_t A);
 

@@ -6,6 +6,7 @@
 #include <string>
 
 #include "hif_impl.hpp"
+#include "prof.hpp"
 
 namespace hif {
 
@@ -175,6 +176,51 @@ hif_status hif_factor_active(hif_factor_t F, int32_t level, uint8_t* mask) {
                 "level out of range");
     const auto& a = F->active_after[level];
     std::memcpy(mask, a.data(), a.size());
+  });
+}
+
+hif_status hif_profile_begin(void) {
+  return guarded([&] {
+    hif::Profiler& p = hif::profiler();
+    for (auto& r : p.recs) {
+      p.recycle(r.a);
+      p.recycle(r.b);
+    }
+    p.recs.clear();
+    p.on = true;
+  });
+}
+
+hif_status hif_profile_end(hif_kernel_stat* out, int32_t cap, int32_t* count) {
+  return guarded([&] {
+    HIF_REQUIRE(count != nullptr, HIF_EINVAL, "count must not be NULL");
+    hif::Profiler& p = hif::profiler();
+    p.on = false;
+    std::vector<hif_kernel_stat> agg(p.names.size());
+    for (size_t i = 0; i < p.names.size(); ++i) {
+      std::memset(&agg[i], 0, sizeof(hif_kernel_stat));
+      std::strncpy(agg[i].name, p.names[i].c_str(), sizeof(agg[i].name) - 1);
+    }
+    for (auto& r : p.recs) {
+      HIF_HIP(hipEventSynchronize(r.b));
+      float ms = 0.f;
+      HIF_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      hif_kernel_stat& k = agg[r.cls];
+      k.launches += 1;
+      k.seconds += ms * 1e-3;
+      k.flops += r.flops;
+      k.bytes += r.bytes;
+      p.recycle(r.a);
+      p.recycle(r.b);
+    }
+    p.recs.clear();
+    int32_t nz = 0;
+    for (auto& k : agg)
+      if (k.launches > 0) {
+        if (out && nz < cap) out[nz] = k;
+        ++nz;
+      }
+    *count = nz;
   });
 }
 

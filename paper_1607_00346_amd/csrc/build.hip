@@ -7,6 +7,7 @@
 #include <cstring>
 
 #include "hif_impl.hpp"
+#include "prof.hpp"
 
 namespace hif {
 namespace {
@@ -58,11 +59,13 @@ __device__ __forceinline__ T lookup(const Src<T>& s, int p, int q) {
   return T(0);
 }
 
-// Front of cell c: Phi(:, j) = A^l([I; S], I_j), rows i >= j only.
+// Front of cell c, column j: A_II(i, j) for i >= j into Phi, A_SI(:, j) into
+// the separate buffer ASI (nS x nI, leading dimension max(1, nS)).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_gather_front(Src<T> s, const int* __restrict__ rows,
                                                      const int64_t* __restrict__ crow_off,
-                                                     const FrontDesc* __restrict__ fd, T* arena) {
+                                                     const FrontDesc* __restrict__ fd, T* arena,
+                                                     T* asi, const int64_t* __restrict__ aoff) {
   const int c = blockIdx.y;
   const FrontDesc f = fd[c];
   const int j = blockIdx.x;
@@ -70,7 +73,26 @@ __global__ __launch_bounds__(NT) void k_gather_front(Src<T> s, const int* __rest
   const int* r = rows + crow_off[c];
   const int q = r[j];
   T* col = arena + f.off + (int64_t)f.ld * j;
-  for (int i = j + threadIdx.x; i < f.nR; i += NT) col[i] = lookup(s, r[i], q);
+  const int nS = f.nR - f.nI;
+  T* scol = asi + aoff[c] + (int64_t)(nS > 0 ? nS : 1) * j;
+  for (int i = j + threadIdx.x; i < f.nR; i += NT) {
+    const T v = lookup(s, r[i], q);
+    if (i < f.nI) col[i] = v;
+    else scol[i - f.nI] = v;
+  }
+}
+
+// Copy the computed lower triangle of each square block to its upper triangle.
+__global__ __launch_bounds__(NT) void k_mirror_lower(double* G, const int64_t* __restrict__ goff,
+                                                     const int* __restrict__ nFa,
+                                                     const int* __restrict__ gld) {
+  const int f = blockIdx.y;
+  const int j = blockIdx.x;
+  const int nF = nFa[f];
+  if (j >= nF) return;
+  double* g = G + goff[f];
+  const int ld = gld[f];
+  for (int i = threadIdx.x; i < j; i += NT) g[i + (int64_t)ld * j] = g[j + (int64_t)ld * i];
 }
 
 template <typename T>
@@ -253,14 +275,19 @@ DevBuf<V> to_dev(const std::vector<V>& h, hipStream_t s) {
 }
 
 template <typename TIn, typename TC>
-void run_gemms(int opa, int opb, int flags, const std::vector<GemmDesc>& h, TC alpha, TC beta,
-               hipStream_t s) {
+void run_gemms(const char* name, int opa, int opb, int flags, const std::vector<GemmDesc>& h,
+               TC alpha, TC beta, hipStream_t s) {
   if (h.empty()) return;
   int mm = 0, mn = 0;
-  for (auto& d : h) { mm = std::max(mm, d.m); mn = std::max(mn, d.n); }
+  double fl = 0.0;
+  for (auto& d : h) {
+    mm = std::max(mm, d.m);
+    mn = std::max(mn, d.n);
+    fl += gemm_flops(d, flags);
+  }
   DevBuf<GemmDesc> d;
   d.upload(h, s);
-  gemm_batched<TIn, TC>(opa, opb, flags, d.get(), (int)h.size(), mm, mn, alpha, beta, s);
+  gemm_batched<TIn, TC>(opa, opb, flags, d.get(), (int)h.size(), mm, mn, alpha, beta, s, name, fl);
   HIF_HIP(hipStreamSynchronize(s));  // descriptors are freed on return
 }
 
@@ -342,18 +369,46 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
     st.cells[level] = P.ncell;
     st.eliminated[level] = lev.ysum;
     if (P.ncell > 0) {
-      dim3 g((unsigned)std::max(1, lev.maxI), (unsigned)P.ncell);
-      hipLaunchKernelGGL((k_gather_front<T>), g, dim3(NT), 0, s, src, lev.rows.get(),
-                         lev.crow_off.get(), lev.fd.get(), lev.front.get());
-      HIF_LAUNCH_CHECK();
+      // A_SI goes to a separate buffer: L_SI = A_SI L_I^{-T} is formed by one GEMM
+      std::vector<int64_t> aoff(P.ncell);
+      int64_t asz = 0;
+      for (int c = 0; c < P.ncell; ++c) {
+        aoff[c] = asz;
+        asz += (int64_t)std::max(1, P.cS[c]) * P.cI[c];
+      }
+      DevBuf<T> ASI(std::max<int64_t>(asz, 1));
+      DevBuf<int64_t> d_aoff = to_dev(aoff, s);
+      {
+        ProfScope ps("gather_front", s);
+        dim3 g((unsigned)std::max(1, lev.maxI), (unsigned)P.ncell);
+        hipLaunchKernelGGL((k_gather_front<T>), g, dim3(NT), 0, s, src, lev.rows.get(),
+                           lev.crow_off.get(), lev.fd.get(), lev.front.get(), ASI.get(),
+                           d_aoff.get());
+        HIF_LAUNCH_CHECK();
+      }
+      // interior Cholesky and in-place inverse on the top nI x nI block
+      std::vector<FrontDesc> top = lev.hfd;
+      for (auto& d : top) d.nR = d.nI;
+      DevBuf<FrontDesc> d_top = to_dev(top, s);
       DevBuf<T> work((size_t)P.ncell * kPanel * std::max(1, lev.maxI));
-      front_factor<T>(lev.front.get(), lev.fd.get(), lev.hfd, work.get(), d_err.get(), s);
+      front_factor<T>(lev.front.get(), d_top.get(), top, work.get(), d_err.get(), s);
       int err = kNoErr;
       HIF_HIP(hipMemcpyAsync(&err, d_err.get(), sizeof(int), hipMemcpyDeviceToHost, s));
       HIF_HIP(hipStreamSynchronize(s));
       if (err != kNoErr)
         throw Error(HIF_ENOTSPD, "non-positive pivot in the interior Cholesky at level " +
                                      std::to_string(level) + ", cell " + std::to_string(err));
+      work.release();
+      // L_SI = A_SI L_I^{-T}  (op(B) = Linv^T is upper triangular)
+      std::vector<GemmDesc> gd;
+      for (int c = 0; c < P.ncell; ++c) {
+        if (P.cS[c] == 0) continue;
+        const FrontDesc& d = lev.hfd[c];
+        T* base = lev.front.get() + d.off;
+        gd.push_back({ASI.get() + aoff[c], base, base + d.nI, P.cS[c], d.nI, d.nI,
+                      std::max(1, P.cS[c]), d.ld, d.ld});
+      }
+      run_gemms<T, T>("gemm_lsi", OP_N, OP_T, GF_B_UPPER, gd, T(1), T(0), s);
     }
 
     if (!P.root) {
@@ -375,7 +430,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
           const T* LSI = lev.front.get() + d.off + d.nI;
           gd.push_back({LSI, LSI, U.get() + uoff[c], P.cS[c], P.cS[c], d.nI, d.ld, d.ld, uld[c]});
         }
-        run_gemms<T, T>(OP_N, OP_T, GF_C_LOWER, gd, T(-1), T(0), s);
+        run_gemms<T, T>("gemm_syrk", OP_N, OP_T, GF_C_LOWER, gd, T(-1), T(0), s);
       }
       // ---- face panels Ã^l([F; R-faces], F) ------------------------------
       std::vector<int64_t> poff(P.nface);
@@ -403,6 +458,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
       if (P.nface > 0) {
         DevBuf<int64_t> d_uoff = to_dev(uoff, s);
         DevBuf<int> d_uld = to_dev(uld, s);
+        ProfScope ps("gather_panel", s);
         dim3 g((unsigned)std::max(1, lev.maxF), (unsigned)P.nface);
         hipLaunchKernelGGL((k_gather_panel<T>), g, dim3(NT), 0, s, src, lev.fpts.get(),
                            lev.fpt_off.get(), lev.fN.get(), lev.rb_face.get(), lev.rb_off.get(),
@@ -440,9 +496,16 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
           gd.push_back({PR, PR, G.get() + goff[f], P.fN[f], P.fN[f], K, pld[f], pld[f], gld[f]});
           flops += 2.0 * K * P.fN[f] * (double)P.fN[f];
         }
-        run_gemms<T, double>(OP_T, OP_N, 0, gd, 1.0, 0.0, s);
+        run_gemms<T, double>("gemm_gram", OP_T, OP_N, GF_C_LOWER, gd, 1.0, 0.0, s);
         DevBuf<int64_t> d_goff = to_dev(goff, s);
         DevBuf<int> d_gld = to_dev(gld, s);
+        {
+          ProfScope ps("gram_mirror", s);
+          dim3 g((unsigned)std::max(1, lev.maxF), (unsigned)P.nface);
+          hipLaunchKernelGGL(k_mirror_lower, g, dim3(NT), 0, s, G.get(), d_goff.get(),
+                             lev.fN.get(), d_gld.get());
+          HIF_LAUNCH_CHECK();
+        }
         {
           dim3 g((unsigned)ceil_div(std::max(1, lev.maxF), NT), (unsigned)P.nface);
           hipLaunchKernelGGL(k_gram_edges, g, dim3(NT), 0, s, A->stencil(), P.w, lev.fpts.get(),
@@ -527,16 +590,13 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
             tg.push_back({L11.get() + o11[i], L21.get() + o21[i], Tdst + d.offT, d.k, d.r, d.k,
                           d.k, d.r, d.k});
           }
-          run_gemms<double, double>(OP_T, OP_T, GF_A_UPPER, tg, 1.0, 0.0, s);
-          if (!std::is_same<T, double>::value) {
-            for (int i = 0; i < nsk; ++i) {
-              const SkelDesc& d = lev.hsk[i];
-              const int64_t cnt = (int64_t)d.k * d.r;
-              if (cnt == 0) continue;
-              hipLaunchKernelGGL((k_convert<T>), dim3((unsigned)std::min<int64_t>(ceil_div(cnt, NT), 1024)),
-                                 dim3(NT), 0, s, Td.get() + d.offT, lev.skel.get() + d.offT, cnt);
-              HIF_LAUNCH_CHECK();
-            }
+          run_gemms<double, double>("gemm_interp", OP_T, OP_T, GF_A_UPPER, tg, 1.0, 0.0, s);
+          if (!std::is_same<T, double>::value && ssz > 0) {
+            ProfScope ps("convert_T", s);
+            hipLaunchKernelGGL((k_convert<T>),
+                               dim3((unsigned)std::min<int64_t>(ceil_div(ssz, NT), 8192)),
+                               dim3(NT), 0, s, Td.get(), lev.skel.get(), ssz);
+            HIF_LAUNCH_CHECK();
           }
           HIF_HIP(hipStreamSynchronize(s));
           L11.release();
@@ -569,9 +629,9 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
             g4.push_back({Acc, Hc, SK + d.offY, d.r, d.k, d.r, r, k, r});  // Y = Lc^{-1} B_hc^T
             g5.push_back({SK + d.offY, SK + d.offY, Hh, d.k, d.k, d.r, r, r, k});  // A_hh -= Y^T Y
           }
-          run_gemms<T, T>(OP_T, OP_N, 0, g1, T(-1), T(1), s);
-          run_gemms<T, T>(OP_N, OP_N, 0, g2, T(-1), T(1), s);
-          run_gemms<T, T>(OP_T, OP_N, 0, g3, T(-1), T(1), s);
+          run_gemms<T, T>("gemm_skel", OP_T, OP_N, 0, g1, T(-1), T(1), s);
+          run_gemms<T, T>("gemm_skel", OP_N, OP_N, 0, g2, T(-1), T(1), s);
+          run_gemms<T, T>("gemm_skel", OP_T, OP_N, 0, g3, T(-1), T(1), s);
           std::vector<FrontDesc> cfd;
           for (int i = 0; i < nsk; ++i)
             cfd.push_back({lev.hsk[i].offL, lev.hsk[i].r, lev.hsk[i].r, lev.hsk[i].r, 0});
@@ -587,8 +647,8 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
                                            std::to_string(level) + ", face " +
                                            std::to_string(lev.hsk[err].face));
           }
-          run_gemms<T, T>(OP_N, OP_T, GF_A_LOWER, g4, T(1), T(0), s);
-          run_gemms<T, T>(OP_T, OP_N, 0, g5, T(-1), T(1), s);
+          run_gemms<T, T>("gemm_skel", OP_N, OP_T, GF_A_LOWER, g4, T(1), T(0), s);
+          run_gemms<T, T>("gemm_skel", OP_T, OP_N, 0, g5, T(-1), T(1), s);
           {
             dim3 g((unsigned)std::max(1, lev.maxk), (unsigned)nsk);
             hipLaunchKernelGGL((k_skel_writeback<T>), g, dim3(NT), 0, s, lev.panel.get(),

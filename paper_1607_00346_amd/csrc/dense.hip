@@ -3,6 +3,7 @@
 #include <cfloat>
 
 #include "dense.hpp"
+#include "prof.hpp"
 
 namespace hif {
 namespace {
@@ -437,8 +438,9 @@ __global__ __launch_bounds__(NTHR) void k_pchol(const double* __restrict__ G, do
 
 template <typename TIn, typename TC>
 void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch, int max_m,
-                  int max_n, TC alpha, TC beta, hipStream_t s) {
+                  int max_n, TC alpha, TC beta, hipStream_t s, const char* name, double flops) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
+  ProfScope ps(name, s, flops);
   for (int b0 = 0; b0 < batch; b0 += 65535) {
     const int nb = std::min(batch - b0, 65535);
     dim3 grid((unsigned)ceil_div(max_n, BN), (unsigned)ceil_div(max_m, BM), (unsigned)nb);
@@ -446,6 +448,33 @@ void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch
                        d_desc + b0, alpha, beta);
     HIF_LAUNCH_CHECK();
   }
+}
+
+double gemm_flops(const GemmDesc& d, int flags) {
+  const double m = d.m, n = d.n, k = d.k;
+  if (d.m <= 0 || d.n <= 0 || d.k <= 0) return 0.0;
+  double t = 0.0;
+  if (flags & GF_C_LOWER) {  // computed outputs: i >= j
+    const double nn = std::min(n, m);
+    return 2.0 * k * (nn * m - nn * (nn - 1) / 2);
+  }
+  if (flags & GF_A_LOWER) {  // row i uses t < min(i+1, k)
+    for (int i = 0; i < d.m; ++i) t += std::min(i + 1, d.k);
+    return 2.0 * n * t;
+  }
+  if (flags & GF_A_UPPER) {  // row i uses t in [i, k)
+    for (int i = 0; i < d.m; ++i) t += std::max(0, d.k - i);
+    return 2.0 * n * t;
+  }
+  if (flags & GF_B_UPPER) {  // column j uses t < min(j+1, k)
+    for (int j = 0; j < d.n; ++j) t += std::min(j + 1, d.k);
+    return 2.0 * m * t;
+  }
+  if (flags & GF_B_LOWER) {  // column j uses t in [j, k)
+    for (int j = 0; j < d.n; ++j) t += std::max(0, d.k - j);
+    return 2.0 * m * t;
+  }
+  return 2.0 * m * n * k;
 }
 
 template <typename T>
@@ -464,15 +493,27 @@ void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
       max_m = std::max(max_m, f.nR - j0 - nb);
       max_n = std::max(max_n, f.nI - j0 - nb);
     }
-    hipLaunchKernelGGL((k_front_diag<T>), dim3((unsigned)batch), dim3(NTHR), 0, s, arena,
-                       d_fronts, j0, err);
-    HIF_LAUNCH_CHECK();
+    {
+      ProfScope ps("potrf_diag", s);
+      hipLaunchKernelGGL((k_front_diag<T>), dim3((unsigned)batch), dim3(NTHR), 0, s, arena,
+                         d_fronts, j0, err);
+      HIF_LAUNCH_CHECK();
+    }
     if (max_m > 0) {
+      ProfScope ps("potrf_panel", s);
       dim3 gp((unsigned)ceil_div(max_m, NTHR), (unsigned)batch);
       hipLaunchKernelGGL((k_front_panel<T>), gp, dim3(NTHR), 0, s, arena, d_fronts, j0);
       HIF_LAUNCH_CHECK();
     }
     if (max_m > 0 && max_n > 0) {
+      double fl = 0.0;
+      for (auto& f : h_fronts) {
+        if (f.nI <= j0) continue;
+        const int nb = std::min(kPanel, f.nI - j0);
+        const double m = f.nR - j0 - nb, n = f.nI - j0 - nb;
+        fl += 2.0 * nb * (n * m - n * (n - 1) / 2);
+      }
+      ProfScope ps("potrf_trailing", s, fl);
       dim3 gt((unsigned)ceil_div(max_n, BN), (unsigned)ceil_div(max_m, BM), (unsigned)batch);
       hipLaunchKernelGGL((k_front_trailing<T>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0);
       HIF_LAUNCH_CHECK();
@@ -491,14 +532,24 @@ void front_invert(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
   for (auto& f : h_fronts) maxI = std::max(maxI, f.nI);
   const int64_t wstride = (int64_t)kPanel * std::max(maxI, 1);
   for (int j0 = 0; j0 < maxI; j0 += kPanel) {
-    hipLaunchKernelGGL((k_trtri_diag<T>), dim3((unsigned)batch), dim3(NTHR), 0, s, arena,
-                       d_fronts, j0);
-    HIF_LAUNCH_CHECK();
+    {
+      ProfScope ps("trtri_diag", s);
+      hipLaunchKernelGGL((k_trtri_diag<T>), dim3((unsigned)batch), dim3(NTHR), 0, s, arena,
+                         d_fronts, j0);
+      HIF_LAUNCH_CHECK();
+    }
     if (j0 > 0) {
+      double fl = 0.0;
+      for (auto& f : h_fronts)
+        if (f.nI > j0) fl += (double)std::min(kPanel, f.nI - j0) * j0 * (j0 + 1);
+      ProfScope ps("trtri_gemm", s, fl);
       dim3 g((unsigned)ceil_div(j0, BN), 1, (unsigned)batch);
       hipLaunchKernelGGL((k_trtri_gemm<T>), g, dim3(NTHR), 0, s, arena, d_fronts, j0, work,
                          wstride);
       HIF_LAUNCH_CHECK();
+    }
+    if (j0 > 0) {
+      ProfScope ps("trtri_apply", s);
       dim3 g2((unsigned)ceil_div(j0, NTHR), (unsigned)batch);
       hipLaunchKernelGGL((k_trtri_apply<T>), g2, dim3(NTHR), 0, s, arena, d_fronts, j0,
                          (const T*)work, wstride);
@@ -511,17 +562,18 @@ void pivoted_cholesky(const double* G, double* L, const int64_t* goff, const int
                       const int* ldg, const int64_t* poff, int* perm, int* k, int batch,
                       double eps, hipStream_t s) {
   if (batch <= 0) return;
+  ProfScope ps("pivoted_cholesky", s);
   hipLaunchKernelGGL(k_pchol, dim3((unsigned)batch), dim3(NTHR), 0, s, G, L, goff, nF, ldg, poff,
                      perm, k, eps);
   HIF_LAUNCH_CHECK();
 }
 
 template void gemm_batched<double, double>(int, int, int, const GemmDesc*, int, int, int, double,
-                                           double, hipStream_t);
+                                           double, hipStream_t, const char*, double);
 template void gemm_batched<float, float>(int, int, int, const GemmDesc*, int, int, int, float,
-                                         float, hipStream_t);
+                                         float, hipStream_t, const char*, double);
 template void gemm_batched<float, double>(int, int, int, const GemmDesc*, int, int, int, double,
-                                          double, hipStream_t);
+                                          double, hipStream_t, const char*, double);
 template void front_factor<double>(double*, const FrontDesc*, const std::vector<FrontDesc>&,
                                    double*, int*, hipStream_t);
 template void front_factor<float>(float*, const FrontDesc*, const std::vector<FrontDesc>&, float*,

@@ -39,7 +39,11 @@ struct GemmDesc {
 // TIn: element type of A and B; TC: accumulation and C type.
 template <typename TIn, typename TC>
 void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch, int max_m,
-                  int max_n, TC alpha, TC beta, hipStream_t s);
+                  int max_n, TC alpha, TC beta, hipStream_t s, const char* name = "gemm",
+                  double flops = 0.0);
+
+// Algorithmic flops of one descriptor under the triangular flags (one flag class).
+double gemm_flops(const GemmDesc& d, int flags);
 
 // One front: element offset of its column-major block in the arena, interior
 // count nI, total rows nR = nI + nS, leading dimension ld >= nR.
@@ -49,7 +53,7 @@ struct FrontDesc {
   int pad_;
 };
 
-constexpr int kPanel = 32;  // block width of the blocked factorizations
+constexpr int kPanel = 64;  // block width of the blocked factorizations
 
 // Partial Cholesky of the first nI columns of every front, then L_I <- L_I^{-1}
 // in place.  work must hold batch * kPanel * max_nI elements.  err[0] receives

@@ -58,6 +58,9 @@ struct Level {
   DevBuf<T> skel;
   int maxk = 0, maxr = 0;
   int64_t redundant = 0;
+  // algorithmic bytes of one sweep over this level (factor words read once,
+  // 8-byte vector entries read and written), for the profiler
+  double bytes_L = 0.0, bytes_S = 0.0, bytes_skel = 0.0;
 };
 
 struct FactorBase {

@@ -5,6 +5,7 @@
 #include <cstring>
 
 #include "hif_impl.hpp"
+#include "prof.hpp"
 
 namespace hif {
 namespace {
@@ -367,6 +368,7 @@ void problem_assemble(hif_problem_s* A, const double* a, const double* b, hipStr
 
 void stencil_matvec(const Stencil& st, const double* x, double* y, hipStream_t s) {
   const int64_t N = (int64_t)st.n * st.n * st.n;
+  ProfScope ps("matvec", s, 13.0 * N, 48.0 * N);
   hipLaunchKernelGGL(k_matvec, dim3((unsigned)ceil_div(N, NT)), dim3(NT), 0, s, st, x, y);
   HIF_LAUNCH_CHECK();
 }
@@ -383,32 +385,53 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   double* zv = zbuf.get();
   double* xsv = zbuf.get() + zmax;
   const int nlev = (int)levels.size();
+  for (auto& lv : levels) {
+    if (lv.bytes_L > 0.0 || lv.P.ncell == 0) continue;
+    for (const FrontDesc& d : lv.hfd) {
+      lv.bytes_L += sizeof(T) * 0.5 * d.nI * (d.nI + 1.0) + 24.0 * d.nI;
+      lv.bytes_S += sizeof(T) * (double)(d.nR - d.nI) * d.nI + 16.0 * (d.nR - d.nI) + 8.0 * d.nI;
+    }
+    for (const SkelDesc& d : lv.hsk)
+      lv.bytes_skel += sizeof(T) * (2.0 * d.k * d.r + 0.5 * d.r * (d.r + 1.0)) +
+                       32.0 * (d.k + d.r);
+  }
   // W^l^T for l = 0..L (level L: L_Sigma^{-1})
   for (int l = 0; l < nlev; ++l) {
     Level<T>& lv = levels[l];
     const int nc = lv.P.ncell;
     if (nc > 0) {
       dim3 gI((unsigned)ceil_div(std::max(1, lv.maxI), NT), (unsigned)nc);
-      hipLaunchKernelGGL(k_gather_cell, gI, dim3(NT), 0, s, u, lv.rows.get(), lv.crow_off.get(),
-                         lv.fd.get(), lv.yoff.get(), lv.zoff.get(), xi, xsv, 0);
-      hipLaunchKernelGGL((k_up_L<T>), gI, dim3(NT), 0, s, lv.front.get(), lv.fd.get(),
-                         lv.yoff.get(), xi, yv);
+      {
+        ProfScope ps("apply_up_L", s, 0.0, lv.bytes_L);
+        hipLaunchKernelGGL(k_gather_cell, gI, dim3(NT), 0, s, u, lv.rows.get(), lv.crow_off.get(),
+                           lv.fd.get(), lv.yoff.get(), lv.zoff.get(), xi, xsv, 0);
+        hipLaunchKernelGGL((k_up_L<T>), gI, dim3(NT), 0, s, lv.front.get(), lv.fd.get(),
+                           lv.yoff.get(), xi, yv);
+      }
       if (lv.maxS > 0) {
+        ProfScope ps("apply_up_S", s, 0.0, lv.bytes_S);
         dim3 gS((unsigned)ceil_div(lv.maxS, NT), (unsigned)nc);
         hipLaunchKernelGGL((k_up_S<T>), gS, dim3(NT), 0, s, lv.front.get(), lv.fd.get(),
                            lv.yoff.get(), lv.zoff.get(), yv, zv);
       }
-      hipLaunchKernelGGL(k_scatter_I, gI, dim3(NT), 0, s, u, lv.rows.get(), lv.crow_off.get(),
-                         lv.fd.get(), lv.yoff.get(), yv);
+      {
+        ProfScope ps("apply_scatter", s);
+        hipLaunchKernelGGL(k_scatter_I, gI, dim3(NT), 0, s, u, lv.rows.get(), lv.crow_off.get(),
+                           lv.fd.get(), lv.yoff.get(), yv);
+      }
       HIF_LAUNCH_CHECK();
     }
     if (!lv.P.root && lv.P.nface > 0) {
-      dim3 gF((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)lv.P.nface);
-      hipLaunchKernelGGL(k_face_sub, gF, dim3(NT), 0, s, u, lv.fpts.get(), lv.fpt_off.get(),
-                         lv.fN.get(), lv.fcellA.get(), lv.fcellB.get(), lv.rb_sa.get(),
-                         lv.rb_sb.get(), lv.zoff.get(), zv);
-      HIF_LAUNCH_CHECK();
+      {
+        ProfScope ps("apply_scatter", s);
+        dim3 gF((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)lv.P.nface);
+        hipLaunchKernelGGL(k_face_sub, gF, dim3(NT), 0, s, u, lv.fpts.get(), lv.fpt_off.get(),
+                           lv.fN.get(), lv.fcellA.get(), lv.fcellB.get(), lv.rb_sa.get(),
+                           lv.rb_sb.get(), lv.zoff.get(), zv);
+        HIF_LAUNCH_CHECK();
+      }
       if (!lv.hsk.empty()) {
+        ProfScope ps("apply_skel", s, 0.0, lv.bytes_skel);
         const size_t shm = sizeof(double) * (lv.maxk + 2 * (size_t)lv.maxr);
         hipLaunchKernelGGL((k_skel_up<T>), dim3((unsigned)lv.hsk.size()), dim3(NT), shm, s, u,
                            lv.skpts.get(), lv.sk.get(), lv.skel.get());
@@ -420,6 +443,7 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   for (int l = nlev - 1; l >= 0; --l) {
     Level<T>& lv = levels[l];
     if (!lv.P.root && !lv.hsk.empty()) {
+      ProfScope ps("apply_skel", s, 0.0, lv.bytes_skel);
       const size_t shm = sizeof(double) * (lv.maxk + 2 * (size_t)lv.maxr);
       hipLaunchKernelGGL((k_skel_down<T>), dim3((unsigned)lv.hsk.size()), dim3(NT), shm, s, u,
                          lv.skpts.get(), lv.sk.get(), lv.skel.get());
@@ -429,13 +453,19 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
     if (nc == 0) continue;
     const int gmax = std::max(lv.maxI, lv.maxI + lv.maxS);
     dim3 gG((unsigned)ceil_div(std::max(1, gmax), NT), (unsigned)nc);
-    hipLaunchKernelGGL(k_gather_cell, gG, dim3(NT), 0, s, u, lv.rows.get(), lv.crow_off.get(),
-                       lv.fd.get(), lv.yoff.get(), lv.zoff.get(), xi, xsv, 1);
     dim3 gW((unsigned)ceil_div(std::max(1, lv.maxI), NT / 64), (unsigned)nc);
-    hipLaunchKernelGGL((k_down_S<T>), gW, dim3(NT), 0, s, lv.front.get(), lv.fd.get(),
-                       lv.yoff.get(), lv.zoff.get(), xi, xsv, yv);
-    hipLaunchKernelGGL((k_down_L<T>), gW, dim3(NT), 0, s, lv.front.get(), lv.fd.get(),
-                       lv.yoff.get(), yv, u, lv.rows.get(), lv.crow_off.get());
+    {
+      ProfScope ps("apply_down_S", s, 0.0, lv.bytes_S);
+      hipLaunchKernelGGL(k_gather_cell, gG, dim3(NT), 0, s, u, lv.rows.get(), lv.crow_off.get(),
+                         lv.fd.get(), lv.yoff.get(), lv.zoff.get(), xi, xsv, 1);
+      hipLaunchKernelGGL((k_down_S<T>), gW, dim3(NT), 0, s, lv.front.get(), lv.fd.get(),
+                         lv.yoff.get(), lv.zoff.get(), xi, xsv, yv);
+    }
+    {
+      ProfScope ps("apply_down_L", s, 0.0, lv.bytes_L);
+      hipLaunchKernelGGL((k_down_L<T>), gW, dim3(NT), 0, s, lv.front.get(), lv.fd.get(),
+                         lv.yoff.get(), yv, u, lv.rows.get(), lv.crow_off.get());
+    }
     HIF_LAUNCH_CHECK();
   }
 }
@@ -450,6 +480,7 @@ struct Dot {
   void run(const double* a, const double* b, const double* c, int64_t N, double* out,
            hipStream_t s) {
     const unsigned nb = (unsigned)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, ceil_div(N, NT)));
+    ProfScope ps("pcg_dot", s, 2.0 * N, (c ? 24.0 : 16.0) * N);
     hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(NT), 0, s, a, b, c, N, part.get());
     hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(NT), 0, s, (const double*)part.get(), (int)nb, out);
     HIF_LAUNCH_CHECK();

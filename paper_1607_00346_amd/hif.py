@@ -21,7 +21,8 @@ HIF_MAX_LEVELS = 16
 EXPORTED = [
     "hif_problem_create", "hif_build", "hif_apply", "hif_matvec", "hif_pcg",
     "hif_factor_stats", "hif_factor_ranks", "hif_factor_active", "hif_factor_destroy",
-    "hif_problem_destroy", "hif_status_string", "hif_last_error",
+    "hif_problem_destroy", "hif_status_string", "hif_last_error", "hif_profile_begin",
+    "hif_profile_end",
 ]
 
 
@@ -62,6 +63,12 @@ class hif_stats(ctypes.Structure):
         }
 
 
+class hif_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int64),
+                ("seconds", ctypes.c_double), ("flops", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
 class HifError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__(f"{where}: status {status}: {detail}")
@@ -90,11 +97,14 @@ def lib():
         L.hif_factor_active.argtypes = [vp, i32, vp]
         L.hif_factor_destroy.argtypes = [vp]
         L.hif_problem_destroy.argtypes = [vp]
+        L.hif_profile_begin.argtypes = []
+        L.hif_profile_end.argtypes = [vp, i32, ctypes.POINTER(i32)]
         L.hif_status_string.argtypes = [i32]
         L.hif_status_string.restype = ctypes.c_char_p
         L.hif_last_error.restype = ctypes.c_char_p
         for name in ("hif_problem_create", "hif_build", "hif_apply", "hif_matvec", "hif_pcg",
-                     "hif_factor_stats", "hif_factor_ranks", "hif_factor_active"):
+                     "hif_factor_stats", "hif_factor_ranks", "hif_factor_active",
+                     "hif_profile_begin", "hif_profile_end"):
             getattr(L, name).restype = ctypes.c_int
         L.hif_factor_destroy.restype = None
         L.hif_problem_destroy.restype = None
@@ -180,6 +190,25 @@ def hif_factor_active(F, level: int, n_dof: int):
     _check(lib().hif_factor_active(F, int(level), m.ctypes.data_as(ctypes.c_void_p)),
            "hif_factor_active")
     return m
+
+
+def hif_profile_begin():
+    _check(lib().hif_profile_begin(), "hif_profile_begin")
+
+
+def hif_profile_end():
+    """Stop recording; returns {kernel class: {launches, seconds, flops, bytes}}."""
+    cap = 256
+    buf = (hif_kernel_stat * cap)()
+    cnt = ctypes.c_int32()
+    _check(lib().hif_profile_end(ctypes.cast(buf, ctypes.c_void_p), cap, ctypes.byref(cnt)),
+           "hif_profile_end")
+    out = {}
+    for i in range(min(cnt.value, cap)):
+        k = buf[i]
+        out[k.name.decode()] = {"launches": k.launches, "seconds": k.seconds, "flops": k.flops,
+                                "bytes": k.bytes}
+    return out
 
 
 def hif_factor_destroy(F):
