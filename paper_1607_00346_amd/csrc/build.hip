@@ -390,15 +390,13 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
       std::vector<FrontDesc> top = lev.hfd;
       for (auto& d : top) d.nR = d.nI;
       DevBuf<FrontDesc> d_top = to_dev(top, s);
-      DevBuf<T> work((size_t)P.ncell * kPanel * std::max(1, lev.maxI));
-      front_factor<T>(lev.front.get(), d_top.get(), top, work.get(), d_err.get(), s);
+      front_factor<T>(lev.front.get(), d_top.get(), top, d_err.get(), s);
       int err = kNoErr;
       HIF_HIP(hipMemcpyAsync(&err, d_err.get(), sizeof(int), hipMemcpyDeviceToHost, s));
       HIF_HIP(hipStreamSynchronize(s));
       if (err != kNoErr)
         throw Error(HIF_ENOTSPD, "non-positive pivot in the interior Cholesky at level " +
                                      std::to_string(level) + ", cell " + std::to_string(err));
-      work.release();
       // L_SI = A_SI L_I^{-T}  (op(B) = Linv^T is upper triangular)
       std::vector<GemmDesc> gd;
       for (int c = 0; c < P.ncell; ++c) {
@@ -576,8 +574,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
             if (lev.hsk[i].k > 0) tri.push_back({o11[i], lev.hsk[i].k, lev.hsk[i].k, lev.hsk[i].k, 0});
           if (!tri.empty()) {
             DevBuf<FrontDesc> d_tri = to_dev(tri, s);
-            DevBuf<double> w((size_t)tri.size() * kPanel * std::max(1, lev.maxk));
-            front_invert<double>(L11.get(), d_tri.get(), tri, w.get(), s);
+            front_invert<double>(L11.get(), d_tri.get(), tri, s);
             HIF_HIP(hipStreamSynchronize(s));
           }
           DevBuf<double> Td;
@@ -637,8 +634,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
             cfd.push_back({lev.hsk[i].offL, lev.hsk[i].r, lev.hsk[i].r, lev.hsk[i].r, 0});
           {
             DevBuf<FrontDesc> d_cfd = to_dev(cfd, s);
-            DevBuf<T> w((size_t)nsk * kPanel * std::max(1, lev.maxr));
-            front_factor<T>(SK, d_cfd.get(), cfd, w.get(), d_err.get(), s);
+            front_factor<T>(SK, d_cfd.get(), cfd, d_err.get(), s);
             int err = kNoErr;
             HIF_HIP(hipMemcpyAsync(&err, d_err.get(), sizeof(int), hipMemcpyDeviceToHost, s));
             HIF_HIP(hipStreamSynchronize(s));

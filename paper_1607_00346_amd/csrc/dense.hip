@@ -39,8 +39,8 @@ constexpr int BM = 64, BN = 64, KC = 16, NTHR = 256;
 // arrangement of 32x32 sub-tiles, K staged through LDS in chunks of 16 with
 // a register prefetch of the next chunk.
 template <typename TIn, typename TC>
-__device__ void gemm_tile(int opa, int opb, int flags, const TIn* __restrict__ A, int lda,
-                          const TIn* __restrict__ B, int ldb, TC* __restrict__ C, int ldc, int m,
+__device__ void gemm_tile(int opa, int opb, int flags, const TIn* A, int lda,
+                          const TIn* __restrict__ B, int ldb, TC* C, int ldc, int m,
                           int n, int k, int m0, int n0, TC alpha, TC beta,
                           TC (*As)[KC][BM], TC (*Bs)[KC][BN]) {
   const int tid = threadIdx.x;
@@ -178,168 +178,103 @@ __global__ __launch_bounds__(NTHR) void k_front_trailing(T* arena, const FrontDe
                   m, n, nb, m0, n0, T(-1), T(1), As, Bs);
 }
 
-// Cholesky of the diagonal block Phi[j0:j1, j0:j1] in LDS, written back in
-// place (one workgroup per front).
+// Cholesky of the diagonal block Phi[j0:j1, j0:j1] and its inverse, by one
+// wave per front (lane = row of the block, LDS-resident).  L_jj is written
+// back in place; L_jj^{-1} goes to dinv (64 x 64, column-major) for the panel.
 template <typename T>
-__global__ __launch_bounds__(NTHR) void k_front_diag(T* arena, const FrontDesc* __restrict__ fd,
-                                                     int j0, int* err) {
+__global__ __launch_bounds__(64) void k_front_diag(T* arena, const FrontDesc* __restrict__ fd,
+                                                   int j0, T* dinv, int* err) {
   __shared__ T D[kPanel][kPanel + 1];
-  __shared__ int bad;
+  __shared__ T Di[kPanel][kPanel + 1];
   const FrontDesc f = fd[blockIdx.x];
   if (j0 >= f.nI) return;
   const int nb = min(kPanel, f.nI - j0);
-  const int tid = threadIdx.x;
-  T* base = arena + f.off;
-  if (tid == 0) bad = 0;
-  for (int e = tid; e < nb * nb; e += NTHR) {
-    const int i = e / nb, t = e % nb;
-    if (t <= i) D[i][t] = base[(j0 + i) + (int64_t)f.ld * (j0 + t)];
+  const int lane = threadIdx.x;
+  T* base = arena + f.off + j0 + (int64_t)f.ld * j0;
+  for (int t = 0; t < nb; ++t)
+    if (lane < nb) D[lane][t] = t <= lane ? base[lane + (int64_t)f.ld * t] : T(0);
+  __syncthreads();
+  bool bad = false;
+  for (int t = 0; t < nb; ++t) {
+    T d = D[t][t];
+    if (!(d > T(0))) { bad = true; d = T(1); }
+    const T ltt = sqrt(d);
+    const T lit = lane > t && lane < nb ? D[lane][t] / ltt : T(0);
+    __syncthreads();
+    if (lane == t) D[t][t] = ltt;
+    if (lane > t && lane < nb) D[lane][t] = lit;
+    __syncthreads();
+    if (lane > t && lane < nb)
+      for (int j = t + 1; j <= lane; ++j) D[lane][j] -= lit * D[j][t];
+    __syncthreads();
+  }
+  if (bad && lane == 0) atomicMin(err, (int)blockIdx.x);
+  // column `lane` of the inverse by forward substitution
+  if (lane < nb) {
+    const int c = lane;
+    for (int i = 0; i < c; ++i) Di[i][c] = T(0);
+    Di[c][c] = T(1) / D[c][c];
+    for (int i = c + 1; i < nb; ++i) {
+      T s = T(0);
+      for (int t = c; t < i; ++t) s += D[i][t] * Di[t][c];
+      Di[i][c] = -s / D[i][i];
+    }
   }
   __syncthreads();
-  for (int t = 0; t < nb; ++t) {
-    if (tid == 0) {
-      T piv = D[t][t];
-      if (!(piv > T(0))) { bad = 1; piv = T(1); }
-      D[t][t] = sqrt(piv);
-    }
-    __syncthreads();
-    if (tid > t && tid < nb) D[tid][t] /= D[t][t];
-    __syncthreads();
-    for (int e = tid; e < nb * nb; e += NTHR) {
-      const int i = e / nb, j = e % nb;
-      if (j > t && j <= i) D[i][j] -= D[i][t] * D[j][t];
-    }
-    __syncthreads();
-  }
-  if (bad && tid == 0) atomicMin(err, (int)blockIdx.x);
-  for (int e = tid; e < nb * nb; e += NTHR) {
-    const int i = e / nb, t = e % nb;
-    if (t <= i) base[(j0 + i) + (int64_t)f.ld * (j0 + t)] = D[i][t];
+  T* dv = dinv + (int64_t)blockIdx.x * kPanel * kPanel;
+  for (int t = 0; t < kPanel; ++t) {
+    if (lane < nb && t <= lane) base[lane + (int64_t)f.ld * t] = D[lane][t];
+    dv[lane + kPanel * t] = (lane < nb && t < nb) ? Di[lane][t] : T(0);
   }
 }
 
-// Panel rows below the factored diagonal block:
-// Phi[r, j0:j1] <- Phi[r, j0:j1] L_jj^{-T}, by substitution (thread per row).
+// Panel rows below the diagonal block, in place:
+// Phi[j1:nR, j0:j1] <- Phi[j1:nR, j0:j1] L_jj^{-T}  (MFMA, each workgroup owns
+// its 64 rows, so reading and overwriting them in one tile is safe).
 template <typename T>
 __global__ __launch_bounds__(NTHR) void k_front_panel(T* arena, const FrontDesc* __restrict__ fd,
-                                                      int j0) {
-  __shared__ T D[kPanel][kPanel + 1];
-  const FrontDesc f = fd[blockIdx.y];
-  if (j0 >= f.nI) return;
-  const int nb = min(kPanel, f.nI - j0);
-  const int r0 = j0 + nb + blockIdx.x * NTHR;
-  if (r0 >= f.nR) return;
-  const int tid = threadIdx.x;
-  T* base = arena + f.off;
-  for (int e = tid; e < nb * nb; e += NTHR) {
-    const int i = e / nb, t = e % nb;
-    if (t <= i) D[i][t] = base[(j0 + i) + (int64_t)f.ld * (j0 + t)];
-  }
-  __syncthreads();
-  const int r = r0 + tid;
-  if (r < f.nR) {
-    T z[kPanel];
-#pragma unroll
-    for (int t = 0; t < kPanel; ++t) {
-      if (t < nb) {
-        T s = base[r + (int64_t)f.ld * (j0 + t)];
-#pragma unroll
-        for (int q = 0; q < t; ++q) s -= z[q] * D[t][q];
-        z[t] = s / D[t][t];
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < kPanel; ++t)
-      if (t < nb) base[r + (int64_t)f.ld * (j0 + t)] = z[t];
-  }
-}
-
-// Block row j0 of the in-place inverse: W = L[j0:j1, 0:j0] Linv[0:j0, 0:j0].
-template <typename T>
-__global__ __launch_bounds__(NTHR) void k_trtri_gemm(T* arena, const FrontDesc* __restrict__ fd,
-                                                     int j0, T* work, int64_t wstride) {
+                                                      int j0, const T* __restrict__ dinv) {
   __shared__ T As[2][KC][BM];
   __shared__ T Bs[2][KC][BN];
   const FrontDesc f = fd[blockIdx.z];
   if (j0 >= f.nI) return;
   const int nb = min(kPanel, f.nI - j0);
-  const int n0 = blockIdx.x * BN;
-  if (n0 >= j0) return;
-  T* base = arena + f.off;
-  gemm_tile<T, T>(OP_N, OP_N, GF_B_LOWER, base + j0, f.ld, base, f.ld,
-                  work + blockIdx.z * wstride, kPanel, nb, j0, j0, 0, n0, T(1), T(0), As, Bs);
+  const int j1 = j0 + nb;
+  const int m = f.nR - j1;
+  const int m0 = blockIdx.y * BM;
+  if (m0 >= m) return;
+  T* P = arena + f.off + j1 + (int64_t)f.ld * j0;
+  gemm_tile<T, T>(OP_N, OP_T, GF_B_UPPER, P, f.ld, dinv + (int64_t)blockIdx.z * kPanel * kPanel,
+                  kPanel, P, f.ld, m, nb, nb, m0, 0, T(1), T(0), As, Bs);
 }
 
-// Linv_jj = L_jj^{-1}, in place on the diagonal block (one workgroup per front).
+// In-place inverse of every 64 x 64 diagonal block of the factored L_I
+// (one wave per block).
 template <typename T>
-__global__ __launch_bounds__(NTHR) void k_trtri_diag(T* arena, const FrontDesc* __restrict__ fd,
-                                                     int j0) {
+__global__ __launch_bounds__(64) void k_diag_inv(T* arena, const FrontDesc* __restrict__ fd) {
   __shared__ T D[kPanel][kPanel + 1];
   __shared__ T Di[kPanel][kPanel + 1];
-  const FrontDesc f = fd[blockIdx.x];
-  if (j0 >= f.nI) return;
-  const int nb = min(kPanel, f.nI - j0);
-  const int tid = threadIdx.x;
-  T* base = arena + f.off;
-  for (int e = tid; e < nb * nb; e += NTHR) {
-    const int i = e / nb, t = e % nb;
-    D[i][t] = t <= i ? base[(j0 + i) + (int64_t)f.ld * (j0 + t)] : T(0);
-  }
-  __syncthreads();
-  if (tid < nb) {
-    const int c = tid;
-    for (int i = 0; i < nb; ++i) {
-      T v;
-      if (i < c) v = T(0);
-      else if (i == c) v = T(1) / D[c][c];
-      else {
-        T s = T(0);
-        for (int t = c; t < i; ++t) s += D[i][t] * Di[t][c];
-        v = -s / D[i][i];
-      }
-      Di[i][c] = v;
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < nb * nb; e += NTHR) {
-    const int i = e / nb, t = e % nb;
-    if (t <= i) base[(j0 + i) + (int64_t)f.ld * (j0 + t)] = Di[i][t];
-  }
-}
-
-// Linv[j0:j1, 0:j0] = -Linv_jj W (the diagonal block already holds Linv_jj).
-template <typename T>
-__global__ __launch_bounds__(NTHR) void k_trtri_apply(T* arena, const FrontDesc* __restrict__ fd,
-                                                      int j0, const T* work, int64_t wstride) {
-  __shared__ T Di[kPanel][kPanel + 1];
   const FrontDesc f = fd[blockIdx.y];
+  const int j0 = blockIdx.x * kPanel;
   if (j0 >= f.nI) return;
-  const int c0 = blockIdx.x * NTHR;
-  if (c0 >= j0) return;
   const int nb = min(kPanel, f.nI - j0);
-  const int tid = threadIdx.x;
-  T* base = arena + f.off;
-  for (int e = tid; e < nb * nb; e += NTHR) {
-    const int i = e / nb, t = e % nb;
-    Di[i][t] = t <= i ? base[(j0 + i) + (int64_t)f.ld * (j0 + t)] : T(0);
-  }
+  const int lane = threadIdx.x;
+  T* base = arena + f.off + j0 + (int64_t)f.ld * j0;
+  for (int t = 0; t < nb; ++t)
+    if (lane < nb) D[lane][t] = t <= lane ? base[lane + (int64_t)f.ld * t] : T(0);
   __syncthreads();
-  const int c = c0 + tid;
-  if (c < j0) {
-    const T* w = work + blockIdx.y * wstride + (int64_t)kPanel * c;
-    T wv[kPanel];
-#pragma unroll
-    for (int t = 0; t < kPanel; ++t) wv[t] = t < nb ? w[t] : T(0);
-#pragma unroll
-    for (int i = 0; i < kPanel; ++i) {
-      if (i < nb) {
-        T s = T(0);
-#pragma unroll
-        for (int t = 0; t <= i; ++t) s += Di[i][t] * wv[t];
-        base[(j0 + i) + (int64_t)f.ld * c] = -s;
-      }
+  if (lane < nb) {
+    const int c = lane;
+    Di[c][c] = T(1) / D[c][c];
+    for (int i = c + 1; i < nb; ++i) {
+      T s = T(0);
+      for (int t = c; t < i; ++t) s += D[i][t] * Di[t][c];
+      Di[i][c] = -s / D[i][i];
     }
   }
+  __syncthreads();
+  for (int t = 0; t < nb; ++t)
+    if (lane < nb && t <= lane) base[lane + (int64_t)f.ld * t] = Di[lane][t];
 }
 
 __global__ __launch_bounds__(NTHR) void k_pchol(const double* __restrict__ G, double* __restrict__ L,
@@ -479,82 +414,107 @@ double gemm_flops(const GemmDesc& d, int flags) {
 
 template <typename T>
 void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  T* work, int* err, hipStream_t s) {
+                  int* err, hipStream_t s) {
   const int batch = (int)h_fronts.size();
   if (batch == 0) return;
   HIF_REQUIRE(batch <= 65535, HIF_EINVAL, "too many fronts in one launch");
   int maxI = 0;
   for (auto& f : h_fronts) maxI = std::max(maxI, f.nI);
+  DevBuf<T> dinv((size_t)batch * kPanel * kPanel);
   for (int j0 = 0; j0 < maxI; j0 += kPanel) {
     int max_m = 0, max_n = 0;
+    double fl_panel = 0.0, fl_trail = 0.0;
     for (auto& f : h_fronts) {
       if (f.nI <= j0) continue;
       const int nb = std::min(kPanel, f.nI - j0);
-      max_m = std::max(max_m, f.nR - j0 - nb);
-      max_n = std::max(max_n, f.nI - j0 - nb);
+      const double m = f.nR - j0 - nb, n = f.nI - j0 - nb;
+      max_m = std::max(max_m, (int)m);
+      max_n = std::max(max_n, (int)n);
+      fl_panel += m * nb * (nb + 1.0);
+      fl_trail += 2.0 * nb * (n * m - n * (n - 1) / 2);
     }
     {
       ProfScope ps("potrf_diag", s);
-      hipLaunchKernelGGL((k_front_diag<T>), dim3((unsigned)batch), dim3(NTHR), 0, s, arena,
-                         d_fronts, j0, err);
+      hipLaunchKernelGGL((k_front_diag<T>), dim3((unsigned)batch), dim3(64), 0, s, arena,
+                         d_fronts, j0, dinv.get(), err);
       HIF_LAUNCH_CHECK();
     }
     if (max_m > 0) {
-      ProfScope ps("potrf_panel", s);
-      dim3 gp((unsigned)ceil_div(max_m, NTHR), (unsigned)batch);
-      hipLaunchKernelGGL((k_front_panel<T>), gp, dim3(NTHR), 0, s, arena, d_fronts, j0);
+      ProfScope ps("potrf_panel", s, fl_panel);
+      dim3 gp(1, (unsigned)ceil_div(max_m, BM), (unsigned)batch);
+      hipLaunchKernelGGL((k_front_panel<T>), gp, dim3(NTHR), 0, s, arena, d_fronts, j0,
+                         (const T*)dinv.get());
       HIF_LAUNCH_CHECK();
     }
     if (max_m > 0 && max_n > 0) {
-      double fl = 0.0;
-      for (auto& f : h_fronts) {
-        if (f.nI <= j0) continue;
-        const int nb = std::min(kPanel, f.nI - j0);
-        const double m = f.nR - j0 - nb, n = f.nI - j0 - nb;
-        fl += 2.0 * nb * (n * m - n * (n - 1) / 2);
-      }
-      ProfScope ps("potrf_trailing", s, fl);
+      ProfScope ps("potrf_trailing", s, fl_trail);
       dim3 gt((unsigned)ceil_div(max_n, BN), (unsigned)ceil_div(max_m, BM), (unsigned)batch);
       hipLaunchKernelGGL((k_front_trailing<T>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0);
       HIF_LAUNCH_CHECK();
     }
   }
-  front_invert<T>(arena, d_fronts, h_fronts, work, s);
+  HIF_HIP(hipStreamSynchronize(s));  // dinv is released on return
+  front_invert<T>(arena, d_fronts, h_fronts, s);
 }
 
+// In-place inverse of the lower-triangular L_I of every front, bottom-up over
+// doubling block sizes: with the two diagonal halves already inverted,
+// inv([[A, 0], [B, C]]) = [[A^-1, 0], [-C^-1 B A^-1, C^-1]].
 template <typename T>
 void front_invert(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  T* work, hipStream_t s) {
+                  hipStream_t s) {
   const int batch = (int)h_fronts.size();
   if (batch == 0) return;
   HIF_REQUIRE(batch <= 65535, HIF_EINVAL, "too many fronts in one launch");
   int maxI = 0;
   for (auto& f : h_fronts) maxI = std::max(maxI, f.nI);
-  const int64_t wstride = (int64_t)kPanel * std::max(maxI, 1);
-  for (int j0 = 0; j0 < maxI; j0 += kPanel) {
-    {
-      ProfScope ps("trtri_diag", s);
-      hipLaunchKernelGGL((k_trtri_diag<T>), dim3((unsigned)batch), dim3(NTHR), 0, s, arena,
-                         d_fronts, j0);
-      HIF_LAUNCH_CHECK();
+  {
+    ProfScope ps("trtri_diag", s);
+    dim3 g((unsigned)ceil_div(maxI, kPanel), (unsigned)batch);
+    hipLaunchKernelGGL((k_diag_inv<T>), g, dim3(64), 0, s, arena, d_fronts);
+    HIF_LAUNCH_CHECK();
+  }
+  int64_t wmax = 0;
+  for (int sz = kPanel; sz < maxI; sz *= 2) {
+    int64_t w = 0;
+    for (auto& f : h_fronts)
+      for (int o = 0; o + sz < f.nI; o += 2 * sz) w += (int64_t)std::min(sz, f.nI - o - sz) * sz;
+    wmax = std::max(wmax, w);
+  }
+  if (wmax == 0) return;
+  DevBuf<T> W(wmax);
+  std::vector<GemmDesc> g1, g2;
+  DevBuf<GemmDesc> d1, d2;
+  for (int sz = kPanel; sz < maxI; sz *= 2) {
+    g1.clear();
+    g2.clear();
+    int64_t w = 0;
+    int mm = 0, mk = 0;
+    double f1 = 0.0, f2 = 0.0;
+    for (auto& f : h_fronts) {
+      T* base = arena + f.off;
+      for (int o = 0; o + sz < f.nI; o += 2 * sz) {
+        const int nc = std::min(sz, f.nI - o - sz);
+        T* Bp = base + (o + sz) + (int64_t)f.ld * o;
+        T* Ai = base + o + (int64_t)f.ld * o;
+        T* Ci = base + (o + sz) + (int64_t)f.ld * (o + sz);
+        g1.push_back({Bp, Ai, W.get() + w, nc, sz, sz, f.ld, f.ld, nc});
+        g2.push_back({Ci, W.get() + w, Bp, nc, sz, nc, f.ld, nc, f.ld});
+        f1 += gemm_flops(g1.back(), GF_B_LOWER);
+        f2 += gemm_flops(g2.back(), GF_A_LOWER);
+        w += (int64_t)nc * sz;
+        mm = std::max(mm, nc);
+      }
     }
-    if (j0 > 0) {
-      double fl = 0.0;
-      for (auto& f : h_fronts)
-        if (f.nI > j0) fl += (double)std::min(kPanel, f.nI - j0) * j0 * (j0 + 1);
-      ProfScope ps("trtri_gemm", s, fl);
-      dim3 g((unsigned)ceil_div(j0, BN), 1, (unsigned)batch);
-      hipLaunchKernelGGL((k_trtri_gemm<T>), g, dim3(NTHR), 0, s, arena, d_fronts, j0, work,
-                         wstride);
-      HIF_LAUNCH_CHECK();
-    }
-    if (j0 > 0) {
-      ProfScope ps("trtri_apply", s);
-      dim3 g2((unsigned)ceil_div(j0, NTHR), (unsigned)batch);
-      hipLaunchKernelGGL((k_trtri_apply<T>), g2, dim3(NTHR), 0, s, arena, d_fronts, j0,
-                         (const T*)work, wstride);
-      HIF_LAUNCH_CHECK();
-    }
+    (void)mk;
+    if (g1.empty()) continue;
+    d1.upload(g1, s);
+    d2.upload(g2, s);
+    gemm_batched<T, T>(OP_N, OP_N, GF_B_LOWER, d1.get(), (int)g1.size(), mm, sz, T(1), T(0), s,
+                       "trtri_gemm", f1);
+    gemm_batched<T, T>(OP_N, OP_N, GF_A_LOWER, d2.get(), (int)g2.size(), mm, sz, T(-1), T(0), s,
+                       "trtri_gemm", f2);
+    HIF_HIP(hipStreamSynchronize(s));  // descriptors are rewritten for the next size
   }
 }
 
@@ -575,12 +535,12 @@ template void gemm_batched<float, float>(int, int, int, const GemmDesc*, int, in
 template void gemm_batched<float, double>(int, int, int, const GemmDesc*, int, int, int, double,
                                           double, hipStream_t, const char*, double);
 template void front_factor<double>(double*, const FrontDesc*, const std::vector<FrontDesc>&,
-                                   double*, int*, hipStream_t);
-template void front_factor<float>(float*, const FrontDesc*, const std::vector<FrontDesc>&, float*,
-                                  int*, hipStream_t);
+                                   int*, hipStream_t);
+template void front_factor<float>(float*, const FrontDesc*, const std::vector<FrontDesc>&, int*,
+                                  hipStream_t);
 template void front_invert<double>(double*, const FrontDesc*, const std::vector<FrontDesc>&,
-                                   double*, hipStream_t);
-template void front_invert<float>(float*, const FrontDesc*, const std::vector<FrontDesc>&, float*,
+                                   hipStream_t);
+template void front_invert<float>(float*, const FrontDesc*, const std::vector<FrontDesc>&,
                                   hipStream_t);
 
 }  // namespace hif

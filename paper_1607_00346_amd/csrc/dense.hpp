@@ -55,17 +55,17 @@ struct FrontDesc {
 
 constexpr int kPanel = 64;  // block width of the blocked factorizations
 
-// Partial Cholesky of the first nI columns of every front, then L_I <- L_I^{-1}
-// in place.  work must hold batch * kPanel * max_nI elements.  err[0] receives
-// the smallest batch index with a non-positive pivot (untouched otherwise).
+// Partial Cholesky of the first nI columns of every front (rows nI..nR-1 get
+// A_SI L_I^{-T}), then L_I <- L_I^{-1} in place.  err[0] receives the smallest
+// batch index with a non-positive pivot (untouched otherwise).
 template <typename T>
 void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  T* work, int* err, hipStream_t s);
+                  int* err, hipStream_t s);
 
 // Only the in-place inverse of an already factored lower-triangular L_I.
 template <typename T>
 void front_invert(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  T* work, hipStream_t s);
+                  hipStream_t s);
 
 // Pivoted Cholesky of each symmetric G_b (nF x nF, FP64, offset goff[b], ld ldg[b]).
 // Writes the pivot columns L (same layout as G, column j = j-th pivot, rows in
