@@ -511,8 +511,10 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
           HIF_LAUNCH_CHECK();
         }
         DevBuf<int> d_k(P.nface);
+        std::vector<int64_t> hpoff(P.fpt_off.begin(), P.fpt_off.end() - 1);
         pivoted_cholesky(G.get(), Lp.get(), d_goff.get(), lev.fN.get(), d_gld.get(),
-                         lev.fpt_off.get(), d_perm.get(), d_k.get(), P.nface, o.eps, s);
+                         lev.fpt_off.get(), d_perm.get(), d_k.get(), P.nface, o.eps, P.fN, goff,
+                         gld, hpoff, s);
         HIF_HIP(hipMemcpyAsync(lev.hk.data(), d_k.get(), sizeof(int) * P.nface,
                                hipMemcpyDeviceToHost, s));
         HIF_HIP(hipMemcpyAsync(hperm.data(), d_perm.get(), sizeof(int) * hperm.size(),

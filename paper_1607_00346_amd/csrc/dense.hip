@@ -178,54 +178,68 @@ __global__ __launch_bounds__(NTHR) void k_front_trailing(T* arena, const FrontDe
                   m, n, nb, m0, n0, T(-1), T(1), As, Bs);
 }
 
+// Lower-triangular inverse of the 64 x 64 block held in LDS (D, rows >= nb
+// padded with the identity): lane c forms column c by forward substitution,
+// reading rows of L as LDS broadcasts; the column stays in registers.
+template <typename T>
+__device__ __forceinline__ void inverse_column(const T (*D)[kPanel + 1], int lane, T (&x)[kPanel]) {
+#pragma unroll
+  for (int i = 0; i < kPanel; ++i) {
+    T s = i == lane ? T(1) : T(0);
+#pragma unroll
+    for (int t = 0; t < i; ++t) s -= D[i][t] * x[t];
+    x[i] = i < lane ? T(0) : s / D[i][i];
+  }
+}
+
 // Cholesky of the diagonal block Phi[j0:j1, j0:j1] and its inverse, by one
-// wave per front (lane = row of the block, LDS-resident).  L_jj is written
-// back in place; L_jj^{-1} goes to dinv (64 x 64, column-major) for the panel.
+// wave per front: lane = row, the row lives in registers, each column is
+// broadcast through LDS.  L_jj is written back in place; L_jj^{-1} goes to
+// dinv (64 x 64, column-major) for the panel.  Rows/columns past nb are
+// padded with the identity.
 template <typename T>
 __global__ __launch_bounds__(64) void k_front_diag(T* arena, const FrontDesc* __restrict__ fd,
                                                    int j0, T* dinv, int* err) {
   __shared__ T D[kPanel][kPanel + 1];
-  __shared__ T Di[kPanel][kPanel + 1];
+  __shared__ T colv[kPanel];
   const FrontDesc f = fd[blockIdx.x];
   if (j0 >= f.nI) return;
   const int nb = min(kPanel, f.nI - j0);
   const int lane = threadIdx.x;
   T* base = arena + f.off + j0 + (int64_t)f.ld * j0;
-  for (int t = 0; t < nb; ++t)
-    if (lane < nb) D[lane][t] = t <= lane ? base[lane + (int64_t)f.ld * t] : T(0);
-  __syncthreads();
+  T a[kPanel];
+#pragma unroll
+  for (int t = 0; t < kPanel; ++t) {
+    T v = lane == t ? T(1) : T(0);
+    if (lane < nb && t < nb && t <= lane) v = base[lane + (int64_t)f.ld * t];
+    a[t] = v;
+  }
   bool bad = false;
-  for (int t = 0; t < nb; ++t) {
-    T d = D[t][t];
+#pragma unroll
+  for (int t = 0; t < kPanel; ++t) {
+    T d = __shfl(a[t], t);
     if (!(d > T(0))) { bad = true; d = T(1); }
     const T ltt = sqrt(d);
-    const T lit = lane > t && lane < nb ? D[lane][t] / ltt : T(0);
+    const T lit = lane > t ? a[t] / ltt : T(0);
+    a[t] = lane == t ? ltt : lit;
+    colv[lane] = lit;
     __syncthreads();
-    if (lane == t) D[t][t] = ltt;
-    if (lane > t && lane < nb) D[lane][t] = lit;
-    __syncthreads();
-    if (lane > t && lane < nb)
-      for (int j = t + 1; j <= lane; ++j) D[lane][j] -= lit * D[j][t];
+#pragma unroll
+    for (int j = t + 1; j < kPanel; ++j)
+      if (lane >= j) a[j] -= lit * colv[j];
     __syncthreads();
   }
   if (bad && lane == 0) atomicMin(err, (int)blockIdx.x);
-  // column `lane` of the inverse by forward substitution
-  if (lane < nb) {
-    const int c = lane;
-    for (int i = 0; i < c; ++i) Di[i][c] = T(0);
-    Di[c][c] = T(1) / D[c][c];
-    for (int i = c + 1; i < nb; ++i) {
-      T s = T(0);
-      for (int t = c; t < i; ++t) s += D[i][t] * Di[t][c];
-      Di[i][c] = -s / D[i][i];
-    }
+#pragma unroll
+  for (int t = 0; t < kPanel; ++t) {
+    D[lane][t] = t <= lane ? a[t] : T(0);
+    if (lane < nb && t < nb && t <= lane) base[lane + (int64_t)f.ld * t] = a[t];
   }
   __syncthreads();
-  T* dv = dinv + (int64_t)blockIdx.x * kPanel * kPanel;
-  for (int t = 0; t < kPanel; ++t) {
-    if (lane < nb && t <= lane) base[lane + (int64_t)f.ld * t] = D[lane][t];
-    dv[lane + kPanel * t] = (lane < nb && t < nb) ? Di[lane][t] : T(0);
-  }
+  inverse_column<T>(D, lane, a);  // a <- column `lane` of L_jj^{-1}
+  T* dv = dinv + (int64_t)blockIdx.x * kPanel * kPanel + (int64_t)kPanel * lane;
+#pragma unroll
+  for (int i = 0; i < kPanel; ++i) dv[i] = (lane < nb && i < nb) ? a[i] : T(0);
 }
 
 // Panel rows below the diagonal block, in place:
@@ -253,57 +267,66 @@ __global__ __launch_bounds__(NTHR) void k_front_panel(T* arena, const FrontDesc*
 template <typename T>
 __global__ __launch_bounds__(64) void k_diag_inv(T* arena, const FrontDesc* __restrict__ fd) {
   __shared__ T D[kPanel][kPanel + 1];
-  __shared__ T Di[kPanel][kPanel + 1];
   const FrontDesc f = fd[blockIdx.y];
   const int j0 = blockIdx.x * kPanel;
   if (j0 >= f.nI) return;
   const int nb = min(kPanel, f.nI - j0);
   const int lane = threadIdx.x;
   T* base = arena + f.off + j0 + (int64_t)f.ld * j0;
-  for (int t = 0; t < nb; ++t)
-    if (lane < nb) D[lane][t] = t <= lane ? base[lane + (int64_t)f.ld * t] : T(0);
-  __syncthreads();
-  if (lane < nb) {
-    const int c = lane;
-    Di[c][c] = T(1) / D[c][c];
-    for (int i = c + 1; i < nb; ++i) {
-      T s = T(0);
-      for (int t = c; t < i; ++t) s += D[i][t] * Di[t][c];
-      Di[i][c] = -s / D[i][i];
-    }
+#pragma unroll
+  for (int t = 0; t < kPanel; ++t) {
+    T v = lane == t ? T(1) : T(0);
+    if (lane < nb && t < nb && t <= lane) v = base[lane + (int64_t)f.ld * t];
+    D[lane][t] = v;
   }
   __syncthreads();
-  for (int t = 0; t < nb; ++t)
-    if (lane < nb && t <= lane) base[lane + (int64_t)f.ld * t] = Di[lane][t];
+  T x[kPanel];
+  inverse_column<T>(D, lane, x);
+#pragma unroll
+  for (int i = 0; i < kPanel; ++i)
+    if (lane < nb && i < nb && i >= lane) base[i + (int64_t)f.ld * lane] = x[i];
 }
 
-__global__ __launch_bounds__(NTHR) void k_pchol(const double* __restrict__ G, double* __restrict__ L,
-                                                const int64_t* __restrict__ goff,
-                                                const int* __restrict__ nFa,
-                                                const int* __restrict__ ldga,
-                                                const int64_t* __restrict__ poff,
-                                                int* __restrict__ perm, int* __restrict__ kout,
-                                                double eps) {
+// One panel (up to kPivPanel pivots) of the diagonal-pivoted Cholesky of a
+// Gram matrix, one workgroup per face.  G is up to date for all columns
+// before j0 (the trailing updates of earlier panels were applied by GEMM);
+// within the panel each new column subtracts the panel's earlier columns.
+// The Schur diagonal d, the pivot flags and the stop state persist in global
+// memory between launches.  Pivot: largest remaining diagonal, ties to the
+// lowest index; stop when it is <= eps^2 times the first pivot.
+constexpr int kPivPanel = 32;
+
+__global__ __launch_bounds__(NTHR) void k_pchol_panel(
+    const double* __restrict__ G, double* __restrict__ L, const int64_t* __restrict__ goff,
+    const int* __restrict__ nFa, const int* __restrict__ ldga, const int64_t* __restrict__ poff,
+    int* __restrict__ perm, double* __restrict__ dbuf, int* __restrict__ pivbuf,
+    int* __restrict__ kst, double* __restrict__ r11, double eps, int j0) {
   __shared__ double d[kPcholMax];
   __shared__ unsigned char piv[kPcholMax];
+  __shared__ double lp[kPivPanel];
   __shared__ double rv[NTHR / 64];
   __shared__ int ri[NTHR / 64];
   __shared__ int s_p, s_stop;
   __shared__ double s_dp, s_r11;
   const int b = blockIdx.x;
   const int nF = nFa[b];
+  if (kst[b] >= 0 || j0 >= nF) return;
   const int ld = ldga[b];
   const double* Gb = G + goff[b];
   double* Lb = L + goff[b];
   int* pb = perm + poff[b];
+  double* db = dbuf + poff[b];
+  int* pvb = pivbuf + poff[b];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int a = tid; a < nF; a += NTHR) {
-    d[a] = Gb[a + (int64_t)ld * a];
-    piv[a] = 0;
+    d[a] = j0 == 0 ? Gb[a + (int64_t)ld * a] : db[a];
+    piv[a] = j0 == 0 ? 0 : (unsigned char)pvb[a];
   }
+  if (tid == 0) s_r11 = j0 == 0 ? 0.0 : r11[b];
   __syncthreads();
-  int k = nF;
-  for (int j = 0; j < nF; ++j) {
+  const int jend = min(j0 + kPivPanel, nF);
+  int stopped = 0;
+  for (int j = j0; j < jend; ++j) {
     double bv = -DBL_MAX;
     int bi = INT_MAX;
     for (int a = tid; a < nF; a += NTHR) {
@@ -326,7 +349,9 @@ __global__ __launch_bounds__(NTHR) void k_pchol(const double* __restrict__ G, do
       if (j == 0) s_r11 = bv;
       const int stop = (j == 0) ? !(bv > 0.0) : !(bv > eps * eps * s_r11);
       s_stop = stop;
-      if (!stop) {
+      if (stop) {
+        kst[b] = j;
+      } else {
         s_p = bi;
         s_dp = bv;
         piv[bi] = 1;
@@ -334,25 +359,20 @@ __global__ __launch_bounds__(NTHR) void k_pchol(const double* __restrict__ G, do
       }
     }
     __syncthreads();
-    if (s_stop) { k = j; break; }
+    if (s_stop) { stopped = 1; break; }
     const int p = s_p;
     const double ljj = sqrt(s_dp);
+    const int np = j - j0;
+    if (tid < np) lp[tid] = Lb[p + (int64_t)ld * (j0 + tid)];
+    __syncthreads();
     for (int a = tid; a < nF; a += NTHR) {
       double v;
       if (a == p) v = ljj;
       else if (piv[a]) v = 0.0;
       else {
         double s = Gb[a + (int64_t)ld * p];
-        const double* la = Lb + a;
-        const double* lp = Lb + p;
-        int t = 0;
-        for (; t + 4 <= j; t += 4) {
-          s -= la[(int64_t)ld * t] * lp[(int64_t)ld * t] +
-               la[(int64_t)ld * (t + 1)] * lp[(int64_t)ld * (t + 1)] +
-               la[(int64_t)ld * (t + 2)] * lp[(int64_t)ld * (t + 2)] +
-               la[(int64_t)ld * (t + 3)] * lp[(int64_t)ld * (t + 3)];
-        }
-        for (; t < j; ++t) s -= la[(int64_t)ld * t] * lp[(int64_t)ld * t];
+        const double* la = Lb + a + (int64_t)ld * j0;
+        for (int t = 0; t < np; ++t) s -= la[(int64_t)ld * t] * lp[t];
         v = s / ljj;
         d[a] -= v * v;
       }
@@ -362,11 +382,33 @@ __global__ __launch_bounds__(NTHR) void k_pchol(const double* __restrict__ G, do
     __syncthreads();
   }
   if (tid == 0) {
-    kout[b] = k;
-    int pos = k;
-    for (int a = 0; a < nF; ++a)
-      if (!piv[a]) pb[pos++] = a;
+    if (!stopped && jend == nF) kst[b] = nF;
+    r11[b] = s_r11;
   }
+  for (int a = tid; a < nF; a += NTHR) {
+    db[a] = d[a];
+    pvb[a] = piv[a];
+  }
+}
+
+// Rank and the tail of the permutation: unpivoted indices ascending.
+__global__ __launch_bounds__(64) void k_pchol_tail(const int* __restrict__ nFa,
+                                                   const int64_t* __restrict__ poff,
+                                                   int* __restrict__ perm,
+                                                   const int* __restrict__ pivbuf,
+                                                   const int* __restrict__ kst,
+                                                   int* __restrict__ kout) {
+  const int b = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  const int nF = nFa[b];
+  int k = kst[b];
+  if (k < 0) k = nF;
+  kout[b] = k;
+  int* pb = perm + poff[b];
+  const int* pvb = pivbuf + poff[b];
+  int pos = k;
+  for (int a = 0; a < nF; ++a)
+    if (!pvb[a]) pb[pos++] = a;
 }
 
 }  // namespace
@@ -518,14 +560,49 @@ void front_invert(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
   }
 }
 
-void pivoted_cholesky(const double* G, double* L, const int64_t* goff, const int* nF,
-                      const int* ldg, const int64_t* poff, int* perm, int* k, int batch,
-                      double eps, hipStream_t s) {
+void pivoted_cholesky(double* G, double* L, const int64_t* goff, const int* nF, const int* ldg,
+                      const int64_t* poff, int* perm, int* k, int batch, double eps,
+                      const std::vector<int>& h_nF, const std::vector<int64_t>& h_goff,
+                      const std::vector<int>& h_ldg, const std::vector<int64_t>& h_poff,
+                      hipStream_t s) {
   if (batch <= 0) return;
-  ProfScope ps("pivoted_cholesky", s);
-  hipLaunchKernelGGL(k_pchol, dim3((unsigned)batch), dim3(NTHR), 0, s, G, L, goff, nF, ldg, poff,
-                     perm, k, eps);
+  int maxF = 0;
+  for (int v : h_nF) maxF = std::max(maxF, v);
+  const int64_t tot = h_poff.back() + h_nF.back();
+  DevBuf<double> dbuf(std::max<int64_t>(tot, 1)), r11(batch);
+  DevBuf<int> pivbuf(std::max<int64_t>(tot, 1)), kst(batch);
+  HIF_HIP(hipMemsetAsync(kst.get(), 0xff, sizeof(int) * batch, s));  // -1: running
+  std::vector<GemmDesc> gd;
+  DevBuf<GemmDesc> dd;
+  for (int j0 = 0; j0 < maxF; j0 += kPivPanel) {
+    {
+      ProfScope ps("pivoted_cholesky", s);
+      hipLaunchKernelGGL(k_pchol_panel, dim3((unsigned)batch), dim3(NTHR), 0, s, G, L, goff, nF,
+                         ldg, poff, perm, dbuf.get(), pivbuf.get(), kst.get(), r11.get(), eps, j0);
+      HIF_LAUNCH_CHECK();
+    }
+    if (j0 + kPivPanel >= maxF) break;
+    gd.clear();
+    int mm = 0;
+    double fl = 0.0;
+    for (int b = 0; b < batch; ++b) {
+      if (h_nF[b] <= j0 + kPivPanel) continue;
+      const int kk = std::min(kPivPanel, h_nF[b] - j0);
+      double* Lp = L + h_goff[b] + (int64_t)h_ldg[b] * j0;
+      gd.push_back({Lp, Lp, G + h_goff[b], h_nF[b], h_nF[b], kk, h_ldg[b], h_ldg[b], h_ldg[b]});
+      mm = std::max(mm, h_nF[b]);
+      fl += 2.0 * kk * (double)h_nF[b] * h_nF[b];
+    }
+    if (gd.empty()) continue;
+    HIF_HIP(hipStreamSynchronize(s));  // previous descriptors may still be in use
+    dd.upload(gd, s);
+    gemm_batched<double, double>(OP_N, OP_T, 0, dd.get(), (int)gd.size(), mm, mm, -1.0, 1.0, s,
+                                 "pivchol_update", fl);
+  }
+  hipLaunchKernelGGL(k_pchol_tail, dim3((unsigned)batch), dim3(64), 0, s, nF, poff, perm,
+                     (const int*)pivbuf.get(), (const int*)kst.get(), k);
   HIF_LAUNCH_CHECK();
+  HIF_HIP(hipStreamSynchronize(s));  // work buffers are released on return
 }
 
 template void gemm_batched<double, double>(int, int, int, const GemmDesc*, int, int, int, double,

@@ -67,13 +67,16 @@ template <typename T>
 void front_invert(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
                   hipStream_t s);
 
-// Pivoted Cholesky of each symmetric G_b (nF x nF, FP64, offset goff[b], ld ldg[b]).
-// Writes the pivot columns L (same layout as G, column j = j-th pivot, rows in
-// original order), perm (nF entries at poff[b]: pivots then the unpivoted
-// indices ascending) and the rank k[b].  eps > 0.
+// Pivoted Cholesky of each symmetric G_b (nF x nF, FP64, offset goff[b], ld
+// ldg[b]), blocked: G is overwritten by its trailing updates.  Writes the
+// pivot columns L (same layout as G; column j = j-th pivot, rows in original
+// order, zero on rows pivoted earlier), perm (nF entries at poff[b]: pivots,
+// then the unpivoted indices ascending) and the rank k[b].  eps > 0.
 constexpr int kPcholMax = 4096;
-void pivoted_cholesky(const double* G, double* L, const int64_t* goff, const int* nF,
-                      const int* ldg, const int64_t* poff, int* perm, int* k, int batch,
-                      double eps, hipStream_t s);
+void pivoted_cholesky(double* G, double* L, const int64_t* goff, const int* nF, const int* ldg,
+                      const int64_t* poff, int* perm, int* k, int batch, double eps,
+                      const std::vector<int>& h_nF, const std::vector<int64_t>& h_goff,
+                      const std::vector<int>& h_ldg, const std::vector<int64_t>& h_poff,
+                      hipStream_t s);
 
 }  // namespace hif
