@@ -95,6 +95,17 @@ def run_gpu(args):
     return out
 
 
+def by_class(prof):
+    """Sum the per-level entries ("name@level") of each kernel class."""
+    out = {}
+    for key, v in prof.items():
+        base = key.split("@")[0]
+        o = out.setdefault(base, {"launches": 0, "seconds": 0.0, "flops": 0.0, "bytes": 0.0})
+        for f in o:
+            o[f] += v[f]
+    return out
+
+
 def roofline(prof, fp64: bool):
     """Dominant kernel class of the timed region against its roofline: flops
     for the matrix-core kernels, bytes for the sweeps."""
@@ -203,14 +214,18 @@ def main():
                    "n": 128, "leaf": 8, "eps_mixed": 1e-4, "eps_fp64": 1e-6},
         "extra": extra,
     }
-    line["roofline"] = roofline(mixed["prof"], fp64=False)
-    apply_classes = {k: v for k, v in mixed["prof"].items() if k.startswith("apply_")}
+    pm = by_class(mixed["prof"])
+    line["roofline"] = roofline(pm, fp64=False)
+    apply_classes = {k: v for k, v in pm.items() if k.startswith("apply_")}
     if apply_classes:
         line["extra"]["roofline_apply"] = roofline(apply_classes, fp64=False)
-    line["extra"]["kernels_mixed"] = kernel_table(mixed["prof"], args.steps)
+    line["extra"]["kernels_mixed"] = kernel_table(pm, args.steps)
+    line["extra"]["kernels_mixed_by_level"] = kernel_table(mixed["prof"], args.steps)[:40]
     if "fp64" in r:
-        line["extra"]["roofline_fp64"] = roofline(r["fp64"]["prof"], fp64=True)
-        line["extra"]["kernels_fp64"] = kernel_table(r["fp64"]["prof"], args.steps)
+        pd = by_class(r["fp64"]["prof"])
+        line["extra"]["roofline_fp64"] = roofline(pd, fp64=True)
+        line["extra"]["kernels_fp64"] = kernel_table(pd, args.steps)
+        line["extra"]["kernels_fp64_by_level"] = kernel_table(r["fp64"]["prof"], args.steps)[:40]
     line["extra"]["stats_mixed"] = {k: mixed["stats"][k] for k in (
         "cells", "faces", "eliminated", "face_dofs", "redundant", "max_front", "level_seconds",
         "factor_flops")}

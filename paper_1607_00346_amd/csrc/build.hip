@@ -327,6 +327,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
 
   for (int level = 0; level <= L; ++level) {
     const double t_level = now_s();
+    profiler().level = level;
     Level<T>& lev = Fi.levels[level];
     Level<T>* prev = level > 0 ? &Fi.levels[level - 1] : nullptr;
     lev.P = plan_level(n, leaf, level, L, active);
@@ -697,6 +698,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
     HIF_HIP(hipStreamSynchronize(s));
     st.level_seconds[level] = now_s() - t_level;
   }
+  profiler().level = -1;
   st.factor_flops = flops;
   st.build_seconds = now_s() - t_begin;
   st.peak_bytes = mem_stats().peak - mem0;

@@ -35,105 +35,137 @@ struct Mfma<float> {
 
 constexpr int BM = 64, BN = 64, KC = 16, NTHR = 256;
 
-// One 64x64 tile of C = alpha op(A) op(B) + beta C, four waves in a 2x2
-// arrangement of 32x32 sub-tiles, K staged through LDS in chunks of 16 with
-// a register prefetch of the next chunk.
-template <typename TIn, typename TC>
-__device__ void gemm_tile(int opa, int opb, int flags, const TIn* A, int lda,
-                          const TIn* __restrict__ B, int ldb, TC* C, int ldc, int m,
-                          int n, int k, int m0, int n0, TC alpha, TC beta,
-                          TC (*As)[KC][BM], TC (*Bs)[KC][BN]) {
+// LDS staging of one K chunk: As[k][m], Bs[k][n], rows padded by one element
+// so that stores along k (transposed operands) do not collide in banks.
+template <typename TC, int TM, int TN>
+struct TileSmem {
+  static constexpr int NBUF = sizeof(TC) * (TM + TN + 2) * KC * 2 <= 36 * 1024 ? 2 : 1;
+  TC As[NBUF][KC][TM + 1];
+  TC Bs[NBUF][KC][TN + 1];
+};
+
+// One TM x TN tile of C = alpha op(A) op(B) + beta C by 256 threads: four
+// waves in a 2 x 2 arrangement, each owning (TM/2) x (TN/2) as 16 x 16 MFMA
+// blocks.  K is staged through LDS in chunks of 16 with a register prefetch of
+// the next chunk.  Masked operand entries (triangular flags, out of range)
+// read as zero.
+template <typename TIn, typename TC, int OPA, int OPB, int TM, int TN>
+__device__ void gemm_tile_t(int flags, const TIn* A, int lda, const TIn* __restrict__ B, int ldb,
+                            TC* C, int ldc, int m, int n, int k, int m0, int n0, TC alpha, TC beta,
+                            TileSmem<TC, TM, TN>& sm) {
+  constexpr int FM = TM / 32, FN = TN / 32;        // 16x16 blocks per wave
+  constexpr int LA = TM * KC / NTHR, LB = TN * KC / NTHR;  // loads per thread
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
   int kb = 0, ke = k;
-  if (flags & GF_A_LOWER) ke = min(ke, m0 + BM);
+  if (flags & GF_A_LOWER) ke = min(ke, m0 + TM);
   if (flags & GF_A_UPPER) kb = max(kb, m0);
   if (flags & GF_B_LOWER) kb = max(kb, n0);
-  if (flags & GF_B_UPPER) ke = min(ke, n0 + BN);
+  if (flags & GF_B_UPPER) ke = min(ke, n0 + TN);
   const int nchunk = ke > kb ? (ke - kb + KC - 1) / KC : 0;
+  const bool inside = m0 + TM <= m && n0 + TN <= n && !(flags & (GF_A_LOWER | GF_A_UPPER | GF_B_LOWER | GF_B_UPPER));
 
-  typename Mfma<TC>::acc_t acc[2][2];
+  typename Mfma<TC>::acc_t acc[FM][FN];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < FM; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < FN; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[x][y][v] = TC(0);
 
-  TC ra[4], rb[4];
+  TC ra[LA], rb[LB];
   auto load = [&](int c) {
     const int t0 = kb + c * KC;
+    const bool kfull = t0 + KC <= ke;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < LA; ++r) {
       int i, t;
-      if (opa == OP_N) { i = tid & 63; t = (tid >> 6) + 4 * r; }
+      if (OPA == OP_N) { i = tid % TM; t = tid / TM + (NTHR / TM) * r; }
       else { t = tid & 15; i = (tid >> 4) + 16 * r; }
       const int gi = m0 + i, gt = t0 + t;
-      bool ok = gi < m && gt < ke;
+      bool ok = (inside && kfull) || (gi < m && gt < ke);
       if (flags & GF_A_LOWER) ok = ok && gt <= gi;
       if (flags & GF_A_UPPER) ok = ok && gt >= gi;
       TC v = TC(0);
-      if (ok) v = (TC)(opa == OP_N ? A[gi + (int64_t)lda * gt] : A[gt + (int64_t)lda * gi]);
+      if (ok) v = (TC)(OPA == OP_N ? A[gi + (int64_t)lda * gt] : A[gt + (int64_t)lda * gi]);
       ra[r] = v;
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < LB; ++r) {
       int j, t;
-      if (opb == OP_N) { t = tid & 15; j = (tid >> 4) + 16 * r; }
-      else { j = tid & 63; t = (tid >> 6) + 4 * r; }
+      if (OPB == OP_N) { t = tid & 15; j = (tid >> 4) + 16 * r; }
+      else { j = tid % TN; t = tid / TN + (NTHR / TN) * r; }
       const int gj = n0 + j, gt = t0 + t;
-      bool ok = gj < n && gt < ke;
+      bool ok = (inside && kfull) || (gj < n && gt < ke);
       if (flags & GF_B_LOWER) ok = ok && gt >= gj;
       if (flags & GF_B_UPPER) ok = ok && gt <= gj;
       TC v = TC(0);
-      if (ok) v = (TC)(opb == OP_N ? B[gt + (int64_t)ldb * gj] : B[gj + (int64_t)ldb * gt]);
+      if (ok) v = (TC)(OPB == OP_N ? B[gt + (int64_t)ldb * gj] : B[gj + (int64_t)ldb * gt]);
       rb[r] = v;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      if (opa == OP_N) As[buf][(tid >> 6) + 4 * r][tid & 63] = ra[r];
-      else As[buf][tid & 15][(tid >> 4) + 16 * r] = ra[r];
-      if (opb == OP_N) Bs[buf][tid & 15][(tid >> 4) + 16 * r] = rb[r];
-      else Bs[buf][(tid >> 6) + 4 * r][tid & 63] = rb[r];
+    for (int r = 0; r < LA; ++r) {
+      if (OPA == OP_N) sm.As[buf][tid / TM + (NTHR / TM) * r][tid % TM] = ra[r];
+      else sm.As[buf][tid & 15][(tid >> 4) + 16 * r] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      if (OPB == OP_N) sm.Bs[buf][tid & 15][(tid >> 4) + 16 * r] = rb[r];
+      else sm.Bs[buf][tid / TN + (NTHR / TN) * r][tid % TN] = rb[r];
+    }
+  };
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      const int kk = 4 * s + (lane >> 4);
+      TC av[FM], bv[FN];
+#pragma unroll
+      for (int x = 0; x < FM; ++x) av[x] = sm.As[buf][kk][wm * (TM / 2) + 16 * x + (lane & 15)];
+#pragma unroll
+      for (int y = 0; y < FN; ++y) bv[y] = sm.Bs[buf][kk][wn * (TN / 2) + 16 * y + (lane & 15)];
+#pragma unroll
+      for (int x = 0; x < FM; ++x)
+#pragma unroll
+        for (int y = 0; y < FN; ++y) acc[x][y] = Mfma<TC>::run(av[x], bv[y], acc[x][y]);
     }
   };
 
   if (nchunk > 0) {
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int c = 0; c < nchunk; ++c) {
-      const int buf = c & 1;
-      if (c + 1 < nchunk) load(c + 1);
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int kk = 4 * s + (lane >> 4);
-        const TC a0 = As[buf][kk][wm * 32 + (lane & 15)];
-        const TC a1 = As[buf][kk][wm * 32 + 16 + (lane & 15)];
-        const TC b0 = Bs[buf][kk][wn * 32 + (lane & 15)];
-        const TC b1 = Bs[buf][kk][wn * 32 + 16 + (lane & 15)];
-        acc[0][0] = Mfma<TC>::run(a0, b0, acc[0][0]);
-        acc[0][1] = Mfma<TC>::run(a0, b1, acc[0][1]);
-        acc[1][0] = Mfma<TC>::run(a1, b0, acc[1][0]);
-        acc[1][1] = Mfma<TC>::run(a1, b1, acc[1][1]);
-      }
-      if (c + 1 < nchunk) store(buf ^ 1);
+    if constexpr (TileSmem<TC, TM, TN>::NBUF == 2) {
+      load(0);
+      store(0);
       __syncthreads();
+      for (int c = 0; c < nchunk; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nchunk) load(c + 1);
+        compute(buf);
+        if (c + 1 < nchunk) store(buf ^ 1);
+        __syncthreads();
+      }
+    } else {
+      load(0);
+      for (int c = 0; c < nchunk; ++c) {
+        store(0);
+        __syncthreads();
+        if (c + 1 < nchunk) load(c + 1);
+        compute(0);
+        __syncthreads();
+      }
     }
   }
 
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < FM; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < FN; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gi = m0 + wm * 32 + x * 16 + Mfma<TC>::row(lane, v);
-        const int gj = n0 + wn * 32 + y * 16 + (lane & 15);
+        const int gi = m0 + wm * (TM / 2) + x * 16 + Mfma<TC>::row(lane, v);
+        const int gj = n0 + wn * (TN / 2) + y * 16 + (lane & 15);
         if (gi < m && gj < n && (!(flags & GF_C_LOWER) || gi >= gj)) {
           const int64_t idx = gi + (int64_t)ldc * gj;
           TC val = alpha * acc[x][y][v];
@@ -143,39 +175,37 @@ __device__ void gemm_tile(int opa, int opb, int flags, const TIn* A, int lda,
       }
 }
 
-template <typename TIn, typename TC>
-__global__ __launch_bounds__(NTHR) void k_gemm_desc(int opa, int opb, int flags,
-                                                    const GemmDesc* __restrict__ desc, TC alpha,
-                                                    TC beta) {
-  __shared__ TC As[2][KC][BM];
-  __shared__ TC Bs[2][KC][BN];
+template <typename TIn, typename TC, int OPA, int OPB, int TM, int TN>
+__global__ __launch_bounds__(NTHR) void k_gemm_desc(int flags, const GemmDesc* __restrict__ desc,
+                                                    TC alpha, TC beta) {
+  __shared__ TileSmem<TC, TM, TN> sm;
   const GemmDesc d = desc[blockIdx.z];
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
   if (m0 >= d.m || n0 >= d.n) return;
-  if ((flags & GF_C_LOWER) && m0 + BM - 1 < n0) return;
-  gemm_tile<TIn, TC>(opa, opb, flags, (const TIn*)d.A, d.lda, (const TIn*)d.B, d.ldb, (TC*)d.C,
-                     d.ldc, d.m, d.n, d.k, m0, n0, alpha, beta, As, Bs);
+  if ((flags & GF_C_LOWER) && m0 + TM - 1 < n0) return;
+  gemm_tile_t<TIn, TC, OPA, OPB, TM, TN>(flags, (const TIn*)d.A, d.lda, (const TIn*)d.B, d.ldb,
+                                         (TC*)d.C, d.ldc, d.m, d.n, d.k, m0, n0, alpha, beta, sm);
 }
 
 // Trailing update of the blocked front Cholesky at block column j0:
 // Phi[j1:nR, j1:nI] -= P[j1:nR] P[j1:nI]^T (lower part), P = Phi[:, j0:j1].
-template <typename T>
+template <typename T, int TS>
 __global__ __launch_bounds__(NTHR) void k_front_trailing(T* arena, const FrontDesc* __restrict__ fd,
                                                          int j0) {
-  __shared__ T As[2][KC][BM];
-  __shared__ T Bs[2][KC][BN];
+  __shared__ TileSmem<T, TS, TS> sm;
   const FrontDesc f = fd[blockIdx.z];
   if (j0 >= f.nI) return;
   const int nb = min(kPanel, f.nI - j0);
   const int j1 = j0 + nb;
   const int m = f.nR - j1, n = f.nI - j1;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int m0 = blockIdx.y * TS, n0 = blockIdx.x * TS;
   if (m0 >= m || n0 >= n) return;
-  if (m0 + BM - 1 < n0) return;
+  if (m0 + TS - 1 < n0) return;
   T* base = arena + f.off;
   const T* P = base + j1 + (int64_t)f.ld * j0;
-  gemm_tile<T, T>(OP_N, OP_T, GF_C_LOWER, P, f.ld, P, f.ld, base + j1 + (int64_t)f.ld * j1, f.ld,
-                  m, n, nb, m0, n0, T(-1), T(1), As, Bs);
+  gemm_tile_t<T, T, OP_N, OP_T, TS, TS>(GF_C_LOWER, P, f.ld, P, f.ld,
+                                        base + j1 + (int64_t)f.ld * j1, f.ld, m, n, nb, m0, n0,
+                                        T(-1), T(1), sm);
 }
 
 // Lower-triangular inverse of the 64 x 64 block held in LDS (D, rows >= nb
@@ -248,8 +278,7 @@ __global__ __launch_bounds__(64) void k_front_diag(T* arena, const FrontDesc* __
 template <typename T>
 __global__ __launch_bounds__(NTHR) void k_front_panel(T* arena, const FrontDesc* __restrict__ fd,
                                                       int j0, const T* __restrict__ dinv) {
-  __shared__ T As[2][KC][BM];
-  __shared__ T Bs[2][KC][BN];
+  __shared__ TileSmem<T, BM, BN> sm;
   const FrontDesc f = fd[blockIdx.z];
   if (j0 >= f.nI) return;
   const int nb = min(kPanel, f.nI - j0);
@@ -258,8 +287,9 @@ __global__ __launch_bounds__(NTHR) void k_front_panel(T* arena, const FrontDesc*
   const int m0 = blockIdx.y * BM;
   if (m0 >= m) return;
   T* P = arena + f.off + j1 + (int64_t)f.ld * j0;
-  gemm_tile<T, T>(OP_N, OP_T, GF_B_UPPER, P, f.ld, dinv + (int64_t)blockIdx.z * kPanel * kPanel,
-                  kPanel, P, f.ld, m, nb, nb, m0, 0, T(1), T(0), As, Bs);
+  gemm_tile_t<T, T, OP_N, OP_T, BM, BN>(GF_B_UPPER, P, f.ld,
+                                        dinv + (int64_t)blockIdx.z * kPanel * kPanel, kPanel, P,
+                                        f.ld, m, nb, nb, m0, 0, T(1), T(0), sm);
 }
 
 // In-place inverse of every 64 x 64 diagonal block of the factored L_I
@@ -413,18 +443,40 @@ __global__ __launch_bounds__(64) void k_pchol_tail(const int* __restrict__ nFa,
 
 }  // namespace
 
+template <typename TIn, typename TC, int OPA, int OPB, int TS>
+void launch_gemm(int flags, const GemmDesc* d_desc, int batch, int max_m, int max_n, TC alpha,
+                 TC beta, hipStream_t s) {
+  for (int b0 = 0; b0 < batch; b0 += 65535) {
+    const int nb = std::min(batch - b0, 65535);
+    dim3 grid((unsigned)ceil_div(max_n, TS), (unsigned)ceil_div(max_m, TS), (unsigned)nb);
+    hipLaunchKernelGGL((k_gemm_desc<TIn, TC, OPA, OPB, TS, TS>), grid, dim3(NTHR), 0, s, flags,
+                       d_desc + b0, alpha, beta);
+    HIF_LAUNCH_CHECK();
+  }
+}
+
+template <typename TIn, typename TC, int TS>
+void dispatch_gemm(int opa, int opb, int flags, const GemmDesc* d_desc, int batch, int max_m,
+                   int max_n, TC alpha, TC beta, hipStream_t s) {
+  if (opa == OP_N && opb == OP_N)
+    launch_gemm<TIn, TC, OP_N, OP_N, TS>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+  else if (opa == OP_N)
+    launch_gemm<TIn, TC, OP_N, OP_T, TS>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+  else if (opb == OP_N)
+    launch_gemm<TIn, TC, OP_T, OP_N, TS>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+  else
+    launch_gemm<TIn, TC, OP_T, OP_T, TS>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+}
+
 template <typename TIn, typename TC>
 void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch, int max_m,
                   int max_n, TC alpha, TC beta, hipStream_t s, const char* name, double flops) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
   ProfScope ps(name, s, flops);
-  for (int b0 = 0; b0 < batch; b0 += 65535) {
-    const int nb = std::min(batch - b0, 65535);
-    dim3 grid((unsigned)ceil_div(max_n, BN), (unsigned)ceil_div(max_m, BM), (unsigned)nb);
-    hipLaunchKernelGGL((k_gemm_desc<TIn, TC>), grid, dim3(NTHR), 0, s, opa, opb, flags,
-                       d_desc + b0, alpha, beta);
-    HIF_LAUNCH_CHECK();
-  }
+  if (max_m >= 1024 && max_n >= 1024)
+    dispatch_gemm<TIn, TC, 128>(opa, opb, flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+  else
+    dispatch_gemm<TIn, TC, 64>(opa, opb, flags, d_desc, batch, max_m, max_n, alpha, beta, s);
 }
 
 double gemm_flops(const GemmDesc& d, int flags) {
@@ -490,8 +542,13 @@ void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
     }
     if (max_m > 0 && max_n > 0) {
       ProfScope ps("potrf_trailing", s, fl_trail);
-      dim3 gt((unsigned)ceil_div(max_n, BN), (unsigned)ceil_div(max_m, BM), (unsigned)batch);
-      hipLaunchKernelGGL((k_front_trailing<T>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0);
+      if (max_n >= 1024) {
+        dim3 gt((unsigned)ceil_div(max_n, 128), (unsigned)ceil_div(max_m, 128), (unsigned)batch);
+        hipLaunchKernelGGL((k_front_trailing<T, 128>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0);
+      } else {
+        dim3 gt((unsigned)ceil_div(max_n, 64), (unsigned)ceil_div(max_m, 64), (unsigned)batch);
+        hipLaunchKernelGGL((k_front_trailing<T, 64>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0);
+      }
       HIF_LAUNCH_CHECK();
     }
   }

@@ -1,6 +1,7 @@
 // Per-kernel-class event timing (see prof.hpp).
 #include "prof.hpp"
 
+#include <cstdio>
 #include <cstring>
 
 namespace hif {
@@ -31,7 +32,13 @@ hipEvent_t Profiler::event() {
 ProfScope::ProfScope(const char* name, hipStream_t s, double flops, double bytes) {
   Profiler& p = profiler();
   if (!p.on) return;
-  rec_.cls = p.class_id(name);
+  if (p.level >= 0) {
+    char buf[64];
+    snprintf(buf, sizeof(buf), "%s@%d", name, p.level);
+    rec_.cls = p.class_id(buf);
+  } else {
+    rec_.cls = p.class_id(name);
+  }
   rec_.a = p.event();
   rec_.b = p.event();
   rec_.flops = flops;

@@ -19,6 +19,7 @@ class Profiler {
     double flops, bytes;
   };
   bool on = false;
+  int level = -1;  // appended to class names as "@level" when >= 0
   std::vector<std::string> names;
   std::vector<Rec> recs;
 

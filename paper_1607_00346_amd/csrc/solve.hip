@@ -398,6 +398,7 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   // W^l^T for l = 0..L (level L: L_Sigma^{-1})
   for (int l = 0; l < nlev; ++l) {
     Level<T>& lv = levels[l];
+    profiler().level = l;
     const int nc = lv.P.ncell;
     if (nc > 0) {
       dim3 gI((unsigned)ceil_div(std::max(1, lv.maxI), NT), (unsigned)nc);
@@ -442,6 +443,7 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   // W^l for l = L..0
   for (int l = nlev - 1; l >= 0; --l) {
     Level<T>& lv = levels[l];
+    profiler().level = l;
     if (!lv.P.root && !lv.hsk.empty()) {
       ProfScope ps("apply_skel", s, 0.0, lv.bytes_skel);
       const size_t shm = sizeof(double) * (lv.maxk + 2 * (size_t)lv.maxr);
@@ -468,6 +470,7 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
     }
     HIF_LAUNCH_CHECK();
   }
+  profiler().level = -1;
 }
 
 template void FactorImpl<double>::apply(const double*, double*, hipStream_t);
