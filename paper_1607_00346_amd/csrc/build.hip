@@ -530,7 +530,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
           const int k = lev.hk[f], r = P.fN[f] - k;
           flops += (double)P.fN[f] * k * k;
           if (r == 0) continue;
-          SkelDesc d;
+          SkelDesc d{};
           d.face = f;
           d.k = k;
           d.r = r;
@@ -542,6 +542,10 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
           ssz += (int64_t)r * r;
           d.offY = ssz;
           ssz += (int64_t)r * k;
+          d.kofs = lev.ksum;
+          d.rofs = lev.rsum;
+          lev.ksum += k;
+          lev.rsum += r;
           lev.hsk.push_back(d);
           o11.push_back(s11);
           s11 += (int64_t)k * k;

@@ -29,6 +29,16 @@ struct SkelDesc {
   int face, k, r, pad_;
   int64_t pts_off;
   int64_t offT, offL, offY;
+  int64_t kofs, rofs;  // offsets of x_F̂ / x_F̌ in the apply scratch vectors
+};
+
+// One matrix of a batched matrix-vector product in the sweeps: A (m x n,
+// column-major, lower triangular if tri), its row-space vector at roff and
+// column-space vector at coff in the scratch arrays.
+struct GemvDesc {
+  const void* A;
+  int m, n, lda, tri;
+  int64_t roff, coff;
 };
 
 template <typename T>
@@ -61,6 +71,11 @@ struct Level {
   // algorithmic bytes of one sweep over this level (factor words read once,
   // 8-byte vector entries read and written), for the profiler
   double bytes_L = 0.0, bytes_S = 0.0, bytes_skel = 0.0;
+  // sweep descriptors (built on the first apply)
+  bool gv_ready = false;
+  DevBuf<GemvDesc> gv_L, gv_S, gv_T, gv_Lc, gv_Y;
+  int gv_nS = 0;  // cells with nS > 0 (gv_S entries)
+  int64_t ksum = 0, rsum = 0;
 };
 
 struct FactorBase {
@@ -75,6 +90,7 @@ struct FactorImpl : FactorBase {
   int64_t N = 0;
   std::vector<Level<T>> levels;
   DevBuf<double> ybuf, zbuf, xs;  // apply scratch
+  DevBuf<double> sbuf;            // skeleton scratch (x_F̂, x_F̌, L_F̌^{-1} x_F̌)
   void apply(const double* f, double* u, hipStream_t s) override;
   int64_t stored_bytes() const override;
 };

@@ -76,42 +76,6 @@ __global__ __launch_bounds__(NT) void k_gather_cell(const double* __restrict__ x
   else if (with_s && i < f.nR) xs[zoff[c] + i - f.nI] = x[r[i]];
 }
 
-// y = L_I^{-1} x_I  (thread per row of the stored lower-triangular inverse)
-template <typename T>
-__global__ __launch_bounds__(NT) void k_up_L(const T* __restrict__ arena,
-                                             const FrontDesc* __restrict__ fd,
-                                             const int64_t* __restrict__ yoff,
-                                             const double* __restrict__ xi, double* y) {
-  const int c = blockIdx.y;
-  const FrontDesc f = fd[c];
-  const int i = blockIdx.x * NT + threadIdx.x;
-  if (i >= f.nI) return;
-  const T* row = arena + f.off + i;
-  const double* xv = xi + yoff[c];
-  double s = 0.0;
-  for (int t = 0; t <= i; ++t) s += (double)row[(int64_t)f.ld * t] * xv[t];
-  y[yoff[c] + i] = s;
-}
-
-// z = L_SI y  (rows of S)
-template <typename T>
-__global__ __launch_bounds__(NT) void k_up_S(const T* __restrict__ arena,
-                                             const FrontDesc* __restrict__ fd,
-                                             const int64_t* __restrict__ yoff,
-                                             const int64_t* __restrict__ zoff,
-                                             const double* __restrict__ y, double* z) {
-  const int c = blockIdx.y;
-  const FrontDesc f = fd[c];
-  const int sidx = blockIdx.x * NT + threadIdx.x;
-  const int nS = f.nR - f.nI;
-  if (sidx >= nS) return;
-  const T* row = arena + f.off + f.nI + sidx;
-  const double* yv = y + yoff[c];
-  double s = 0.0;
-  for (int t = 0; t < f.nI; ++t) s += (double)row[(int64_t)f.ld * t] * yv[t];
-  z[zoff[c] + sidx] = s;
-}
-
 __global__ __launch_bounds__(NT) void k_scatter_I(double* x, const int* __restrict__ rows,
                                                   const int64_t* __restrict__ crow_off,
                                                   const FrontDesc* __restrict__ fd,
@@ -147,132 +111,85 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// S_F̌^T Q_F^T: x_F̌ -= T^T x_F̂; x_F̌ <- L_F̌^{-1} x_F̌; x_F̂ -= Y^T x_F̌.
+// y[roff + i] (+)= alpha sum_t A(i, t) x[coff + t]: 64 rows per workgroup,
+// the columns split over the four waves in groups of 8 (independent loads in
+// flight), partial sums reduced through LDS.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_skel_up(double* x, const int* __restrict__ skpts,
-                                                const SkelDesc* __restrict__ sk,
-                                                const T* __restrict__ skel) {
-  extern __shared__ double sm[];
-  const SkelDesc d = sk[blockIdx.x];
-  const int k = d.k, r = d.r;
-  double* xh = sm;
-  double* xc = sm + k;
-  double* xt = xc + r;
-  const int* pts = skpts + d.pts_off;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < k; i += NT) xh[i] = x[pts[i]];
-  for (int b = tid; b < r; b += NT) xc[b] = x[pts[k + b]];
-  __syncthreads();
-  const T* Tm = skel + d.offT;
-  for (int b = wave; b < r; b += NT / 64) {
-    double s = 0.0;
-    for (int i = lane; i < k; i += 64) s += (double)Tm[i + (int64_t)k * b] * xh[i];
-    s = wave_sum(s);
-    if (lane == 0) xc[b] -= s;
+__global__ __launch_bounds__(NT) void k_gemv_n(const GemvDesc* __restrict__ dd,
+                                               const double* __restrict__ x, double* y,
+                                               double alpha, int accumulate) {
+  __shared__ double part[NT / 64][64];
+  const GemvDesc d = dd[blockIdx.y];
+  const int r0 = blockIdx.x * 64;
+  if (r0 >= d.m) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = r0 + lane;
+  const bool row_ok = i < d.m;
+  const int tend = d.tri ? min(d.n, r0 + 64) : d.n;
+  const T* A = (const T*)d.A + (row_ok ? i : 0);
+  const double* xv = x + d.coff;
+  double s0 = 0.0, s1 = 0.0;
+  for (int t0 = wave * 8; t0 < tend; t0 += 32) {
+    if (t0 + 8 <= tend && (!d.tri || t0 + 8 <= r0)) {
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = (double)A[(int64_t)d.lda * (t0 + u)];
+#pragma unroll
+      for (int u = 0; u < 8; u += 2) {
+        s0 += a[u] * xv[t0 + u];
+        s1 += a[u + 1] * xv[t0 + u + 1];
+      }
+    } else {
+      for (int t = t0; t < min(t0 + 8, tend); ++t)
+        if (!d.tri || t <= i) s0 += (double)A[(int64_t)d.lda * t] * xv[t];
+    }
   }
+  part[wave][lane] = row_ok ? s0 + s1 : 0.0;
   __syncthreads();
-  const T* Lc = skel + d.offL;
-  for (int a = tid; a < r; a += NT) {
-    double s = 0.0;
-    for (int t = 0; t <= a; ++t) s += (double)Lc[a + (int64_t)r * t] * xc[t];
-    xt[a] = s;
+  if (wave == 0 && row_ok) {
+    const double v = alpha * (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
+    double* yo = y + d.roff + i;
+    *yo = accumulate ? *yo + v : v;
   }
-  __syncthreads();
-  const T* Y = skel + d.offY;
-  for (int i = wave; i < k; i += NT / 64) {
-    double s = 0.0;
-    for (int b = lane; b < r; b += 64) s += (double)Y[b + (int64_t)r * i] * xt[b];
-    s = wave_sum(s);
-    if (lane == 0) xh[i] -= s;
-  }
-  __syncthreads();
-  for (int i = tid; i < k; i += NT) x[pts[i]] = xh[i];
-  for (int b = tid; b < r; b += NT) x[pts[k + b]] = xt[b];
 }
 
-// Q_F S_F̌: x_F̌ <- L_F̌^{-T}(x_F̌ - Y x_F̂); x_F̂ -= T x_F̌.
+// y[coff + j] (+)= alpha sum_i A(i, j) x[roff + i]: one wave per column.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_skel_down(double* x, const int* __restrict__ skpts,
-                                                  const SkelDesc* __restrict__ sk,
-                                                  const T* __restrict__ skel) {
-  extern __shared__ double sm[];
-  const SkelDesc d = sk[blockIdx.x];
-  const int k = d.k, r = d.r;
-  double* xh = sm;
-  double* xc = sm + k;
-  double* xt = xc + r;
-  const int* pts = skpts + d.pts_off;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < k; i += NT) xh[i] = x[pts[i]];
-  for (int b = tid; b < r; b += NT) xc[b] = x[pts[k + b]];
-  __syncthreads();
-  const T* Y = skel + d.offY;
-  for (int b = tid; b < r; b += NT) {
-    double s = 0.0;
-    for (int i = 0; i < k; ++i) s += (double)Y[b + (int64_t)r * i] * xh[i];
-    xt[b] = xc[b] - s;
-  }
-  __syncthreads();
-  const T* Lc = skel + d.offL;
-  for (int b = wave; b < r; b += NT / 64) {
-    double s = 0.0;
-    for (int t = b + lane; t < r; t += 64) s += (double)Lc[t + (int64_t)r * b] * xt[t];
-    s = wave_sum(s);
-    if (lane == 0) xc[b] = s;
-  }
-  __syncthreads();
-  const T* Tm = skel + d.offT;
-  for (int i = tid; i < k; i += NT) {
-    double s = 0.0;
-    for (int b = 0; b < r; ++b) s += (double)Tm[i + (int64_t)k * b] * xc[b];
-    xh[i] -= s;
-  }
-  __syncthreads();
-  for (int i = tid; i < k; i += NT) x[pts[i]] = xh[i];
-  for (int b = tid; b < r; b += NT) x[pts[k + b]] = xc[b];
-}
-
-// t = x_I - L_SI^T x_S  (wave per column)
-template <typename T>
-__global__ __launch_bounds__(NT) void k_down_S(const T* __restrict__ arena,
-                                               const FrontDesc* __restrict__ fd,
-                                               const int64_t* __restrict__ yoff,
-                                               const int64_t* __restrict__ zoff,
-                                               const double* __restrict__ xi,
-                                               const double* __restrict__ xs, double* t) {
-  const int c = blockIdx.y;
-  const FrontDesc f = fd[c];
+__global__ __launch_bounds__(NT) void k_gemv_t(const GemvDesc* __restrict__ dd,
+                                               const double* __restrict__ x, double* y,
+                                               double alpha, int accumulate) {
+  const GemvDesc d = dd[blockIdx.y];
+  const int j = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (j >= d.n) return;
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
-  if (i >= f.nI) return;
-  const int nS = f.nR - f.nI;
-  const T* col = arena + f.off + f.nI + (int64_t)f.ld * i;
-  const double* xv = xs + zoff[c];
-  double s = 0.0;
-  for (int q = lane; q < nS; q += 64) s += (double)col[q] * xv[q];
-  s = wave_sum(s);
-  if (lane == 0) t[yoff[c] + i] = xi[yoff[c] + i] - s;
+  const T* col = (const T*)d.A + (int64_t)d.lda * j;
+  const double* xv = x + d.roff;
+  double s0 = 0.0, s1 = 0.0;
+  int i = (d.tri ? j : 0) + lane;
+  for (; i + 64 < d.m; i += 128) {
+    s0 += (double)col[i] * xv[i];
+    s1 += (double)col[i + 64] * xv[i + 64];
+  }
+  if (i < d.m) s0 += (double)col[i] * xv[i];
+  const double v = alpha * wave_sum(s0 + s1);
+  if (lane == 0) {
+    double* yo = y + d.coff + j;
+    *yo = accumulate ? *yo + v : v;
+  }
 }
 
-// x_I = L_I^{-T} t  (wave per column of the stored inverse)
-template <typename T>
-__global__ __launch_bounds__(NT) void k_down_L(const T* __restrict__ arena,
-                                               const FrontDesc* __restrict__ fd,
-                                               const int64_t* __restrict__ yoff,
-                                               const double* __restrict__ t, double* x,
-                                               const int* __restrict__ rows,
-                                               const int64_t* __restrict__ crow_off) {
-  const int c = blockIdx.y;
-  const FrontDesc f = fd[c];
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
-  if (i >= f.nI) return;
-  const T* col = arena + f.off + (int64_t)f.ld * i;
-  const double* tv = t + yoff[c];
-  double s = 0.0;
-  for (int q = i + lane; q < f.nI; q += 64) s += (double)col[q] * tv[q];
-  s = wave_sum(s);
-  if (lane == 0) x[rows[crow_off[c] + i]] = s;
+// Skeleton vectors: xh[kofs + i] = u[F̂_i], xc[rofs + b] = u[F̌_b] (gather) or
+// the reverse (scatter).
+__global__ __launch_bounds__(NT) void k_skel_move(double* u, const int* __restrict__ skpts,
+                                                  const SkelDesc* __restrict__ sk, double* xh,
+                                                  double* xc, int to_u) {
+  const SkelDesc d = sk[blockIdx.y];
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= d.k + d.r) return;
+  const int p = skpts[d.pts_off + i];
+  double* s = i < d.k ? xh + d.kofs + i : xc + d.rofs + (i - d.k);
+  if (to_u) u[p] = *s;
+  else *s = u[p];
 }
 
 // ---- PCG vector kernels --------------------------------------------------
@@ -374,26 +291,78 @@ void stencil_matvec(const Stencil& st, const double* x, double* y, hipStream_t s
 }
 
 template <typename T>
+void gemv_launch(bool trans, const GemvDesc* d, int batch, int maxm, int maxn, const double* x,
+                 double* y, double alpha, int acc, hipStream_t s) {
+  if (batch <= 0 || maxm <= 0 || maxn <= 0) return;
+  if (trans) {
+    dim3 g((unsigned)ceil_div(maxn, NT / 64), (unsigned)batch);
+    hipLaunchKernelGGL((k_gemv_t<T>), g, dim3(NT), 0, s, d, x, y, alpha, acc);
+  } else {
+    dim3 g((unsigned)ceil_div(maxm, 64), (unsigned)batch);
+    hipLaunchKernelGGL((k_gemv_n<T>), g, dim3(NT), 0, s, d, x, y, alpha, acc);
+  }
+  HIF_LAUNCH_CHECK();
+}
+
+template <typename T>
 void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   if (u != f) HIF_HIP(hipMemcpyAsync(u, f, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-  int64_t ymax = 1, zmax = 1;
-  for (auto& l : levels) { ymax = std::max(ymax, l.ysum); zmax = std::max(zmax, l.zsum); }
+  int64_t ymax = 1, zmax = 1, kmax = 1, rmax = 1;
+  for (auto& l : levels) {
+    ymax = std::max(ymax, l.ysum);
+    zmax = std::max(zmax, l.zsum);
+    kmax = std::max(kmax, l.ksum);
+    rmax = std::max(rmax, l.rsum);
+  }
   if ((int64_t)ybuf.size() < 2 * ymax) ybuf.alloc(2 * ymax);
   if ((int64_t)zbuf.size() < 2 * zmax) zbuf.alloc(2 * zmax);
+  if ((int64_t)sbuf.size() < kmax + 2 * rmax) sbuf.alloc(kmax + 2 * rmax);
   double* xi = ybuf.get();
   double* yv = ybuf.get() + ymax;
   double* zv = zbuf.get();
   double* xsv = zbuf.get() + zmax;
+  double* sh = sbuf.get();
+  double* sc = sbuf.get() + kmax;
+  double* sc2 = sc + rmax;
   const int nlev = (int)levels.size();
   for (auto& lv : levels) {
-    if (lv.bytes_L > 0.0 || lv.P.ncell == 0) continue;
+    if (lv.gv_ready) continue;
+    std::vector<GemvDesc> gl, gs, gt, gc, gy;
     for (const FrontDesc& d : lv.hfd) {
       lv.bytes_L += sizeof(T) * 0.5 * d.nI * (d.nI + 1.0) + 24.0 * d.nI;
       lv.bytes_S += sizeof(T) * (double)(d.nR - d.nI) * d.nI + 16.0 * (d.nR - d.nI) + 8.0 * d.nI;
     }
-    for (const SkelDesc& d : lv.hsk)
-      lv.bytes_skel += sizeof(T) * (2.0 * d.k * d.r + 0.5 * d.r * (d.r + 1.0)) +
-                       32.0 * (d.k + d.r);
+    std::vector<int64_t> yoff(lv.P.ncell), zoff(lv.P.ncell);
+    int64_t ya = 0, za = 0;
+    for (int c = 0; c < lv.P.ncell; ++c) {
+      yoff[c] = ya;
+      zoff[c] = za;
+      ya += lv.hfd[c].nI;
+      za += lv.hfd[c].nR - lv.hfd[c].nI;
+    }
+    for (int c = 0; c < lv.P.ncell; ++c) {
+      const FrontDesc& d = lv.hfd[c];
+      const T* base = lv.front.get() + d.off;
+      gl.push_back({base, d.nI, d.nI, d.ld, 1, yoff[c], yoff[c]});
+      if (d.nR > d.nI) gs.push_back({base + d.nI, d.nR - d.nI, d.nI, d.ld, 0, zoff[c], yoff[c]});
+    }
+    for (const SkelDesc& d : lv.hsk) {
+      HIF_REQUIRE(d.k >= 0 && d.r > 0 && d.kofs >= 0 && d.rofs >= 0 && d.kofs + d.k <= lv.ksum &&
+                      d.rofs + d.r <= lv.rsum && d.k + d.r <= lv.maxF,
+                  HIF_EDEVICE, "inconsistent skeleton descriptor");
+      const T* sk = lv.skel.get();
+      gt.push_back({sk + d.offT, d.k, d.r, std::max(1, d.k), 0, d.kofs, d.rofs});
+      gc.push_back({sk + d.offL, d.r, d.r, d.r, 1, d.rofs, d.rofs});
+      gy.push_back({sk + d.offY, d.r, d.k, d.r, 0, d.rofs, d.kofs});
+      lv.bytes_skel += sizeof(T) * (2.0 * d.k * d.r + 0.5 * d.r * (d.r + 1.0)) + 32.0 * (d.k + d.r);
+    }
+    lv.gv_L.upload(gl, s);
+    lv.gv_S.upload(gs, s);
+    lv.gv_T.upload(gt, s);
+    lv.gv_Lc.upload(gc, s);
+    lv.gv_Y.upload(gy, s);
+    lv.gv_nS = (int)gs.size();
+    lv.gv_ready = true;
   }
   // W^l^T for l = 0..L (level L: L_Sigma^{-1})
   for (int l = 0; l < nlev; ++l) {
@@ -406,14 +375,11 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
         ProfScope ps("apply_up_L", s, 0.0, lv.bytes_L);
         hipLaunchKernelGGL(k_gather_cell, gI, dim3(NT), 0, s, u, lv.rows.get(), lv.crow_off.get(),
                            lv.fd.get(), lv.yoff.get(), lv.zoff.get(), xi, xsv, 0);
-        hipLaunchKernelGGL((k_up_L<T>), gI, dim3(NT), 0, s, lv.front.get(), lv.fd.get(),
-                           lv.yoff.get(), xi, yv);
+        gemv_launch<T>(false, lv.gv_L.get(), nc, lv.maxI, lv.maxI, xi, yv, 1.0, 0, s);
       }
-      if (lv.maxS > 0) {
+      if (lv.gv_nS > 0) {
         ProfScope ps("apply_up_S", s, 0.0, lv.bytes_S);
-        dim3 gS((unsigned)ceil_div(lv.maxS, NT), (unsigned)nc);
-        hipLaunchKernelGGL((k_up_S<T>), gS, dim3(NT), 0, s, lv.front.get(), lv.fd.get(),
-                           lv.yoff.get(), lv.zoff.get(), yv, zv);
+        gemv_launch<T>(false, lv.gv_S.get(), lv.gv_nS, lv.maxS, lv.maxI, yv, zv, 1.0, 0, s);
       }
       {
         ProfScope ps("apply_scatter", s);
@@ -431,11 +397,18 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
                            lv.rb_sb.get(), lv.zoff.get(), zv);
         HIF_LAUNCH_CHECK();
       }
-      if (!lv.hsk.empty()) {
+      const int ns = (int)lv.hsk.size();
+      if (ns > 0) {
         ProfScope ps("apply_skel", s, 0.0, lv.bytes_skel);
-        const size_t shm = sizeof(double) * (lv.maxk + 2 * (size_t)lv.maxr);
-        hipLaunchKernelGGL((k_skel_up<T>), dim3((unsigned)lv.hsk.size()), dim3(NT), shm, s, u,
-                           lv.skpts.get(), lv.sk.get(), lv.skel.get());
+        dim3 gM((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)ns);
+        hipLaunchKernelGGL(k_skel_move, gM, dim3(NT), 0, s, u, lv.skpts.get(), lv.sk.get(), sh, sc,
+                           0);
+        // x_F̌ -= T^T x_F̂ ; x_F̌ <- L_F̌^{-1} x_F̌ ; x_F̂ -= Y^T x_F̌
+        gemv_launch<T>(true, lv.gv_T.get(), ns, lv.maxk, lv.maxr, sh, sc, -1.0, 1, s);
+        gemv_launch<T>(false, lv.gv_Lc.get(), ns, lv.maxr, lv.maxr, sc, sc2, 1.0, 0, s);
+        gemv_launch<T>(true, lv.gv_Y.get(), ns, lv.maxr, lv.maxk, sc2, sh, -1.0, 1, s);
+        hipLaunchKernelGGL(k_skel_move, gM, dim3(NT), 0, s, u, lv.skpts.get(), lv.sk.get(), sh,
+                           sc2, 1);
         HIF_LAUNCH_CHECK();
       }
     }
@@ -444,29 +417,36 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   for (int l = nlev - 1; l >= 0; --l) {
     Level<T>& lv = levels[l];
     profiler().level = l;
-    if (!lv.P.root && !lv.hsk.empty()) {
+    const int ns = (int)lv.hsk.size();
+    if (!lv.P.root && ns > 0) {
       ProfScope ps("apply_skel", s, 0.0, lv.bytes_skel);
-      const size_t shm = sizeof(double) * (lv.maxk + 2 * (size_t)lv.maxr);
-      hipLaunchKernelGGL((k_skel_down<T>), dim3((unsigned)lv.hsk.size()), dim3(NT), shm, s, u,
-                         lv.skpts.get(), lv.sk.get(), lv.skel.get());
+      dim3 gM((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)ns);
+      hipLaunchKernelGGL(k_skel_move, gM, dim3(NT), 0, s, u, lv.skpts.get(), lv.sk.get(), sh, sc, 0);
+      // x_F̌ -= Y x_F̂ ; x_F̌ <- L_F̌^{-T} x_F̌ ; x_F̂ -= T x_F̌
+      gemv_launch<T>(false, lv.gv_Y.get(), ns, lv.maxr, lv.maxk, sh, sc, -1.0, 1, s);
+      gemv_launch<T>(true, lv.gv_Lc.get(), ns, lv.maxr, lv.maxr, sc, sc2, 1.0, 0, s);
+      gemv_launch<T>(false, lv.gv_T.get(), ns, lv.maxk, lv.maxr, sc2, sh, -1.0, 1, s);
+      hipLaunchKernelGGL(k_skel_move, gM, dim3(NT), 0, s, u, lv.skpts.get(), lv.sk.get(), sh, sc2,
+                         1);
       HIF_LAUNCH_CHECK();
     }
     const int nc = lv.P.ncell;
     if (nc == 0) continue;
     const int gmax = std::max(lv.maxI, lv.maxI + lv.maxS);
     dim3 gG((unsigned)ceil_div(std::max(1, gmax), NT), (unsigned)nc);
-    dim3 gW((unsigned)ceil_div(std::max(1, lv.maxI), NT / 64), (unsigned)nc);
+    dim3 gI((unsigned)ceil_div(std::max(1, lv.maxI), NT), (unsigned)nc);
     {
       ProfScope ps("apply_down_S", s, 0.0, lv.bytes_S);
       hipLaunchKernelGGL(k_gather_cell, gG, dim3(NT), 0, s, u, lv.rows.get(), lv.crow_off.get(),
                          lv.fd.get(), lv.yoff.get(), lv.zoff.get(), xi, xsv, 1);
-      hipLaunchKernelGGL((k_down_S<T>), gW, dim3(NT), 0, s, lv.front.get(), lv.fd.get(),
-                         lv.yoff.get(), lv.zoff.get(), xi, xsv, yv);
+      // x_I -= L_SI^T x_S
+      gemv_launch<T>(true, lv.gv_S.get(), lv.gv_nS, lv.maxS, lv.maxI, xsv, xi, -1.0, 1, s);
     }
     {
       ProfScope ps("apply_down_L", s, 0.0, lv.bytes_L);
-      hipLaunchKernelGGL((k_down_L<T>), gW, dim3(NT), 0, s, lv.front.get(), lv.fd.get(),
-                         lv.yoff.get(), yv, u, lv.rows.get(), lv.crow_off.get());
+      gemv_launch<T>(true, lv.gv_L.get(), nc, lv.maxI, lv.maxI, xi, yv, 1.0, 0, s);
+      hipLaunchKernelGGL(k_scatter_I, gI, dim3(NT), 0, s, u, lv.rows.get(), lv.crow_off.get(),
+                         lv.fd.get(), lv.yoff.get(), yv);
     }
     HIF_LAUNCH_CHECK();
   }
