@@ -276,7 +276,7 @@ DevBuf<V> to_dev(const std::vector<V>& h, hipStream_t s) {
 
 template <typename TIn, typename TC>
 void run_gemms(const char* name, int opa, int opb, int flags, const std::vector<GemmDesc>& h,
-               TC alpha, TC beta, hipStream_t s) {
+               TC alpha, TC beta, hipStream_t s, int cls = GC_GENERIC) {
   if (h.empty()) return;
   int mm = 0, mn = 0;
   double fl = 0.0;
@@ -287,7 +287,8 @@ void run_gemms(const char* name, int opa, int opb, int flags, const std::vector<
   }
   DevBuf<GemmDesc> d;
   d.upload(h, s);
-  gemm_batched<TIn, TC>(opa, opb, flags, d.get(), (int)h.size(), mm, mn, alpha, beta, s, name, fl);
+  gemm_batched<TIn, TC>(opa, opb, flags, d.get(), (int)h.size(), mm, mn, alpha, beta, s, name, fl,
+                        cls);
   HIF_HIP(hipStreamSynchronize(s));  // descriptors are freed on return
 }
 
@@ -407,7 +408,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
         gd.push_back({ASI.get() + aoff[c], base, base + d.nI, P.cS[c], d.nI, d.nI,
                       std::max(1, P.cS[c]), d.ld, d.ld});
       }
-      run_gemms<T, T>("gemm_lsi", OP_N, OP_T, GF_B_UPPER, gd, T(1), T(0), s);
+      run_gemms<T, T>("gemm_lsi", OP_N, OP_T, GF_B_UPPER, gd, T(1), T(0), s, GC_LSI);
     }
 
     if (!P.root) {
@@ -429,7 +430,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
           const T* LSI = lev.front.get() + d.off + d.nI;
           gd.push_back({LSI, LSI, U.get() + uoff[c], P.cS[c], P.cS[c], d.nI, d.ld, d.ld, uld[c]});
         }
-        run_gemms<T, T>("gemm_syrk", OP_N, OP_T, GF_C_LOWER, gd, T(-1), T(0), s);
+        run_gemms<T, T>("gemm_syrk", OP_N, OP_T, GF_C_LOWER, gd, T(-1), T(0), s, GC_SYRK);
       }
       // ---- face panels Ã^l([F; R-faces], F) ------------------------------
       std::vector<int64_t> poff(P.nface);
@@ -495,7 +496,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
           gd.push_back({PR, PR, G.get() + goff[f], P.fN[f], P.fN[f], K, pld[f], pld[f], gld[f]});
           flops += 2.0 * K * P.fN[f] * (double)P.fN[f];
         }
-        run_gemms<T, double>("gemm_gram", OP_T, OP_N, GF_C_LOWER, gd, 1.0, 0.0, s);
+        run_gemms<T, double>("gemm_gram", OP_T, OP_N, GF_C_LOWER, gd, 1.0, 0.0, s, GC_GRAM);
         DevBuf<int64_t> d_goff = to_dev(goff, s);
         DevBuf<int> d_gld = to_dev(gld, s);
         {

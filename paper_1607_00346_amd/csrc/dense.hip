@@ -175,7 +175,9 @@ __device__ void gemm_tile_t(int flags, const TIn* A, int lda, const TIn* __restr
       }
 }
 
-template <typename TIn, typename TC, int OPA, int OPB, int TM, int TN>
+// CLS only gives each use (generic, Schur SYRK, L_SI, Gram) its own kernel
+// symbol for profilers.
+template <typename TIn, typename TC, int OPA, int OPB, int TM, int TN, int CLS>
 __global__ __launch_bounds__(NTHR) void k_gemm_desc(int flags, const GemmDesc* __restrict__ desc,
                                                     TC alpha, TC beta) {
   __shared__ TileSmem<TC, TM, TN> sm;
@@ -443,40 +445,47 @@ __global__ __launch_bounds__(64) void k_pchol_tail(const int* __restrict__ nFa,
 
 }  // namespace
 
-template <typename TIn, typename TC, int OPA, int OPB, int TS>
+template <typename TIn, typename TC, int OPA, int OPB, int TS, int CLS>
 void launch_gemm(int flags, const GemmDesc* d_desc, int batch, int max_m, int max_n, TC alpha,
                  TC beta, hipStream_t s) {
   for (int b0 = 0; b0 < batch; b0 += 65535) {
     const int nb = std::min(batch - b0, 65535);
     dim3 grid((unsigned)ceil_div(max_n, TS), (unsigned)ceil_div(max_m, TS), (unsigned)nb);
-    hipLaunchKernelGGL((k_gemm_desc<TIn, TC, OPA, OPB, TS, TS>), grid, dim3(NTHR), 0, s, flags,
-                       d_desc + b0, alpha, beta);
+    hipLaunchKernelGGL((k_gemm_desc<TIn, TC, OPA, OPB, TS, TS, CLS>), grid, dim3(NTHR), 0, s,
+                       flags, d_desc + b0, alpha, beta);
     HIF_LAUNCH_CHECK();
   }
 }
 
 template <typename TIn, typename TC, int TS>
-void dispatch_gemm(int opa, int opb, int flags, const GemmDesc* d_desc, int batch, int max_m,
-                   int max_n, TC alpha, TC beta, hipStream_t s) {
-  if (opa == OP_N && opb == OP_N)
-    launch_gemm<TIn, TC, OP_N, OP_N, TS>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+void dispatch_gemm(int opa, int opb, int flags, int cls, const GemmDesc* d_desc, int batch,
+                   int max_m, int max_n, TC alpha, TC beta, hipStream_t s) {
+  if (cls == GC_SYRK && opa == OP_N && opb == OP_T)
+    launch_gemm<TIn, TC, OP_N, OP_T, TS, GC_SYRK>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+  else if (cls == GC_LSI && opa == OP_N && opb == OP_T)
+    launch_gemm<TIn, TC, OP_N, OP_T, TS, GC_LSI>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+  else if (cls == GC_GRAM && opa == OP_T && opb == OP_N)
+    launch_gemm<TIn, TC, OP_T, OP_N, TS, GC_GRAM>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+  else if (opa == OP_N && opb == OP_N)
+    launch_gemm<TIn, TC, OP_N, OP_N, TS, 0>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
   else if (opa == OP_N)
-    launch_gemm<TIn, TC, OP_N, OP_T, TS>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+    launch_gemm<TIn, TC, OP_N, OP_T, TS, 0>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
   else if (opb == OP_N)
-    launch_gemm<TIn, TC, OP_T, OP_N, TS>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+    launch_gemm<TIn, TC, OP_T, OP_N, TS, 0>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
   else
-    launch_gemm<TIn, TC, OP_T, OP_T, TS>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+    launch_gemm<TIn, TC, OP_T, OP_T, TS, 0>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
 }
 
 template <typename TIn, typename TC>
 void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch, int max_m,
-                  int max_n, TC alpha, TC beta, hipStream_t s, const char* name, double flops) {
+                  int max_n, TC alpha, TC beta, hipStream_t s, const char* name, double flops,
+                  int cls) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
   ProfScope ps(name, s, flops);
   if (max_m >= 1024 && max_n >= 1024)
-    dispatch_gemm<TIn, TC, 128>(opa, opb, flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+    dispatch_gemm<TIn, TC, 128>(opa, opb, flags, cls, d_desc, batch, max_m, max_n, alpha, beta, s);
   else
-    dispatch_gemm<TIn, TC, 64>(opa, opb, flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+    dispatch_gemm<TIn, TC, 64>(opa, opb, flags, cls, d_desc, batch, max_m, max_n, alpha, beta, s);
 }
 
 double gemm_flops(const GemmDesc& d, int flags) {
@@ -663,11 +672,11 @@ void pivoted_cholesky(double* G, double* L, const int64_t* goff, const int* nF, 
 }
 
 template void gemm_batched<double, double>(int, int, int, const GemmDesc*, int, int, int, double,
-                                           double, hipStream_t, const char*, double);
+                                           double, hipStream_t, const char*, double, int);
 template void gemm_batched<float, float>(int, int, int, const GemmDesc*, int, int, int, float,
-                                         float, hipStream_t, const char*, double);
+                                         float, hipStream_t, const char*, double, int);
 template void gemm_batched<float, double>(int, int, int, const GemmDesc*, int, int, int, double,
-                                          double, hipStream_t, const char*, double);
+                                          double, hipStream_t, const char*, double, int);
 template void front_factor<double>(double*, const FrontDesc*, const std::vector<FrontDesc>&,
                                    int*, hipStream_t);
 template void front_factor<float>(float*, const FrontDesc*, const std::vector<FrontDesc>&, int*,

@@ -37,10 +37,12 @@ struct GemmDesc {
 };
 
 // TIn: element type of A and B; TC: accumulation and C type.
+enum : int { GC_GENERIC = 0, GC_SYRK = 1, GC_LSI = 2, GC_GRAM = 3 };  // kernel symbol per use
+
 template <typename TIn, typename TC>
 void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch, int max_m,
                   int max_n, TC alpha, TC beta, hipStream_t s, const char* name = "gemm",
-                  double flops = 0.0);
+                  double flops = 0.0, int cls = GC_GENERIC);
 
 // Algorithmic flops of one descriptor under the triangular flags (one flag class).
 double gemm_flops(const GemmDesc& d, int flags);
