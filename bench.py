@@ -95,6 +95,28 @@ def run_gpu(args):
     return out
 
 
+TRAFFIC_FILES = {"gemm_syrk": "profiles/gemm_syrk_c128_mixed_traffic.txt"}
+KERNEL_SOURCE = "paper_1607_00346_amd/csrc/dense.hip"
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed counter summary of this kernel,
+    or None when there is none or the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, TRAFFIC_FILES.get(kernel, ""))
+    if kernel not in TRAFFIC_FILES or not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(os.path.join(ROOT, KERNEL_SOURCE), "rb").read()).hexdigest()
+    if fields.get("source_sha256") != sha:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def by_class(prof):
     """Sum the per-level entries ("name@level") of each kernel class."""
     out = {}
@@ -116,7 +138,7 @@ def roofline(prof, fp64: bool):
             else PEAK["fp32_tflops"]
         ach = k["flops"] / k["seconds"] / 1e12
         return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None, "kernel": name,
+                "frac": ach / peak, "traffic": measured_traffic(name), "kernel": name,
                 "launches": k["launches"], "avg_launch_us": avg * 1e6,
                 "flops_per_launch": k["flops"] / max(k["launches"], 1)}
     ach = k["bytes"] / k["seconds"] / 1e9
