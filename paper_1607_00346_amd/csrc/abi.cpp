@@ -2,6 +2,8 @@
 // thread-local error text.  No exception crosses this boundary.
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -19,6 +21,71 @@ void set_last_error(const std::string& msg) { g_last_error = msg; }
 MemStats& mem_stats() {
   static MemStats ms;
   return ms;
+}
+
+namespace {
+struct Pool {
+  std::mutex mu;
+  std::multimap<size_t, void*> free_blocks;
+  int64_t cached = 0;
+  bool dirty = false;  // blocks were released since the last device synchronization
+  ~Pool() {
+    for (auto& kv : free_blocks) (void)hipFree(kv.second);
+  }
+};
+Pool& pool() {
+  static Pool p;
+  return p;
+}
+}  // namespace
+
+size_t pool_round(size_t bytes) {
+  const size_t g = bytes >= (size_t(1) << 20) ? (size_t(2) << 20) : 256;
+  return (bytes + g - 1) / g * g;
+}
+
+void* pool_alloc(size_t bytes) {
+  const size_t r = pool_round(bytes);
+  Pool& P = pool();
+  std::lock_guard<std::mutex> lock(P.mu);
+  auto it = P.free_blocks.find(r);
+  if (it != P.free_blocks.end()) {
+    // kernels issued before the release (on any stream) must be done with it
+    if (P.dirty) {
+      HIF_HIP(hipDeviceSynchronize());
+      P.dirty = false;
+    }
+    void* p = it->second;
+    P.free_blocks.erase(it);
+    P.cached -= (int64_t)r;
+    return p;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, r);
+  if (e == hipErrorOutOfMemory && !P.free_blocks.empty()) {
+    (void)hipGetLastError();
+    for (auto& kv : P.free_blocks) (void)hipFree(kv.second);
+    P.free_blocks.clear();
+    P.cached = 0;
+    e = hipMalloc(&p, r);
+  }
+  if (e != hipSuccess)
+    throw Error(e == hipErrorOutOfMemory ? HIF_ENOMEM : HIF_EDEVICE,
+                std::string("hipMalloc: ") + hipGetErrorString(e));
+  return p;
+}
+
+void pool_free(void* p, size_t bytes) {
+  const size_t r = pool_round(bytes);
+  Pool& P = pool();
+  std::lock_guard<std::mutex> lock(P.mu);
+  if (P.cached + (int64_t)r > kPoolCap) {
+    (void)hipFree(p);
+    return;
+  }
+  P.free_blocks.emplace(r, p);
+  P.cached += (int64_t)r;
+  P.dirty = true;
 }
 
 }  // namespace hif

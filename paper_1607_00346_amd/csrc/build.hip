@@ -320,6 +320,10 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
   const int64_t mem0 = mem_stats().live;
   mem_stats().peak = mem0;
 
+  if (A->geom_leaf != leaf) {
+    A->geom = plan_geometry(n, leaf);
+    A->geom_leaf = leaf;
+  }
   std::vector<uint8_t> active(N, 1);
   std::vector<int> pface(N, -1), ploc(N, -1);
   DevBuf<int> d_pface, d_ploc, d_err(1);
@@ -331,7 +335,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
     profiler().level = level;
     Level<T>& lev = Fi.levels[level];
     Level<T>* prev = level > 0 ? &Fi.levels[level - 1] : nullptr;
-    lev.P = plan_level(n, leaf, level, L, active);
+    lev.P = plan_level(A->geom[level], active);
     const LevelPlan& P = lev.P;
     if (level > 0) {
       d_pface.upload(pface, s);
@@ -680,7 +684,6 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
       st.redundant[level] = lev.redundant;
 
       // ---- next level's active set and lookup maps --------------------
-      for (int64_t t = 0; t < (int64_t)P.rows.size(); ++t) (void)0;
       for (int c = 0; c < P.ncell; ++c)
         for (int64_t t = P.crow_off[c]; t < P.crow_off[c] + P.cI[c]; ++t) active[P.rows[t]] = 0;
       std::fill(pface.begin(), pface.end(), -1);

@@ -45,6 +45,14 @@ struct MemStats {
 };
 MemStats& mem_stats();
 
+// Device memory with a size-exact cache: released blocks are kept for reuse by
+// a later allocation of the same rounded size (repeated builds of one problem
+// then allocate nothing new).  The cache holds at most kPoolCap bytes.
+constexpr int64_t kPoolCap = int64_t(48) << 30;
+void* pool_alloc(size_t bytes);
+void pool_free(void* p, size_t bytes);
+size_t pool_round(size_t bytes);
+
 // Owning device allocation.  Move-only; frees on destruction.
 template <typename T>
 class DevBuf {
@@ -63,7 +71,7 @@ class DevBuf {
   void alloc(size_t count) {
     release();
     if (count == 0) return;
-    HIF_HIP(hipMalloc(&p_, count * sizeof(T)));
+    p_ = static_cast<T*>(pool_alloc(count * sizeof(T)));
     n_ = count;
     auto& ms = mem_stats();
     ms.live += (int64_t)(count * sizeof(T));
@@ -71,7 +79,7 @@ class DevBuf {
   }
   void release() {
     if (p_) {
-      (void)hipFree(p_);
+      pool_free(p_, n_ * sizeof(T));
       mem_stats().live -= (int64_t)(n_ * sizeof(T));
     }
     p_ = nullptr;

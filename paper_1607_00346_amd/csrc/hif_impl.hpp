@@ -102,6 +102,9 @@ struct hif_problem_s {
   int n = 0;
   int64_t N = 0;
   hif::DevBuf<double> diag, cx, cy, cz;
+  // cell/face geometry of every level, computed on the first build with a leaf
+  mutable int geom_leaf = -1;
+  mutable std::vector<hif::LevelGeom> geom;
   hif::Stencil stencil() const { return {n, diag.get(), cx.get(), cy.get(), cz.get()}; }
 };
 

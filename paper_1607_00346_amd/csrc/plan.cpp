@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <stdexcept>
+#include <string>
 
 namespace hif {
 
@@ -36,145 +37,206 @@ inline int cell_id(int nc, int cx, int cy, int cz) { return (cz * nc + cy) * nc 
 
 }  // namespace
 
-LevelPlan plan_level(int n, int leaf, int level, int L, const std::vector<uint8_t>& active) {
-  LevelPlan P;
-  P.level = level;
-  P.w = leaf << level;
-  P.nc = n / P.w;
-  P.root = (level == L);
-  const int w = P.w, nc = P.nc;
-  P.ncell = nc * nc * nc;
-  P.nface = 3 * (nc - 1) * nc * nc;
+std::vector<LevelGeom> plan_geometry(int n, int leaf) {
+  const int L = levels_for(n, leaf);
+  if (L < 0) throw std::invalid_argument("n must be leaf * 2^L");
   const int64_t N = (int64_t)n * n * n;
-
-  // Pass 1: classify active points, count per cell / face.
-  std::vector<int> owner(N, -1);  // >= 0: cell id; <= -2: -(face id) - 2
-  P.cI.assign(P.ncell, 0);
-  P.fN.assign(P.nface, 0);
-  for (int64_t p = 0; p < N; ++p) {
-    if (!active[p]) continue;
-    const int c[3] = {(int)(p % n), (int)((p / n) % n), (int)(p / ((int64_t)n * n))};
-    int nsep = 0, dsep = -1;
-    for (int d = 0; d < 3; ++d)
-      if (c[d] % w == 0 && c[d] != 0) { ++nsep; dsep = d; }
-    if (nsep == 0) {
-      const int id = cell_id(nc, c[0] / w, c[1] / w, c[2] / w);
-      owner[p] = id;
-      ++P.cI[id];
-    } else if (nsep == 1) {
-      const int o1 = dsep == 0 ? 1 : 0;
-      const int o2 = dsep == 2 ? 1 : 2;
-      const int id = face_id(nc, dsep, c[dsep] / w, c[o1] / w, c[o2] / w);
-      owner[p] = -id - 2;
-      ++P.fN[id];
+  std::vector<LevelGeom> out(L + 1);
+  std::vector<int> owner(N);
+  std::vector<int> sep(n), cidx(n);
+  for (int level = 0; level <= L; ++level) {
+    LevelGeom& G = out[level];
+    G.level = level;
+    G.w = leaf << level;
+    G.nc = n / G.w;
+    G.root = level == L;
+    const int w = G.w, nc = G.nc;
+    G.ncell = nc * nc * nc;
+    G.nface = 3 * (nc - 1) * nc * nc;
+    for (int x = 0; x < n; ++x) {
+      sep[x] = (x % w == 0 && x != 0);
+      cidx[x] = x / w;
     }
-  }
-
-  // Face point lists (ascending because p is visited in order).
-  P.fpt_off.assign(P.nface + 1, 0);
-  for (int f = 0; f < P.nface; ++f) P.fpt_off[f + 1] = P.fpt_off[f] + P.fN[f];
-  P.fpts.resize(P.fpt_off[P.nface]);
-  {
-    std::vector<int64_t> cur(P.fpt_off.begin(), P.fpt_off.end() - 1);
-    for (int64_t p = 0; p < N; ++p)
-      if (owner[p] <= -2) P.fpts[cur[-owner[p] - 2]++] = (int)p;
-  }
-
-  // Faces of each cell, S offsets.
-  P.cface.assign((size_t)P.ncell * 6, -1);
-  P.cface_off.assign((size_t)P.ncell * 6, -1);
-  P.cS.assign(P.ncell, 0);
-  for (int cz = 0; cz < nc; ++cz)
-    for (int cy = 0; cy < nc; ++cy)
-      for (int cx = 0; cx < nc; ++cx) {
-        const int id = cell_id(nc, cx, cy, cz);
-        const int cc[3] = {cx, cy, cz};
-        int off = 0;
-        for (int d = 0; d < 3; ++d) {
-          const int o1 = d == 0 ? 1 : 0;
-          const int o2 = d == 2 ? 1 : 2;
-          for (int up = 0; up < 2; ++up) {
-            const int plane = cc[d] + up;
-            if (plane < 1 || plane > nc - 1) continue;
-            const int f = face_id(nc, d, plane, cc[o1], cc[o2]);
-            P.cface[(size_t)id * 6 + 2 * d + up] = f;
-            P.cface_off[(size_t)id * 6 + 2 * d + up] = off;
-            off += P.fN[f];
+    // candidates: points with no separator coordinate at any earlier level
+    // (equivalently at level-1, the separators being nested), classified now
+    std::vector<int> cntI(G.ncell, 0), cntF(G.nface, 0);
+    const int wp = level > 0 ? (leaf << (level - 1)) : 0;
+    for (int z = 0; z < n; ++z)
+      for (int y = 0; y < n; ++y) {
+        const int64_t row = ((int64_t)z * n + y) * n;
+        for (int x = 0; x < n; ++x) {
+          const int64_t p = row + x;
+          owner[p] = -1;
+          if (level > 0) {
+            const bool sp = (x % wp == 0 && x != 0) || (y % wp == 0 && y != 0) ||
+                            (z % wp == 0 && z != 0);
+            if (!sp) continue;  // eliminated as an interior point at an earlier level
+          }
+          const int ns = sep[x] + sep[y] + sep[z];
+          if (ns == 0) {
+            const int id = (cidx[z] * nc + cidx[y]) * nc + cidx[x];
+            owner[p] = id;
+            ++cntI[id];
+          } else if (ns == 1) {
+            const int c3[3] = {x, y, z};
+            const int d = sep[x] ? 0 : (sep[y] ? 1 : 2);
+            const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+            const int id = face_id(nc, d, cidx[c3[d]], cidx[c3[o1]], cidx[c3[o2]]);
+            owner[p] = -id - 2;
+            ++cntF[id];
           }
         }
-        P.cS[id] = off;
       }
-
-  // Rows of each front: I then S.
-  P.crow_off.assign(P.ncell + 1, 0);
-  for (int c = 0; c < P.ncell; ++c) P.crow_off[c + 1] = P.crow_off[c] + P.cI[c] + P.cS[c];
-  P.rows.resize(P.crow_off[P.ncell]);
-  {
-    std::vector<int64_t> cur(P.ncell);
-    for (int c = 0; c < P.ncell; ++c) cur[c] = P.crow_off[c];
-    for (int64_t p = 0; p < N; ++p)
-      if (owner[p] >= 0) P.rows[cur[owner[p]]++] = (int)p;
-    for (int c = 0; c < P.ncell; ++c) {
-      int64_t o = P.crow_off[c] + P.cI[c];
-      for (int s = 0; s < 6; ++s) {
-        const int f = P.cface[(size_t)c * 6 + s];
-        if (f < 0) continue;
-        for (int64_t t = P.fpt_off[f]; t < P.fpt_off[f + 1]; ++t) P.rows[o++] = P.fpts[t];
+    G.cand_I_off.assign(G.ncell + 1, 0);
+    for (int c = 0; c < G.ncell; ++c) G.cand_I_off[c + 1] = G.cand_I_off[c] + cntI[c];
+    G.cand_F_off.assign(G.nface + 1, 0);
+    for (int f = 0; f < G.nface; ++f) G.cand_F_off[f + 1] = G.cand_F_off[f] + cntF[f];
+    G.cand_I.resize(G.cand_I_off[G.ncell]);
+    G.cand_F.resize(G.cand_F_off[G.nface]);
+    {
+      std::vector<int64_t> ci(G.cand_I_off.begin(), G.cand_I_off.end() - 1);
+      std::vector<int64_t> cf(G.cand_F_off.begin(), G.cand_F_off.end() - 1);
+      for (int64_t p = 0; p < N; ++p) {
+        const int o = owner[p];
+        if (o >= 0) G.cand_I[ci[o]++] = (int)p;
+        else if (o <= -2) G.cand_F[cf[-o - 2]++] = (int)p;
       }
     }
+    G.cface.assign((size_t)G.ncell * 6, -1);
+    for (int cz = 0; cz < nc; ++cz)
+      for (int cy = 0; cy < nc; ++cy)
+        for (int cx = 0; cx < nc; ++cx) {
+          const int id = cell_id(nc, cx, cy, cz);
+          const int cc[3] = {cx, cy, cz};
+          for (int d = 0; d < 3; ++d) {
+            const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+            for (int up = 0; up < 2; ++up) {
+              const int plane = cc[d] + up;
+              if (plane < 1 || plane > nc - 1) continue;
+              G.cface[(size_t)id * 6 + 2 * d + up] = face_id(nc, d, plane, cc[o1], cc[o2]);
+            }
+          }
+        }
+    G.fcellA.assign(G.nface, -1);
+    G.fcellB.assign(G.nface, -1);
+    G.rb_face.assign((size_t)G.nface * kRowBlocks, -1);
+    G.rb_slotA.assign((size_t)G.nface * kRowBlocks, -1);
+    G.rb_slotB.assign((size_t)G.nface * kRowBlocks, -1);
+    for (int d = 0; d < 3; ++d) {
+      const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+      for (int plane = 1; plane < nc; ++plane)
+        for (int ihi = 0; ihi < nc; ++ihi)
+          for (int ilo = 0; ilo < nc; ++ilo) {
+            const int f = face_id(nc, d, plane, ilo, ihi);
+            int ca[3], cb[3];
+            ca[d] = plane - 1;
+            cb[d] = plane;
+            ca[o1] = cb[o1] = ilo;
+            ca[o2] = cb[o2] = ihi;
+            const int A = cell_id(nc, ca[0], ca[1], ca[2]);
+            const int B = cell_id(nc, cb[0], cb[1], cb[2]);
+            G.fcellA[f] = A;
+            G.fcellB[f] = B;
+            const int slotA = 2 * d + 1, slotB = 2 * d;
+            const size_t base = (size_t)f * kRowBlocks;
+            int t = 0;
+            G.rb_face[base] = f;
+            G.rb_slotA[base] = slotA;
+            G.rb_slotB[base] = slotB;
+            ++t;
+            for (int side = 0; side < 2; ++side) {
+              const int cell = side == 0 ? A : B;
+              const int skip = side == 0 ? slotA : slotB;
+              for (int s = 0; s < 6; ++s) {
+                const int g = G.cface[(size_t)cell * 6 + s];
+                if (s == skip || g < 0) continue;
+                G.rb_face[base + t] = g;
+                if (side == 0) G.rb_slotA[base + t] = s;
+                else G.rb_slotB[base + t] = s;
+                ++t;
+              }
+            }
+          }
+    }
   }
+  return out;
+}
 
-  // Neighbouring cells of each face and the panel row blocks.
-  P.fcellA.assign(P.nface, -1);
-  P.fcellB.assign(P.nface, -1);
-  P.rb_face.assign((size_t)P.nface * kRowBlocks, -1);
+LevelPlan plan_level(const LevelGeom& G, const std::vector<uint8_t>& active) {
+  LevelPlan P;
+  P.level = G.level;
+  P.w = G.w;
+  P.nc = G.nc;
+  P.root = G.root;
+  P.ncell = G.ncell;
+  P.nface = G.nface;
+  // active face points
+  P.fN.assign(P.nface, 0);
+  P.fpt_off.assign(P.nface + 1, 0);
+  P.fpts.clear();
+  P.fpts.reserve(G.cand_F.size());
+  for (int f = 0; f < P.nface; ++f) {
+    for (int64_t t = G.cand_F_off[f]; t < G.cand_F_off[f + 1]; ++t) {
+      const int p = G.cand_F[t];
+      if (active[p]) P.fpts.push_back(p);
+    }
+    P.fpt_off[f + 1] = (int64_t)P.fpts.size();
+    P.fN[f] = (int)(P.fpt_off[f + 1] - P.fpt_off[f]);
+  }
+  // cells: I then S
+  P.cface = G.cface;
+  P.cface_off.assign((size_t)P.ncell * 6, -1);
+  P.cI.assign(P.ncell, 0);
+  P.cS.assign(P.ncell, 0);
+  P.crow_off.assign(P.ncell + 1, 0);
+  P.rows.clear();
+  P.rows.reserve(G.cand_I.size() + 6 * P.fpts.size());
+  for (int c = 0; c < P.ncell; ++c) {
+    for (int64_t t = G.cand_I_off[c]; t < G.cand_I_off[c + 1]; ++t) {
+      const int p = G.cand_I[t];
+      if (active[p]) P.rows.push_back(p);
+    }
+    P.cI[c] = (int)((int64_t)P.rows.size() - P.crow_off[c]);
+    int off = 0;
+    for (int s = 0; s < 6; ++s) {
+      const int f = P.cface[(size_t)c * 6 + s];
+      if (f < 0) continue;
+      P.cface_off[(size_t)c * 6 + s] = off;
+      P.rows.insert(P.rows.end(), P.fpts.begin() + P.fpt_off[f], P.fpts.begin() + P.fpt_off[f + 1]);
+      off += P.fN[f];
+    }
+    P.cS[c] = off;
+    P.crow_off[c + 1] = (int64_t)P.rows.size();
+  }
+  // panel row blocks
+  P.fcellA = G.fcellA;
+  P.fcellB = G.fcellB;
+  P.rb_face = G.rb_face;
   P.rb_off.assign((size_t)P.nface * kRowBlocks, 0);
   P.rb_sa.assign((size_t)P.nface * kRowBlocks, -1);
   P.rb_sb.assign((size_t)P.nface * kRowBlocks, -1);
   P.prow.assign(P.nface, 0);
-  for (int d = 0; d < 3; ++d) {
-    const int o1 = d == 0 ? 1 : 0;
-    const int o2 = d == 2 ? 1 : 2;
-    for (int plane = 1; plane < nc; ++plane)
-      for (int ihi = 0; ihi < nc; ++ihi)
-        for (int ilo = 0; ilo < nc; ++ilo) {
-          const int f = face_id(nc, d, plane, ilo, ihi);
-          int ca[3], cb[3];
-          ca[d] = plane - 1;
-          cb[d] = plane;
-          ca[o1] = cb[o1] = ilo;
-          ca[o2] = cb[o2] = ihi;
-          const int A = cell_id(nc, ca[0], ca[1], ca[2]);
-          const int B = cell_id(nc, cb[0], cb[1], cb[2]);
-          P.fcellA[f] = A;
-          P.fcellB[f] = B;
-          const int slotA = 2 * d + 1, slotB = 2 * d;
-          size_t base = (size_t)f * kRowBlocks;
-          int t = 0, ro = 0;
-          P.rb_face[base] = f;
-          P.rb_off[base] = 0;
-          P.rb_sa[base] = P.cface_off[(size_t)A * 6 + slotA];
-          P.rb_sb[base] = P.cface_off[(size_t)B * 6 + slotB];
-          ro += P.fN[f];
-          ++t;
-          for (int side = 0; side < 2; ++side) {
-            const int cell = side == 0 ? A : B;
-            const int skip = side == 0 ? slotA : slotB;
-            for (int s = 0; s < 6; ++s) {
-              const int g = P.cface[(size_t)cell * 6 + s];
-              if (s == skip || g < 0) continue;
-              P.rb_face[base + t] = g;
-              P.rb_off[base + t] = ro;
-              if (side == 0) P.rb_sa[base + t] = P.cface_off[(size_t)cell * 6 + s];
-              else P.rb_sb[base + t] = P.cface_off[(size_t)cell * 6 + s];
-              ro += P.fN[g];
-              ++t;
-            }
-          }
-          P.prow[f] = ro;
-        }
+  for (int f = 0; f < P.nface; ++f) {
+    const size_t base = (size_t)f * kRowBlocks;
+    const int A = P.fcellA[f], B = P.fcellB[f];
+    int ro = 0;
+    for (int t = 0; t < kRowBlocks; ++t) {
+      const int g = P.rb_face[base + t];
+      if (g < 0) break;
+      P.rb_off[base + t] = ro;
+      if (G.rb_slotA[base + t] >= 0) P.rb_sa[base + t] = P.cface_off[(size_t)A * 6 + G.rb_slotA[base + t]];
+      if (G.rb_slotB[base + t] >= 0) P.rb_sb[base + t] = P.cface_off[(size_t)B * 6 + G.rb_slotB[base + t]];
+      ro += P.fN[g];
+    }
+    P.prow[f] = ro;
   }
   return P;
+}
+
+LevelPlan plan_level(int n, int leaf, int level, int L, const std::vector<uint8_t>& active) {
+  (void)L;
+  const std::vector<LevelGeom> G = plan_geometry(n, leaf);
+  return plan_level(G[level], active);
 }
 
 }  // namespace hif

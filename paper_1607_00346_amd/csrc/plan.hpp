@@ -53,8 +53,28 @@ struct LevelPlan {
   int64_t sum_S() const;
 };
 
-// Plan level `level` of an n^3 grid with leaf width `leaf` from the current
-// active mask (1 byte per grid point).
+// Geometry of one level that does not depend on ranks: the candidate points of
+// every cell interior and every face (points not interior at any earlier
+// level, ascending), the faces of each cell and the panel row-block faces.
+struct LevelGeom {
+  int level = 0, w = 0, nc = 0, ncell = 0, nface = 0;
+  bool root = false;
+  std::vector<int64_t> cand_I_off, cand_F_off;
+  std::vector<int> cand_I, cand_F;
+  std::vector<int> cface;    // ncell * 6
+  std::vector<int> fcellA, fcellB;
+  std::vector<int> rb_face;  // nface * kRowBlocks
+  std::vector<int> rb_slotA, rb_slotB;  // slot of the block's face in cell A / B, or -1
+};
+
+// Geometry of every level 0..L of an n^3 grid with leaf width `leaf`.
+std::vector<LevelGeom> plan_geometry(int n, int leaf);
+
+// Plan level `level` from its geometry and the current active mask (1 byte per
+// grid point): the candidates that are still active.
+LevelPlan plan_level(const LevelGeom& G, const std::vector<uint8_t>& active);
+
+// Plan level `level` of an n^3 grid directly (geometry + filter).
 LevelPlan plan_level(int n, int leaf, int level, int L, const std::vector<uint8_t>& active);
 
 // Number of levels L with n = leaf * 2^L, or -1 if n is not of that form.
