@@ -59,13 +59,11 @@ __device__ __forceinline__ T lookup(const Src<T>& s, int p, int q) {
   return T(0);
 }
 
-// Front of cell c, column j: A_II(i, j) for i >= j into Phi, A_SI(:, j) into
-// the separate buffer ASI (nS x nI, leading dimension max(1, nS)).
+// Front of cell c, column j: A_II(i, j) for i >= j into Phi.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_gather_front(Src<T> s, const int* __restrict__ rows,
                                                      const int64_t* __restrict__ crow_off,
-                                                     const FrontDesc* __restrict__ fd, T* arena,
-                                                     T* asi, const int64_t* __restrict__ aoff) {
+                                                     const FrontDesc* __restrict__ fd, T* arena) {
   const int c = blockIdx.y;
   const FrontDesc f = fd[c];
   const int j = blockIdx.x;
@@ -73,13 +71,23 @@ __global__ __launch_bounds__(NT) void k_gather_front(Src<T> s, const int* __rest
   const int* r = rows + crow_off[c];
   const int q = r[j];
   T* col = arena + f.off + (int64_t)f.ld * j;
-  const int nS = f.nR - f.nI;
-  T* scol = asi + aoff[c] + (int64_t)(nS > 0 ? nS : 1) * j;
-  for (int i = j + threadIdx.x; i < f.nR; i += NT) {
-    const T v = lookup(s, r[i], q);
-    if (i < f.nI) col[i] = v;
-    else scol[i - f.nI] = v;
-  }
+  for (int i = j + threadIdx.x; i < f.nI; i += NT) col[i] = lookup(s, r[i], q);
+}
+
+// A_IS of cell c, column s (the s-th shell point): nI x nS, leading dimension nI.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_gather_front_IS(Src<T> s, const int* __restrict__ rows,
+                                                        const int64_t* __restrict__ crow_off,
+                                                        const FrontDesc* __restrict__ fd, T* ais,
+                                                        const int64_t* __restrict__ aoff) {
+  const int c = blockIdx.y;
+  const FrontDesc f = fd[c];
+  const int sj = blockIdx.x;
+  if (sj >= f.nR - f.nI) return;
+  const int* r = rows + crow_off[c];
+  const int q = r[f.nI + sj];
+  T* col = ais + aoff[c] + (int64_t)f.nI * sj;
+  for (int i = threadIdx.x; i < f.nI; i += NT) col[i] = lookup(s, r[i], q);
 }
 
 // Copy the computed lower triangle of each square block to its upper triangle.
@@ -374,23 +382,29 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
     lev.front.alloc(off);
     st.cells[level] = P.ncell;
     st.eliminated[level] = lev.ysum;
+    // X = L_I^{-1} A_IS (nI x nS per cell) is kept until the Schur update
+    std::vector<int64_t> xoff(P.ncell);
+    int64_t xsz = 0;
+    for (int c = 0; c < P.ncell; ++c) {
+      xoff[c] = xsz;
+      xsz += (int64_t)P.cI[c] * P.cS[c];
+    }
+    DevBuf<T> X(std::max<int64_t>(xsz, 1));
     if (P.ncell > 0) {
-      // A_SI goes to a separate buffer: L_SI = A_SI L_I^{-T} is formed by one GEMM
-      std::vector<int64_t> aoff(P.ncell);
-      int64_t asz = 0;
-      for (int c = 0; c < P.ncell; ++c) {
-        aoff[c] = asz;
-        asz += (int64_t)std::max(1, P.cS[c]) * P.cI[c];
-      }
-      DevBuf<T> ASI(std::max<int64_t>(asz, 1));
-      DevBuf<int64_t> d_aoff = to_dev(aoff, s);
+      DevBuf<T> AIS(std::max<int64_t>(xsz, 1));
+      DevBuf<int64_t> d_xoff = to_dev(xoff, s);
       {
         ProfScope ps("gather_front", s);
         dim3 g((unsigned)std::max(1, lev.maxI), (unsigned)P.ncell);
         hipLaunchKernelGGL((k_gather_front<T>), g, dim3(NT), 0, s, src, lev.rows.get(),
-                           lev.crow_off.get(), lev.fd.get(), lev.front.get(), ASI.get(),
-                           d_aoff.get());
+                           lev.crow_off.get(), lev.fd.get(), lev.front.get());
         HIF_LAUNCH_CHECK();
+        if (lev.maxS > 0) {
+          dim3 g2((unsigned)lev.maxS, (unsigned)P.ncell);
+          hipLaunchKernelGGL((k_gather_front_IS<T>), g2, dim3(NT), 0, s, src, lev.rows.get(),
+                             lev.crow_off.get(), lev.fd.get(), AIS.get(), d_xoff.get());
+          HIF_LAUNCH_CHECK();
+        }
       }
       // interior Cholesky and in-place inverse on the top nI x nI block
       std::vector<FrontDesc> top = lev.hfd;
@@ -403,16 +417,23 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
       if (err != kNoErr)
         throw Error(HIF_ENOTSPD, "non-positive pivot in the interior Cholesky at level " +
                                      std::to_string(level) + ", cell " + std::to_string(err));
-      // L_SI = A_SI L_I^{-T}  (op(B) = Linv^T is upper triangular)
+      // X = L_I^{-1} A_IS, then L_SI = X^T into the front below L_I^{-1}
       std::vector<GemmDesc> gd;
+      std::vector<TransDesc> td;
       for (int c = 0; c < P.ncell; ++c) {
         if (P.cS[c] == 0) continue;
         const FrontDesc& d = lev.hfd[c];
         T* base = lev.front.get() + d.off;
-        gd.push_back({ASI.get() + aoff[c], base, base + d.nI, P.cS[c], d.nI, d.nI,
-                      std::max(1, P.cS[c]), d.ld, d.ld});
+        gd.push_back({base, AIS.get() + xoff[c], X.get() + xoff[c], d.nI, P.cS[c], d.nI, d.ld,
+                      d.nI, d.nI});
+        td.push_back({X.get() + xoff[c], base + d.nI, d.nI, P.cS[c], d.nI, d.ld});
       }
-      run_gemms<T, T>("gemm_lsi", OP_N, OP_T, GF_B_UPPER, gd, T(1), T(0), s, GC_LSI);
+      run_gemms<T, T>("gemm_lsi", OP_N, OP_N, GF_A_LOWER, gd, T(1), T(0), s, GC_LSI);
+      if (!td.empty()) {
+        DevBuf<TransDesc> d_td = to_dev(td, s);
+        transpose_batched<T>(d_td.get(), (int)td.size(), lev.maxI, lev.maxS, s, "lsi_transpose");
+        HIF_HIP(hipStreamSynchronize(s));
+      }
     }
 
     if (!P.root) {
@@ -432,9 +453,11 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
           if (P.cS[c] == 0) continue;
           const FrontDesc& d = lev.hfd[c];
           const T* LSI = lev.front.get() + d.off + d.nI;
-          gd.push_back({LSI, LSI, U.get() + uoff[c], P.cS[c], P.cS[c], d.nI, d.ld, d.ld, uld[c]});
+          gd.push_back({LSI, X.get() + xoff[c], U.get() + uoff[c], P.cS[c], P.cS[c], d.nI, d.ld,
+                        d.nI, uld[c]});
         }
-        run_gemms<T, T>("gemm_syrk", OP_N, OP_T, GF_C_LOWER, gd, T(-1), T(0), s, GC_SYRK);
+        run_gemms<T, T>("gemm_syrk", OP_N, OP_N, GF_C_LOWER, gd, T(-1), T(0), s, GC_SYRK);
+        X.release();
       }
       // ---- face panels Ã^l([F; R-faces], F) ------------------------------
       std::vector<int64_t> poff(P.nface);
@@ -494,13 +517,33 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
           gsz += (int64_t)gld[f] * P.fN[f];
         }
         DevBuf<double> G(std::max<int64_t>(gsz, 1)), Lp(std::max<int64_t>(gsz, 1));
+        // M^T (|F| x K per face) for an NN Gram product
+        std::vector<int64_t> toff(P.nface);
+        int64_t tsz = 0;
+        int maxK = 0;
+        for (int f = 0; f < P.nface; ++f) {
+          toff[f] = tsz;
+          const int K = P.prow[f] - P.fN[f];
+          tsz += (int64_t)P.fN[f] * K;
+          maxK = std::max(maxK, K);
+        }
+        DevBuf<T> MT(std::max<int64_t>(tsz, 1));
+        std::vector<TransDesc> td;
         for (int f = 0; f < P.nface; ++f) {
           const T* PR = lev.panel.get() + poff[f] + P.fN[f];
           const int K = P.prow[f] - P.fN[f];
-          gd.push_back({PR, PR, G.get() + goff[f], P.fN[f], P.fN[f], K, pld[f], pld[f], gld[f]});
+          td.push_back({PR, MT.get() + toff[f], K, P.fN[f], pld[f], std::max(1, P.fN[f])});
+          gd.push_back({MT.get() + toff[f], PR, G.get() + goff[f], P.fN[f], P.fN[f], K,
+                        std::max(1, P.fN[f]), pld[f], gld[f]});
           flops += 2.0 * K * P.fN[f] * (double)P.fN[f];
         }
-        run_gemms<T, double>("gemm_gram", OP_T, OP_N, GF_C_LOWER, gd, 1.0, 0.0, s, GC_GRAM);
+        {
+          DevBuf<TransDesc> d_td = to_dev(td, s);
+          transpose_batched<T>(d_td.get(), (int)td.size(), maxK, lev.maxF, s, "gram_transpose");
+          HIF_HIP(hipStreamSynchronize(s));
+        }
+        run_gemms<T, double>("gemm_gram", OP_N, OP_N, GF_C_LOWER, gd, 1.0, 0.0, s, GC_GRAM);
+        MT.release();
         DevBuf<int64_t> d_goff = to_dev(goff, s);
         DevBuf<int> d_gld = to_dev(gld, s);
         {

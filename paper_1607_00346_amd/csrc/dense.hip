@@ -50,7 +50,7 @@ struct TileSmem {
 // the next chunk.  Masked operand entries (triangular flags, out of range)
 // read as zero.
 template <typename TIn, typename TC, int OPA, int OPB, int TM, int TN>
-__device__ void gemm_tile_t(int flags, const TIn* A, int lda, const TIn* __restrict__ B, int ldb,
+__device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, const TIn* __restrict__ B, int ldb,
                             TC* C, int ldc, int m, int n, int k, int m0, int n0, TC alpha, TC beta,
                             TileSmem<TC, TM, TN>& sm) {
   constexpr int FM = TM / 32, FN = TN / 32;        // 16x16 blocks per wave
@@ -142,7 +142,10 @@ __device__ void gemm_tile_t(int flags, const TIn* A, int lda, const TIn* __restr
       for (int c = 0; c < nchunk; ++c) {
         const int buf = c & 1;
         if (c + 1 < nchunk) load(c + 1);
+        // keep the next chunk's global loads issued ahead of this chunk's MFMAs
+        __builtin_amdgcn_sched_barrier(0);
         compute(buf);
+        __builtin_amdgcn_sched_barrier(0);
         if (c + 1 < nchunk) store(buf ^ 1);
         __syncthreads();
       }
@@ -152,6 +155,7 @@ __device__ void gemm_tile_t(int flags, const TIn* A, int lda, const TIn* __restr
         store(0);
         __syncthreads();
         if (c + 1 < nchunk) load(c + 1);
+        __builtin_amdgcn_sched_barrier(0);
         compute(0);
         __syncthreads();
       }
@@ -177,12 +181,28 @@ __device__ void gemm_tile_t(int flags, const TIn* A, int lda, const TIn* __restr
 
 // CLS only gives each use (generic, Schur SYRK, L_SI, Gram) its own kernel
 // symbol for profilers.
+// Workgroups are dealt to the 8 XCDs round-robin; remap the linear block id
+// so that each XCD runs a contiguous range of tiles (neighbouring tiles share
+// A and B panels in that XCD's L2).
+__device__ __forceinline__ void xcd_remap(unsigned& bx, unsigned& by, unsigned& bz) {
+  const unsigned gx = gridDim.x, gy = gridDim.y;
+  const unsigned T = gx * gy * gridDim.z;
+  unsigned L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const unsigned per = T / 8;
+  if (L < 8 * per) L = (L % 8) * per + L / 8;
+  bx = L % gx;
+  by = (L / gx) % gy;
+  bz = L / (gx * gy);
+}
+
 template <typename TIn, typename TC, int OPA, int OPB, int TM, int TN, int CLS>
 __global__ __launch_bounds__(NTHR) void k_gemm_desc(int flags, const GemmDesc* __restrict__ desc,
                                                     TC alpha, TC beta) {
   __shared__ TileSmem<TC, TM, TN> sm;
-  const GemmDesc d = desc[blockIdx.z];
-  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  unsigned bx, by, bz;
+  xcd_remap(bx, by, bz);
+  const GemmDesc d = desc[bz];
+  const int m0 = by * TM, n0 = bx * TN;
   if (m0 >= d.m || n0 >= d.n) return;
   if ((flags & GF_C_LOWER) && m0 + TM - 1 < n0) return;
   gemm_tile_t<TIn, TC, OPA, OPB, TM, TN>(flags, (const TIn*)d.A, d.lda, (const TIn*)d.B, d.ldb,
@@ -191,21 +211,26 @@ __global__ __launch_bounds__(NTHR) void k_gemm_desc(int flags, const GemmDesc* _
 
 // Trailing update of the blocked front Cholesky at block column j0:
 // Phi[j1:nR, j1:nI] -= P[j1:nR] P[j1:nI]^T (lower part), P = Phi[:, j0:j1].
+// PT holds the panel transposed (kPanel x (nR - j1) per front, stride pstride)
+// so that the update is a plain NN product.
 template <typename T, int TS>
 __global__ __launch_bounds__(NTHR) void k_front_trailing(T* arena, const FrontDesc* __restrict__ fd,
-                                                         int j0) {
+                                                         int j0, const T* __restrict__ PT,
+                                                         int64_t pstride) {
   __shared__ TileSmem<T, TS, TS> sm;
-  const FrontDesc f = fd[blockIdx.z];
+  unsigned bx, by, bz;
+  xcd_remap(bx, by, bz);
+  const FrontDesc f = fd[bz];
   if (j0 >= f.nI) return;
   const int nb = min(kPanel, f.nI - j0);
   const int j1 = j0 + nb;
   const int m = f.nR - j1, n = f.nI - j1;
-  const int m0 = blockIdx.y * TS, n0 = blockIdx.x * TS;
+  const int m0 = by * TS, n0 = bx * TS;
   if (m0 >= m || n0 >= n) return;
   if (m0 + TS - 1 < n0) return;
   T* base = arena + f.off;
   const T* P = base + j1 + (int64_t)f.ld * j0;
-  gemm_tile_t<T, T, OP_N, OP_T, TS, TS>(GF_C_LOWER, P, f.ld, P, f.ld,
+  gemm_tile_t<T, T, OP_N, OP_N, TS, TS>(GF_C_LOWER, P, f.ld, PT + bz * pstride, kPanel,
                                         base + j1 + (int64_t)f.ld * j1, f.ld, m, n, nb, m0, n0,
                                         T(-1), T(1), sm);
 }
@@ -423,6 +448,29 @@ __global__ __launch_bounds__(NTHR) void k_pchol_panel(
   }
 }
 
+// 32 x 32 tiles through LDS; reads and writes are both along columns.
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_transpose(const TransDesc* __restrict__ dd) {
+  __shared__ T tile[32][33];
+  const TransDesc d = dd[blockIdx.z];
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  if (r0 >= d.rows || c0 >= d.cols) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const T* src = (const T*)d.src;
+  T* dst = (T*)d.dst;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = r0 + tx, c = c0 + ty + 8 * k;
+    if (r < d.rows && c < d.cols) tile[ty + 8 * k][tx] = src[r + (int64_t)d.lds * c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = c0 + tx, r = r0 + ty + 8 * k;
+    if (r < d.rows && c < d.cols) dst[c + (int64_t)d.ldd * r] = tile[tx][ty + 8 * k];
+  }
+}
+
 // Rank and the tail of the permutation: unpivoted indices ascending.
 __global__ __launch_bounds__(64) void k_pchol_tail(const int* __restrict__ nFa,
                                                    const int64_t* __restrict__ poff,
@@ -460,12 +508,12 @@ void launch_gemm(int flags, const GemmDesc* d_desc, int batch, int max_m, int ma
 template <typename TIn, typename TC, int TS>
 void dispatch_gemm(int opa, int opb, int flags, int cls, const GemmDesc* d_desc, int batch,
                    int max_m, int max_n, TC alpha, TC beta, hipStream_t s) {
-  if (cls == GC_SYRK && opa == OP_N && opb == OP_T)
-    launch_gemm<TIn, TC, OP_N, OP_T, TS, GC_SYRK>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
-  else if (cls == GC_LSI && opa == OP_N && opb == OP_T)
-    launch_gemm<TIn, TC, OP_N, OP_T, TS, GC_LSI>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
-  else if (cls == GC_GRAM && opa == OP_T && opb == OP_N)
-    launch_gemm<TIn, TC, OP_T, OP_N, TS, GC_GRAM>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+  if (cls == GC_SYRK && opa == OP_N && opb == OP_N)
+    launch_gemm<TIn, TC, OP_N, OP_N, TS, GC_SYRK>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+  else if (cls == GC_LSI && opa == OP_N && opb == OP_N)
+    launch_gemm<TIn, TC, OP_N, OP_N, TS, GC_LSI>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+  else if (cls == GC_GRAM && opa == OP_N && opb == OP_N)
+    launch_gemm<TIn, TC, OP_N, OP_N, TS, GC_GRAM>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
   else if (opa == OP_N && opb == OP_N)
     launch_gemm<TIn, TC, OP_N, OP_N, TS, 0>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
   else if (opa == OP_N)
@@ -482,11 +530,26 @@ void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch
                   int cls) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
   ProfScope ps(name, s, flops);
-  if (max_m >= 1024 && max_n >= 1024)
+  if (sizeof(TC) == 4 && max_m >= 1024 && max_n >= 1024)
     dispatch_gemm<TIn, TC, 128>(opa, opb, flags, cls, d_desc, batch, max_m, max_n, alpha, beta, s);
   else
     dispatch_gemm<TIn, TC, 64>(opa, opb, flags, cls, d_desc, batch, max_m, max_n, alpha, beta, s);
 }
+
+template <typename T>
+void transpose_batched(const TransDesc* d_desc, int batch, int max_rows, int max_cols,
+                       hipStream_t s, const char* name) {
+  if (batch <= 0 || max_rows <= 0 || max_cols <= 0) return;
+  ProfScope ps(name, s);
+  for (int b0 = 0; b0 < batch; b0 += 65535) {
+    const int nb = std::min(batch - b0, 65535);
+    dim3 g((unsigned)ceil_div(max_cols, 32), (unsigned)ceil_div(max_rows, 32), (unsigned)nb);
+    hipLaunchKernelGGL((k_transpose<T>), g, dim3(NTHR), 0, s, d_desc + b0);
+    HIF_LAUNCH_CHECK();
+  }
+}
+template void transpose_batched<double>(const TransDesc*, int, int, int, hipStream_t, const char*);
+template void transpose_batched<float>(const TransDesc*, int, int, int, hipStream_t, const char*);
 
 double gemm_flops(const GemmDesc& d, int flags) {
   const double m = d.m, n = d.n, k = d.k;
@@ -524,6 +587,25 @@ void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
   int maxI = 0;
   for (auto& f : h_fronts) maxI = std::max(maxI, f.nI);
   DevBuf<T> dinv((size_t)batch * kPanel * kPanel);
+  int maxR = 0;
+  for (auto& f : h_fronts) maxR = std::max(maxR, f.nR);
+  const int64_t pstride = (int64_t)kPanel * std::max(maxR, 1);
+  DevBuf<T> PT((size_t)batch * pstride);
+  // transpose descriptors of every step, uploaded once
+  const int nsteps = (int)ceil_div(maxI, kPanel);
+  std::vector<TransDesc> td((size_t)nsteps * batch);
+  for (int st = 0; st < nsteps; ++st) {
+    const int j0 = st * kPanel;
+    for (int b = 0; b < batch; ++b) {
+      const FrontDesc& f = h_fronts[b];
+      const int nb = std::max(0, std::min(kPanel, f.nI - j0));
+      const int rows = f.nI > j0 ? f.nR - j0 - nb : 0;
+      td[(size_t)st * batch + b] = {arena + f.off + (j0 + nb) + (int64_t)f.ld * j0,
+                                    PT.get() + b * pstride, rows, nb, f.ld, kPanel};
+    }
+  }
+  DevBuf<TransDesc> d_td;
+  d_td.upload(td, s);
   for (int j0 = 0; j0 < maxI; j0 += kPanel) {
     int max_m = 0, max_n = 0;
     double fl_panel = 0.0, fl_trail = 0.0;
@@ -550,13 +632,17 @@ void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
       HIF_LAUNCH_CHECK();
     }
     if (max_m > 0 && max_n > 0) {
+      transpose_batched<T>(d_td.get() + (size_t)(j0 / kPanel) * batch, batch, max_m, kPanel, s,
+                           "potrf_transpose");
       ProfScope ps("potrf_trailing", s, fl_trail);
-      if (max_n >= 1024) {
+      if (sizeof(T) == 4 && max_n >= 1024) {
         dim3 gt((unsigned)ceil_div(max_n, 128), (unsigned)ceil_div(max_m, 128), (unsigned)batch);
-        hipLaunchKernelGGL((k_front_trailing<T, 128>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0);
+        hipLaunchKernelGGL((k_front_trailing<T, 128>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0,
+                           (const T*)PT.get(), pstride);
       } else {
         dim3 gt((unsigned)ceil_div(max_n, 64), (unsigned)ceil_div(max_m, 64), (unsigned)batch);
-        hipLaunchKernelGGL((k_front_trailing<T, 64>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0);
+        hipLaunchKernelGGL((k_front_trailing<T, 64>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0,
+                           (const T*)PT.get(), pstride);
       }
       HIF_LAUNCH_CHECK();
     }
@@ -639,7 +725,10 @@ void pivoted_cholesky(double* G, double* L, const int64_t* goff, const int* nF, 
   DevBuf<int> pivbuf(std::max<int64_t>(tot, 1)), kst(batch);
   HIF_HIP(hipMemsetAsync(kst.get(), 0xff, sizeof(int) * batch, s));  // -1: running
   std::vector<GemmDesc> gd;
+  std::vector<TransDesc> td;
   DevBuf<GemmDesc> dd;
+  DevBuf<TransDesc> dt;
+  DevBuf<double> LT((size_t)std::max<int64_t>(tot, 1) * kPivPanel);  // panel of L, transposed
   for (int j0 = 0; j0 < maxF; j0 += kPivPanel) {
     {
       ProfScope ps("pivoted_cholesky", s);
@@ -649,20 +738,25 @@ void pivoted_cholesky(double* G, double* L, const int64_t* goff, const int* nF, 
     }
     if (j0 + kPivPanel >= maxF) break;
     gd.clear();
+    td.clear();
     int mm = 0;
     double fl = 0.0;
     for (int b = 0; b < batch; ++b) {
       if (h_nF[b] <= j0 + kPivPanel) continue;
       const int kk = std::min(kPivPanel, h_nF[b] - j0);
       double* Lp = L + h_goff[b] + (int64_t)h_ldg[b] * j0;
-      gd.push_back({Lp, Lp, G + h_goff[b], h_nF[b], h_nF[b], kk, h_ldg[b], h_ldg[b], h_ldg[b]});
+      double* Lt = LT.get() + h_poff[b] * kPivPanel;
+      td.push_back({Lp, Lt, h_nF[b], kk, h_ldg[b], kPivPanel});
+      gd.push_back({Lp, Lt, G + h_goff[b], h_nF[b], h_nF[b], kk, h_ldg[b], kPivPanel, h_ldg[b]});
       mm = std::max(mm, h_nF[b]);
       fl += 2.0 * kk * (double)h_nF[b] * h_nF[b];
     }
     if (gd.empty()) continue;
     HIF_HIP(hipStreamSynchronize(s));  // previous descriptors may still be in use
+    dt.upload(td, s);
     dd.upload(gd, s);
-    gemm_batched<double, double>(OP_N, OP_T, 0, dd.get(), (int)gd.size(), mm, mm, -1.0, 1.0, s,
+    transpose_batched<double>(dt.get(), (int)td.size(), mm, kPivPanel, s, "pivchol_transpose");
+    gemm_batched<double, double>(OP_N, OP_N, 0, dd.get(), (int)gd.size(), mm, mm, -1.0, 1.0, s,
                                  "pivchol_update", fl);
   }
   hipLaunchKernelGGL(k_pchol_tail, dim3((unsigned)batch), dim3(64), 0, s, nF, poff, perm,

@@ -47,6 +47,17 @@ void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch
 // Algorithmic flops of one descriptor under the triangular flags (one flag class).
 double gemm_flops(const GemmDesc& d, int flags);
 
+// Batched out-of-place transpose: dst (cols x rows, leading dimension ldd) =
+// src (rows x cols, leading dimension lds)^T, column-major.
+struct TransDesc {
+  const void* src;
+  void* dst;
+  int rows, cols, lds, ldd;
+};
+template <typename T>
+void transpose_batched(const TransDesc* d_desc, int batch, int max_rows, int max_cols,
+                       hipStream_t s, const char* name = "transpose");
+
 // One front: element offset of its column-major block in the arena, interior
 // count nI, total rows nR = nI + nS, leading dimension ld >= nR.
 struct FrontDesc {
