@@ -2,8 +2,6 @@
 // thread-local error text.  No exception crosses this boundary.
 #include <cmath>
 #include <cstring>
-#include <map>
-#include <mutex>
 #include <new>
 #include <string>
 
@@ -21,71 +19,6 @@ void set_last_error(const std::string& msg) { g_last_error = msg; }
 MemStats& mem_stats() {
   static MemStats ms;
   return ms;
-}
-
-namespace {
-struct Pool {
-  std::mutex mu;
-  std::multimap<size_t, void*> free_blocks;
-  int64_t cached = 0;
-  bool dirty = false;  // blocks were released since the last device synchronization
-  ~Pool() {
-    for (auto& kv : free_blocks) (void)hipFree(kv.second);
-  }
-};
-Pool& pool() {
-  static Pool p;
-  return p;
-}
-}  // namespace
-
-size_t pool_round(size_t bytes) {
-  const size_t g = bytes >= (size_t(1) << 20) ? (size_t(2) << 20) : 256;
-  return (bytes + g - 1) / g * g;
-}
-
-void* pool_alloc(size_t bytes) {
-  const size_t r = pool_round(bytes);
-  Pool& P = pool();
-  std::lock_guard<std::mutex> lock(P.mu);
-  auto it = P.free_blocks.find(r);
-  if (it != P.free_blocks.end()) {
-    // kernels issued before the release (on any stream) must be done with it
-    if (P.dirty) {
-      HIF_HIP(hipDeviceSynchronize());
-      P.dirty = false;
-    }
-    void* p = it->second;
-    P.free_blocks.erase(it);
-    P.cached -= (int64_t)r;
-    return p;
-  }
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, r);
-  if (e == hipErrorOutOfMemory && !P.free_blocks.empty()) {
-    (void)hipGetLastError();
-    for (auto& kv : P.free_blocks) (void)hipFree(kv.second);
-    P.free_blocks.clear();
-    P.cached = 0;
-    e = hipMalloc(&p, r);
-  }
-  if (e != hipSuccess)
-    throw Error(e == hipErrorOutOfMemory ? HIF_ENOMEM : HIF_EDEVICE,
-                std::string("hipMalloc: ") + hipGetErrorString(e));
-  return p;
-}
-
-void pool_free(void* p, size_t bytes) {
-  const size_t r = pool_round(bytes);
-  Pool& P = pool();
-  std::lock_guard<std::mutex> lock(P.mu);
-  if (P.cached + (int64_t)r > kPoolCap) {
-    (void)hipFree(p);
-    return;
-  }
-  P.free_blocks.emplace(r, p);
-  P.cached += (int64_t)r;
-  P.dirty = true;
 }
 
 }  // namespace hif
@@ -138,6 +71,7 @@ hif_status hif_problem_create(const hif_options* opts, const double* a, const do
     HIF_REQUIRE(out != nullptr, HIF_EINVAL, "out must not be NULL");
     check_options(opts);
     HIF_REQUIRE(a != nullptr && b != nullptr, HIF_EINVAL, "a and b must not be NULL");
+    hif::StreamScope scope(as_stream(stream));
     auto* A = new hif_problem_s();
     try {
       A->opts = *opts;
@@ -158,6 +92,8 @@ hif_status hif_build(hif_problem_t A, const hif_options* opts, void* stream, hif
     HIF_REQUIRE(out != nullptr && A != nullptr, HIF_EINVAL, "NULL handle");
     check_options(opts);
     HIF_REQUIRE(opts->n == A->n, HIF_EINVAL, "options describe another grid than the problem");
+    hif::StreamScope scope(as_stream(stream));
+    hif::Staging staging(as_stream(stream));  // synchronizes the stream when the build ends
     auto* F = new hif_factor_s();
     try {
       F->opts = *opts;
@@ -181,6 +117,7 @@ hif_status hif_apply(hif_factor_t F, const double* f, double* u, int32_t nrhs, v
     if (nrhs == 0) return;
     HIF_REQUIRE(f != nullptr && u != nullptr, HIF_EINVAL, "NULL vector");
     const int64_t N = F->stats.n_dof;
+    hif::StreamScope scope(as_stream(stream));
     for (int c = 0; c < nrhs; ++c) F->impl->apply(f + c * N, u + c * N, as_stream(stream));
   });
 }
@@ -191,6 +128,7 @@ hif_status hif_matvec(hif_problem_t A, const double* x, double* y, int32_t nrhs,
     HIF_REQUIRE(nrhs >= 0, HIF_EINVAL, "nrhs must be >= 0");
     if (nrhs == 0) return;
     HIF_REQUIRE(x != nullptr && y != nullptr && x != y, HIF_EINVAL, "bad vectors");
+    hif::StreamScope scope(as_stream(stream));
     for (int c = 0; c < nrhs; ++c)
       hif::stencil_matvec(A->stencil(), x + c * A->N, y + c * A->N, as_stream(stream));
   });
@@ -206,6 +144,7 @@ hif_status hif_pcg(hif_problem_t A, hif_factor_t F, const double* f, double* u, 
     if (nrhs == 0) return;
     HIF_REQUIRE(f != nullptr && u != nullptr && info != nullptr && f != u, HIF_EINVAL,
                 "bad vectors");
+    hif::StreamScope scope(as_stream(stream));
     bool all = true;
     for (int c = 0; c < nrhs; ++c) {
       hif::pcg_solve(A, F, f + c * A->N, u + c * A->N, tol, maxit, &info[c], as_stream(stream));

@@ -260,6 +260,24 @@ __global__ __launch_bounds__(NT) void k_perm_points(const int* __restrict__ fpts
   skpts[o + j] = fpts[o + perm[o + j]];
 }
 
+// Lookup maps for the next level: the face of every face point and its index
+// within the face (-1 for every other point; the fill runs first).
+__global__ __launch_bounds__(NT) void k_fill_int(int* p, int64_t n, int v) {
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+    p[i] = v;
+}
+
+__global__ __launch_bounds__(NT) void k_face_map(const int* __restrict__ fpts,
+                                                 const int64_t* __restrict__ fpt_off,
+                                                 const int* __restrict__ fN, int* pface, int* ploc) {
+  const int f = blockIdx.y;
+  const int j = blockIdx.x * NT + threadIdx.x;
+  if (j >= fN[f]) return;
+  const int p = fpts[fpt_off[f] + j];
+  pface[p] = f;
+  ploc[p] = j;
+}
+
 template <typename T>
 Src<T> make_src(const hif_problem_s* A, const Level<T>* prev, const int* pface, const int* ploc) {
   Src<T> s;
@@ -297,7 +315,6 @@ void run_gemms(const char* name, int opa, int opb, int flags, const std::vector<
   d.upload(h, s);
   gemm_batched<TIn, TC>(opa, opb, flags, d.get(), (int)h.size(), mm, mn, alpha, beta, s, name, fl,
                         cls);
-  HIF_HIP(hipStreamSynchronize(s));  // descriptors are freed on return
 }
 
 double now_s() {
@@ -333,23 +350,45 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
     A->geom_leaf = leaf;
   }
   std::vector<uint8_t> active(N, 1);
-  std::vector<int> pface(N, -1), ploc(N, -1);
-  DevBuf<int> d_pface, d_ploc, d_err(1);
+  // face / local index of every level-(l-1) face point, for the A^l lookup
+  DevBuf<int> d_pface(L > 0 ? N : 0), d_ploc(L > 0 ? N : 0);
+  // failure flags: per level, the interior Cholesky (cell) and the Cholesky of
+  // B_F̌F̌ (skeleton index); checked whenever the host synchronizes anyway
   const int kNoErr = INT_MAX;
+  std::vector<int> h_err(2 * (L + 1), kNoErr);
+  DevBuf<int> d_err = to_dev(h_err, s);
+  auto check_errors = [&]() {
+    HIF_HIP(hipMemcpyAsync(h_err.data(), d_err.get(), sizeof(int) * h_err.size(),
+                           hipMemcpyDeviceToHost, s));
+    HIF_HIP(hipStreamSynchronize(s));
+    for (int l = 0; l <= L; ++l) {
+      if (h_err[2 * l] != kNoErr)
+        throw Error(HIF_ENOTSPD, "non-positive pivot in the interior Cholesky at level " +
+                                     std::to_string(l) + ", cell " + std::to_string(h_err[2 * l]));
+      if (h_err[2 * l + 1] != kNoErr)
+        throw Error(HIF_ENOTSPD, "non-positive pivot in B_F̌F̌ at level " + std::to_string(l) +
+                                     ", face " +
+                                     std::to_string(Fi.levels[l].hsk[h_err[2 * l + 1]].face));
+    }
+  };
+  // device-side level timing
+  struct Events {
+    std::vector<hipEvent_t> e;
+    ~Events() {
+      for (hipEvent_t x : e) (void)hipEventDestroy(x);
+    }
+  } ev;
+  ev.e.resize(L + 2, nullptr);
+  for (auto& x : ev.e) HIF_HIP(hipEventCreate(&x));
   double flops = 0.0;
 
   for (int level = 0; level <= L; ++level) {
-    const double t_level = now_s();
+    HIF_HIP(hipEventRecord(ev.e[level], s));
     profiler().level = level;
     Level<T>& lev = Fi.levels[level];
     Level<T>* prev = level > 0 ? &Fi.levels[level - 1] : nullptr;
     lev.P = plan_level(A->geom[level], active);
     const LevelPlan& P = lev.P;
-    if (level > 0) {
-      d_pface.upload(pface, s);
-      d_ploc.upload(ploc, s);
-    }
-    HIF_HIP(hipMemcpyAsync(d_err.get(), &kNoErr, sizeof(int), hipMemcpyHostToDevice, s));
     const Src<T> src = make_src<T>(A, prev, d_pface.get(), d_ploc.get());
 
     // ---- fronts: gather, partial Cholesky + inverse (Section 2.2) -------
@@ -410,13 +449,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
       std::vector<FrontDesc> top = lev.hfd;
       for (auto& d : top) d.nR = d.nI;
       DevBuf<FrontDesc> d_top = to_dev(top, s);
-      front_factor<T>(lev.front.get(), d_top.get(), top, d_err.get(), s);
-      int err = kNoErr;
-      HIF_HIP(hipMemcpyAsync(&err, d_err.get(), sizeof(int), hipMemcpyDeviceToHost, s));
-      HIF_HIP(hipStreamSynchronize(s));
-      if (err != kNoErr)
-        throw Error(HIF_ENOTSPD, "non-positive pivot in the interior Cholesky at level " +
-                                     std::to_string(level) + ", cell " + std::to_string(err));
+      front_factor<T>(lev.front.get(), d_top.get(), top, d_err.get() + 2 * level, s);
       // X = L_I^{-1} A_IS, then L_SI = X^T into the front below L_I^{-1}
       std::vector<GemmDesc> gd;
       std::vector<TransDesc> td;
@@ -432,7 +465,6 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
       if (!td.empty()) {
         DevBuf<TransDesc> d_td = to_dev(td, s);
         transpose_batched<T>(d_td.get(), (int)td.size(), lev.maxI, lev.maxS, s, "lsi_transpose");
-        HIF_HIP(hipStreamSynchronize(s));
       }
     }
 
@@ -493,7 +525,6 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
                            U.get(), d_uoff.get(), d_uld.get(), lev.panel.get(),
                            lev.panel_off.get(), lev.panel_ld.get());
         HIF_LAUNCH_CHECK();
-        HIF_HIP(hipStreamSynchronize(s));
       }
       U.release();
       if (prev) {  // A^l has been read for the last time
@@ -540,7 +571,6 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
         {
           DevBuf<TransDesc> d_td = to_dev(td, s);
           transpose_batched<T>(d_td.get(), (int)td.size(), maxK, lev.maxF, s, "gram_transpose");
-          HIF_HIP(hipStreamSynchronize(s));
         }
         run_gemms<T, double>("gemm_gram", OP_N, OP_N, GF_C_LOWER, gd, 1.0, 0.0, s, GC_GRAM);
         MT.release();
@@ -568,7 +598,8 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
                                hipMemcpyDeviceToHost, s));
         HIF_HIP(hipMemcpyAsync(hperm.data(), d_perm.get(), sizeof(int) * hperm.size(),
                                hipMemcpyDeviceToHost, s));
-        HIF_HIP(hipStreamSynchronize(s));
+        check_errors();  // synchronizes: ranks, pivots and flags are on the host
+        staging_synced(s);
         G.release();
 
         // skeleton descriptors and arena
@@ -630,7 +661,6 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
           if (!tri.empty()) {
             DevBuf<FrontDesc> d_tri = to_dev(tri, s);
             front_invert<double>(L11.get(), d_tri.get(), tri, s);
-            HIF_HIP(hipStreamSynchronize(s));
           }
           DevBuf<double> Td;
           if (!std::is_same<T, double>::value) Td.alloc(std::max<int64_t>(ssz, 1));
@@ -650,7 +680,6 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
                                dim3(NT), 0, s, Td.get(), lev.skel.get(), ssz);
             HIF_LAUNCH_CHECK();
           }
-          HIF_HIP(hipStreamSynchronize(s));
           L11.release();
           L21.release();
           Lp.release();
@@ -689,14 +718,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
             cfd.push_back({lev.hsk[i].offL, lev.hsk[i].r, lev.hsk[i].r, lev.hsk[i].r, 0});
           {
             DevBuf<FrontDesc> d_cfd = to_dev(cfd, s);
-            front_factor<T>(SK, d_cfd.get(), cfd, d_err.get(), s);
-            int err = kNoErr;
-            HIF_HIP(hipMemcpyAsync(&err, d_err.get(), sizeof(int), hipMemcpyDeviceToHost, s));
-            HIF_HIP(hipStreamSynchronize(s));
-            if (err != kNoErr)
-              throw Error(HIF_ENOTSPD, "non-positive pivot in B_F̌F̌ at level " +
-                                           std::to_string(level) + ", face " +
-                                           std::to_string(lev.hsk[err].face));
+            front_factor<T>(SK, d_cfd.get(), cfd, d_err.get() + 2 * level + 1, s);
           }
           run_gemms<T, T>("gemm_skel", OP_N, OP_T, GF_A_LOWER, g4, T(1), T(0), s);
           run_gemms<T, T>("gemm_skel", OP_T, OP_N, 0, g5, T(-1), T(1), s);
@@ -706,7 +728,6 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
                                lev.panel_off.get(), lev.panel_ld.get(), d_perm.get(),
                                lev.fpt_off.get(), lev.sk.get(), Ahh.get(), d_ohh.get());
             HIF_LAUNCH_CHECK();
-            HIF_HIP(hipStreamSynchronize(s));
           }
         }
       } else {
@@ -727,16 +748,21 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
       st.redundant[level] = lev.redundant;
 
       // ---- next level's active set and lookup maps --------------------
+      {
+        hipLaunchKernelGGL(k_fill_int, dim3((unsigned)std::min<int64_t>(ceil_div(N, NT), 8192)),
+                           dim3(NT), 0, s, d_pface.get(), N, -1);
+        HIF_LAUNCH_CHECK();
+        if (P.nface > 0) {
+          dim3 g((unsigned)ceil_div(std::max(1, lev.maxF), NT), (unsigned)P.nface);
+          hipLaunchKernelGGL(k_face_map, g, dim3(NT), 0, s, lev.fpts.get(), lev.fpt_off.get(),
+                             lev.fN.get(), d_pface.get(), d_ploc.get());
+          HIF_LAUNCH_CHECK();
+        }
+      }
       for (int c = 0; c < P.ncell; ++c)
         for (int64_t t = P.crow_off[c]; t < P.crow_off[c] + P.cI[c]; ++t) active[P.rows[t]] = 0;
-      std::fill(pface.begin(), pface.end(), -1);
       for (int f = 0; f < P.nface; ++f) {
         const int64_t o0 = P.fpt_off[f];
-        for (int j = 0; j < P.fN[f]; ++j) {
-          const int p = P.fpts[o0 + j];
-          pface[p] = f;
-          ploc[p] = j;
-        }
         for (int j = lev.hk[f]; j < P.fN[f]; ++j) active[P.fpts[o0 + hperm[o0 + j]]] = 0;
       }
       F->active_after.push_back(active);
@@ -746,8 +772,15 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
       st.root_size = lev.ysum;
       if (prev) prev->panel.release();
     }
-    HIF_HIP(hipStreamSynchronize(s));
-    st.level_seconds[level] = now_s() - t_level;
+  }
+  HIF_HIP(hipEventRecord(ev.e[L + 1], s));
+  Fi.prepare(s);
+  check_errors();
+  staging_synced(s);
+  for (int level = 0; level <= L; ++level) {
+    float ms = 0.f;
+    HIF_HIP(hipEventElapsedTime(&ms, ev.e[level], ev.e[level + 1]));
+    st.level_seconds[level] = 1e-3 * ms;
   }
   profiler().level = -1;
   st.factor_flops = flops;

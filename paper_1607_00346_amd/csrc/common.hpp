@@ -48,10 +48,63 @@ MemStats& mem_stats();
 // Device memory with a size-exact cache: released blocks are kept for reuse by
 // a later allocation of the same rounded size (repeated builds of one problem
 // then allocate nothing new).  The cache holds at most kPoolCap bytes.
+//
+// Reuse is stream ordered: a block released while a StreamScope for stream s
+// is active on this thread is handed out again, without any synchronization,
+// to an allocation made under a scope for the same s (later work on s runs
+// after the work that used the block).  Blocks released outside any scope, or
+// wanted by another stream, are reused only after a device synchronization.
 constexpr int64_t kPoolCap = int64_t(48) << 30;
 void* pool_alloc(size_t bytes);
 void pool_free(void* p, size_t bytes);
 size_t pool_round(size_t bytes);
+
+// The stream that all device work of the current library call is ordered on.
+class StreamScope {
+ public:
+  explicit StreamScope(hipStream_t s);
+  ~StreamScope();
+  StreamScope(const StreamScope&) = delete;
+  StreamScope& operator=(const StreamScope&) = delete;
+
+ private:
+  hipStream_t prev_;
+  bool prev_set_;
+};
+
+// Pinned host memory through which uploads are staged, so that an upload
+// enqueued behind running kernels does not wait for them (a copy from pageable
+// memory does).  While a Staging object is alive on this thread, upload_bytes
+// on its stream copies the source into pinned chunks and returns at once.  The
+// chunks are rewound by synced() (the stream has been synchronized, so every
+// staged copy is complete) and returned to a process-wide cache by the
+// destructor, which synchronizes the stream first.
+class Staging {
+ public:
+  explicit Staging(hipStream_t s);
+  ~Staging();
+  Staging(const Staging&) = delete;
+  Staging& operator=(const Staging&) = delete;
+  void copy(void* dst, const void* src, size_t bytes);
+  void synced();
+  hipStream_t stream() const { return s_; }
+
+ private:
+  struct Chunk {
+    char* p;
+    size_t cap, used;
+  };
+  hipStream_t s_;
+  Staging* prev_;
+  std::vector<Chunk> chunks_;
+};
+
+// Host-to-device copy of `bytes` ordered on stream s; the source may be reused
+// as soon as the call returns.
+void upload_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+// Stream s has just been synchronized: rewind this thread's staging for s.
+void staging_synced(hipStream_t s);
 
 // Owning device allocation.  Move-only; frees on destruction.
 template <typename T>
@@ -91,7 +144,7 @@ class DevBuf {
 
   void upload(const std::vector<T>& h, hipStream_t s) {
     if (h.size() != n_) alloc(h.size());
-    if (n_) HIF_HIP(hipMemcpyAsync(p_, h.data(), n_ * sizeof(T), hipMemcpyHostToDevice, s));
+    if (n_) upload_bytes(p_, h.data(), n_ * sizeof(T), s);
   }
   void download(std::vector<T>& h, hipStream_t s) const {
     h.resize(n_);

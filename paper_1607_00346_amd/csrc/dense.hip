@@ -647,7 +647,6 @@ void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
       HIF_LAUNCH_CHECK();
     }
   }
-  HIF_HIP(hipStreamSynchronize(s));  // dinv is released on return
   front_invert<T>(arena, d_fronts, h_fronts, s);
 }
 
@@ -708,7 +707,6 @@ void front_invert(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
                        "trtri_gemm", f1);
     gemm_batched<T, T>(OP_N, OP_N, GF_A_LOWER, d2.get(), (int)g2.size(), mm, sz, T(-1), T(0), s,
                        "trtri_gemm", f2);
-    HIF_HIP(hipStreamSynchronize(s));  // descriptors are rewritten for the next size
   }
 }
 
@@ -752,7 +750,6 @@ void pivoted_cholesky(double* G, double* L, const int64_t* goff, const int* nF, 
       fl += 2.0 * kk * (double)h_nF[b] * h_nF[b];
     }
     if (gd.empty()) continue;
-    HIF_HIP(hipStreamSynchronize(s));  // previous descriptors may still be in use
     dt.upload(td, s);
     dd.upload(gd, s);
     transpose_batched<double>(dt.get(), (int)td.size(), mm, kPivPanel, s, "pivchol_transpose");
@@ -762,7 +759,6 @@ void pivoted_cholesky(double* G, double* L, const int64_t* goff, const int* nF, 
   hipLaunchKernelGGL(k_pchol_tail, dim3((unsigned)batch), dim3(64), 0, s, nF, poff, perm,
                      (const int*)pivbuf.get(), (const int*)kst.get(), k);
   HIF_LAUNCH_CHECK();
-  HIF_HIP(hipStreamSynchronize(s));  // work buffers are released on return
 }
 
 template void gemm_batched<double, double>(int, int, int, const GemmDesc*, int, int, int, double,

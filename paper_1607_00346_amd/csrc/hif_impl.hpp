@@ -71,7 +71,7 @@ struct Level {
   // algorithmic bytes of one sweep over this level (factor words read once,
   // 8-byte vector entries read and written), for the profiler
   double bytes_L = 0.0, bytes_S = 0.0, bytes_skel = 0.0;
-  // sweep descriptors (built on the first apply)
+  // sweep descriptors (built at the end of the build)
   bool gv_ready = false;
   DevBuf<GemvDesc> gv_L, gv_S, gv_T, gv_Lc, gv_Y;
   int gv_nS = 0;  // cells with nS > 0 (gv_S entries)
@@ -91,6 +91,10 @@ struct FactorImpl : FactorBase {
   std::vector<Level<T>> levels;
   DevBuf<double> ybuf, zbuf, xs;  // apply scratch
   DevBuf<double> sbuf;            // skeleton scratch (x_F̂, x_F̌, L_F̌^{-1} x_F̌)
+  int64_t ymax = 1, zmax = 1, kmax = 1, rmax = 1;  // scratch segment sizes
+  bool prepared = false;
+  // Sweep descriptors and scratch of the apply (idempotent).
+  void prepare(hipStream_t s);
   void apply(const double* f, double* u, hipStream_t s) override;
   int64_t stored_bytes() const override;
 };

@@ -305,9 +305,8 @@ void gemv_launch(bool trans, const GemvDesc* d, int batch, int maxm, int maxn, c
 }
 
 template <typename T>
-void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
-  if (u != f) HIF_HIP(hipMemcpyAsync(u, f, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-  int64_t ymax = 1, zmax = 1, kmax = 1, rmax = 1;
+void FactorImpl<T>::prepare(hipStream_t s) {
+  if (prepared) return;
   for (auto& l : levels) {
     ymax = std::max(ymax, l.ysum);
     zmax = std::max(zmax, l.zsum);
@@ -317,14 +316,6 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   if ((int64_t)ybuf.size() < 2 * ymax) ybuf.alloc(2 * ymax);
   if ((int64_t)zbuf.size() < 2 * zmax) zbuf.alloc(2 * zmax);
   if ((int64_t)sbuf.size() < kmax + 2 * rmax) sbuf.alloc(kmax + 2 * rmax);
-  double* xi = ybuf.get();
-  double* yv = ybuf.get() + ymax;
-  double* zv = zbuf.get();
-  double* xsv = zbuf.get() + zmax;
-  double* sh = sbuf.get();
-  double* sc = sbuf.get() + kmax;
-  double* sc2 = sc + rmax;
-  const int nlev = (int)levels.size();
   for (auto& lv : levels) {
     if (lv.gv_ready) continue;
     std::vector<GemvDesc> gl, gs, gt, gc, gy;
@@ -364,6 +355,21 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
     lv.gv_nS = (int)gs.size();
     lv.gv_ready = true;
   }
+  prepared = true;
+}
+
+template <typename T>
+void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
+  prepare(s);
+  if (u != f) HIF_HIP(hipMemcpyAsync(u, f, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  double* xi = ybuf.get();
+  double* yv = ybuf.get() + ymax;
+  double* zv = zbuf.get();
+  double* xsv = zbuf.get() + zmax;
+  double* sh = sbuf.get();
+  double* sc = sbuf.get() + kmax;
+  double* sc2 = sc + rmax;
+  const int nlev = (int)levels.size();
   // W^l^T for l = 0..L (level L: L_Sigma^{-1})
   for (int l = 0; l < nlev; ++l) {
     Level<T>& lv = levels[l];
@@ -453,6 +459,8 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   profiler().level = -1;
 }
 
+template void FactorImpl<double>::prepare(hipStream_t);
+template void FactorImpl<float>::prepare(hipStream_t);
 template void FactorImpl<double>::apply(const double*, double*, hipStream_t);
 template void FactorImpl<float>::apply(const double*, double*, hipStream_t);
 
