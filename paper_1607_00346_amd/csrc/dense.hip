@@ -195,6 +195,14 @@ __device__ __forceinline__ void xcd_remap(unsigned& bx, unsigned& by, unsigned& 
   bz = L / (gx * gy);
 }
 
+// Element at a 32-bit byte offset from a wave-uniform base: the base stays in
+// scalar registers and only the offset occupies a vector register, which keeps
+// a column-per-step loop from holding 64 vector addresses live.
+template <typename T>
+__device__ __forceinline__ T& at_bytes(T* base, uint32_t off) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+}
+
 template <typename TIn, typename TC, int OPA, int OPB, int TM, int TN, int CLS>
 __global__ __launch_bounds__(NTHR) void k_gemm_desc(int flags, const GemmDesc* __restrict__ desc,
                                                     TC alpha, TC beta) {
@@ -210,138 +218,171 @@ __global__ __launch_bounds__(NTHR) void k_gemm_desc(int flags, const GemmDesc* _
 }
 
 // Trailing update of the blocked front Cholesky at block column j0:
-// Phi[j1:nR, j1:nI] -= P[j1:nR] P[j1:nI]^T (lower part), P = Phi[:, j0:j1].
-// PT holds the panel transposed (kPanel x (nR - j1) per front, stride pstride)
-// so that the update is a plain NN product.
+// Phi[j1:nR, j1:nI] -= P[j1:nR] P[j1:nI]^T (lower part), P = Phi[:, j0:j1],
+// with the panel read in place as both operands.  Workgroup (0, 0) of each
+// front first copies the step's factored diagonal block from dblk into place
+// (it cannot be written by the step kernel, whose workgroups read the block
+// unfactored); launched with a (1, 1, batch) grid it does only that.
 template <typename T, int TS>
 __global__ __launch_bounds__(NTHR) void k_front_trailing(T* arena, const FrontDesc* __restrict__ fd,
-                                                         int j0, const T* __restrict__ PT,
-                                                         int64_t pstride) {
+                                                         int j0, const T* __restrict__ dblk) {
   __shared__ TileSmem<T, TS, TS> sm;
   unsigned bx, by, bz;
   xcd_remap(bx, by, bz);
   const FrontDesc f = fd[bz];
   if (j0 >= f.nI) return;
   const int nb = min(kPanel, f.nI - j0);
+  T* base = arena + f.off;
+  if (bx == 0 && by == 0) {
+    const T* D = dblk + (int64_t)bz * kPanel * kPanel;
+    for (int e = threadIdx.x; e < kPanel * kPanel; e += NTHR) {
+      const int c = e >> 6, r = e & 63;
+      if (r < nb && c < nb && c <= r) base[j0 + r + (int64_t)f.ld * (j0 + c)] = D[e];
+    }
+  }
   const int j1 = j0 + nb;
   const int m = f.nR - j1, n = f.nI - j1;
   const int m0 = by * TS, n0 = bx * TS;
   if (m0 >= m || n0 >= n) return;
   if (m0 + TS - 1 < n0) return;
-  T* base = arena + f.off;
   const T* P = base + j1 + (int64_t)f.ld * j0;
-  gemm_tile_t<T, T, OP_N, OP_N, TS, TS>(GF_C_LOWER, P, f.ld, PT + bz * pstride, kPanel,
+  gemm_tile_t<T, T, OP_N, OP_T, TS, TS>(GF_C_LOWER, P, f.ld, P, f.ld,
                                         base + j1 + (int64_t)f.ld * j1, f.ld, m, n, nb, m0, n0,
                                         T(-1), T(1), sm);
 }
 
-// Lower-triangular inverse of the 64 x 64 block held in LDS (D, rows >= nb
-// padded with the identity): lane c forms column c by forward substitution,
-// reading rows of L as LDS broadcasts; the column stays in registers.
+// One step of the blocked right-looking Cholesky at block column j0, fused.
+// Every workgroup factors the diagonal block L_jj itself (wave 0, lane = row;
+// the redundant work across workgroups costs less than a launch and a round
+// trip through memory), workgroup 0 stores it to dblk (64 x 64, column-major;
+// the trailing kernel puts it in place), then each thread solves one panel
+// row below the block, x L_jj^T = p, by forward substitution.  Both loops run
+// over the step t at run time on a register window that shifts by one column
+// per step (w[u] holds column t + u), so every register index is static; the
+// columns of L sit in LDS, padded with zeros up to 2 * 64 rows so that the
+// window may read past the block.
 template <typename T>
-__device__ __forceinline__ void inverse_column(const T (*D)[kPanel + 1], int lane, T (&x)[kPanel]) {
-#pragma unroll
-  for (int i = 0; i < kPanel; ++i) {
-    T s = i == lane ? T(1) : T(0);
-#pragma unroll
-    for (int t = 0; t < i; ++t) s -= D[i][t] * x[t];
-    x[i] = i < lane ? T(0) : s / D[i][i];
-  }
-}
-
-// Cholesky of the diagonal block Phi[j0:j1, j0:j1] and its inverse, by one
-// wave per front: lane = row, the row lives in registers, each column is
-// broadcast through LDS.  L_jj is written back in place; L_jj^{-1} goes to
-// dinv (64 x 64, column-major) for the panel.  Rows/columns past nb are
-// padded with the identity.
-template <typename T>
-__global__ __launch_bounds__(64) void k_front_diag(T* arena, const FrontDesc* __restrict__ fd,
-                                                   int j0, T* dinv, int* err) {
-  __shared__ T D[kPanel][kPanel + 1];
-  __shared__ T colv[kPanel];
-  const FrontDesc f = fd[blockIdx.x];
-  if (j0 >= f.nI) return;
-  const int nb = min(kPanel, f.nI - j0);
-  const int lane = threadIdx.x;
-  T* base = arena + f.off + j0 + (int64_t)f.ld * j0;
-  T a[kPanel];
-#pragma unroll
-  for (int t = 0; t < kPanel; ++t) {
-    T v = lane == t ? T(1) : T(0);
-    if (lane < nb && t < nb && t <= lane) v = base[lane + (int64_t)f.ld * t];
-    a[t] = v;
-  }
-  bool bad = false;
-#pragma unroll
-  for (int t = 0; t < kPanel; ++t) {
-    T d = __shfl(a[t], t);
-    if (!(d > T(0))) { bad = true; d = T(1); }
-    const T ltt = sqrt(d);
-    const T lit = lane > t ? a[t] / ltt : T(0);
-    a[t] = lane == t ? ltt : lit;
-    colv[lane] = lit;
-    __syncthreads();
-#pragma unroll
-    for (int j = t + 1; j < kPanel; ++j)
-      if (lane >= j) a[j] -= lit * colv[j];
-    __syncthreads();
-  }
-  if (bad && lane == 0) atomicMin(err, (int)blockIdx.x);
-#pragma unroll
-  for (int t = 0; t < kPanel; ++t) {
-    D[lane][t] = t <= lane ? a[t] : T(0);
-    if (lane < nb && t < nb && t <= lane) base[lane + (int64_t)f.ld * t] = a[t];
-  }
-  __syncthreads();
-  inverse_column<T>(D, lane, a);  // a <- column `lane` of L_jj^{-1}
-  T* dv = dinv + (int64_t)blockIdx.x * kPanel * kPanel + (int64_t)kPanel * lane;
-#pragma unroll
-  for (int i = 0; i < kPanel; ++i) dv[i] = (lane < nb && i < nb) ? a[i] : T(0);
-}
-
-// Panel rows below the diagonal block, in place:
-// Phi[j1:nR, j0:j1] <- Phi[j1:nR, j0:j1] L_jj^{-T}  (MFMA, each workgroup owns
-// its 64 rows, so reading and overwriting them in one tile is safe).
-template <typename T>
-__global__ __launch_bounds__(NTHR) void k_front_panel(T* arena, const FrontDesc* __restrict__ fd,
-                                                      int j0, const T* __restrict__ dinv) {
-  __shared__ TileSmem<T, BM, BN> sm;
-  const FrontDesc f = fd[blockIdx.z];
+__global__ __launch_bounds__(NTHR) void k_front_step(T* arena, const FrontDesc* __restrict__ fd,
+                                                     int j0, T* __restrict__ dblk, int* err) {
+  __shared__ T Lz[kPanel][2 * kPanel];  // Lz[t][v] = L_jj(v, t), zero for v >= nb
+  __shared__ T rd[kPanel];              // 1 / L_jj(t, t)
+  const FrontDesc f = fd[blockIdx.y];
   if (j0 >= f.nI) return;
   const int nb = min(kPanel, f.nI - j0);
   const int j1 = j0 + nb;
   const int m = f.nR - j1;
-  const int m0 = blockIdx.y * BM;
-  if (m0 >= m) return;
-  T* P = arena + f.off + j1 + (int64_t)f.ld * j0;
-  gemm_tile_t<T, T, OP_N, OP_T, BM, BN>(GF_B_UPPER, P, f.ld,
-                                        dinv + (int64_t)blockIdx.z * kPanel * kPanel, kPanel, P,
-                                        f.ld, m, nb, nb, m0, 0, T(1), T(0), sm);
+  const int r0 = blockIdx.x * NTHR;
+  if (blockIdx.x > 0 && r0 >= m) return;
+  T* col0 = arena + f.off + (int64_t)f.ld * j0;  // column j0 of the front
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kPanel * 2 * kPanel; e += NTHR) (&Lz[0][0])[e] = T(0);
+  __syncthreads();
+  if (tid < 64) {
+    // one wave: its LDS accesses complete in issue order, no barriers needed
+    const int lane = tid;
+    const int rl = min(lane, nb - 1);
+    T w[kPanel];
+#pragma unroll
+    for (int u = 0; u < kPanel; ++u) {
+      const T g = col0[(int64_t)f.ld * min(u, nb - 1) + j0 + rl];
+      w[u] = (lane < nb && u < nb && u <= lane) ? g : T(0);
+    }
+    bool bad = false;
+    for (int t = 0; t < nb; ++t) {
+      T d = __shfl(w[0], t);
+      bad = bad || !(d > T(0));
+      d = d > T(0) ? d : T(1);
+      const T ltt = sqrt(d);
+      const T lit = lane > t ? w[0] / ltt : (lane == t ? ltt : T(0));
+      Lz[t][lane] = lit;
+#pragma unroll
+      for (int u = 1; u < kPanel; ++u) w[u - 1] = w[u] - lit * Lz[t][t + u];
+      w[kPanel - 1] = T(0);
+    }
+    if (lane < nb) rd[lane] = T(1) / Lz[lane][lane];
+    if (blockIdx.x == 0) {
+      if (bad && lane == 0) atomicMin(err, (int)blockIdx.y);
+      T* D = dblk + (int64_t)blockIdx.y * kPanel * kPanel;
+      for (int e = lane; e < kPanel * kPanel; e += 64) D[e] = Lz[e >> 6][e & 63];
+    }
+  }
+  __syncthreads();
+  const int i = r0 + tid;
+  if (i < m) {
+    T* row = col0 + j1 + i;
+    T w[kPanel];
+#pragma unroll
+    for (int u = 0; u < kPanel; ++u) {
+      const T g = row[(int64_t)f.ld * min(u, nb - 1)];
+      w[u] = u < nb ? g : T(0);
+    }
+    // first half on the full window, then on its lower half
+    const int tm = min(nb, kPanel / 2);
+    for (int t = 0; t < tm; ++t) {
+      const T x = w[0] * rd[t];
+      row[(int64_t)f.ld * t] = x;
+#pragma unroll
+      for (int u = 1; u < kPanel; ++u) w[u - 1] = w[u] - Lz[t][t + u] * x;
+      w[kPanel - 1] = T(0);
+    }
+    for (int t = tm; t < nb; ++t) {
+      const T x = w[0] * rd[t];
+      row[(int64_t)f.ld * t] = x;
+#pragma unroll
+      for (int u = 1; u < kPanel / 2; ++u) w[u - 1] = w[u] - Lz[t][t + u] * x;
+      w[kPanel / 2 - 1] = T(0);
+    }
+  }
 }
 
-// In-place inverse of every 64 x 64 diagonal block of the factored L_I
-// (one wave per block).
+// In-place inverse of every 64 x 64 diagonal block of the factored L_I, one
+// wave per block: lane c forms column c of the inverse, right-looking (after
+// x_t is final it is eliminated from every later row at once, so the updates
+// of one step are independent), with the columns of L read as LDS
+// broadcasts.  Rows and columns past nb are padded with the identity.
 template <typename T>
 __global__ __launch_bounds__(64) void k_diag_inv(T* arena, const FrontDesc* __restrict__ fd) {
-  __shared__ T D[kPanel][kPanel + 1];
+  __shared__ T Lc[kPanel][kPanel];      // Lc[t][i] = L(i, t)
+  __shared__ T Xs[kPanel][kPanel + 1];  // Xs[c][i] = L^{-1}(i, c)
+  __shared__ T rd[kPanel];
   const FrontDesc f = fd[blockIdx.y];
   const int j0 = blockIdx.x * kPanel;
   if (j0 >= f.nI) return;
   const int nb = min(kPanel, f.nI - j0);
   const int lane = threadIdx.x;
   T* base = arena + f.off + j0 + (int64_t)f.ld * j0;
+  // one wave: its LDS accesses complete in issue order, no barriers needed
+#pragma unroll 4
+  for (int e = lane; e < kPanel * kPanel; e += 64) {
+    const int c = e >> 6, r = e & 63;
+    T v = r == c ? T(1) : T(0);
+    if (r < nb && c < nb && c <= r) v = base[(int64_t)f.ld * c + r];
+    Lc[c][r] = v;
+    if (r == c) rd[c] = T(1) / v;
+  }
+  T x[kPanel];
+#pragma unroll
+  for (int i = 0; i < kPanel; ++i) x[i] = T(0);
+  // x = e_lane: set through LDS so that no per-row lane mask is kept
+  Xs[lane][lane] = T(1);
+#pragma unroll
+  for (int i = 0; i < kPanel; ++i) Xs[lane][i] = i == lane ? T(1) : T(0);
+#pragma unroll
+  for (int i = 0; i < kPanel; ++i) x[i] = Xs[lane][i];
 #pragma unroll
   for (int t = 0; t < kPanel; ++t) {
-    T v = lane == t ? T(1) : T(0);
-    if (lane < nb && t < nb && t <= lane) v = base[lane + (int64_t)f.ld * t];
-    D[lane][t] = v;
-  }
-  __syncthreads();
-  T x[kPanel];
-  inverse_column<T>(D, lane, x);
+    x[t] *= rd[t];
 #pragma unroll
-  for (int i = 0; i < kPanel; ++i)
-    if (lane < nb && i < nb && i >= lane) base[i + (int64_t)f.ld * lane] = x[i];
+    for (int u = t + 1; u < kPanel; ++u) x[u] -= Lc[t][u] * x[t];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int i = 0; i < kPanel; ++i) Xs[lane][i] = x[i];
+#pragma unroll 4
+  for (int e = lane; e < kPanel * kPanel; e += 64) {
+    const int c = e >> 6, r = e & 63;
+    if (r < nb && c < nb && c <= r) base[(int64_t)f.ld * c + r] = Xs[c][r];
+  }
 }
 
 // One panel (up to kPivPanel pivots) of the diagonal-pivoted Cholesky of a
@@ -586,63 +627,39 @@ void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
   HIF_REQUIRE(batch <= 65535, HIF_EINVAL, "too many fronts in one launch");
   int maxI = 0;
   for (auto& f : h_fronts) maxI = std::max(maxI, f.nI);
-  DevBuf<T> dinv((size_t)batch * kPanel * kPanel);
-  int maxR = 0;
-  for (auto& f : h_fronts) maxR = std::max(maxR, f.nR);
-  const int64_t pstride = (int64_t)kPanel * std::max(maxR, 1);
-  DevBuf<T> PT((size_t)batch * pstride);
-  // transpose descriptors of every step, uploaded once
-  const int nsteps = (int)ceil_div(maxI, kPanel);
-  std::vector<TransDesc> td((size_t)nsteps * batch);
-  for (int st = 0; st < nsteps; ++st) {
-    const int j0 = st * kPanel;
-    for (int b = 0; b < batch; ++b) {
-      const FrontDesc& f = h_fronts[b];
-      const int nb = std::max(0, std::min(kPanel, f.nI - j0));
-      const int rows = f.nI > j0 ? f.nR - j0 - nb : 0;
-      td[(size_t)st * batch + b] = {arena + f.off + (j0 + nb) + (int64_t)f.ld * j0,
-                                    PT.get() + b * pstride, rows, nb, f.ld, kPanel};
-    }
-  }
-  DevBuf<TransDesc> d_td;
-  d_td.upload(td, s);
+  DevBuf<T> dblk((size_t)batch * kPanel * kPanel);
   for (int j0 = 0; j0 < maxI; j0 += kPanel) {
     int max_m = 0, max_n = 0;
-    double fl_panel = 0.0, fl_trail = 0.0;
+    double fl_step = 0.0, fl_trail = 0.0;
     for (auto& f : h_fronts) {
       if (f.nI <= j0) continue;
       const int nb = std::min(kPanel, f.nI - j0);
       const double m = f.nR - j0 - nb, n = f.nI - j0 - nb;
       max_m = std::max(max_m, (int)m);
       max_n = std::max(max_n, (int)n);
-      fl_panel += m * nb * (nb + 1.0);
+      fl_step += nb * (double)nb * nb / 3.0 + m * nb * (double)nb;
       fl_trail += 2.0 * nb * (n * m - n * (n - 1) / 2);
     }
     {
-      ProfScope ps("potrf_diag", s);
-      hipLaunchKernelGGL((k_front_diag<T>), dim3((unsigned)batch), dim3(64), 0, s, arena,
-                         d_fronts, j0, dinv.get(), err);
+      ProfScope ps("potrf_step", s, fl_step);
+      dim3 g((unsigned)std::max<int64_t>(1, ceil_div(max_m, NTHR)), (unsigned)batch);
+      hipLaunchKernelGGL((k_front_step<T>), g, dim3(NTHR), 0, s, arena, d_fronts, j0, dblk.get(),
+                         err);
       HIF_LAUNCH_CHECK();
     }
-    if (max_m > 0) {
-      ProfScope ps("potrf_panel", s, fl_panel);
-      dim3 gp(1, (unsigned)ceil_div(max_m, BM), (unsigned)batch);
-      hipLaunchKernelGGL((k_front_panel<T>), gp, dim3(NTHR), 0, s, arena, d_fronts, j0,
-                         (const T*)dinv.get());
-      HIF_LAUNCH_CHECK();
-    }
-    if (max_m > 0 && max_n > 0) {
-      transpose_batched<T>(d_td.get() + (size_t)(j0 / kPanel) * batch, batch, max_m, kPanel, s,
-                           "potrf_transpose");
+    {
+      // always launched: it also puts the factored diagonal blocks in place
       ProfScope ps("potrf_trailing", s, fl_trail);
+      const T* D = dblk.get();
       if (sizeof(T) == 4 && max_n >= 1024) {
         dim3 gt((unsigned)ceil_div(max_n, 128), (unsigned)ceil_div(max_m, 128), (unsigned)batch);
         hipLaunchKernelGGL((k_front_trailing<T, 128>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0,
-                           (const T*)PT.get(), pstride);
+                           D);
       } else {
-        dim3 gt((unsigned)ceil_div(max_n, 64), (unsigned)ceil_div(max_m, 64), (unsigned)batch);
+        dim3 gt((unsigned)std::max<int64_t>(1, ceil_div(max_n, 64)),
+                (unsigned)std::max<int64_t>(1, ceil_div(max_m, 64)), (unsigned)batch);
         hipLaunchKernelGGL((k_front_trailing<T, 64>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0,
-                           (const T*)PT.get(), pstride);
+                           D);
       }
       HIF_LAUNCH_CHECK();
     }
