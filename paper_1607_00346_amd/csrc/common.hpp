@@ -156,6 +156,26 @@ class DevBuf {
   size_t n_ = 0;
 };
 
+// Pointers that came out of memory (batch descriptors) are generic to the
+// compiler, which then emits flat accesses; flat loads also count against the
+// LDS wait counter, so waiting for LDS operands would wait for the prefetch
+// of the next chunk too.  These casts declare them global.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* as_global(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+// Element at a 32-bit byte offset from a wave-uniform global base: the base
+// stays in scalar registers, the offset in one vector register.
+template <typename T>
+__device__ __forceinline__ T load_global(const T* base, uint32_t off) {
+  return *(const __attribute__((address_space(1))) T*)((const char*)base + off);
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int pad_ld(int rows) { return rows < 1 ? 1 : (int)(ceil_div(rows, 4) * 4); }
 

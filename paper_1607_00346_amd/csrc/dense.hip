@@ -53,6 +53,9 @@ template <typename TIn, typename TC, int OPA, int OPB, int TM, int TN>
 __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, const TIn* __restrict__ B, int ldb,
                             TC* C, int ldc, int m, int n, int k, int m0, int n0, TC alpha, TC beta,
                             TileSmem<TC, TM, TN>& sm) {
+  const auto gA = as_global(A);
+  const auto gB = as_global(B);
+  const auto gC = as_global(C);
   constexpr int FM = TM / 32, FN = TN / 32;        // 16x16 blocks per wave
   constexpr int LA = TM * KC / NTHR, LB = TN * KC / NTHR;  // loads per thread
   const int tid = threadIdx.x;
@@ -65,7 +68,7 @@ __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, co
   if (flags & GF_B_LOWER) kb = max(kb, n0);
   if (flags & GF_B_UPPER) ke = min(ke, n0 + TN);
   const int nchunk = ke > kb ? (ke - kb + KC - 1) / KC : 0;
-  const bool inside = m0 + TM <= m && n0 + TN <= n && !(flags & (GF_A_LOWER | GF_A_UPPER | GF_B_LOWER | GF_B_UPPER));
+  const bool inside_mn = m0 + TM <= m && n0 + TN <= n;
 
   typename Mfma<TC>::acc_t acc[FM][FN];
 #pragma unroll
@@ -75,48 +78,76 @@ __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, co
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[x][y][v] = TC(0);
 
+  // Element coordinates of this thread's loads inside a chunk (fixed for the
+  // tile): along the operand's contiguous dimension, consecutive threads.
+  static_assert(NTHR % TM == 0 && NTHR % TN == 0 && NTHR % KC == 0, "load mapping");
+  int ai[LA], at[LA], bj[LB], bt[LB];
+#pragma unroll
+  for (int r = 0; r < LA; ++r) {
+    if (OPA == OP_N) { ai[r] = tid % TM; at[r] = tid / TM + (NTHR / TM) * r; }
+    else { at[r] = tid % KC; ai[r] = tid / KC + (NTHR / KC) * r; }
+  }
+#pragma unroll
+  for (int r = 0; r < LB; ++r) {
+    if (OPB == OP_N) { bt[r] = tid % KC; bj[r] = tid / KC + (NTHR / KC) * r; }
+    else { bj[r] = tid % TN; bt[r] = tid / TN + (NTHR / TN) * r; }
+  }
+  // Byte offsets of those elements from the chunk's corner: a chunk that needs
+  // no masking is then one load instruction per element off a uniform base.
+  uint32_t oa[LA], ob[LB];
+#pragma unroll
+  for (int r = 0; r < LA; ++r)
+    oa[r] = (uint32_t)((OPA == OP_N ? ai[r] + lda * at[r] : at[r] + lda * ai[r]) * sizeof(TIn));
+#pragma unroll
+  for (int r = 0; r < LB; ++r)
+    ob[r] = (uint32_t)((OPB == OP_N ? bt[r] + ldb * bj[r] : bj[r] + ldb * bt[r]) * sizeof(TIn));
+  auto clean = [&](int t0) {
+    bool c = inside_mn && t0 + KC <= ke;
+    if (flags & GF_A_LOWER) c = c && t0 + KC - 1 <= m0;
+    if (flags & GF_A_UPPER) c = c && t0 >= m0 + TM - 1;
+    if (flags & GF_B_LOWER) c = c && t0 >= n0 + TN - 1;
+    if (flags & GF_B_UPPER) c = c && t0 + KC - 1 <= n0;
+    return c;
+  };
+
   TC ra[LA], rb[LB];
   auto load = [&](int c) {
     const int t0 = kb + c * KC;
-    const bool kfull = t0 + KC <= ke;
+    if (clean(t0)) {
+      const TIn* ca = OPA == OP_N ? A + m0 + (int64_t)lda * t0 : A + t0 + (int64_t)lda * m0;
+      const TIn* cb = OPB == OP_N ? B + t0 + (int64_t)ldb * n0 : B + n0 + (int64_t)ldb * t0;
+#pragma unroll
+      for (int r = 0; r < LA; ++r) ra[r] = (TC)load_global(ca, oa[r]);
+#pragma unroll
+      for (int r = 0; r < LB; ++r) rb[r] = (TC)load_global(cb, ob[r]);
+      return;
+    }
 #pragma unroll
     for (int r = 0; r < LA; ++r) {
-      int i, t;
-      if (OPA == OP_N) { i = tid % TM; t = tid / TM + (NTHR / TM) * r; }
-      else { t = tid & 15; i = (tid >> 4) + 16 * r; }
-      const int gi = m0 + i, gt = t0 + t;
-      bool ok = (inside && kfull) || (gi < m && gt < ke);
+      const int gi = m0 + ai[r], gt = t0 + at[r];
+      bool ok = gi < m && gt < ke;
       if (flags & GF_A_LOWER) ok = ok && gt <= gi;
       if (flags & GF_A_UPPER) ok = ok && gt >= gi;
       TC v = TC(0);
-      if (ok) v = (TC)(OPA == OP_N ? A[gi + (int64_t)lda * gt] : A[gt + (int64_t)lda * gi]);
+      if (ok) v = (TC)(OPA == OP_N ? gA[gi + (int64_t)lda * gt] : gA[gt + (int64_t)lda * gi]);
       ra[r] = v;
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
-      int j, t;
-      if (OPB == OP_N) { t = tid & 15; j = (tid >> 4) + 16 * r; }
-      else { j = tid % TN; t = tid / TN + (NTHR / TN) * r; }
-      const int gj = n0 + j, gt = t0 + t;
-      bool ok = (inside && kfull) || (gj < n && gt < ke);
+      const int gj = n0 + bj[r], gt = t0 + bt[r];
+      bool ok = gj < n && gt < ke;
       if (flags & GF_B_LOWER) ok = ok && gt >= gj;
       if (flags & GF_B_UPPER) ok = ok && gt <= gj;
       TC v = TC(0);
-      if (ok) v = (TC)(OPB == OP_N ? B[gt + (int64_t)ldb * gj] : B[gj + (int64_t)ldb * gt]);
+      if (ok) v = (TC)(OPB == OP_N ? gB[gt + (int64_t)ldb * gj] : gB[gj + (int64_t)ldb * gt]);
       rb[r] = v;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < LA; ++r) {
-      if (OPA == OP_N) sm.As[buf][tid / TM + (NTHR / TM) * r][tid % TM] = ra[r];
-      else sm.As[buf][tid & 15][(tid >> 4) + 16 * r] = ra[r];
-    }
+    for (int r = 0; r < LA; ++r) sm.As[buf][at[r]][ai[r]] = ra[r];
 #pragma unroll
-    for (int r = 0; r < LB; ++r) {
-      if (OPB == OP_N) sm.Bs[buf][tid & 15][(tid >> 4) + 16 * r] = rb[r];
-      else sm.Bs[buf][tid / TN + (NTHR / TN) * r][tid % TN] = rb[r];
-    }
+    for (int r = 0; r < LB; ++r) sm.Bs[buf][bt[r]][bj[r]] = rb[r];
   };
   auto compute = [&](int buf) {
 #pragma unroll
@@ -173,8 +204,8 @@ __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, co
         if (gi < m && gj < n && (!(flags & GF_C_LOWER) || gi >= gj)) {
           const int64_t idx = gi + (int64_t)ldc * gj;
           TC val = alpha * acc[x][y][v];
-          if (beta != TC(0)) val += beta * C[idx];
-          C[idx] = val;
+          if (beta != TC(0)) val += beta * gC[idx];
+          gC[idx] = val;
         }
       }
 }
@@ -193,14 +224,6 @@ __device__ __forceinline__ void xcd_remap(unsigned& bx, unsigned& by, unsigned& 
   bx = L % gx;
   by = (L / gx) % gy;
   bz = L / (gx * gy);
-}
-
-// Element at a 32-bit byte offset from a wave-uniform base: the base stays in
-// scalar registers and only the offset occupies a vector register, which keeps
-// a column-per-step loop from holding 64 vector addresses live.
-template <typename T>
-__device__ __forceinline__ T& at_bytes(T* base, uint32_t off) {
-  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
 }
 
 template <typename TIn, typename TC, int OPA, int OPB, int TM, int TN, int CLS>
@@ -497,8 +520,8 @@ __global__ __launch_bounds__(NTHR) void k_transpose(const TransDesc* __restrict_
   const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
   if (r0 >= d.rows || c0 >= d.cols) return;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const T* src = (const T*)d.src;
-  T* dst = (T*)d.dst;
+  const auto src = as_global((const T*)d.src);
+  const auto dst = as_global((T*)d.dst);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int r = r0 + tx, c = c0 + ty + 8 * k;

@@ -126,8 +126,8 @@ __global__ __launch_bounds__(NT) void k_gemv_n(const GemvDesc* __restrict__ dd,
   const int i = r0 + lane;
   const bool row_ok = i < d.m;
   const int tend = d.tri ? min(d.n, r0 + 64) : d.n;
-  const T* A = (const T*)d.A + (row_ok ? i : 0);
-  const double* xv = x + d.coff;
+  const auto A = as_global((const T*)d.A + (row_ok ? i : 0));
+  const auto xv = as_global(x + d.coff);
   double s0 = 0.0, s1 = 0.0;
   for (int t0 = wave * 8; t0 < tend; t0 += 32) {
     if (t0 + 8 <= tend && (!d.tri || t0 + 8 <= r0)) {
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(NT) void k_gemv_n(const GemvDesc* __restrict__ dd,
   __syncthreads();
   if (wave == 0 && row_ok) {
     const double v = alpha * (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
-    double* yo = y + d.roff + i;
+    const auto yo = as_global(y + d.roff + i);
     *yo = accumulate ? *yo + v : v;
   }
 }
@@ -162,8 +162,8 @@ __global__ __launch_bounds__(NT) void k_gemv_t(const GemvDesc* __restrict__ dd,
   const int j = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
   if (j >= d.n) return;
   const int lane = threadIdx.x & 63;
-  const T* col = (const T*)d.A + (int64_t)d.lda * j;
-  const double* xv = x + d.roff;
+  const auto col = as_global((const T*)d.A + (int64_t)d.lda * j);
+  const auto xv = as_global(x + d.roff);
   double s0 = 0.0, s1 = 0.0;
   int i = (d.tri ? j : 0) + lane;
   for (; i + 64 < d.m; i += 128) {
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(NT) void k_gemv_t(const GemvDesc* __restrict__ dd,
   if (i < d.m) s0 += (double)col[i] * xv[i];
   const double v = alpha * wave_sum(s0 + s1);
   if (lane == 0) {
-    double* yo = y + d.coff + j;
+    const auto yo = as_global(y + d.coff + j);
     *yo = accumulate ? *yo + v : v;
   }
 }
