@@ -68,7 +68,6 @@ __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, co
   if (flags & GF_B_LOWER) kb = max(kb, n0);
   if (flags & GF_B_UPPER) ke = min(ke, n0 + TN);
   const int nchunk = ke > kb ? (ke - kb + KC - 1) / KC : 0;
-  const bool inside_mn = m0 + TM <= m && n0 + TN <= n;
 
   typename Mfma<TC>::acc_t acc[FM][FN];
 #pragma unroll
@@ -94,15 +93,21 @@ __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, co
   }
   // Byte offsets of those elements from the chunk's corner: a chunk that needs
   // no masking is then one load instruction per element off a uniform base.
+  // Rows past m (columns past n) are clamped onto the last one: they only
+  // feed entries of C that are never written.
   uint32_t oa[LA], ob[LB];
 #pragma unroll
-  for (int r = 0; r < LA; ++r)
-    oa[r] = (uint32_t)((OPA == OP_N ? ai[r] + lda * at[r] : at[r] + lda * ai[r]) * sizeof(TIn));
+  for (int r = 0; r < LA; ++r) {
+    const int i = min(ai[r], m - 1 - m0);
+    oa[r] = (uint32_t)((OPA == OP_N ? i + lda * at[r] : at[r] + lda * i) * sizeof(TIn));
+  }
 #pragma unroll
-  for (int r = 0; r < LB; ++r)
-    ob[r] = (uint32_t)((OPB == OP_N ? bt[r] + ldb * bj[r] : bj[r] + ldb * bt[r]) * sizeof(TIn));
+  for (int r = 0; r < LB; ++r) {
+    const int j = min(bj[r], n - 1 - n0);
+    ob[r] = (uint32_t)((OPB == OP_N ? bt[r] + ldb * j : j + ldb * bt[r]) * sizeof(TIn));
+  }
   auto clean = [&](int t0) {
-    bool c = inside_mn && t0 + KC <= ke;
+    bool c = t0 + KC <= ke;
     if (flags & GF_A_LOWER) c = c && t0 + KC - 1 <= m0;
     if (flags & GF_A_UPPER) c = c && t0 >= m0 + TM - 1;
     if (flags & GF_B_LOWER) c = c && t0 >= n0 + TN - 1;
@@ -274,21 +279,67 @@ __global__ __launch_bounds__(NTHR) void k_front_trailing(T* arena, const FrontDe
                                         T(-1), T(1), sm);
 }
 
+// Forward substitution of one row against a factored block, steps [tb, te):
+// w[u] holds column t + u of the row (a window of W columns that shifts by one
+// per step, so every register index is static), Lsh[t][u] = L(t + u, t).
+// Each step's column of L is read from LDS one step ahead, into two register
+// buffers used in turn, so its latency hides behind the previous step.
+template <typename T, int W>
+__device__ __forceinline__ void window_solve(T (&w)[kPanel], const T (*Lsh)[kPanel],
+                                             const T* rd, T* row, int64_t ld, int tb, int te) {
+  T la[W], lb[W];
+  auto fetch = [&](T (&d)[W], int t) {
+#pragma unroll
+    for (int u = 0; u < W; ++u) d[u] = Lsh[t][u];
+  };
+  auto step = [&](const T (&l)[W], int t) {
+    const T x = w[0] * rd[t];
+    row[ld * t] = x;
+#pragma unroll
+    for (int u = 1; u < W; ++u) w[u - 1] = w[u] - l[u] * x;
+    w[W - 1] = T(0);
+  };
+  if (tb >= te) return;
+  fetch(la, tb);
+  for (int t = tb; t < te; t += 2) {
+    if (t + 1 < te) fetch(lb, t + 1);
+    step(la, t);
+    if (t + 1 >= te) break;
+    if (t + 2 < te) fetch(la, t + 2);
+    step(lb, t + 1);
+  }
+}
+
+// Value of v in lane l of the wave (l uniform).
+template <typename T>
+__device__ __forceinline__ T read_lane(T v, int l) {
+  if constexpr (sizeof(T) == 4) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+  } else {
+    const long long x = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(x & 0xffffffffll), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(x >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  }
+}
+
 // One step of the blocked right-looking Cholesky at block column j0, fused.
-// Every workgroup factors the diagonal block L_jj itself (wave 0, lane = row;
-// the redundant work across workgroups costs less than a launch and a round
-// trip through memory), workgroup 0 stores it to dblk (64 x 64, column-major;
-// the trailing kernel puts it in place), then each thread solves one panel
-// row below the block, x L_jj^T = p, by forward substitution.  Both loops run
-// over the step t at run time on a register window that shifts by one column
-// per step (w[u] holds column t + u), so every register index is static; the
-// columns of L sit in LDS, padded with zeros up to 2 * 64 rows so that the
-// window may read past the block.
+// Every workgroup factors the diagonal block L_jj itself (the redundant work
+// across workgroups costs less than a launch and a round trip through memory)
+// and workgroup 0 stores it to dblk (64 x 64, column-major; the trailing
+// kernel puts it in place).  The four waves share the factorization: lane =
+// row, wave q holds columns 16q .. 16q + 15; at step t the wave owning column
+// t forms L(:, t) and publishes it through LDS, then every wave updates its
+// later columns.  Then each thread solves one panel row below the block,
+// x L_jj^T = p, by forward substitution on a shifting register window, with
+// the columns of L in LDS shifted to start at their diagonal,
+// Lsh[t][u] = L_jj(t + u, t), zero past the block.
 template <typename T>
 __global__ __launch_bounds__(NTHR) void k_front_step(T* arena, const FrontDesc* __restrict__ fd,
                                                      int j0, T* __restrict__ dblk, int* err) {
-  __shared__ T Lz[kPanel][2 * kPanel];  // Lz[t][v] = L_jj(v, t), zero for v >= nb
-  __shared__ T rd[kPanel];              // 1 / L_jj(t, t)
+  __shared__ __align__(16) T Lcol[kPanel][kPanel];  // Lcol[t][i] = L_jj(i, t)
+  __shared__ __align__(16) T Lsh[kPanel][kPanel];
+  __shared__ T rd[kPanel];  // 1 / L_jj(t, t)
   const FrontDesc f = fd[blockIdx.y];
   if (j0 >= f.nI) return;
   const int nb = min(kPanel, f.nI - j0);
@@ -298,35 +349,67 @@ __global__ __launch_bounds__(NTHR) void k_front_step(T* arena, const FrontDesc* 
   if (blockIdx.x > 0 && r0 >= m) return;
   T* col0 = arena + f.off + (int64_t)f.ld * j0;  // column j0 of the front
   const int tid = threadIdx.x;
-  for (int e = tid; e < kPanel * 2 * kPanel; e += NTHR) (&Lz[0][0])[e] = T(0);
-  __syncthreads();
-  if (tid < 64) {
-    // one wave: its LDS accesses complete in issue order, no barriers needed
-    const int lane = tid;
+  for (int e = tid; e < kPanel * kPanel; e += NTHR) (&Lsh[0][0])[e] = T(0);
+  {
+    const int lane = tid & 63;
+    const int q = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
     const int rl = min(lane, nb - 1);
-    T w[kPanel];
+    T w[16];
 #pragma unroll
-    for (int u = 0; u < kPanel; ++u) {
-      const T g = col0[(int64_t)f.ld * min(u, nb - 1) + j0 + rl];
-      w[u] = (lane < nb && u < nb && u <= lane) ? g : T(0);
+    for (int v = 0; v < 16; ++v) {
+      const int c = 16 * q + v;
+      const T g = col0[(int64_t)f.ld * min(c, nb - 1) + j0 + rl];
+      w[v] = (lane < nb && c < nb && c <= lane) ? g : T(0);
     }
+    __syncthreads();
     bool bad = false;
-    for (int t = 0; t < nb; ++t) {
-      T d = __shfl(w[0], t);
-      bad = bad || !(d > T(0));
-      d = d > T(0) ? d : T(1);
-      const T ltt = sqrt(d);
-      const T lit = lane > t ? w[0] / ltt : (lane == t ? ltt : T(0));
-      Lz[t][lane] = lit;
+    for (int qt = 0; 16 * qt < nb; ++qt) {
 #pragma unroll
-      for (int u = 1; u < kPanel; ++u) w[u - 1] = w[u] - lit * Lz[t][t + u];
-      w[kPanel - 1] = T(0);
+      for (int v = 0; v < 16; ++v) {
+        const int t = 16 * qt + v;
+        if (t < nb) {  // uniform; a break here would keep the loop rolled
+          if (q == qt) {
+            T d = read_lane(w[v], t);
+            bad = bad || !(d > T(0));
+            d = d > T(0) ? d : T(1);
+            T ltt, r;
+            if constexpr (sizeof(T) == 4) {
+              r = __builtin_amdgcn_rsqf(d);  // 1 ulp; shortens the serial chain
+              ltt = d * r;
+            } else {
+              ltt = sqrt(d);
+              r = T(1) / ltt;
+            }
+            const T lit = lane > t ? w[v] * r : (lane == t ? ltt : T(0));
+            w[v] = lit;
+            Lcol[t][lane] = lit;
+            if (lane >= t) Lsh[t][lane - t] = lit;
+          }
+          __syncthreads();
+          if (q >= qt) {
+            const T li = Lcol[t][lane];
+            T lc[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) lc[u] = Lcol[t][16 * q + u];
+            if (q > qt) {
+#pragma unroll
+              for (int u = 0; u < 16; ++u) w[u] -= li * lc[u];
+            } else {
+#pragma unroll
+              for (int u = v + 1; u < 16; ++u) w[u] -= li * lc[u];
+            }
+          }
+        }
+      }
     }
-    if (lane < nb) rd[lane] = T(1) / Lz[lane][lane];
-    if (blockIdx.x == 0) {
-      if (bad && lane == 0) atomicMin(err, (int)blockIdx.y);
-      T* D = dblk + (int64_t)blockIdx.y * kPanel * kPanel;
-      for (int e = lane; e < kPanel * kPanel; e += 64) D[e] = Lz[e >> 6][e & 63];
+    if (blockIdx.x == 0 && bad && lane == 0) atomicMin(err, (int)blockIdx.y);
+  }
+  if (tid < nb) rd[tid] = T(1) / Lcol[tid][tid];
+  if (blockIdx.x == 0) {
+    T* D = dblk + (int64_t)blockIdx.y * kPanel * kPanel;
+    for (int e = tid; e < kPanel * kPanel; e += NTHR) {
+      const int c = e >> 6, r = e & 63;
+      D[e] = (r >= c && c < nb) ? Lcol[c][r] : T(0);
     }
   }
   __syncthreads();
@@ -341,20 +424,8 @@ __global__ __launch_bounds__(NTHR) void k_front_step(T* arena, const FrontDesc* 
     }
     // first half on the full window, then on its lower half
     const int tm = min(nb, kPanel / 2);
-    for (int t = 0; t < tm; ++t) {
-      const T x = w[0] * rd[t];
-      row[(int64_t)f.ld * t] = x;
-#pragma unroll
-      for (int u = 1; u < kPanel; ++u) w[u - 1] = w[u] - Lz[t][t + u] * x;
-      w[kPanel - 1] = T(0);
-    }
-    for (int t = tm; t < nb; ++t) {
-      const T x = w[0] * rd[t];
-      row[(int64_t)f.ld * t] = x;
-#pragma unroll
-      for (int u = 1; u < kPanel / 2; ++u) w[u - 1] = w[u] - Lz[t][t + u] * x;
-      w[kPanel / 2 - 1] = T(0);
-    }
+    window_solve<T, kPanel>(w, Lsh, rd, row, f.ld, 0, tm);
+    window_solve<T, kPanel / 2>(w, Lsh, rd, row, f.ld, tm, nb);
   }
 }
 
