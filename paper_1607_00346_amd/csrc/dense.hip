@@ -245,37 +245,38 @@ __global__ __launch_bounds__(NTHR) void k_gemm_desc(int flags, const GemmDesc* _
                                          (TC*)d.C, d.ldc, d.m, d.n, d.k, m0, n0, alpha, beta, sm);
 }
 
-// Trailing update of the blocked front Cholesky at block column j0:
-// Phi[j1:nR, j1:nI] -= P[j1:nR] P[j1:nI]^T (lower part), P = Phi[:, j0:j1],
-// with the panel read in place as both operands.  Workgroup (0, 0) of each
-// front first copies the step's factored diagonal block from dblk into place
-// (it cannot be written by the step kernel, whose workgroups read the block
+// Trailing update of the blocked front Cholesky with the factored panel
+// columns [p0, p0 + pw): Phi[c0:nR, c0:c0 + cw] -= P[c0:nR] P[c0:c0 + cw]^T
+// (lower part), P = Phi[:, p0:p0 + pw], all ranges clipped to the front, with
+// the panel read in place as both operands.  If j0 >= 0, workgroup (0, 0) of
+// each front first copies the step's factored diagonal block from dblk into
+// place (the step kernel cannot write it: its workgroups read the block
 // unfactored); launched with a (1, 1, batch) grid it does only that.
 template <typename T, int TS>
 __global__ __launch_bounds__(NTHR) void k_front_trailing(T* arena, const FrontDesc* __restrict__ fd,
-                                                         int j0, const T* __restrict__ dblk) {
+                                                         int j0, int p0, int pw, int c0, int cw,
+                                                         const T* __restrict__ dblk) {
   __shared__ TileSmem<T, TS, TS> sm;
   unsigned bx, by, bz;
   xcd_remap(bx, by, bz);
   const FrontDesc f = fd[bz];
-  if (j0 >= f.nI) return;
-  const int nb = min(kPanel, f.nI - j0);
   T* base = arena + f.off;
-  if (bx == 0 && by == 0) {
+  if (j0 >= 0 && j0 < f.nI && bx == 0 && by == 0) {
+    const int nb = min(kPanel, f.nI - j0);
     const T* D = dblk + (int64_t)bz * kPanel * kPanel;
     for (int e = threadIdx.x; e < kPanel * kPanel; e += NTHR) {
       const int c = e >> 6, r = e & 63;
       if (r < nb && c < nb && c <= r) base[j0 + r + (int64_t)f.ld * (j0 + c)] = D[e];
     }
   }
-  const int j1 = j0 + nb;
-  const int m = f.nR - j1, n = f.nI - j1;
+  const int k = min(p0 + pw, f.nI) - p0;
+  const int m = f.nR - c0, n = min(c0 + cw, f.nI) - c0;
   const int m0 = by * TS, n0 = bx * TS;
-  if (m0 >= m || n0 >= n) return;
+  if (k <= 0 || m0 >= m || n0 >= n) return;
   if (m0 + TS - 1 < n0) return;
-  const T* P = base + j1 + (int64_t)f.ld * j0;
+  const T* P = base + c0 + (int64_t)f.ld * p0;
   gemm_tile_t<T, T, OP_N, OP_T, TS, TS>(GF_C_LOWER, P, f.ld, P, f.ld,
-                                        base + j1 + (int64_t)f.ld * j1, f.ld, m, n, nb, m0, n0,
+                                        base + c0 + (int64_t)f.ld * c0, f.ld, m, n, k, m0, n0,
                                         T(-1), T(1), sm);
 }
 
@@ -722,41 +723,62 @@ void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
   int maxI = 0;
   for (auto& f : h_fronts) maxI = std::max(maxI, f.nI);
   DevBuf<T> dblk((size_t)batch * kPanel * kPanel);
-  for (int j0 = 0; j0 < maxI; j0 += kPanel) {
+  // Trailing update of panel columns [p0, p0 + pw) into [c0, c0 + cw) (j0 >= 0:
+  // also put step j0's diagonal blocks in place).
+  auto trailing = [&](int j0, int p0, int pw, int c0, int cw) {
     int max_m = 0, max_n = 0;
-    double fl_step = 0.0, fl_trail = 0.0;
+    double fl = 0.0;
     for (auto& f : h_fronts) {
-      if (f.nI <= j0) continue;
-      const int nb = std::min(kPanel, f.nI - j0);
-      const double m = f.nR - j0 - nb, n = f.nI - j0 - nb;
-      max_m = std::max(max_m, (int)m);
-      max_n = std::max(max_n, (int)n);
-      fl_step += nb * (double)nb * nb / 3.0 + m * nb * (double)nb;
-      fl_trail += 2.0 * nb * (n * m - n * (n - 1) / 2);
+      const double k = std::min(p0 + pw, f.nI) - p0;
+      const int m = f.nR - c0, n = std::min(c0 + cw, f.nI) - c0;
+      if (k <= 0 || m <= 0 || n <= 0) continue;
+      max_m = std::max(max_m, m);
+      max_n = std::max(max_n, n);
+      fl += 2.0 * k * ((double)n * m - (double)n * (n - 1) / 2);
     }
-    {
-      ProfScope ps("potrf_step", s, fl_step);
-      dim3 g((unsigned)std::max<int64_t>(1, ceil_div(max_m, NTHR)), (unsigned)batch);
-      hipLaunchKernelGGL((k_front_step<T>), g, dim3(NTHR), 0, s, arena, d_fronts, j0, dblk.get(),
-                         err);
-      HIF_LAUNCH_CHECK();
+    if (j0 < 0 && max_n == 0) return;
+    ProfScope ps("potrf_trailing", s, fl);
+    const T* D = dblk.get();
+    if (sizeof(T) == 4 && max_n >= 1024) {
+      dim3 gt((unsigned)ceil_div(max_n, 128), (unsigned)ceil_div(max_m, 128), (unsigned)batch);
+      hipLaunchKernelGGL((k_front_trailing<T, 128>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0,
+                         p0, pw, c0, cw, D);
+    } else {
+      dim3 gt((unsigned)std::max<int64_t>(1, ceil_div(max_n, 64)),
+              (unsigned)std::max<int64_t>(1, ceil_div(max_m, 64)), (unsigned)batch);
+      hipLaunchKernelGGL((k_front_trailing<T, 64>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0,
+                         p0, pw, c0, cw, D);
     }
-    {
-      // always launched: it also puts the factored diagonal blocks in place
-      ProfScope ps("potrf_trailing", s, fl_trail);
-      const T* D = dblk.get();
-      if (sizeof(T) == 4 && max_n >= 1024) {
-        dim3 gt((unsigned)ceil_div(max_n, 128), (unsigned)ceil_div(max_m, 128), (unsigned)batch);
-        hipLaunchKernelGGL((k_front_trailing<T, 128>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0,
-                           D);
-      } else {
-        dim3 gt((unsigned)std::max<int64_t>(1, ceil_div(max_n, 64)),
-                (unsigned)std::max<int64_t>(1, ceil_div(max_m, 64)), (unsigned)batch);
-        hipLaunchKernelGGL((k_front_trailing<T, 64>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0,
-                           D);
+    HIF_LAUNCH_CHECK();
+  };
+  // Super-panels of kSuper columns: inside one, each step updates only the
+  // columns up to the super-panel's end; the rest of the trailing matrix is
+  // updated once per super-panel with all of its columns (rank kSuper), which
+  // reads and writes the trailing matrix kSuper / kPanel times less often.
+  constexpr int kSuper = 4 * kPanel;
+  for (int J = 0; J < maxI; J += kSuper) {
+    const int Je = std::min(J + kSuper, maxI);
+    for (int j0 = J; j0 < Je; j0 += kPanel) {
+      int max_m = 0;
+      double fl_step = 0.0;
+      for (auto& f : h_fronts) {
+        if (f.nI <= j0) continue;
+        const int nb = std::min(kPanel, f.nI - j0);
+        const double m = f.nR - j0 - nb;
+        max_m = std::max(max_m, (int)m);
+        fl_step += nb * (double)nb * nb / 3.0 + m * nb * (double)nb;
       }
-      HIF_LAUNCH_CHECK();
+      {
+        ProfScope ps("potrf_step", s, fl_step);
+        dim3 g((unsigned)std::max<int64_t>(1, ceil_div(max_m, NTHR)), (unsigned)batch);
+        hipLaunchKernelGGL((k_front_step<T>), g, dim3(NTHR), 0, s, arena, d_fronts, j0,
+                           dblk.get(), err);
+        HIF_LAUNCH_CHECK();
+      }
+      // always launched: it also puts the factored diagonal blocks in place
+      trailing(j0, j0, kPanel, j0 + kPanel, J + kSuper - (j0 + kPanel));
     }
+    if (J + kSuper < maxI) trailing(-1, J, kSuper, J + kSuper, maxI);
   }
   front_invert<T>(arena, d_fronts, h_fronts, s);
 }
