@@ -178,10 +178,16 @@ hif_status hif_factor_ranks(hif_factor_t F, int32_t level, int32_t* ranks, int32
 hif_status hif_factor_active(hif_factor_t F, int32_t level, uint8_t* mask) {
   return guarded([&] {
     HIF_REQUIRE(F != nullptr && mask != nullptr, HIF_EINVAL, "NULL argument");
-    HIF_REQUIRE(level >= 0 && level < (int)F->active_after.size(), HIF_EINVAL,
+    HIF_REQUIRE(F->impl, HIF_EINVAL, "NULL factor");
+    HIF_REQUIRE(level >= 0 && level < (int)F->redundant_pts.size(), HIF_EINVAL,
                 "level out of range");
-    const auto& a = F->active_after[level];
-    std::memcpy(mask, a.data(), a.size());
+    std::memset(mask, 1, (size_t)F->stats.n_dof);
+    for (int l = 0; l <= level; ++l) {
+      const hif::LevelPlan& P = F->impl->level_plan(l);
+      for (int c = 0; c < P.ncell; ++c)
+        for (int64_t t = P.crow_off[c]; t < P.crow_off[c] + P.cI[c]; ++t) mask[P.rows[t]] = 0;
+      for (int p : F->redundant_pts[l]) mask[p] = 0;
+    }
   });
 }
 

@@ -347,8 +347,12 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
 
   if (A->geom_leaf != leaf) {
     A->geom = plan_geometry(n, leaf);
+    A->plan0 = std::make_shared<const LevelPlan>(
+        plan_level(A->geom[0], std::vector<uint8_t>((size_t)N, 1)));
     A->geom_leaf = leaf;
   }
+  // 0 for points the ID has left out so far (the candidates of a level are
+  // separator points of the level below, so interior points never need it)
   std::vector<uint8_t> active(N, 1);
   // face / local index of every level-(l-1) face point, for the A^l lookup
   DevBuf<int> d_pface(L > 0 ? N : 0), d_ploc(L > 0 ? N : 0);
@@ -387,8 +391,9 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
     profiler().level = level;
     Level<T>& lev = Fi.levels[level];
     Level<T>* prev = level > 0 ? &Fi.levels[level - 1] : nullptr;
-    lev.P = plan_level(A->geom[level], active);
-    const LevelPlan& P = lev.P;
+    lev.plan = level == 0 ? A->plan0
+                          : std::make_shared<const LevelPlan>(plan_level(A->geom[level], active));
+    const LevelPlan& P = *lev.plan;
     const Src<T> src = make_src<T>(A, prev, d_pface.get(), d_ploc.get());
 
     // ---- fronts: gather, partial Cholesky + inverse (Section 2.2) -------
@@ -759,13 +764,17 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
           HIF_LAUNCH_CHECK();
         }
       }
-      for (int c = 0; c < P.ncell; ++c)
-        for (int64_t t = P.crow_off[c]; t < P.crow_off[c] + P.cI[c]; ++t) active[P.rows[t]] = 0;
+      std::vector<int> red;
+      red.reserve(lev.redundant);
       for (int f = 0; f < P.nface; ++f) {
         const int64_t o0 = P.fpt_off[f];
-        for (int j = lev.hk[f]; j < P.fN[f]; ++j) active[P.fpts[o0 + hperm[o0 + j]]] = 0;
+        for (int j = lev.hk[f]; j < P.fN[f]; ++j) {
+          const int p = P.fpts[o0 + hperm[o0 + j]];
+          active[p] = 0;
+          red.push_back(p);
+        }
       }
-      F->active_after.push_back(active);
+      F->redundant_pts.push_back(std::move(red));
       F->ranks.push_back(lev.hk);
       F->sizes.push_back(P.fN);
     } else {

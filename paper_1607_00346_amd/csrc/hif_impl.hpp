@@ -43,7 +43,7 @@ struct GemvDesc {
 
 template <typename T>
 struct Level {
-  LevelPlan P;
+  std::shared_ptr<const LevelPlan> plan;  // shared: the level-0 plan is cached per problem
   // cells
   DevBuf<int> rows;
   DevBuf<int64_t> crow_off;
@@ -82,6 +82,7 @@ struct FactorBase {
   virtual ~FactorBase() = default;
   virtual void apply(const double* f, double* u, hipStream_t s) = 0;
   virtual int64_t stored_bytes() const = 0;
+  virtual const LevelPlan& level_plan(int level) const = 0;
 };
 
 template <typename T>
@@ -97,6 +98,7 @@ struct FactorImpl : FactorBase {
   void prepare(hipStream_t s);
   void apply(const double* f, double* u, hipStream_t s) override;
   int64_t stored_bytes() const override;
+  const LevelPlan& level_plan(int level) const override { return *levels[level].plan; }
 };
 
 }  // namespace hif
@@ -109,6 +111,7 @@ struct hif_problem_s {
   // cell/face geometry of every level, computed on the first build with a leaf
   mutable int geom_leaf = -1;
   mutable std::vector<hif::LevelGeom> geom;
+  mutable std::shared_ptr<const hif::LevelPlan> plan0;  // level 0: every point active
   hif::Stencil stencil() const { return {n, diag.get(), cx.get(), cy.get(), cz.get()}; }
 };
 
@@ -116,8 +119,8 @@ struct hif_factor_s {
   hif_options opts;
   std::unique_ptr<hif::FactorBase> impl;
   hif_stats stats;
-  std::vector<std::vector<uint8_t>> active_after;  // per level l < L
-  std::vector<std::vector<int>> ranks, sizes;      // per level l < L
+  std::vector<std::vector<int>> redundant_pts;  // per level l < L: points left out by the ID
+  std::vector<std::vector<int>> ranks, sizes;  // per level l < L
 };
 
 namespace hif {

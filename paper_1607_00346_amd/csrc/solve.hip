@@ -323,15 +323,15 @@ void FactorImpl<T>::prepare(hipStream_t s) {
       lv.bytes_L += sizeof(T) * 0.5 * d.nI * (d.nI + 1.0) + 24.0 * d.nI;
       lv.bytes_S += sizeof(T) * (double)(d.nR - d.nI) * d.nI + 16.0 * (d.nR - d.nI) + 8.0 * d.nI;
     }
-    std::vector<int64_t> yoff(lv.P.ncell), zoff(lv.P.ncell);
+    std::vector<int64_t> yoff(lv.plan->ncell), zoff(lv.plan->ncell);
     int64_t ya = 0, za = 0;
-    for (int c = 0; c < lv.P.ncell; ++c) {
+    for (int c = 0; c < lv.plan->ncell; ++c) {
       yoff[c] = ya;
       zoff[c] = za;
       ya += lv.hfd[c].nI;
       za += lv.hfd[c].nR - lv.hfd[c].nI;
     }
-    for (int c = 0; c < lv.P.ncell; ++c) {
+    for (int c = 0; c < lv.plan->ncell; ++c) {
       const FrontDesc& d = lv.hfd[c];
       const T* base = lv.front.get() + d.off;
       gl.push_back({base, d.nI, d.nI, d.ld, 1, yoff[c], yoff[c]});
@@ -374,7 +374,7 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   for (int l = 0; l < nlev; ++l) {
     Level<T>& lv = levels[l];
     profiler().level = l;
-    const int nc = lv.P.ncell;
+    const int nc = lv.plan->ncell;
     if (nc > 0) {
       dim3 gI((unsigned)ceil_div(std::max(1, lv.maxI), NT), (unsigned)nc);
       {
@@ -394,10 +394,10 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
       }
       HIF_LAUNCH_CHECK();
     }
-    if (!lv.P.root && lv.P.nface > 0) {
+    if (!lv.plan->root && lv.plan->nface > 0) {
       {
         ProfScope ps("apply_scatter", s);
-        dim3 gF((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)lv.P.nface);
+        dim3 gF((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)lv.plan->nface);
         hipLaunchKernelGGL(k_face_sub, gF, dim3(NT), 0, s, u, lv.fpts.get(), lv.fpt_off.get(),
                            lv.fN.get(), lv.fcellA.get(), lv.fcellB.get(), lv.rb_sa.get(),
                            lv.rb_sb.get(), lv.zoff.get(), zv);
@@ -424,7 +424,7 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
     Level<T>& lv = levels[l];
     profiler().level = l;
     const int ns = (int)lv.hsk.size();
-    if (!lv.P.root && ns > 0) {
+    if (!lv.plan->root && ns > 0) {
       ProfScope ps("apply_skel", s, 0.0, lv.bytes_skel);
       dim3 gM((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)ns);
       hipLaunchKernelGGL(k_skel_move, gM, dim3(NT), 0, s, u, lv.skpts.get(), lv.sk.get(), sh, sc, 0);
@@ -436,7 +436,7 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
                          1);
       HIF_LAUNCH_CHECK();
     }
-    const int nc = lv.P.ncell;
+    const int nc = lv.plan->ncell;
     if (nc == 0) continue;
     const int gmax = std::max(lv.maxI, lv.maxI + lv.maxS);
     dim3 gG((unsigned)ceil_div(std::max(1, gmax), NT), (unsigned)nc);
