@@ -349,6 +349,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
     A->geom = plan_geometry(n, leaf);
     A->plan0 = std::make_shared<const LevelPlan>(
         plan_level(A->geom[0], std::vector<uint8_t>((size_t)N, 1)));
+    A->dev0 = {};
     A->geom_leaf = leaf;
   }
   // 0 for points the ID has left out so far (the candidates of a level are
@@ -395,10 +396,16 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
                           : std::make_shared<const LevelPlan>(plan_level(A->geom[level], active));
     const LevelPlan& P = *lev.plan;
     const Src<T> src = make_src<T>(A, prev, d_pface.get(), d_ploc.get());
+    // index arrays of the plan; level 0's are uploaded once per problem
+    auto arr = [&](auto& cached, const auto& host) {
+      if (level > 0) return dev_arr(host, s);
+      if (!cached.buf) cached = dev_arr(host, s);
+      return cached;
+    };
 
     // ---- fronts: gather, partial Cholesky + inverse (Section 2.2) -------
-    lev.rows = to_dev(P.rows, s);
-    lev.crow_off = to_dev(P.crow_off, s);
+    lev.rows = arr(A->dev0.rows, P.rows);
+    lev.crow_off = arr(A->dev0.crow_off, P.crow_off);
     lev.hfd.resize(P.ncell);
     int64_t off = 0;
     std::vector<int64_t> yoff(P.ncell), zoff(P.ncell);
@@ -506,15 +513,15 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
         psz += (int64_t)pld[f] * P.fN[f];
         lev.maxF = std::max(lev.maxF, P.fN[f]);
       }
-      lev.fpts = to_dev(P.fpts, s);
-      lev.fpt_off = to_dev(P.fpt_off, s);
-      lev.fN = to_dev(P.fN, s);
-      lev.fcellA = to_dev(P.fcellA, s);
-      lev.fcellB = to_dev(P.fcellB, s);
-      lev.rb_face = to_dev(P.rb_face, s);
-      lev.rb_off = to_dev(P.rb_off, s);
-      lev.rb_sa = to_dev(P.rb_sa, s);
-      lev.rb_sb = to_dev(P.rb_sb, s);
+      lev.fpts = arr(A->dev0.fpts, P.fpts);
+      lev.fpt_off = arr(A->dev0.fpt_off, P.fpt_off);
+      lev.fN = arr(A->dev0.fN, P.fN);
+      lev.fcellA = arr(A->dev0.fcellA, P.fcellA);
+      lev.fcellB = arr(A->dev0.fcellB, P.fcellB);
+      lev.rb_face = arr(A->dev0.rb_face, P.rb_face);
+      lev.rb_off = arr(A->dev0.rb_off, P.rb_off);
+      lev.rb_sa = arr(A->dev0.rb_sa, P.rb_sa);
+      lev.rb_sb = arr(A->dev0.rb_sb, P.rb_sb);
       lev.panel_off = to_dev(poff, s);
       lev.panel_ld = to_dev(pld, s);
       lev.panel.alloc(std::max<int64_t>(psz, 1));

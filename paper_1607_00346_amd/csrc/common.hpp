@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -174,6 +175,23 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) 
 template <typename T>
 __device__ __forceinline__ T load_global(const T* base, uint32_t off) {
   return *(const __attribute__((address_space(1))) T*)((const char*)base + off);
+}
+
+// Device array whose storage may be shared (the level-0 index arrays of a
+// problem are uploaded once and shared by every factor built from it).
+template <typename V>
+struct DevArr {
+  std::shared_ptr<DevBuf<V>> buf;
+  V* get() const { return buf ? buf->get() : nullptr; }
+  size_t size() const { return buf ? buf->size() : 0; }
+};
+
+template <typename V>
+DevArr<V> dev_arr(const std::vector<V>& h, hipStream_t s) {
+  DevArr<V> a;
+  a.buf = std::make_shared<DevBuf<V>>();
+  a.buf->upload(h, s);
+  return a;
 }
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -45,8 +45,8 @@ template <typename T>
 struct Level {
   std::shared_ptr<const LevelPlan> plan;  // shared: the level-0 plan is cached per problem
   // cells
-  DevBuf<int> rows;
-  DevBuf<int64_t> crow_off;
+  DevArr<int> rows;
+  DevArr<int64_t> crow_off;
   std::vector<FrontDesc> hfd;
   DevBuf<FrontDesc> fd;
   DevBuf<T> front;  // per cell [L_I^{-1}; L_SI], (nI+nS) x nI column-major
@@ -54,8 +54,8 @@ struct Level {
   int64_t ysum = 0, zsum = 0;
   int maxI = 0, maxS = 0;
   // faces
-  DevBuf<int> fpts, fN, fcellA, fcellB, rb_face, rb_off, rb_sa, rb_sb;
-  DevBuf<int64_t> fpt_off;
+  DevArr<int> fpts, fN, fcellA, fcellB, rb_face, rb_off, rb_sa, rb_sb;
+  DevArr<int64_t> fpt_off;
   DevBuf<T> panel;  // per face Ã^l([F; other faces of both cells], F)
   DevBuf<int64_t> panel_off;
   DevBuf<int> panel_ld;
@@ -112,6 +112,12 @@ struct hif_problem_s {
   mutable int geom_leaf = -1;
   mutable std::vector<hif::LevelGeom> geom;
   mutable std::shared_ptr<const hif::LevelPlan> plan0;  // level 0: every point active
+  // device copies of plan0's index arrays
+  struct Level0Arrays {
+    hif::DevArr<int> rows, fpts, fN, fcellA, fcellB, rb_face, rb_off, rb_sa, rb_sb;
+    hif::DevArr<int64_t> crow_off, fpt_off;
+  };
+  mutable Level0Arrays dev0;
   hif::Stencil stencil() const { return {n, diag.get(), cx.get(), cy.get(), cz.get()}; }
 };
 
