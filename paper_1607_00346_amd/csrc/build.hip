@@ -31,24 +31,56 @@ struct Src {
   const int* prb_off;
 };
 
+// The part of an A^l lookup that depends only on the column point q, hoisted
+// out of the loops over rows: q's previous-level face, the column of that
+// face's panel, and the panel's row-block faces with their row offsets.
 template <typename T>
-__device__ __forceinline__ T lookup(const Src<T>& s, int p, int q) {
-  if (s.has_prev) {
-    const int fq = s.pface[q];
-    const int fp = s.pface[p];
-    if (fq >= 0 && fp >= 0) {
-      const int* rb = s.prb_face + kRowBlocks * fq;
-#pragma unroll 1
-      for (int t = 0; t < kRowBlocks; ++t) {
-        const int g = rb[t];
-        if (g < 0) break;
-        if (g == fp)
-          return s.panels[s.poff[fq] + (int64_t)(s.prb_off[kRowBlocks * fq + t] + s.ploc[p]) +
-                          (int64_t)s.pld[fq] * s.ploc[q]];
-      }
-      return T(0);
+struct ColLookup {
+  int q, fq;
+  const T* pcol;
+  int gface[kRowBlocks], goff[kRowBlocks];
+};
+
+template <typename T>
+__device__ __forceinline__ ColLookup<T> col_lookup(const Src<T>& s, int q) {
+  ColLookup<T> c;
+  c.q = q;
+  c.fq = s.has_prev ? s.pface[q] : -1;
+  c.pcol = nullptr;
+#pragma unroll
+  for (int t = 0; t < kRowBlocks; ++t) {
+    c.gface[t] = -1;
+    c.goff[t] = 0;
+  }
+  if (c.fq >= 0) {
+    c.pcol = s.panels + s.poff[c.fq] + (int64_t)s.pld[c.fq] * s.ploc[q];
+#pragma unroll
+    for (int t = 0; t < kRowBlocks; ++t) {
+      c.gface[t] = s.prb_face[kRowBlocks * c.fq + t];
+      c.goff[t] = s.prb_off[kRowBlocks * c.fq + t];
     }
   }
+  return c;
+}
+
+// A^l(p, q).  At level 0, A^0 is the stencil.  At level l >= 1 the entry
+// between two points of level-(l-1) faces lives in the panel of the column
+// point's face (zero if the row point's face is not one of its row blocks),
+// and every entry that involves an edge or corner point is still the stencil
+// value.
+template <typename T>
+__device__ __forceinline__ T row_lookup(const Src<T>& s, const ColLookup<T>& c, int p) {
+  if (c.fq >= 0) {
+    const int fp = s.pface[p];
+    if (fp >= 0) {
+      int off = -1;
+#pragma unroll
+      for (int t = 0; t < kRowBlocks; ++t)
+        if (c.gface[t] == fp) off = c.goff[t];
+      return off >= 0 ? c.pcol[off + s.ploc[p]] : T(0);
+    }
+  }
+  const int q = c.q;
   if (p == q) return (T)s.st.diag[p];
   const int dl = q - p;
   const int lo = p < q ? p : q;
@@ -69,9 +101,9 @@ __global__ __launch_bounds__(NT) void k_gather_front(Src<T> s, const int* __rest
   const int j = blockIdx.x;
   if (j >= f.nI) return;
   const int* r = rows + crow_off[c];
-  const int q = r[j];
+  const ColLookup<T> cl = col_lookup(s, r[j]);
   T* col = arena + f.off + (int64_t)f.ld * j;
-  for (int i = j + threadIdx.x; i < f.nI; i += NT) col[i] = lookup(s, r[i], q);
+  for (int i = j + threadIdx.x; i < f.nI; i += NT) col[i] = row_lookup(s, cl, r[i]);
 }
 
 // A_IS of cell c, column s (the s-th shell point): nI x nS, leading dimension nI.
@@ -85,9 +117,9 @@ __global__ __launch_bounds__(NT) void k_gather_front_IS(Src<T> s, const int* __r
   const int sj = blockIdx.x;
   if (sj >= f.nR - f.nI) return;
   const int* r = rows + crow_off[c];
-  const int q = r[f.nI + sj];
+  const ColLookup<T> cl = col_lookup(s, r[f.nI + sj]);
   T* col = ais + aoff[c] + (int64_t)f.nI * sj;
-  for (int i = threadIdx.x; i < f.nI; i += NT) col[i] = lookup(s, r[i], q);
+  for (int i = threadIdx.x; i < f.nI; i += NT) col[i] = row_lookup(s, cl, r[i]);
 }
 
 // Copy the computed lower triangle of each square block to its upper triangle.
@@ -103,11 +135,6 @@ __global__ __launch_bounds__(NT) void k_mirror_lower(double* G, const int64_t* _
   for (int i = threadIdx.x; i < j; i += NT) g[i + (int64_t)ld * j] = g[j + (int64_t)ld * i];
 }
 
-template <typename T>
-__device__ __forceinline__ T usym(const T* U, int ld, int a, int b) {
-  return a >= b ? U[a + (int64_t)ld * b] : U[b + (int64_t)ld * a];
-}
-
 // Panel of face f, column j: Ã^l(rows, F_j) = A^l(rows, F_j) + U_A + U_B, the
 // Schur updates of the two neighbouring cells added in a fixed order.
 template <typename T>
@@ -121,7 +148,7 @@ __global__ __launch_bounds__(NT) void k_gather_panel(
   const int f = blockIdx.y;
   const int j = blockIdx.x;
   if (j >= fN[f]) return;
-  const int q = fpts[fpt_off[f] + j];
+  const ColLookup<T> cl = col_lookup(s, fpts[fpt_off[f] + j]);
   const int A = fcellA[f], B = fcellB[f];
   const size_t base = (size_t)f * kRowBlocks;
   const int colA = rb_sa[base] + j, colB = rb_sb[base] + j;
@@ -136,9 +163,9 @@ __global__ __launch_bounds__(NT) void k_gather_panel(
     const int ng = fN[g];
     const int* G = fpts + fpt_off[g];
     for (int i = threadIdx.x; i < ng; i += NT) {
-      T v = lookup(s, G[i], q);
-      if (sa >= 0) v += usym(UA, ldA, sa + i, colA);
-      if (sb >= 0) v += usym(UB, ldB, sb + i, colB);
+      T v = row_lookup(s, cl, G[i]);
+      if (sa >= 0) v += UA[(sa + i) + (int64_t)ldA * colA];
+      if (sb >= 0) v += UB[(sb + i) + (int64_t)ldB * colB];
       col[ro + i] = v;
     }
   }
@@ -481,7 +508,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
     }
 
     if (!P.root) {
-      // ---- Schur updates U_c = -L_SI L_SI^T (lower) ---------------------
+      // ---- Schur updates U_c = -L_SI L_SI^T (both triangles) -----------
       std::vector<int64_t> uoff(P.ncell);
       std::vector<int> uld(P.ncell);
       int64_t usz = 0;
@@ -500,7 +527,9 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
           gd.push_back({LSI, X.get() + xoff[c], U.get() + uoff[c], P.cS[c], P.cS[c], d.nI, d.ld,
                         d.nI, uld[c]});
         }
-        run_gemms<T, T>("gemm_syrk", OP_N, OP_N, GF_C_LOWER, gd, T(-1), T(0), s, GC_SYRK);
+        // both triangles of U, so that the panel gather reads columns only
+        run_gemms<T, T>("gemm_syrk", OP_N, OP_N, GF_C_LOWER | GF_C_MIRROR, gd, T(-1), T(0), s,
+                        GC_SYRK);
         X.release();
       }
       // ---- face panels Ã^l([F; R-faces], F) ------------------------------

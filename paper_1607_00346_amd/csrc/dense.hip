@@ -211,6 +211,7 @@ __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, co
           TC val = alpha * acc[x][y][v];
           if (beta != TC(0)) val += beta * gC[idx];
           gC[idx] = val;
+          if ((flags & GF_C_MIRROR) && gi > gj) gC[gj + (int64_t)ldc * gi] = val;
         }
       }
 }

@@ -26,6 +26,7 @@ enum : int {
   GF_B_LOWER = 4,   // op(B)(t,j) = 0 for t < j
   GF_B_UPPER = 8,   // op(B)(t,j) = 0 for t > j
   GF_C_LOWER = 16,  // only C(i,j) with i >= j is computed and written
+  GF_C_MIRROR = 32, // with GF_C_LOWER (square C): C(j,i) is written too
 };
 
 struct GemmDesc {
