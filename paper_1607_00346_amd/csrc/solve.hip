@@ -111,9 +111,11 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// y[roff + i] (+)= alpha sum_t A(i, t) x[coff + t]: 64 rows per workgroup,
-// the columns split over the four waves in groups of 8 (independent loads in
-// flight), partial sums reduced through LDS.
+// y[roff + i] (+)= alpha sum_t A(i, t) x[coff + t] (tri: t <= i only): 64
+// rows per workgroup, the columns split over the four waves in groups of 8
+// (independent loads in flight), partial sums reduced through LDS.  Groups
+// that straddle the diagonal load all 8 columns (the stored upper triangle
+// is in bounds) and drop the entries above it by selects.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_gemv_n(const GemvDesc* __restrict__ dd,
                                                const double* __restrict__ x, double* y,
@@ -130,17 +132,22 @@ __global__ __launch_bounds__(NT) void k_gemv_n(const GemvDesc* __restrict__ dd,
   const auto xv = as_global(x + d.coff);
   double s0 = 0.0, s1 = 0.0;
   for (int t0 = wave * 8; t0 < tend; t0 += 32) {
-    if (t0 + 8 <= tend && (!d.tri || t0 + 8 <= r0)) {
+    if (t0 + 8 <= tend) {
       double a[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) a[u] = (double)A[(int64_t)d.lda * (t0 + u)];
+      if (!d.tri || t0 + 8 <= r0) {
 #pragma unroll
-      for (int u = 0; u < 8; u += 2) {
-        s0 += a[u] * xv[t0 + u];
-        s1 += a[u + 1] * xv[t0 + u + 1];
+        for (int u = 0; u < 8; u += 2) {
+          s0 += a[u] * xv[t0 + u];
+          s1 += a[u + 1] * xv[t0 + u + 1];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s0 += t0 + u <= i ? a[u] * xv[t0 + u] : 0.0;
       }
     } else {
-      for (int t = t0; t < min(t0 + 8, tend); ++t)
+      for (int t = t0; t < tend; ++t)
         if (!d.tri || t <= i) s0 += (double)A[(int64_t)d.lda * t] * xv[t];
     }
   }
@@ -153,28 +160,68 @@ __global__ __launch_bounds__(NT) void k_gemv_n(const GemvDesc* __restrict__ dd,
   }
 }
 
-// y[coff + j] (+)= alpha sum_i A(i, j) x[roff + i]: one wave per column.
+// Sixteen bytes of matrix elements, and the matching entries of x.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  static constexpr int N = 4;
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Vec16<double> {
+  static constexpr int N = 2;
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+
+// y[coff + j] (+)= alpha sum_i A(i, j) x[roff + i] (tri: i >= j only): 16
+// lanes per column, 16 columns at a time, 64 columns per workgroup.  Each
+// column is read as 16-byte vectors (two full cache lines per load across its
+// 16 lanes) after a scalar head up to the first aligned row, then a scalar
+// tail.
+constexpr int kGemvTCols = 64;
 template <typename T>
 __global__ __launch_bounds__(NT) void k_gemv_t(const GemvDesc* __restrict__ dd,
                                                const double* __restrict__ x, double* y,
                                                double alpha, int accumulate) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::N;
   const GemvDesc d = dd[blockIdx.y];
-  const int j = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
-  if (j >= d.n) return;
-  const int lane = threadIdx.x & 63;
-  const auto col = as_global((const T*)d.A + (int64_t)d.lda * j);
+  const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
   const auto xv = as_global(x + d.roff);
-  double s0 = 0.0, s1 = 0.0;
-  int i = (d.tri ? j : 0) + lane;
-  for (; i + 64 < d.m; i += 128) {
-    s0 += (double)col[i] * xv[i];
-    s1 += (double)col[i + 64] * xv[i + 64];
-  }
-  if (i < d.m) s0 += (double)col[i] * xv[i];
-  const double v = alpha * wave_sum(s0 + s1);
-  if (lane == 0) {
-    const auto yo = as_global(y + d.coff + j);
-    *yo = accumulate ? *yo + v : v;
+  const int jend = min(d.n, (int)(blockIdx.x + 1) * kGemvTCols);
+  for (int jb = blockIdx.x * kGemvTCols; jb < jend; jb += NT / 16) {
+    const int j = jb + g;
+    double s0 = 0.0, s1 = 0.0;
+    if (j < jend) {
+      const T* col = (const T*)d.A + (int64_t)d.lda * j;
+      const int i0 = d.tri ? j : 0;
+      const int head = min(d.m - i0, (int)(((16 - ((uintptr_t)(col + i0) & 15)) & 15) / sizeof(T)));
+      if (l < head) s0 += (double)as_global(col)[i0 + l] * xv[i0 + l];
+      const int ib = i0 + head;
+      const int nv = (d.m - ib) / VN;
+      const auto cv = as_global((const V*)(col + ib));
+      for (int v = l; v < nv; v += 16) {
+        const V a = cv[v];
+        const int i = ib + VN * v;
+#pragma unroll
+        for (int e = 0; e < VN; e += 2) {
+          s0 += (double)a[e] * xv[i + e];
+          s1 += (double)a[e + 1] * xv[i + e + 1];
+        }
+      }
+      const int it = ib + VN * nv + l;
+      if (it < d.m) s0 += (double)as_global(col)[it] * xv[it];
+    }
+    double v = s0 + s1;
+    v += __shfl_xor(v, 8, 16);
+    v += __shfl_xor(v, 4, 16);
+    v += __shfl_xor(v, 2, 16);
+    v += __shfl_xor(v, 1, 16);
+    if (j < jend && l == 0) {
+      const auto yo = as_global(y + d.coff + j);
+      *yo = accumulate ? *yo + alpha * v : alpha * v;
+    }
   }
 }
 
@@ -295,7 +342,7 @@ void gemv_launch(bool trans, const GemvDesc* d, int batch, int maxm, int maxn, c
                  double* y, double alpha, int acc, hipStream_t s) {
   if (batch <= 0 || maxm <= 0 || maxn <= 0) return;
   if (trans) {
-    dim3 g((unsigned)ceil_div(maxn, NT / 64), (unsigned)batch);
+    dim3 g((unsigned)ceil_div(maxn, kGemvTCols), (unsigned)batch);
     hipLaunchKernelGGL((k_gemv_t<T>), g, dim3(NT), 0, s, d, x, y, alpha, acc);
   } else {
     dim3 g((unsigned)ceil_div(maxm, 64), (unsigned)batch);
