@@ -73,6 +73,7 @@ struct Level {
   double bytes_L = 0.0, bytes_S = 0.0, bytes_skel = 0.0;
   // sweep descriptors (built at the end of the build)
   bool gv_ready = false;
+  bool gv_L_vec = true;  // every L_I^{-1} starts 16-byte aligned (vector row GEMV)
   DevBuf<GemvDesc> gv_L, gv_S, gv_T, gv_Lc, gv_Y;
   int gv_nS = 0;  // cells with nS > 0 (gv_S entries)
   int64_t ksum = 0, rsum = 0;

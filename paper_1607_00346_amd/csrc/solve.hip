@@ -225,6 +225,62 @@ __global__ __launch_bounds__(NT) void k_gemv_t(const GemvDesc* __restrict__ dd,
   }
 }
 
+// y[roff + i] (+)= alpha sum_t A(i, t) x[coff + t] (tri: t <= i only) for
+// matrices whose columns start 16-byte aligned: lane l of group g reads VN
+// consecutive rows as one 16-byte vector, the 16 groups take every 16th
+// column, partial sums are reduced through LDS.  Rows past m are read only
+// by the lanes that hold both valid and invalid rows, element by element.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_gemv_nv(const GemvDesc* __restrict__ dd,
+                                                const double* __restrict__ x, double* y,
+                                                double alpha, int accumulate) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::N;
+  constexpr int R = 16 * VN;  // rows per workgroup
+  __shared__ double part[16][R + 1];
+  const GemvDesc d = dd[blockIdx.y];
+  const int r0 = blockIdx.x * R;
+  if (r0 >= d.m) return;
+  const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
+  const int i = r0 + VN * l;
+  const int tend = d.tri ? min(d.n, r0 + R) : d.n;
+  const auto xv = as_global(x + d.coff);
+  const bool full = i + VN <= d.m;
+  double acc[VN];
+#pragma unroll
+  for (int e = 0; e < VN; ++e) acc[e] = 0.0;
+#pragma unroll 4
+  for (int t = g; t < tend; t += 16) {
+    const double xt = xv[t];
+    const T* col = (const T*)d.A + (int64_t)d.lda * t;
+    T a[VN];
+    if (full) {
+      const V v = *as_global((const V*)(col + i));
+#pragma unroll
+      for (int e = 0; e < VN; ++e) a[e] = v[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < VN; ++e) a[e] = i + e < d.m ? as_global(col)[i + e] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < VN; ++e) acc[e] += (!d.tri || t <= i + e) ? (double)a[e] * xt : 0.0;
+  }
+#pragma unroll
+  for (int e = 0; e < VN; ++e) part[g][VN * l + e] = acc[e];
+  __syncthreads();
+  if (threadIdx.x < R) {
+    const int row = r0 + threadIdx.x;
+    if (row < d.m) {
+      double sum = 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) sum += part[q][threadIdx.x];
+      const double v = alpha * sum;
+      const auto yo = as_global(y + d.roff + row);
+      *yo = accumulate ? *yo + v : v;
+    }
+  }
+}
+
 // Skeleton vectors: xh[kofs + i] = u[F̂_i], xc[rofs + b] = u[F̌_b] (gather) or
 // the reverse (scatter).
 __global__ __launch_bounds__(NT) void k_skel_move(double* u, const int* __restrict__ skpts,
@@ -339,9 +395,12 @@ void stencil_matvec(const Stencil& st, const double* x, double* y, hipStream_t s
 
 template <typename T>
 void gemv_launch(bool trans, const GemvDesc* d, int batch, int maxm, int maxn, const double* x,
-                 double* y, double alpha, int acc, hipStream_t s) {
+                 double* y, double alpha, int acc, hipStream_t s, bool aligned = false) {
   if (batch <= 0 || maxm <= 0 || maxn <= 0) return;
-  if (trans) {
+  if (!trans && aligned) {
+    dim3 g((unsigned)ceil_div(maxm, 16 * Vec16<T>::N), (unsigned)batch);
+    hipLaunchKernelGGL((k_gemv_nv<T>), g, dim3(NT), 0, s, d, x, y, alpha, acc);
+  } else if (trans) {
     dim3 g((unsigned)ceil_div(maxn, kGemvTCols), (unsigned)batch);
     hipLaunchKernelGGL((k_gemv_t<T>), g, dim3(NT), 0, s, d, x, y, alpha, acc);
   } else {
@@ -382,6 +441,7 @@ void FactorImpl<T>::prepare(hipStream_t s) {
       const FrontDesc& d = lv.hfd[c];
       const T* base = lv.front.get() + d.off;
       gl.push_back({base, d.nI, d.nI, d.ld, 1, yoff[c], yoff[c]});
+      if (((uintptr_t)base % 16) != 0 || d.ld % Vec16<T>::N != 0) lv.gv_L_vec = false;
       if (d.nR > d.nI) gs.push_back({base + d.nI, d.nR - d.nI, d.nI, d.ld, 0, zoff[c], yoff[c]});
     }
     for (const SkelDesc& d : lv.hsk) {
@@ -428,7 +488,8 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
         ProfScope ps("apply_up_L", s, 0.0, lv.bytes_L);
         hipLaunchKernelGGL(k_gather_cell, gI, dim3(NT), 0, s, u, lv.rows.get(), lv.crow_off.get(),
                            lv.fd.get(), lv.yoff.get(), lv.zoff.get(), xi, xsv, 0);
-        gemv_launch<T>(false, lv.gv_L.get(), nc, lv.maxI, lv.maxI, xi, yv, 1.0, 0, s);
+        gemv_launch<T>(false, lv.gv_L.get(), nc, lv.maxI, lv.maxI, xi, yv, 1.0, 0, s,
+                       lv.gv_L_vec);
       }
       if (lv.gv_nS > 0) {
         ProfScope ps("apply_up_S", s, 0.0, lv.bytes_S);
