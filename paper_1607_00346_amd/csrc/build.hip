@@ -91,6 +91,15 @@ __device__ __forceinline__ T row_lookup(const Src<T>& s, const ColLookup<T>& c, 
   return T(0);
 }
 
+// The gathers give each wave one column (four columns per workgroup): the
+// column's lookup state is then wave-uniform (scalar registers) and columns
+// of a few dozen rows still keep most lanes busy.
+constexpr int kGatherCols = NT / 64;
+
+__device__ __forceinline__ int wave_column(int block) {
+  return block * kGatherCols + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
 // Front of cell c, column j: A_II(i, j) for i >= j into Phi.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_gather_front(Src<T> s, const int* __restrict__ rows,
@@ -98,12 +107,13 @@ __global__ __launch_bounds__(NT) void k_gather_front(Src<T> s, const int* __rest
                                                      const FrontDesc* __restrict__ fd, T* arena) {
   const int c = blockIdx.y;
   const FrontDesc f = fd[c];
-  const int j = blockIdx.x;
+  const int j = wave_column(blockIdx.x);
   if (j >= f.nI) return;
+  const int lane = threadIdx.x & 63;
   const int* r = rows + crow_off[c];
   const ColLookup<T> cl = col_lookup(s, r[j]);
   T* col = arena + f.off + (int64_t)f.ld * j;
-  for (int i = j + threadIdx.x; i < f.nI; i += NT) col[i] = row_lookup(s, cl, r[i]);
+  for (int i = j + lane; i < f.nI; i += 64) col[i] = row_lookup(s, cl, r[i]);
 }
 
 // A_IS of cell c, column s (the s-th shell point): nI x nS, leading dimension nI.
@@ -114,12 +124,13 @@ __global__ __launch_bounds__(NT) void k_gather_front_IS(Src<T> s, const int* __r
                                                         const int64_t* __restrict__ aoff) {
   const int c = blockIdx.y;
   const FrontDesc f = fd[c];
-  const int sj = blockIdx.x;
+  const int sj = wave_column(blockIdx.x);
   if (sj >= f.nR - f.nI) return;
+  const int lane = threadIdx.x & 63;
   const int* r = rows + crow_off[c];
   const ColLookup<T> cl = col_lookup(s, r[f.nI + sj]);
   T* col = ais + aoff[c] + (int64_t)f.nI * sj;
-  for (int i = threadIdx.x; i < f.nI; i += NT) col[i] = row_lookup(s, cl, r[i]);
+  for (int i = lane; i < f.nI; i += 64) col[i] = row_lookup(s, cl, r[i]);
 }
 
 // Copy the computed lower triangle of each square block to its upper triangle.
@@ -146,8 +157,9 @@ __global__ __launch_bounds__(NT) void k_gather_panel(
     const int* __restrict__ uld, T* panels, const int64_t* __restrict__ poff,
     const int* __restrict__ pld) {
   const int f = blockIdx.y;
-  const int j = blockIdx.x;
+  const int j = wave_column(blockIdx.x);
   if (j >= fN[f]) return;
+  const int lane = threadIdx.x & 63;
   const ColLookup<T> cl = col_lookup(s, fpts[fpt_off[f] + j]);
   const int A = fcellA[f], B = fcellB[f];
   const size_t base = (size_t)f * kRowBlocks;
@@ -162,7 +174,7 @@ __global__ __launch_bounds__(NT) void k_gather_panel(
     const int ro = rb_off[base + t], sa = rb_sa[base + t], sb = rb_sb[base + t];
     const int ng = fN[g];
     const int* G = fpts + fpt_off[g];
-    for (int i = threadIdx.x; i < ng; i += NT) {
+    for (int i = lane; i < ng; i += 64) {
       T v = row_lookup(s, cl, G[i]);
       if (sa >= 0) v += UA[(sa + i) + (int64_t)ldA * colA];
       if (sb >= 0) v += UB[(sb + i) + (int64_t)ldB * colB];
@@ -473,12 +485,12 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
       DevBuf<int64_t> d_xoff = to_dev(xoff, s);
       {
         ProfScope ps("gather_front", s);
-        dim3 g((unsigned)std::max(1, lev.maxI), (unsigned)P.ncell);
+        dim3 g((unsigned)ceil_div(std::max(1, lev.maxI), kGatherCols), (unsigned)P.ncell);
         hipLaunchKernelGGL((k_gather_front<T>), g, dim3(NT), 0, s, src, lev.rows.get(),
                            lev.crow_off.get(), lev.fd.get(), lev.front.get());
         HIF_LAUNCH_CHECK();
         if (lev.maxS > 0) {
-          dim3 g2((unsigned)lev.maxS, (unsigned)P.ncell);
+          dim3 g2((unsigned)ceil_div(lev.maxS, kGatherCols), (unsigned)P.ncell);
           hipLaunchKernelGGL((k_gather_front_IS<T>), g2, dim3(NT), 0, s, src, lev.rows.get(),
                              lev.crow_off.get(), lev.fd.get(), AIS.get(), d_xoff.get());
           HIF_LAUNCH_CHECK();
@@ -559,7 +571,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
         DevBuf<int64_t> d_uoff = to_dev(uoff, s);
         DevBuf<int> d_uld = to_dev(uld, s);
         ProfScope ps("gather_panel", s);
-        dim3 g((unsigned)std::max(1, lev.maxF), (unsigned)P.nface);
+        dim3 g((unsigned)ceil_div(std::max(1, lev.maxF), kGatherCols), (unsigned)P.nface);
         hipLaunchKernelGGL((k_gather_panel<T>), g, dim3(NT), 0, s, src, lev.fpts.get(),
                            lev.fpt_off.get(), lev.fN.get(), lev.rb_face.get(), lev.rb_off.get(),
                            lev.rb_sa.get(), lev.rb_sb.get(), lev.fcellA.get(), lev.fcellB.get(),

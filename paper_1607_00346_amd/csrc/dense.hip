@@ -438,8 +438,12 @@ __global__ __launch_bounds__(NTHR) void k_front_step(T* arena, const FrontDesc* 
 // broadcasts.  Rows and columns past nb are padded with the identity.
 template <typename T>
 __global__ __launch_bounds__(64) void k_diag_inv(T* arena, const FrontDesc* __restrict__ fd) {
-  __shared__ T Lc[kPanel][kPanel];      // Lc[t][i] = L(i, t)
-  __shared__ T Xs[kPanel][kPanel + 1];  // Xs[c][i] = L^{-1}(i, c)
+  // Lc[t][i] = L(i, t) while the inverse is formed, then Xs[c][i] = L^{-1}(i, c)
+  // in the same storage (one wave: its LDS accesses complete in issue order),
+  // which doubles the waves per CU of this latency-bound kernel
+  __shared__ __align__(16) T buf[kPanel * (kPanel + 1)];
+  T(*Lc)[kPanel] = reinterpret_cast<T(*)[kPanel]>(buf);
+  T(*Xs)[kPanel + 1] = reinterpret_cast<T(*)[kPanel + 1]>(buf);
   __shared__ T rd[kPanel];
   const FrontDesc f = fd[blockIdx.y];
   const int j0 = blockIdx.x * kPanel;
@@ -456,15 +460,9 @@ __global__ __launch_bounds__(64) void k_diag_inv(T* arena, const FrontDesc* __re
     Lc[c][r] = v;
     if (r == c) rd[c] = T(1) / v;
   }
-  T x[kPanel];
+  T x[kPanel];  // column `lane` of the inverse, from e_lane
 #pragma unroll
-  for (int i = 0; i < kPanel; ++i) x[i] = T(0);
-  // x = e_lane: set through LDS so that no per-row lane mask is kept
-  Xs[lane][lane] = T(1);
-#pragma unroll
-  for (int i = 0; i < kPanel; ++i) Xs[lane][i] = i == lane ? T(1) : T(0);
-#pragma unroll
-  for (int i = 0; i < kPanel; ++i) x[i] = Xs[lane][i];
+  for (int i = 0; i < kPanel; ++i) x[i] = i == lane ? T(1) : T(0);
 #pragma unroll
   for (int t = 0; t < kPanel; ++t) {
     x[t] *= rd[t];
