@@ -486,9 +486,12 @@ __global__ __launch_bounds__(64) void k_diag_inv(T* arena, const FrontDesc* __re
 // The Schur diagonal d, the pivot flags and the stop state persist in global
 // memory between launches.  Pivot: largest remaining diagonal, ties to the
 // lowest index; stop when it is <= eps^2 times the first pivot.
-constexpr int kPivPanel = 32;
+constexpr int kPivPanel = 64;
 
-__global__ __launch_bounds__(NTHR) void k_pchol_panel(
+// NTP threads per face: 1024 for large faces (few faces, each pivot's column
+// spread over more lanes), 256 otherwise.
+template <int NTP>
+__global__ __launch_bounds__(NTP) void k_pchol_panel(
     const double* __restrict__ G, double* __restrict__ L, const int64_t* __restrict__ goff,
     const int* __restrict__ nFa, const int* __restrict__ ldga, const int64_t* __restrict__ poff,
     int* __restrict__ perm, double* __restrict__ dbuf, int* __restrict__ pivbuf,
@@ -496,8 +499,8 @@ __global__ __launch_bounds__(NTHR) void k_pchol_panel(
   __shared__ double d[kPcholMax];
   __shared__ unsigned char piv[kPcholMax];
   __shared__ double lp[kPivPanel];
-  __shared__ double rv[NTHR / 64];
-  __shared__ int ri[NTHR / 64];
+  __shared__ double rv[NTP / 64];
+  __shared__ int ri[NTP / 64];
   __shared__ int s_p, s_stop;
   __shared__ double s_dp, s_r11;
   const int b = blockIdx.x;
@@ -510,7 +513,7 @@ __global__ __launch_bounds__(NTHR) void k_pchol_panel(
   double* db = dbuf + poff[b];
   int* pvb = pivbuf + poff[b];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int a = tid; a < nF; a += NTHR) {
+  for (int a = tid; a < nF; a += NTP) {
     d[a] = j0 == 0 ? Gb[a + (int64_t)ld * a] : db[a];
     piv[a] = j0 == 0 ? 0 : (unsigned char)pvb[a];
   }
@@ -521,7 +524,7 @@ __global__ __launch_bounds__(NTHR) void k_pchol_panel(
   for (int j = j0; j < jend; ++j) {
     double bv = -DBL_MAX;
     int bi = INT_MAX;
-    for (int a = tid; a < nF; a += NTHR) {
+    for (int a = tid; a < nF; a += NTP) {
       if (!piv[a]) {
         const double v = d[a];
         if (v > bv || (v == bv && a < bi)) { bv = v; bi = a; }
@@ -536,7 +539,7 @@ __global__ __launch_bounds__(NTHR) void k_pchol_panel(
     if (lane == 0) { rv[wave] = bv; ri[wave] = bi; }
     __syncthreads();
     if (tid == 0) {
-      for (int w = 1; w < NTHR / 64; ++w)
+      for (int w = 1; w < NTP / 64; ++w)
         if (rv[w] > bv || (rv[w] == bv && ri[w] < bi)) { bv = rv[w]; bi = ri[w]; }
       if (j == 0) s_r11 = bv;
       const int stop = (j == 0) ? !(bv > 0.0) : !(bv > eps * eps * s_r11);
@@ -557,15 +560,22 @@ __global__ __launch_bounds__(NTHR) void k_pchol_panel(
     const int np = j - j0;
     if (tid < np) lp[tid] = Lb[p + (int64_t)ld * (j0 + tid)];
     __syncthreads();
-    for (int a = tid; a < nF; a += NTHR) {
+    for (int a = tid; a < nF; a += NTP) {
       double v;
       if (a == p) v = ljj;
       else if (piv[a]) v = 0.0;
       else {
-        double s = Gb[a + (int64_t)ld * p];
         const double* la = Lb + a + (int64_t)ld * j0;
-        for (int t = 0; t < np; ++t) s -= la[(int64_t)ld * t] * lp[t];
-        v = s / ljj;
+        double s0 = Gb[a + (int64_t)ld * p], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int t = 0;
+        for (; t + 4 <= np; t += 4) {
+          s0 -= la[(int64_t)ld * t] * lp[t];
+          s1 -= la[(int64_t)ld * (t + 1)] * lp[t + 1];
+          s2 -= la[(int64_t)ld * (t + 2)] * lp[t + 2];
+          s3 -= la[(int64_t)ld * (t + 3)] * lp[t + 3];
+        }
+        for (; t < np; ++t) s0 -= la[(int64_t)ld * t] * lp[t];
+        v = ((s0 + s1) + (s2 + s3)) / ljj;
         d[a] -= v * v;
       }
       Lb[a + (int64_t)ld * j] = v;
@@ -577,7 +587,7 @@ __global__ __launch_bounds__(NTHR) void k_pchol_panel(
     if (!stopped && jend == nF) kst[b] = nF;
     r11[b] = s_r11;
   }
-  for (int a = tid; a < nF; a += NTHR) {
+  for (int a = tid; a < nF; a += NTP) {
     db[a] = d[a];
     pvb[a] = piv[a];
   }
@@ -855,38 +865,37 @@ void pivoted_cholesky(double* G, double* L, const int64_t* goff, const int* nF, 
   DevBuf<int> pivbuf(std::max<int64_t>(tot, 1)), kst(batch);
   HIF_HIP(hipMemsetAsync(kst.get(), 0xff, sizeof(int) * batch, s));  // -1: running
   std::vector<GemmDesc> gd;
-  std::vector<TransDesc> td;
   DevBuf<GemmDesc> dd;
-  DevBuf<TransDesc> dt;
-  DevBuf<double> LT((size_t)std::max<int64_t>(tot, 1) * kPivPanel);  // panel of L, transposed
   for (int j0 = 0; j0 < maxF; j0 += kPivPanel) {
     {
       ProfScope ps("pivoted_cholesky", s);
-      hipLaunchKernelGGL(k_pchol_panel, dim3((unsigned)batch), dim3(NTHR), 0, s, G, L, goff, nF,
-                         ldg, poff, perm, dbuf.get(), pivbuf.get(), kst.get(), r11.get(), eps, j0);
+      if (maxF > 256)
+        hipLaunchKernelGGL(k_pchol_panel<1024>, dim3((unsigned)batch), dim3(1024), 0, s, G, L,
+                           goff, nF, ldg, poff, perm, dbuf.get(), pivbuf.get(), kst.get(),
+                           r11.get(), eps, j0);
+      else
+        hipLaunchKernelGGL(k_pchol_panel<NTHR>, dim3((unsigned)batch), dim3(NTHR), 0, s, G, L,
+                           goff, nF, ldg, poff, perm, dbuf.get(), pivbuf.get(), kst.get(),
+                           r11.get(), eps, j0);
       HIF_LAUNCH_CHECK();
     }
     if (j0 + kPivPanel >= maxF) break;
+    // G -= L_p L_p^T with the panel's columns L_p (lower part computed, both written)
     gd.clear();
-    td.clear();
     int mm = 0;
     double fl = 0.0;
     for (int b = 0; b < batch; ++b) {
       if (h_nF[b] <= j0 + kPivPanel) continue;
       const int kk = std::min(kPivPanel, h_nF[b] - j0);
       double* Lp = L + h_goff[b] + (int64_t)h_ldg[b] * j0;
-      double* Lt = LT.get() + h_poff[b] * kPivPanel;
-      td.push_back({Lp, Lt, h_nF[b], kk, h_ldg[b], kPivPanel});
-      gd.push_back({Lp, Lt, G + h_goff[b], h_nF[b], h_nF[b], kk, h_ldg[b], kPivPanel, h_ldg[b]});
+      gd.push_back({Lp, Lp, G + h_goff[b], h_nF[b], h_nF[b], kk, h_ldg[b], h_ldg[b], h_ldg[b]});
       mm = std::max(mm, h_nF[b]);
-      fl += 2.0 * kk * (double)h_nF[b] * h_nF[b];
+      fl += gemm_flops(gd.back(), GF_C_LOWER);
     }
     if (gd.empty()) continue;
-    dt.upload(td, s);
     dd.upload(gd, s);
-    transpose_batched<double>(dt.get(), (int)td.size(), mm, kPivPanel, s, "pivchol_transpose");
-    gemm_batched<double, double>(OP_N, OP_N, 0, dd.get(), (int)gd.size(), mm, mm, -1.0, 1.0, s,
-                                 "pivchol_update", fl);
+    gemm_batched<double, double>(OP_N, OP_T, GF_C_LOWER | GF_C_MIRROR, dd.get(), (int)gd.size(),
+                                 mm, mm, -1.0, 1.0, s, "pivchol_update", fl);
   }
   hipLaunchKernelGGL(k_pchol_tail, dim3((unsigned)batch), dim3(64), 0, s, nF, poff, perm,
                      (const int*)pivbuf.get(), (const int*)kst.get(), k);
