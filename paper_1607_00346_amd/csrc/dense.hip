@@ -489,7 +489,7 @@ __global__ __launch_bounds__(64) void k_diag_inv(T* arena, const FrontDesc* __re
 constexpr int kPivPanel = 64;
 
 // NTP threads per face: 1024 for large faces (few faces, each pivot's column
-// spread over more lanes), 256 otherwise.
+// spread over more lanes), 64 for faces of at most 64 points, 256 otherwise.
 template <int NTP>
 __global__ __launch_bounds__(NTP) void k_pchol_panel(
     const double* __restrict__ G, double* __restrict__ L, const int64_t* __restrict__ goff,
@@ -873,6 +873,10 @@ void pivoted_cholesky(double* G, double* L, const int64_t* goff, const int* nF, 
         hipLaunchKernelGGL(k_pchol_panel<1024>, dim3((unsigned)batch), dim3(1024), 0, s, G, L,
                            goff, nF, ldg, poff, perm, dbuf.get(), pivbuf.get(), kst.get(),
                            r11.get(), eps, j0);
+      else if (maxF <= 64)
+        hipLaunchKernelGGL(k_pchol_panel<64>, dim3((unsigned)batch), dim3(64), 0, s, G, L, goff,
+                           nF, ldg, poff, perm, dbuf.get(), pivbuf.get(), kst.get(), r11.get(),
+                           eps, j0);
       else
         hipLaunchKernelGGL(k_pchol_panel<NTHR>, dim3((unsigned)batch), dim3(NTHR), 0, s, G, L,
                            goff, nF, ldg, poff, perm, dbuf.get(), pivbuf.get(), kst.get(),
