@@ -116,34 +116,22 @@ __global__ __launch_bounds__(NT) void k_gather_front(Src<T> s, const int* __rest
   for (int i = j + lane; i < f.nI; i += 64) col[i] = row_lookup(s, cl, r[i]);
 }
 
-// A_IS of cell c, column s (the s-th shell point): nI x nS, leading dimension nI.
+// A_SI of cell c, column j (the j-th interior point): nS x nI, leading dimension nS.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_gather_front_IS(Src<T> s, const int* __restrict__ rows,
+__global__ __launch_bounds__(NT) void k_gather_front_SI(Src<T> s, const int* __restrict__ rows,
                                                         const int64_t* __restrict__ crow_off,
-                                                        const FrontDesc* __restrict__ fd, T* ais,
+                                                        const FrontDesc* __restrict__ fd, T* asi,
                                                         const int64_t* __restrict__ aoff) {
   const int c = blockIdx.y;
   const FrontDesc f = fd[c];
-  const int sj = wave_column(blockIdx.x);
-  if (sj >= f.nR - f.nI) return;
+  const int j = wave_column(blockIdx.x);
+  if (j >= f.nI) return;
+  const int nS = f.nR - f.nI;
   const int lane = threadIdx.x & 63;
   const int* r = rows + crow_off[c];
-  const ColLookup<T> cl = col_lookup(s, r[f.nI + sj]);
-  T* col = ais + aoff[c] + (int64_t)f.nI * sj;
-  for (int i = lane; i < f.nI; i += 64) col[i] = row_lookup(s, cl, r[i]);
-}
-
-// Copy the computed lower triangle of each square block to its upper triangle.
-__global__ __launch_bounds__(NT) void k_mirror_lower(double* G, const int64_t* __restrict__ goff,
-                                                     const int* __restrict__ nFa,
-                                                     const int* __restrict__ gld) {
-  const int f = blockIdx.y;
-  const int j = blockIdx.x;
-  const int nF = nFa[f];
-  if (j >= nF) return;
-  double* g = G + goff[f];
-  const int ld = gld[f];
-  for (int i = threadIdx.x; i < j; i += NT) g[i + (int64_t)ld * j] = g[j + (int64_t)ld * i];
+  const ColLookup<T> cl = col_lookup(s, r[j]);
+  T* col = asi + aoff[c] + (int64_t)nS * j;
+  for (int i = lane; i < nS; i += 64) col[i] = row_lookup(s, cl, r[f.nI + i]);
 }
 
 // Panel of face f, column j: Ã^l(rows, F_j) = A^l(rows, F_j) + U_A + U_B, the
@@ -472,16 +460,15 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
     lev.front.alloc(off);
     st.cells[level] = P.ncell;
     st.eliminated[level] = lev.ysum;
-    // X = L_I^{-1} A_IS (nI x nS per cell) is kept until the Schur update
+    // A_SI (nS x nI per cell) until L_SI = A_SI L_I^{-T} is formed
     std::vector<int64_t> xoff(P.ncell);
     int64_t xsz = 0;
     for (int c = 0; c < P.ncell; ++c) {
       xoff[c] = xsz;
       xsz += (int64_t)P.cI[c] * P.cS[c];
     }
-    DevBuf<T> X(std::max<int64_t>(xsz, 1));
     if (P.ncell > 0) {
-      DevBuf<T> AIS(std::max<int64_t>(xsz, 1));
+      DevBuf<T> ASI(std::max<int64_t>(xsz, 1));
       DevBuf<int64_t> d_xoff = to_dev(xoff, s);
       {
         ProfScope ps("gather_front", s);
@@ -490,9 +477,9 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
                            lev.crow_off.get(), lev.fd.get(), lev.front.get());
         HIF_LAUNCH_CHECK();
         if (lev.maxS > 0) {
-          dim3 g2((unsigned)ceil_div(lev.maxS, kGatherCols), (unsigned)P.ncell);
-          hipLaunchKernelGGL((k_gather_front_IS<T>), g2, dim3(NT), 0, s, src, lev.rows.get(),
-                             lev.crow_off.get(), lev.fd.get(), AIS.get(), d_xoff.get());
+          dim3 g2((unsigned)ceil_div(std::max(1, lev.maxI), kGatherCols), (unsigned)P.ncell);
+          hipLaunchKernelGGL((k_gather_front_SI<T>), g2, dim3(NT), 0, s, src, lev.rows.get(),
+                             lev.crow_off.get(), lev.fd.get(), ASI.get(), d_xoff.get());
           HIF_LAUNCH_CHECK();
         }
       }
@@ -501,22 +488,16 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
       for (auto& d : top) d.nR = d.nI;
       DevBuf<FrontDesc> d_top = to_dev(top, s);
       front_factor<T>(lev.front.get(), d_top.get(), top, d_err.get() + 2 * level, s);
-      // X = L_I^{-1} A_IS, then L_SI = X^T into the front below L_I^{-1}
+      // L_SI = A_SI L_I^{-T} into the front below L_I^{-1} (L_I^{-T} is upper)
       std::vector<GemmDesc> gd;
-      std::vector<TransDesc> td;
       for (int c = 0; c < P.ncell; ++c) {
         if (P.cS[c] == 0) continue;
         const FrontDesc& d = lev.hfd[c];
         T* base = lev.front.get() + d.off;
-        gd.push_back({base, AIS.get() + xoff[c], X.get() + xoff[c], d.nI, P.cS[c], d.nI, d.ld,
-                      d.nI, d.nI});
-        td.push_back({X.get() + xoff[c], base + d.nI, d.nI, P.cS[c], d.nI, d.ld});
+        gd.push_back({ASI.get() + xoff[c], base, base + d.nI, P.cS[c], d.nI, d.nI, P.cS[c], d.ld,
+                      d.ld});
       }
-      run_gemms<T, T>("gemm_lsi", OP_N, OP_N, GF_A_LOWER, gd, T(1), T(0), s, GC_LSI);
-      if (!td.empty()) {
-        DevBuf<TransDesc> d_td = to_dev(td, s);
-        transpose_batched<T>(d_td.get(), (int)td.size(), lev.maxI, lev.maxS, s, "lsi_transpose");
-      }
+      run_gemms<T, T>("gemm_lsi", OP_N, OP_T, GF_B_UPPER, gd, T(1), T(0), s, GC_LSI);
     }
 
     if (!P.root) {
@@ -536,13 +517,11 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
           if (P.cS[c] == 0) continue;
           const FrontDesc& d = lev.hfd[c];
           const T* LSI = lev.front.get() + d.off + d.nI;
-          gd.push_back({LSI, X.get() + xoff[c], U.get() + uoff[c], P.cS[c], P.cS[c], d.nI, d.ld,
-                        d.nI, uld[c]});
+          gd.push_back({LSI, LSI, U.get() + uoff[c], P.cS[c], P.cS[c], d.nI, d.ld, d.ld, uld[c]});
         }
         // both triangles of U, so that the panel gather reads columns only
-        run_gemms<T, T>("gemm_syrk", OP_N, OP_N, GF_C_LOWER | GF_C_MIRROR, gd, T(-1), T(0), s,
+        run_gemms<T, T>("gemm_syrk", OP_N, OP_T, GF_C_LOWER | GF_C_MIRROR, gd, T(-1), T(0), s,
                         GC_SYRK);
-        X.release();
       }
       // ---- face panels Ã^l([F; R-faces], F) ------------------------------
       std::vector<int64_t> poff(P.nface);
@@ -601,41 +580,18 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
           gsz += (int64_t)gld[f] * P.fN[f];
         }
         DevBuf<double> G(std::max<int64_t>(gsz, 1)), Lp(std::max<int64_t>(gsz, 1));
-        // M^T (|F| x K per face) for an NN Gram product
-        std::vector<int64_t> toff(P.nface);
-        int64_t tsz = 0;
-        int maxK = 0;
-        for (int f = 0; f < P.nface; ++f) {
-          toff[f] = tsz;
-          const int K = P.prow[f] - P.fN[f];
-          tsz += (int64_t)P.fN[f] * K;
-          maxK = std::max(maxK, K);
-        }
-        DevBuf<T> MT(std::max<int64_t>(tsz, 1));
-        std::vector<TransDesc> td;
+        // G = M^T M with M = the panel rows outside F (K x |F| per face), read in
+        // place; the lower part is computed and both triangles are written
         for (int f = 0; f < P.nface; ++f) {
           const T* PR = lev.panel.get() + poff[f] + P.fN[f];
           const int K = P.prow[f] - P.fN[f];
-          td.push_back({PR, MT.get() + toff[f], K, P.fN[f], pld[f], std::max(1, P.fN[f])});
-          gd.push_back({MT.get() + toff[f], PR, G.get() + goff[f], P.fN[f], P.fN[f], K,
-                        std::max(1, P.fN[f]), pld[f], gld[f]});
+          gd.push_back({PR, PR, G.get() + goff[f], P.fN[f], P.fN[f], K, pld[f], pld[f], gld[f]});
           flops += 2.0 * K * P.fN[f] * (double)P.fN[f];
         }
-        {
-          DevBuf<TransDesc> d_td = to_dev(td, s);
-          transpose_batched<T>(d_td.get(), (int)td.size(), maxK, lev.maxF, s, "gram_transpose");
-        }
-        run_gemms<T, double>("gemm_gram", OP_N, OP_N, GF_C_LOWER, gd, 1.0, 0.0, s, GC_GRAM);
-        MT.release();
+        run_gemms<T, double>("gemm_gram", OP_T, OP_N, GF_C_LOWER | GF_C_MIRROR, gd, 1.0, 0.0, s,
+                             GC_GRAM);
         DevBuf<int64_t> d_goff = to_dev(goff, s);
         DevBuf<int> d_gld = to_dev(gld, s);
-        {
-          ProfScope ps("gram_mirror", s);
-          dim3 g((unsigned)std::max(1, lev.maxF), (unsigned)P.nface);
-          hipLaunchKernelGGL(k_mirror_lower, g, dim3(NT), 0, s, G.get(), d_goff.get(),
-                             lev.fN.get(), d_gld.get());
-          HIF_LAUNCH_CHECK();
-        }
         {
           dim3 g((unsigned)ceil_div(std::max(1, lev.maxF), NT), (unsigned)P.nface);
           hipLaunchKernelGGL(k_gram_edges, g, dim3(NT), 0, s, A->stencil(), P.w, lev.fpts.get(),

@@ -653,12 +653,12 @@ void launch_gemm(int flags, const GemmDesc* d_desc, int batch, int max_m, int ma
 template <typename TIn, typename TC, int TS>
 void dispatch_gemm(int opa, int opb, int flags, int cls, const GemmDesc* d_desc, int batch,
                    int max_m, int max_n, TC alpha, TC beta, hipStream_t s) {
-  if (cls == GC_SYRK && opa == OP_N && opb == OP_N)
-    launch_gemm<TIn, TC, OP_N, OP_N, TS, GC_SYRK>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
-  else if (cls == GC_LSI && opa == OP_N && opb == OP_N)
-    launch_gemm<TIn, TC, OP_N, OP_N, TS, GC_LSI>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
-  else if (cls == GC_GRAM && opa == OP_N && opb == OP_N)
-    launch_gemm<TIn, TC, OP_N, OP_N, TS, GC_GRAM>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+  if (cls == GC_SYRK && opa == OP_N && opb == OP_T)
+    launch_gemm<TIn, TC, OP_N, OP_T, TS, GC_SYRK>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+  else if (cls == GC_LSI && opa == OP_N && opb == OP_T)
+    launch_gemm<TIn, TC, OP_N, OP_T, TS, GC_LSI>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+  else if (cls == GC_GRAM && opa == OP_T && opb == OP_N)
+    launch_gemm<TIn, TC, OP_T, OP_N, TS, GC_GRAM>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
   else if (opa == OP_N && opb == OP_N)
     launch_gemm<TIn, TC, OP_N, OP_N, TS, 0>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
   else if (opa == OP_N)
