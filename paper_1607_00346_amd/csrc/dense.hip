@@ -34,6 +34,8 @@ struct Mfma<float> {
 };
 
 constexpr int BM = 64, BN = 64, KC = 16, NTHR = 256;
+// Fronts of at most this many interior columns are factored one per workgroup.
+constexpr int kSmallFront = 512;
 
 // LDS staging of one K chunk: As[k][m], Bs[k][n], rows padded by one element
 // so that stores along k (transposed operands) do not collide in banks.
@@ -325,23 +327,133 @@ __device__ __forceinline__ T read_lane(T v, int l) {
   }
 }
 
+// LDS of one diagonal-block step: Lcol[t][i] = L_jj(i, t); the same columns
+// shifted to start at their diagonal, Lsh[t][u] = L_jj(t + u, t) (zero past
+// the block); rd[t] = 1 / L_jj(t, t).
+template <typename T>
+struct StepSmem {
+  __align__(16) T Lcol[kPanel][kPanel];
+  __align__(16) T Lsh[kPanel][kPanel];
+  T rd[kPanel];
+};
+
+// Cholesky of the diagonal block A(j0:j0+nb, j0:j0+nb) held in the column
+// block col0 (leading dimension ld) into LDS, by the four waves of the
+// workgroup: lane = row, wave q holds columns 16q .. 16q + 15; at step t the
+// wave owning column t forms L(:, t) and publishes it through LDS, then every
+// wave updates its later columns.  Ends with a barrier.  Returns, per thread,
+// whether its wave met a non-positive pivot (replaced by 1 to continue).
+template <typename T>
+__device__ __forceinline__ bool diag_factor(const T* col0, int64_t ld, int j0, int nb,
+                                            StepSmem<T>& ss) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kPanel * kPanel; e += NTHR) (&ss.Lsh[0][0])[e] = T(0);
+  const int lane = tid & 63;
+  const int q = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
+  const int rl = min(lane, nb - 1);
+  T w[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int c = 16 * q + v;
+    const T g = col0[ld * min(c, nb - 1) + j0 + rl];
+    w[v] = (lane < nb && c < nb && c <= lane) ? g : T(0);
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int qt = 0; 16 * qt < nb; ++qt) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int t = 16 * qt + v;
+      if (t < nb) {  // uniform; a break here would keep the loop rolled
+        if (q == qt) {
+          T d = read_lane(w[v], t);
+          bad = bad || !(d > T(0));
+          d = d > T(0) ? d : T(1);
+          T ltt, r;
+          if constexpr (sizeof(T) == 4) {
+            r = __builtin_amdgcn_rsqf(d);  // 1 ulp; shortens the serial chain
+            ltt = d * r;
+          } else {
+            ltt = sqrt(d);
+            r = T(1) / ltt;
+          }
+          const T lit = lane > t ? w[v] * r : (lane == t ? ltt : T(0));
+          w[v] = lit;
+          ss.Lcol[t][lane] = lit;
+          if (lane >= t) ss.Lsh[t][lane - t] = lit;
+        }
+        __syncthreads();
+        if (q >= qt) {
+          const T li = ss.Lcol[t][lane];
+          T lc[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) lc[u] = ss.Lcol[t][16 * q + u];
+          if (q > qt) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) w[u] -= li * lc[u];
+          } else {
+#pragma unroll
+            for (int u = v + 1; u < 16; ++u) w[u] -= li * lc[u];
+          }
+        }
+      }
+    }
+  }
+  if (tid < nb) ss.rd[tid] = T(1) / ss.Lcol[tid][tid];
+  __syncthreads();
+  return bad;
+}
+
+// One panel row below the factored diagonal block: x L_jj^T = p in place
+// (row points at column j0 of the row, leading dimension ld).
+template <typename T>
+__device__ __forceinline__ void panel_row(T* row, int64_t ld, int nb, const StepSmem<T>& ss) {
+  T w[kPanel];
+#pragma unroll
+  for (int u = 0; u < kPanel; ++u) {
+    const T g = row[ld * min(u, nb - 1)];
+    w[u] = u < nb ? g : T(0);
+  }
+  // first half on the full window, then on its lower half
+  const int tm = min(nb, kPanel / 2);
+  window_solve<T, kPanel>(w, ss.Lsh, ss.rd, row, ld, 0, tm);
+  window_solve<T, kPanel / 2>(w, ss.Lsh, ss.rd, row, ld, tm, nb);
+}
+
+// The same solve without the look-ahead buffers (about a third of the
+// registers); for kernels that rely on other resident workgroups to hide the
+// LDS latency instead.
+template <typename T>
+__device__ __forceinline__ void panel_row_light(T* row, int64_t ld, int nb,
+                                                const StepSmem<T>& ss) {
+  T w[kPanel];
+#pragma unroll
+  for (int u = 0; u < kPanel; ++u) {
+    const T g = row[ld * min(u, nb - 1)];
+    w[u] = u < nb ? g : T(0);
+  }
+  for (int t = 0; t < nb; ++t) {
+    T l[kPanel];
+#pragma unroll
+    for (int u = 0; u < kPanel; ++u) l[u] = ss.Lsh[t][u];
+    const T x = w[0] * ss.rd[t];
+    row[ld * t] = x;
+#pragma unroll
+    for (int u = 1; u < kPanel; ++u) w[u - 1] = w[u] - l[u] * x;
+    w[kPanel - 1] = T(0);
+  }
+}
+
 // One step of the blocked right-looking Cholesky at block column j0, fused.
 // Every workgroup factors the diagonal block L_jj itself (the redundant work
 // across workgroups costs less than a launch and a round trip through memory)
 // and workgroup 0 stores it to dblk (64 x 64, column-major; the trailing
-// kernel puts it in place).  The four waves share the factorization: lane =
-// row, wave q holds columns 16q .. 16q + 15; at step t the wave owning column
-// t forms L(:, t) and publishes it through LDS, then every wave updates its
-// later columns.  Then each thread solves one panel row below the block,
-// x L_jj^T = p, by forward substitution on a shifting register window, with
-// the columns of L in LDS shifted to start at their diagonal,
-// Lsh[t][u] = L_jj(t + u, t), zero past the block.
+// kernel puts it in place).  Then each thread solves one panel row below the
+// block by forward substitution.
 template <typename T>
 __global__ __launch_bounds__(NTHR) void k_front_step(T* arena, const FrontDesc* __restrict__ fd,
                                                      int j0, T* __restrict__ dblk, int* err) {
-  __shared__ __align__(16) T Lcol[kPanel][kPanel];  // Lcol[t][i] = L_jj(i, t)
-  __shared__ __align__(16) T Lsh[kPanel][kPanel];
-  __shared__ T rd[kPanel];  // 1 / L_jj(t, t)
+  __shared__ StepSmem<T> ss;
   const FrontDesc f = fd[blockIdx.y];
   if (j0 >= f.nI) return;
   const int nb = min(kPanel, f.nI - j0);
@@ -351,84 +463,58 @@ __global__ __launch_bounds__(NTHR) void k_front_step(T* arena, const FrontDesc* 
   if (blockIdx.x > 0 && r0 >= m) return;
   T* col0 = arena + f.off + (int64_t)f.ld * j0;  // column j0 of the front
   const int tid = threadIdx.x;
-  for (int e = tid; e < kPanel * kPanel; e += NTHR) (&Lsh[0][0])[e] = T(0);
-  {
-    const int lane = tid & 63;
-    const int q = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
-    const int rl = min(lane, nb - 1);
-    T w[16];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int c = 16 * q + v;
-      const T g = col0[(int64_t)f.ld * min(c, nb - 1) + j0 + rl];
-      w[v] = (lane < nb && c < nb && c <= lane) ? g : T(0);
-    }
-    __syncthreads();
-    bool bad = false;
-    for (int qt = 0; 16 * qt < nb; ++qt) {
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int t = 16 * qt + v;
-        if (t < nb) {  // uniform; a break here would keep the loop rolled
-          if (q == qt) {
-            T d = read_lane(w[v], t);
-            bad = bad || !(d > T(0));
-            d = d > T(0) ? d : T(1);
-            T ltt, r;
-            if constexpr (sizeof(T) == 4) {
-              r = __builtin_amdgcn_rsqf(d);  // 1 ulp; shortens the serial chain
-              ltt = d * r;
-            } else {
-              ltt = sqrt(d);
-              r = T(1) / ltt;
-            }
-            const T lit = lane > t ? w[v] * r : (lane == t ? ltt : T(0));
-            w[v] = lit;
-            Lcol[t][lane] = lit;
-            if (lane >= t) Lsh[t][lane - t] = lit;
-          }
-          __syncthreads();
-          if (q >= qt) {
-            const T li = Lcol[t][lane];
-            T lc[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) lc[u] = Lcol[t][16 * q + u];
-            if (q > qt) {
-#pragma unroll
-              for (int u = 0; u < 16; ++u) w[u] -= li * lc[u];
-            } else {
-#pragma unroll
-              for (int u = v + 1; u < 16; ++u) w[u] -= li * lc[u];
-            }
-          }
-        }
-      }
-    }
-    if (blockIdx.x == 0 && bad && lane == 0) atomicMin(err, (int)blockIdx.y);
-  }
-  if (tid < nb) rd[tid] = T(1) / Lcol[tid][tid];
+  const bool bad = diag_factor<T>(col0, f.ld, j0, nb, ss);
   if (blockIdx.x == 0) {
+    if (bad && (tid & 63) == 0) atomicMin(err, (int)blockIdx.y);
     T* D = dblk + (int64_t)blockIdx.y * kPanel * kPanel;
     for (int e = tid; e < kPanel * kPanel; e += NTHR) {
       const int c = e >> 6, r = e & 63;
-      D[e] = (r >= c && c < nb) ? Lcol[c][r] : T(0);
+      D[e] = (r >= c && c < nb) ? ss.Lcol[c][r] : T(0);
     }
   }
-  __syncthreads();
   const int i = r0 + tid;
-  if (i < m) {
-    T* row = col0 + j1 + i;
-    T w[kPanel];
-#pragma unroll
-    for (int u = 0; u < kPanel; ++u) {
-      const T g = row[(int64_t)f.ld * min(u, nb - 1)];
-      w[u] = u < nb ? g : T(0);
+  if (i < m) panel_row<T>(col0 + j1 + i, f.ld, nb, ss);
+}
+
+// The whole blocked Cholesky of one small front per workgroup (every step's
+// diagonal block, panel rows and trailing update in one launch), for the many
+// small fronts of the lowest level, where per-step launches would leave the
+// chip waiting on latency.  The step buffers and the GEMM tile share LDS.
+template <typename T>
+__global__ __launch_bounds__(NTHR, 8 / sizeof(T)) void k_front_small(T* arena,
+                                                         const FrontDesc* __restrict__ fd,
+                                                         int* err) {
+  constexpr size_t kBytes = sizeof(StepSmem<T>) > sizeof(TileSmem<T, 64, 64>)
+                                ? sizeof(StepSmem<T>)
+                                : sizeof(TileSmem<T, 64, 64>);
+  __shared__ __align__(16) char smem[kBytes];
+  StepSmem<T>& ss = *reinterpret_cast<StepSmem<T>*>(smem);
+  TileSmem<T, 64, 64>& ts = *reinterpret_cast<TileSmem<T, 64, 64>*>(smem);
+  const FrontDesc f = fd[blockIdx.x];
+  T* base = arena + f.off;
+  const int tid = threadIdx.x;
+  bool bad_any = false;
+  for (int j0 = 0; j0 < f.nI; j0 += kPanel) {
+    const int nb = min(kPanel, f.nI - j0);
+    const int j1 = j0 + nb;
+    T* col0 = base + (int64_t)f.ld * j0;
+    bad_any = diag_factor<T>(col0, f.ld, j0, nb, ss) || bad_any;
+    for (int e = tid; e < kPanel * kPanel; e += NTHR) {
+      const int c = e >> 6, r = e & 63;
+      if (r < nb && c < nb && c <= r) col0[j0 + r + (int64_t)f.ld * c] = ss.Lcol[c][r];
     }
-    // first half on the full window, then on its lower half
-    const int tm = min(nb, kPanel / 2);
-    window_solve<T, kPanel>(w, Lsh, rd, row, f.ld, 0, tm);
-    window_solve<T, kPanel / 2>(w, Lsh, rd, row, f.ld, tm, nb);
+    for (int i = tid; i < f.nR - j1; i += NTHR) panel_row_light<T>(col0 + j1 + i, f.ld, nb, ss);
+    __syncthreads();  // panel rows visible to the whole workgroup; LDS free
+    const int m = f.nR - j1, n = f.nI - j1;
+    const T* P = col0 + j1;
+    for (int n0 = 0; n0 < n; n0 += 64)
+      for (int m0 = n0; m0 < m; m0 += 64)
+        gemm_tile_t<T, T, OP_N, OP_T, 64, 64>(GF_C_LOWER, P, f.ld, P, f.ld,
+                                              base + j1 + (int64_t)f.ld * j1, f.ld, m, n, nb, m0,
+                                              n0, T(-1), T(1), ts);
+    __syncthreads();
   }
+  if (bad_any && (tid & 63) == 0) atomicMin(err, (int)blockIdx.x);
 }
 
 // In-place inverse of every 64 x 64 diagonal block of the factored L_I, one
@@ -731,6 +817,21 @@ void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
   HIF_REQUIRE(batch <= 65535, HIF_EINVAL, "too many fronts in one launch");
   int maxI = 0;
   for (auto& f : h_fronts) maxI = std::max(maxI, f.nI);
+  if (maxI <= kSmallFront) {
+    double fl = 0.0;
+    for (auto& f : h_fronts) {
+      const double nI = f.nI, nS = f.nR - f.nI;
+      fl += nI * nI * nI / 3.0 + nS * nI * nI;
+    }
+    {
+      ProfScope ps("potrf_small", s, fl);
+      hipLaunchKernelGGL((k_front_small<T>), dim3((unsigned)batch), dim3(NTHR), 0, s, arena,
+                         d_fronts, err);
+      HIF_LAUNCH_CHECK();
+    }
+    front_invert<T>(arena, d_fronts, h_fronts, s);
+    return;
+  }
   DevBuf<T> dblk((size_t)batch * kPanel * kPanel);
   // Trailing update of panel columns [p0, p0 + pw) into [c0, c0 + cw) (j0 >= 0:
   // also put step j0's diagonal blocks in place).
