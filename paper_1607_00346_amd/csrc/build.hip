@@ -100,7 +100,9 @@ __device__ __forceinline__ int wave_column(int block) {
   return block * kGatherCols + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 }
 
-// Front of cell c, column j: A_II(i, j) for i >= j into Phi.
+// Front of cell c, column j: A_II(i, j) for i >= j into Phi, and zeros above
+// the diagonal (the factorization keeps them, so the inverse's products need
+// no triangular masks).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_gather_front(Src<T> s, const int* __restrict__ rows,
                                                      const int64_t* __restrict__ crow_off,
@@ -113,6 +115,7 @@ __global__ __launch_bounds__(NT) void k_gather_front(Src<T> s, const int* __rest
   const int* r = rows + crow_off[c];
   const ColLookup<T> cl = col_lookup(s, r[j]);
   T* col = arena + f.off + (int64_t)f.ld * j;
+  for (int i = lane; i < j; i += 64) col[i] = T(0);
   for (int i = j + lane; i < f.nI; i += 64) col[i] = row_lookup(s, cl, r[i]);
 }
 
@@ -487,7 +490,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
       std::vector<FrontDesc> top = lev.hfd;
       for (auto& d : top) d.nR = d.nI;
       DevBuf<FrontDesc> d_top = to_dev(top, s);
-      front_factor<T>(lev.front.get(), d_top.get(), top, d_err.get() + 2 * level, s);
+      front_factor<T>(lev.front.get(), d_top.get(), top, d_err.get() + 2 * level, s, true);
       // L_SI = A_SI L_I^{-T} into the front below L_I^{-1} (L_I^{-T} is upper)
       std::vector<GemmDesc> gd;
       for (int c = 0; c < P.ncell; ++c) {
@@ -497,7 +500,8 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
         gd.push_back({ASI.get() + xoff[c], base, base + d.nI, P.cS[c], d.nI, d.nI, P.cS[c], d.ld,
                       d.ld});
       }
-      run_gemms<T, T>("gemm_lsi", OP_N, OP_T, GF_B_UPPER, gd, T(1), T(0), s, GC_LSI);
+      run_gemms<T, T>("gemm_lsi", OP_N, OP_T, GF_B_UPPER | GF_TRI_ZEROS, gd, T(1), T(0), s,
+                      GC_LSI);
     }
 
     if (!P.root) {
@@ -669,7 +673,8 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
             if (lev.hsk[i].k > 0) tri.push_back({o11[i], lev.hsk[i].k, lev.hsk[i].k, lev.hsk[i].k, 0});
           if (!tri.empty()) {
             DevBuf<FrontDesc> d_tri = to_dev(tri, s);
-            front_invert<double>(L11.get(), d_tri.get(), tri, s);
+            // L11 holds zeros above the diagonal (rows pivoted earlier)
+            front_invert<double>(L11.get(), d_tri.get(), tri, s, true);
           }
           DevBuf<double> Td;
           if (!std::is_same<T, double>::value) Td.alloc(std::max<int64_t>(ssz, 1));
@@ -727,7 +732,7 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
             cfd.push_back({lev.hsk[i].offL, lev.hsk[i].r, lev.hsk[i].r, lev.hsk[i].r, 0});
           {
             DevBuf<FrontDesc> d_cfd = to_dev(cfd, s);
-            front_factor<T>(SK, d_cfd.get(), cfd, d_err.get() + 2 * level + 1, s);
+            front_factor<T>(SK, d_cfd.get(), cfd, d_err.get() + 2 * level + 1, s, false);
           }
           run_gemms<T, T>("gemm_skel", OP_N, OP_T, GF_A_LOWER, g4, T(1), T(0), s);
           run_gemms<T, T>("gemm_skel", OP_T, OP_N, 0, g5, T(-1), T(1), s);

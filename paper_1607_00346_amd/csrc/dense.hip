@@ -110,6 +110,7 @@ __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, co
   }
   auto clean = [&](int t0) {
     bool c = t0 + KC <= ke;
+    if (flags & GF_TRI_ZEROS) return c;
     if (flags & GF_A_LOWER) c = c && t0 + KC - 1 <= m0;
     if (flags & GF_A_UPPER) c = c && t0 >= m0 + TM - 1;
     if (flags & GF_B_LOWER) c = c && t0 >= n0 + TN - 1;
@@ -811,7 +812,7 @@ double gemm_flops(const GemmDesc& d, int flags) {
 
 template <typename T>
 void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  int* err, hipStream_t s) {
+                  int* err, hipStream_t s, bool upper_zero) {
   const int batch = (int)h_fronts.size();
   if (batch == 0) return;
   HIF_REQUIRE(batch <= 65535, HIF_EINVAL, "too many fronts in one launch");
@@ -829,7 +830,7 @@ void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
                          d_fronts, err);
       HIF_LAUNCH_CHECK();
     }
-    front_invert<T>(arena, d_fronts, h_fronts, s);
+    front_invert<T>(arena, d_fronts, h_fronts, s, upper_zero);
     return;
   }
   DevBuf<T> dblk((size_t)batch * kPanel * kPanel);
@@ -890,7 +891,7 @@ void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
     }
     if (J + kSuper < maxI) trailing(-1, J, kSuper, J + kSuper, maxI);
   }
-  front_invert<T>(arena, d_fronts, h_fronts, s);
+  front_invert<T>(arena, d_fronts, h_fronts, s, upper_zero);
 }
 
 // In-place inverse of the lower-triangular L_I of every front, bottom-up over
@@ -898,7 +899,8 @@ void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
 // inv([[A, 0], [B, C]]) = [[A^-1, 0], [-C^-1 B A^-1, C^-1]].
 template <typename T>
 void front_invert(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  hipStream_t s) {
+                  hipStream_t s, bool upper_zero) {
+  const int zf = upper_zero ? GF_TRI_ZEROS : 0;
   const int batch = (int)h_fronts.size();
   if (batch == 0) return;
   HIF_REQUIRE(batch <= 65535, HIF_EINVAL, "too many fronts in one launch");
@@ -946,9 +948,9 @@ void front_invert(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
     if (g1.empty()) continue;
     d1.upload(g1, s);
     d2.upload(g2, s);
-    gemm_batched<T, T>(OP_N, OP_N, GF_B_LOWER, d1.get(), (int)g1.size(), mm, sz, T(1), T(0), s,
+    gemm_batched<T, T>(OP_N, OP_N, GF_B_LOWER | zf, d1.get(), (int)g1.size(), mm, sz, T(1), T(0), s,
                        "trtri_gemm", f1);
-    gemm_batched<T, T>(OP_N, OP_N, GF_A_LOWER, d2.get(), (int)g2.size(), mm, sz, T(-1), T(0), s,
+    gemm_batched<T, T>(OP_N, OP_N, GF_A_LOWER | zf, d2.get(), (int)g2.size(), mm, sz, T(-1), T(0), s,
                        "trtri_gemm", f2);
   }
 }
@@ -1014,12 +1016,12 @@ template void gemm_batched<float, float>(int, int, int, const GemmDesc*, int, in
 template void gemm_batched<float, double>(int, int, int, const GemmDesc*, int, int, int, double,
                                           double, hipStream_t, const char*, double, int);
 template void front_factor<double>(double*, const FrontDesc*, const std::vector<FrontDesc>&,
-                                   int*, hipStream_t);
+                                   int*, hipStream_t, bool);
 template void front_factor<float>(float*, const FrontDesc*, const std::vector<FrontDesc>&, int*,
-                                  hipStream_t);
+                                  hipStream_t, bool);
 template void front_invert<double>(double*, const FrontDesc*, const std::vector<FrontDesc>&,
-                                   hipStream_t);
+                                   hipStream_t, bool);
 template void front_invert<float>(float*, const FrontDesc*, const std::vector<FrontDesc>&,
-                                  hipStream_t);
+                                  hipStream_t, bool);
 
 }  // namespace hif

@@ -27,6 +27,8 @@ enum : int {
   GF_B_UPPER = 8,   // op(B)(t,j) = 0 for t > j
   GF_C_LOWER = 16,  // only C(i,j) with i >= j is computed and written
   GF_C_MIRROR = 32, // with GF_C_LOWER (square C): C(j,i) is written too
+  GF_TRI_ZEROS = 64, // the entries that GF_A_* / GF_B_* mask are stored as zeros, so the
+                     // masks only shorten the K range of a tile
 };
 
 struct GemmDesc {
@@ -71,15 +73,17 @@ constexpr int kPanel = 64;  // block width of the blocked factorizations
 
 // Partial Cholesky of the first nI columns of every front (rows nI..nR-1 get
 // A_SI L_I^{-T}), then L_I <- L_I^{-1} in place.  err[0] receives the smallest
-// batch index with a non-positive pivot (untouched otherwise).
+// batch index with a non-positive pivot (untouched otherwise).  upper_zero:
+// the strict upper triangle of every nI x nI block is stored as zeros (the
+// factorization keeps it so, and the inverse can then skip its masks).
 template <typename T>
 void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  int* err, hipStream_t s);
+                  int* err, hipStream_t s, bool upper_zero);
 
 // Only the in-place inverse of an already factored lower-triangular L_I.
 template <typename T>
 void front_invert(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  hipStream_t s);
+                  hipStream_t s, bool upper_zero);
 
 // Pivoted Cholesky of each symmetric G_b (nF x nF, FP64, offset goff[b], ld
 // ldg[b]), blocked: G is overwritten by its trailing updates.  Writes the
