@@ -98,6 +98,19 @@ hif_status hif_problem_create(const hif_options* opts, const double* a, const do
 hif_status hif_build(hif_problem_t A, const hif_options* opts, void* stream,
                      hif_factor_t* out);
 
+/* Factor `count` problems together (paper, Sections 2.2-2.4 and 3.2, as in
+ * hif_build): level l of every problem, counted from the leaves, runs as one
+ * set of batched launches over the fronts and faces of all problems, and the
+ * host waits once per level for all of them.  A, opts and out are host
+ * arrays of `count` entries; opts[i] describes A[i] (grids and leaf sizes may
+ * differ; precision and eps must be the same for all).  A problem listed
+ * twice needs the same leaf both times.  On success out[i] receives the
+ * factor of A[i], which is used and destroyed like one from hif_build; its
+ * level_seconds and build_seconds are those of the joint build.  On error
+ * every out[i] is NULL and nothing leaks.  Blocks the calling thread. */
+hif_status hif_build_batched(int32_t count, const hif_problem_t* A, const hif_options* opts,
+                             void* stream, hif_factor_t* out);
+
 /* u = F^{-1} f for nrhs column-major vectors (paper, Section 2.4: the
  * product W^0..W^L D^{-1} W^L^T..W^0^T).  FP64 in and out (the mixed factor
  * is read in FP32, accumulated in FP64).  u may alias f.  Asynchronous on

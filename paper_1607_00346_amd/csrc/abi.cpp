@@ -110,6 +110,43 @@ hif_status hif_build(hif_problem_t A, const hif_options* opts, void* stream, hif
   });
 }
 
+hif_status hif_build_batched(int32_t count, const hif_problem_t* A, const hif_options* opts,
+                             void* stream, hif_factor_t* out) {
+  if (out && count > 0)
+    for (int32_t i = 0; i < count; ++i) out[i] = nullptr;
+  return guarded([&] {
+    HIF_REQUIRE(count >= 1, HIF_EINVAL, "count must be >= 1");
+    HIF_REQUIRE(A != nullptr && opts != nullptr && out != nullptr, HIF_EINVAL, "NULL array");
+    for (int32_t i = 0; i < count; ++i) {
+      HIF_REQUIRE(A[i] != nullptr, HIF_EINVAL, "NULL problem handle");
+      check_options(&opts[i]);
+      HIF_REQUIRE(opts[i].n == A[i]->n, HIF_EINVAL,
+                  "options describe another grid than the problem");
+      HIF_REQUIRE(opts[i].precision == opts[0].precision && opts[i].eps == opts[0].eps,
+                  HIF_EINVAL, "the problems of a batch must share precision and eps");
+    }
+    hif::StreamScope scope(as_stream(stream));
+    hif::Staging staging(as_stream(stream));  // synchronizes the stream when the build ends
+    std::vector<std::unique_ptr<hif_factor_s>> F(count);
+    std::vector<hif::BuildRequest> req(count);
+    for (int32_t i = 0; i < count; ++i) {
+      F[i].reset(new hif_factor_s());
+      F[i]->opts = opts[i];
+      req[i] = {A[i], opts[i], F[i].get()};
+    }
+    try {
+      if (opts[0].precision == HIF_MIXED)
+        hif::build_factors<float>(req, as_stream(stream));
+      else
+        hif::build_factors<double>(req, as_stream(stream));
+    } catch (...) {
+      (void)hipStreamSynchronize(as_stream(stream));
+      throw;
+    }
+    for (int32_t i = 0; i < count; ++i) out[i] = F[i].release();
+  });
+}
+
 hif_status hif_apply(hif_factor_t F, const double* f, double* u, int32_t nrhs, void* stream) {
   return guarded([&] {
     HIF_REQUIRE(F != nullptr && F->impl, HIF_EINVAL, "NULL factor");

@@ -106,7 +106,7 @@ __device__ __forceinline__ int wave_column(int block) {
 template <typename T>
 __global__ __launch_bounds__(NT) void k_gather_front(Src<T> s, const int* __restrict__ rows,
                                                      const int64_t* __restrict__ crow_off,
-                                                     const FrontDesc* __restrict__ fd, T* arena) {
+                                                     const FrontDesc* __restrict__ fd) {
   const int c = blockIdx.y;
   const FrontDesc f = fd[c];
   const int j = wave_column(blockIdx.x);
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(NT) void k_gather_front(Src<T> s, const int* __rest
   const int lane = threadIdx.x & 63;
   const int* r = rows + crow_off[c];
   const ColLookup<T> cl = col_lookup(s, r[j]);
-  T* col = arena + f.off + (int64_t)f.ld * j;
+  T* col = static_cast<T*>(f.ptr) + (int64_t)f.ld * j;
   for (int i = lane; i < j; i += 64) col[i] = T(0);
   for (int i = j + lane; i < f.nI; i += 64) col[i] = row_lookup(s, cl, r[i]);
 }
@@ -353,57 +353,121 @@ double now_s() {
 
 }  // namespace
 
+namespace {
+
+// One problem of a batch while the batch is factored level by level.
 template <typename T>
-void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, hif_factor_s* F) {
-  const int n = A->n;
-  const int leaf = o.leaf;
-  const int L = levels_for(n, leaf);
-  HIF_REQUIRE(L >= 0 && L <= HIF_MAX_LEVELS - 1, HIF_EINVAL, "n must be leaf * 2^L");
-  const int64_t N = A->N;
-  auto impl = std::make_unique<FactorImpl<T>>();
-  FactorImpl<T>& Fi = *impl;
-  Fi.n = n;
-  Fi.L = L;
-  Fi.N = N;
-  Fi.levels.resize(L + 1);
-  hif_stats& st = F->stats;
-  std::memset(&st, 0, sizeof(st));
-  st.levels = L;
-  st.precision = o.precision;
-  st.n_dof = N;
+struct Job {
+  const hif_problem_s* A = nullptr;
+  hif_options o{};
+  hif_factor_s* F = nullptr;
+  std::unique_ptr<FactorImpl<T>> impl;
+  int L = 0;
+  int64_t N = 0;
+  double flops = 0.0;
+  // 0 for points the ID has left out so far (the candidates of a level are
+  // separator points of the level below, so interior points never need it)
+  std::vector<uint8_t> active;
+  // face / local index of every level-(l-1) face point, for the A^l lookup
+  DevBuf<int> d_pface, d_ploc;
+  // temporaries of the current level
+  DevBuf<T> ASI, U, Ahh, Ahc;
+  DevBuf<int64_t> d_xoff, d_o11, d_o21, d_ohh, d_ohc;
+  DevBuf<double> L11, L21, Td;
+  std::vector<int64_t> uoff, poff, o11, o21, ohh, ohc;
+  std::vector<int> uld, pld, hperm;
+  int64_t face0 = 0;  // first face of this problem in the level's joint ID arrays
+  int64_t pt0 = 0;    // first face point of this problem in the joint pivot order
+  int64_t ssz = 0;    // skeleton arena size of the level
+};
+
+// The problem and the cell (or skeleton) that a front id of a joint launch names.
+struct Owner {
+  int job, index;
+};
+
+}  // namespace
+
+// Factors a batch of problems together: level l of every problem (counted from
+// the leaves) is one set of launches, so fronts and faces of all problems share
+// each batched kernel, and the host waits once per level for all of them.
+template <typename T>
+void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
+  const int nj = (int)req.size();
+  HIF_REQUIRE(nj >= 1, HIF_EINVAL, "no problems to factor");
   const double t_begin = now_s();
   const int64_t mem0 = mem_stats().live;
   mem_stats().peak = mem0;
-
-  if (A->geom_leaf != leaf) {
-    A->geom = plan_geometry(n, leaf);
-    A->plan0 = std::make_shared<const LevelPlan>(
-        plan_level(A->geom[0], std::vector<uint8_t>((size_t)N, 1)));
-    A->dev0 = {};
-    A->geom_leaf = leaf;
+  const double eps = req[0].o.eps;
+  for (int j = 0; j < nj; ++j) {
+    HIF_REQUIRE(req[j].o.eps == eps, HIF_EINVAL, "the problems of a batch must share eps");
+    for (int i = 0; i < j; ++i)
+      HIF_REQUIRE(req[i].A != req[j].A || req[i].o.leaf == req[j].o.leaf, HIF_EINVAL,
+                  "a problem listed twice in a batch needs the same leaf size");
   }
-  // 0 for points the ID has left out so far (the candidates of a level are
-  // separator points of the level below, so interior points never need it)
-  std::vector<uint8_t> active(N, 1);
-  // face / local index of every level-(l-1) face point, for the A^l lookup
-  DevBuf<int> d_pface(L > 0 ? N : 0), d_ploc(L > 0 ? N : 0);
-  // failure flags: per level, the interior Cholesky (cell) and the Cholesky of
-  // B_F̌F̌ (skeleton index); checked whenever the host synchronizes anyway
+  std::vector<Job<T>> jobs(nj);
+  int maxL = 0;
+  for (int j = 0; j < nj; ++j) {
+    Job<T>& J = jobs[j];
+    J.A = req[j].A;
+    J.o = req[j].o;
+    J.F = req[j].F;
+    const int n = J.A->n;
+    J.L = levels_for(n, J.o.leaf);
+    HIF_REQUIRE(J.L >= 0 && J.L <= HIF_MAX_LEVELS - 1, HIF_EINVAL, "n must be leaf * 2^L");
+    J.N = J.A->N;
+    J.impl = std::make_unique<FactorImpl<T>>();
+    J.impl->n = n;
+    J.impl->L = J.L;
+    J.impl->N = J.N;
+    J.impl->levels.resize(J.L + 1);
+    hif_stats& st = J.F->stats;
+    std::memset(&st, 0, sizeof(st));
+    st.levels = J.L;
+    st.precision = J.o.precision;
+    st.n_dof = J.N;
+    const hif_problem_s* A = J.A;
+    if (A->geom_leaf != J.o.leaf) {
+      A->geom = plan_geometry(n, J.o.leaf);
+      A->plan0 = std::make_shared<const LevelPlan>(
+          plan_level(A->geom[0], std::vector<uint8_t>((size_t)J.N, 1)));
+      A->dev0 = {};
+      A->geom_leaf = J.o.leaf;
+    }
+    J.active.assign((size_t)J.N, 1);
+    if (J.L > 0) {
+      J.d_pface.alloc(J.N);
+      J.d_ploc.alloc(J.N);
+    }
+    maxL = std::max(maxL, J.L);
+  }
+  auto of_problem = [&](int j) {
+    return nj > 1 ? " of problem " + std::to_string(j) : std::string();
+  };
+  // failure flags: per level, the interior Cholesky (front id) and the Cholesky
+  // of B_F̌F̌ (skeleton id); checked whenever the host synchronizes anyway
   const int kNoErr = INT_MAX;
-  std::vector<int> h_err(2 * (L + 1), kNoErr);
+  std::vector<int> h_err(2 * (maxL + 1), kNoErr);
   DevBuf<int> d_err = to_dev(h_err, s);
+  std::vector<std::vector<Owner>> own_front(maxL + 1), own_skel(maxL + 1);
   auto check_errors = [&]() {
     HIF_HIP(hipMemcpyAsync(h_err.data(), d_err.get(), sizeof(int) * h_err.size(),
                            hipMemcpyDeviceToHost, s));
     HIF_HIP(hipStreamSynchronize(s));
-    for (int l = 0; l <= L; ++l) {
-      if (h_err[2 * l] != kNoErr)
+    for (int l = 0; l <= maxL; ++l) {
+      if (h_err[2 * l] != kNoErr) {
+        const Owner w = own_front[l].at(h_err[2 * l]);
         throw Error(HIF_ENOTSPD, "non-positive pivot in the interior Cholesky at level " +
-                                     std::to_string(l) + ", cell " + std::to_string(h_err[2 * l]));
-      if (h_err[2 * l + 1] != kNoErr)
-        throw Error(HIF_ENOTSPD, "non-positive pivot in B_F̌F̌ at level " + std::to_string(l) +
-                                     ", face " +
-                                     std::to_string(Fi.levels[l].hsk[h_err[2 * l + 1]].face));
+                                     std::to_string(l) + ", cell " + std::to_string(w.index) +
+                                     of_problem(w.job));
+      }
+      if (h_err[2 * l + 1] != kNoErr) {
+        const Owner w = own_skel[l].at(h_err[2 * l + 1]);
+        throw Error(HIF_ENOTSPD,
+                    "non-positive pivot in B_F̌F̌ at level " + std::to_string(l) + ", face " +
+                        std::to_string(jobs[w.job].impl->levels[l].hsk[w.index].face) +
+                        of_problem(w.job));
+      }
     }
   };
   // device-side level timing
@@ -413,128 +477,174 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
       for (hipEvent_t x : e) (void)hipEventDestroy(x);
     }
   } ev;
-  ev.e.resize(L + 2, nullptr);
+  ev.e.resize(maxL + 2, nullptr);
   for (auto& x : ev.e) HIF_HIP(hipEventCreate(&x));
-  double flops = 0.0;
 
-  for (int level = 0; level <= L; ++level) {
+  for (int level = 0; level <= maxL; ++level) {
     HIF_HIP(hipEventRecord(ev.e[level], s));
     profiler().level = level;
-    Level<T>& lev = Fi.levels[level];
-    Level<T>* prev = level > 0 ? &Fi.levels[level - 1] : nullptr;
-    lev.plan = level == 0 ? A->plan0
-                          : std::make_shared<const LevelPlan>(plan_level(A->geom[level], active));
-    const LevelPlan& P = *lev.plan;
-    const Src<T> src = make_src<T>(A, prev, d_pface.get(), d_ploc.get());
-    // index arrays of the plan; level 0's are uploaded once per problem
-    auto arr = [&](auto& cached, const auto& host) {
-      if (level > 0) return dev_arr(host, s);
-      if (!cached.buf) cached = dev_arr(host, s);
-      return cached;
-    };
+    std::vector<int> here, below;  // problems with this level; those for which it is not the root
+    for (int j = 0; j < nj; ++j) {
+      if (level <= jobs[j].L) here.push_back(j);
+      if (level < jobs[j].L) below.push_back(j);
+    }
 
     // ---- fronts: gather, partial Cholesky + inverse (Section 2.2) -------
-    lev.rows = arr(A->dev0.rows, P.rows);
-    lev.crow_off = arr(A->dev0.crow_off, P.crow_off);
-    lev.hfd.resize(P.ncell);
-    int64_t off = 0;
-    std::vector<int64_t> yoff(P.ncell), zoff(P.ncell);
-    for (int c = 0; c < P.ncell; ++c) {
-      FrontDesc& d = lev.hfd[c];
-      d.off = off;
-      d.nI = P.cI[c];
-      d.nR = P.cI[c] + P.cS[c];
-      d.ld = pad_ld(d.nR);
-      d.pad_ = 0;
-      off += (int64_t)d.ld * d.nI;
-      yoff[c] = lev.ysum;
-      zoff[c] = lev.zsum;
-      lev.ysum += d.nI;
-      lev.zsum += P.cS[c];
-      lev.maxI = std::max(lev.maxI, d.nI);
-      lev.maxS = std::max(lev.maxS, P.cS[c]);
-      const double nI = d.nI, nS = P.cS[c];
-      flops += nI * nI * nI / 3.0 + nS * nI * nI + nI * nI * nI / 3.0 + nS * nS * nI;
-      st.max_front[level] = std::max<int64_t>(st.max_front[level], d.nR);
-    }
-    lev.fd = to_dev(lev.hfd, s);
-    lev.yoff = to_dev(yoff, s);
-    lev.zoff = to_dev(zoff, s);
-    lev.front.alloc(off);
-    st.cells[level] = P.ncell;
-    st.eliminated[level] = lev.ysum;
-    // A_SI (nS x nI per cell) until L_SI = A_SI L_I^{-T} is formed
-    std::vector<int64_t> xoff(P.ncell);
-    int64_t xsz = 0;
-    for (int c = 0; c < P.ncell; ++c) {
-      xoff[c] = xsz;
-      xsz += (int64_t)P.cI[c] * P.cS[c];
-    }
-    if (P.ncell > 0) {
-      DevBuf<T> ASI(std::max<int64_t>(xsz, 1));
-      DevBuf<int64_t> d_xoff = to_dev(xoff, s);
+    std::vector<FrontDesc> tops;
+    std::vector<GemmDesc> g_lsi;
+    for (int j : here) {
+      Job<T>& J = jobs[j];
+      const hif_problem_s* A = J.A;
+      hif_stats& st = J.F->stats;
+      Level<T>& lev = J.impl->levels[level];
+      Level<T>* prev = level > 0 ? &J.impl->levels[level - 1] : nullptr;
+      lev.plan = level == 0 ? A->plan0
+                            : std::make_shared<const LevelPlan>(plan_level(A->geom[level], J.active));
+      const LevelPlan& P = *lev.plan;
+      const Src<T> src = make_src<T>(A, prev, J.d_pface.get(), J.d_ploc.get());
+      // index arrays of the plan; level 0's are uploaded once per problem
+      auto arr = [&](auto& cached, const auto& host) {
+        if (level > 0) return dev_arr(host, s);
+        if (!cached.buf) cached = dev_arr(host, s);
+        return cached;
+      };
+      lev.rows = arr(A->dev0.rows, P.rows);
+      lev.crow_off = arr(A->dev0.crow_off, P.crow_off);
+      lev.hfd.resize(P.ncell);
+      int64_t off = 0;
+      std::vector<int64_t> foff(P.ncell), yoff(P.ncell), zoff(P.ncell);
+      for (int c = 0; c < P.ncell; ++c) {
+        FrontDesc& d = lev.hfd[c];
+        foff[c] = off;
+        d.nI = P.cI[c];
+        d.nR = P.cI[c] + P.cS[c];
+        d.ld = pad_ld(d.nR);
+        d.id = c;
+        off += (int64_t)d.ld * d.nI;
+        yoff[c] = lev.ysum;
+        zoff[c] = lev.zsum;
+        lev.ysum += d.nI;
+        lev.zsum += P.cS[c];
+        lev.maxI = std::max(lev.maxI, d.nI);
+        lev.maxS = std::max(lev.maxS, P.cS[c]);
+        const double nI = d.nI, nS = P.cS[c];
+        J.flops += nI * nI * nI / 3.0 + nS * nI * nI + nI * nI * nI / 3.0 + nS * nS * nI;
+        st.max_front[level] = std::max<int64_t>(st.max_front[level], d.nR);
+      }
+      lev.front.alloc(off);
+      for (int c = 0; c < P.ncell; ++c) lev.hfd[c].ptr = lev.front.get() + foff[c];
+      lev.fd = to_dev(lev.hfd, s);
+      lev.yoff = to_dev(yoff, s);
+      lev.zoff = to_dev(zoff, s);
+      st.cells[level] = P.ncell;
+      st.eliminated[level] = lev.ysum;
+      if (P.ncell == 0) continue;
+      // A_SI (nS x nI per cell) until L_SI = A_SI L_I^{-T} is formed
+      std::vector<int64_t> xoff(P.ncell);
+      int64_t xsz = 0;
+      for (int c = 0; c < P.ncell; ++c) {
+        xoff[c] = xsz;
+        xsz += (int64_t)P.cI[c] * P.cS[c];
+      }
+      J.ASI.alloc(std::max<int64_t>(xsz, 1));
+      J.d_xoff = to_dev(xoff, s);
       {
         ProfScope ps("gather_front", s);
         dim3 g((unsigned)ceil_div(std::max(1, lev.maxI), kGatherCols), (unsigned)P.ncell);
         hipLaunchKernelGGL((k_gather_front<T>), g, dim3(NT), 0, s, src, lev.rows.get(),
-                           lev.crow_off.get(), lev.fd.get(), lev.front.get());
+                           lev.crow_off.get(), lev.fd.get());
         HIF_LAUNCH_CHECK();
         if (lev.maxS > 0) {
-          dim3 g2((unsigned)ceil_div(std::max(1, lev.maxI), kGatherCols), (unsigned)P.ncell);
-          hipLaunchKernelGGL((k_gather_front_SI<T>), g2, dim3(NT), 0, s, src, lev.rows.get(),
-                             lev.crow_off.get(), lev.fd.get(), ASI.get(), d_xoff.get());
+          hipLaunchKernelGGL((k_gather_front_SI<T>), g, dim3(NT), 0, s, src, lev.rows.get(),
+                             lev.crow_off.get(), lev.fd.get(), J.ASI.get(), J.d_xoff.get());
           HIF_LAUNCH_CHECK();
         }
       }
       // interior Cholesky and in-place inverse on the top nI x nI block
-      std::vector<FrontDesc> top = lev.hfd;
-      for (auto& d : top) d.nR = d.nI;
-      DevBuf<FrontDesc> d_top = to_dev(top, s);
-      front_factor<T>(lev.front.get(), d_top.get(), top, d_err.get() + 2 * level, s, true);
+      for (int c = 0; c < P.ncell; ++c) {
+        FrontDesc t = lev.hfd[c];
+        t.nR = t.nI;
+        t.id = (int)own_front[level].size();
+        own_front[level].push_back({j, c});
+        tops.push_back(t);
+      }
       // L_SI = A_SI L_I^{-T} into the front below L_I^{-1} (L_I^{-T} is upper)
-      std::vector<GemmDesc> gd;
       for (int c = 0; c < P.ncell; ++c) {
         if (P.cS[c] == 0) continue;
         const FrontDesc& d = lev.hfd[c];
-        T* base = lev.front.get() + d.off;
-        gd.push_back({ASI.get() + xoff[c], base, base + d.nI, P.cS[c], d.nI, d.nI, P.cS[c], d.ld,
-                      d.ld});
+        T* base = static_cast<T*>(d.ptr);
+        g_lsi.push_back({J.ASI.get() + xoff[c], base, base + d.nI, P.cS[c], d.nI, d.nI, P.cS[c],
+                         d.ld, d.ld});
       }
-      run_gemms<T, T>("gemm_lsi", OP_N, OP_T, GF_B_UPPER | GF_TRI_ZEROS, gd, T(1), T(0), s,
-                      GC_LSI);
     }
-
-    if (!P.root) {
-      // ---- Schur updates U_c = -L_SI L_SI^T (both triangles) -----------
-      std::vector<int64_t> uoff(P.ncell);
-      std::vector<int> uld(P.ncell);
-      int64_t usz = 0;
-      for (int c = 0; c < P.ncell; ++c) {
-        uoff[c] = usz;
-        uld[c] = std::max(1, P.cS[c]);
-        usz += (int64_t)uld[c] * P.cS[c];
+    if (!tops.empty()) {
+      DevBuf<FrontDesc> d_top = to_dev(tops, s);
+      front_factor<T>(d_top.get(), tops, d_err.get() + 2 * level, s, true);
+    }
+    run_gemms<T, T>("gemm_lsi", OP_N, OP_T, GF_B_UPPER | GF_TRI_ZEROS, g_lsi, T(1), T(0), s,
+                    GC_LSI);
+    for (int j : here) {
+      jobs[j].ASI.release();
+      jobs[j].d_xoff.release();
+      if (level == jobs[j].L) {  // the root: a dense factor, no faces
+        Level<T>& lev = jobs[j].impl->levels[level];
+        jobs[j].F->stats.root_size = lev.ysum;
+        if (level > 0) jobs[j].impl->levels[level - 1].panel.release();
       }
-      DevBuf<T> U(std::max<int64_t>(usz, 1));
-      {
-        std::vector<GemmDesc> gd;
+    }
+    if (below.empty()) continue;
+
+    // ---- Schur updates U_c = -L_SI L_SI^T (both triangles) ---------------
+    {
+      std::vector<GemmDesc> gd;
+      for (int j : below) {
+        Job<T>& J = jobs[j];
+        Level<T>& lev = J.impl->levels[level];
+        const LevelPlan& P = *lev.plan;
+        J.uoff.assign(P.ncell, 0);
+        J.uld.assign(P.ncell, 1);
+        int64_t usz = 0;
+        for (int c = 0; c < P.ncell; ++c) {
+          J.uoff[c] = usz;
+          J.uld[c] = std::max(1, P.cS[c]);
+          usz += (int64_t)J.uld[c] * P.cS[c];
+        }
+        J.U.alloc(std::max<int64_t>(usz, 1));
         for (int c = 0; c < P.ncell; ++c) {
           if (P.cS[c] == 0) continue;
           const FrontDesc& d = lev.hfd[c];
-          const T* LSI = lev.front.get() + d.off + d.nI;
-          gd.push_back({LSI, LSI, U.get() + uoff[c], P.cS[c], P.cS[c], d.nI, d.ld, d.ld, uld[c]});
+          const T* LSI = static_cast<const T*>(d.ptr) + d.nI;
+          gd.push_back(
+              {LSI, LSI, J.U.get() + J.uoff[c], P.cS[c], P.cS[c], d.nI, d.ld, d.ld, J.uld[c]});
         }
-        // both triangles of U, so that the panel gather reads columns only
-        run_gemms<T, T>("gemm_syrk", OP_N, OP_T, GF_C_LOWER | GF_C_MIRROR, gd, T(-1), T(0), s,
-                        GC_SYRK);
       }
-      // ---- face panels Ã^l([F; R-faces], F) ------------------------------
-      std::vector<int64_t> poff(P.nface);
-      std::vector<int> pld(P.nface);
+      // both triangles of U, so that the panel gather reads columns only
+      run_gemms<T, T>("gemm_syrk", OP_N, OP_T, GF_C_LOWER | GF_C_MIRROR, gd, T(-1), T(0), s,
+                      GC_SYRK);
+    }
+
+    // ---- face panels Ã^l([F; R-faces], F) --------------------------------
+    int64_t nface_all = 0, npt_all = 0;
+    for (int j : below) {
+      Job<T>& J = jobs[j];
+      const hif_problem_s* A = J.A;
+      hif_stats& st = J.F->stats;
+      Level<T>& lev = J.impl->levels[level];
+      Level<T>* prev = level > 0 ? &J.impl->levels[level - 1] : nullptr;
+      const LevelPlan& P = *lev.plan;
+      const Src<T> src = make_src<T>(A, prev, J.d_pface.get(), J.d_ploc.get());
+      auto arr = [&](auto& cached, const auto& host) {
+        if (level > 0) return dev_arr(host, s);
+        if (!cached.buf) cached = dev_arr(host, s);
+        return cached;
+      };
+      J.poff.assign(P.nface, 0);
+      J.pld.assign(P.nface, 1);
       int64_t psz = 0;
       for (int f = 0; f < P.nface; ++f) {
-        poff[f] = psz;
-        pld[f] = pad_ld(P.prow[f]);
-        psz += (int64_t)pld[f] * P.fN[f];
+        J.poff[f] = psz;
+        J.pld[f] = pad_ld(P.prow[f]);
+        psz += (int64_t)J.pld[f] * P.fN[f];
         lev.maxF = std::max(lev.maxF, P.fN[f]);
       }
       lev.fpts = arr(A->dev0.fpts, P.fpts);
@@ -546,81 +656,126 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
       lev.rb_off = arr(A->dev0.rb_off, P.rb_off);
       lev.rb_sa = arr(A->dev0.rb_sa, P.rb_sa);
       lev.rb_sb = arr(A->dev0.rb_sb, P.rb_sb);
-      lev.panel_off = to_dev(poff, s);
-      lev.panel_ld = to_dev(pld, s);
+      lev.panel_off = to_dev(J.poff, s);
+      lev.panel_ld = to_dev(J.pld, s);
       lev.panel.alloc(std::max<int64_t>(psz, 1));
       st.faces[level] = P.nface;
       if (P.nface > 0) {
-        DevBuf<int64_t> d_uoff = to_dev(uoff, s);
-        DevBuf<int> d_uld = to_dev(uld, s);
+        DevBuf<int64_t> d_uoff = to_dev(J.uoff, s);
+        DevBuf<int> d_uld = to_dev(J.uld, s);
         ProfScope ps("gather_panel", s);
         dim3 g((unsigned)ceil_div(std::max(1, lev.maxF), kGatherCols), (unsigned)P.nface);
         hipLaunchKernelGGL((k_gather_panel<T>), g, dim3(NT), 0, s, src, lev.fpts.get(),
                            lev.fpt_off.get(), lev.fN.get(), lev.rb_face.get(), lev.rb_off.get(),
                            lev.rb_sa.get(), lev.rb_sb.get(), lev.fcellA.get(), lev.fcellB.get(),
-                           U.get(), d_uoff.get(), d_uld.get(), lev.panel.get(),
+                           J.U.get(), d_uoff.get(), d_uld.get(), lev.panel.get(),
                            lev.panel_off.get(), lev.panel_ld.get());
         HIF_LAUNCH_CHECK();
       }
-      U.release();
-      if (prev) {  // A^l has been read for the last time
-        prev->panel.release();
+      J.U.release();
+      if (prev) prev->panel.release();  // A^l has been read for the last time
+      for (int f = 0; f < P.nface; ++f) st.face_dofs[level] += P.fN[f];
+      lev.hk.assign(P.nface, 0);
+      J.hperm.assign(P.fpts.size(), 0);
+      J.face0 = nface_all;
+      J.pt0 = npt_all;
+      nface_all += P.nface;
+      npt_all += (int64_t)P.fpts.size();
+    }
+
+    // ---- interpolative decomposition of every face (Section 2.3) ---------
+    // one joint pivot order, rank list and Gram arena for the faces of all problems
+    DevBuf<int> d_perm(std::max<int64_t>(npt_all, 1));
+    DevBuf<double> Lp;
+    DevBuf<int64_t> d_goff;
+    DevBuf<int> d_gld;
+    if (eps > 0.0 && nface_all > 0) {
+      std::vector<int64_t> goff(nface_all), ppoff(nface_all);
+      std::vector<int> gld(nface_all), nF(nface_all);
+      int64_t gsz = 0;
+      for (int j : below) {
+        Job<T>& J = jobs[j];
+        const Level<T>& lev = J.impl->levels[level];
+        const LevelPlan& P = *lev.plan;
+        HIF_REQUIRE(lev.maxF <= kPcholMax, HIF_EINVAL, "face larger than the ID kernel supports");
+        for (int f = 0; f < P.nface; ++f) {
+          const int64_t i = J.face0 + f;
+          goff[i] = gsz;
+          gld[i] = std::max(1, P.fN[f]);
+          nF[i] = P.fN[f];
+          ppoff[i] = J.pt0 + P.fpt_off[f];
+          gsz += (int64_t)gld[i] * P.fN[f];
+        }
+      }
+      DevBuf<double> G(std::max<int64_t>(gsz, 1));
+      Lp.alloc(std::max<int64_t>(gsz, 1));
+      // G = M^T M with M = the panel rows outside F (K x |F| per face), read in
+      // place; the lower part is computed and both triangles are written
+      std::vector<GemmDesc> gd;
+      for (int j : below) {
+        Job<T>& J = jobs[j];
+        const Level<T>& lev = J.impl->levels[level];
+        const LevelPlan& P = *lev.plan;
+        for (int f = 0; f < P.nface; ++f) {
+          const T* PR = lev.panel.get() + J.poff[f] + P.fN[f];
+          const int K = P.prow[f] - P.fN[f];
+          const int64_t i = J.face0 + f;
+          gd.push_back(
+              {PR, PR, G.get() + goff[i], P.fN[f], P.fN[f], K, J.pld[f], J.pld[f], gld[i]});
+          J.flops += 2.0 * K * P.fN[f] * (double)P.fN[f];
+        }
+      }
+      run_gemms<T, double>("gemm_gram", OP_T, OP_N, GF_C_LOWER | GF_C_MIRROR, gd, 1.0, 0.0, s,
+                           GC_GRAM);
+      d_goff = to_dev(goff, s);
+      d_gld = to_dev(gld, s);
+      DevBuf<int> d_nF = to_dev(nF, s);
+      DevBuf<int64_t> d_ppoff = to_dev(ppoff, s);
+      for (int j : below) {
+        Job<T>& J = jobs[j];
+        const Level<T>& lev = J.impl->levels[level];
+        const LevelPlan& P = *lev.plan;
+        if (P.nface == 0) continue;
+        dim3 g((unsigned)ceil_div(std::max(1, lev.maxF), NT), (unsigned)P.nface);
+        hipLaunchKernelGGL(k_gram_edges, g, dim3(NT), 0, s, J.A->stencil(), P.w, lev.fpts.get(),
+                           lev.fpt_off.get(), lev.fN.get(), G.get(), d_goff.get() + J.face0,
+                           d_gld.get() + J.face0);
+        HIF_LAUNCH_CHECK();
+      }
+      DevBuf<int> d_k(nface_all);
+      pivoted_cholesky(G.get(), Lp.get(), d_goff.get(), d_nF.get(), d_gld.get(), d_ppoff.get(),
+                       d_perm.get(), d_k.get(), (int)nface_all, eps, nF, goff, gld, ppoff, s);
+      std::vector<int> k_all(nface_all), perm_all(npt_all);
+      HIF_HIP(hipMemcpyAsync(k_all.data(), d_k.get(), sizeof(int) * nface_all,
+                             hipMemcpyDeviceToHost, s));
+      HIF_HIP(hipMemcpyAsync(perm_all.data(), d_perm.get(), sizeof(int) * npt_all,
+                             hipMemcpyDeviceToHost, s));
+      check_errors();  // synchronizes: ranks, pivots and flags are on the host
+      staging_synced(s);
+      G.release();
+      for (int j : below) {
+        Job<T>& J = jobs[j];
+        Level<T>& lev = J.impl->levels[level];
+        std::copy(k_all.begin() + J.face0, k_all.begin() + J.face0 + lev.plan->nface,
+                  lev.hk.begin());
+        std::copy(perm_all.begin() + J.pt0, perm_all.begin() + J.pt0 + J.hperm.size(),
+                  J.hperm.begin());
       }
 
-      // ---- interpolative decomposition of every face (Section 2.3) -------
-      std::vector<int> hperm(P.fpts.size());
-      lev.hk.assign(P.nface, 0);
-      DevBuf<int> d_perm(std::max<size_t>(P.fpts.size(), 1));
-      for (int f = 0; f < P.nface; ++f) st.face_dofs[level] += P.fN[f];
-      if (o.eps > 0.0 && P.nface > 0) {
-        HIF_REQUIRE(lev.maxF <= kPcholMax, HIF_EINVAL, "face larger than the ID kernel supports");
-        std::vector<int64_t> goff(P.nface);
-        std::vector<int> gld(P.nface);
-        int64_t gsz = 0;
-        std::vector<GemmDesc> gd;
-        for (int f = 0; f < P.nface; ++f) {
-          goff[f] = gsz;
-          gld[f] = std::max(1, P.fN[f]);
-          gsz += (int64_t)gld[f] * P.fN[f];
-        }
-        DevBuf<double> G(std::max<int64_t>(gsz, 1)), Lp(std::max<int64_t>(gsz, 1));
-        // G = M^T M with M = the panel rows outside F (K x |F| per face), read in
-        // place; the lower part is computed and both triangles are written
-        for (int f = 0; f < P.nface; ++f) {
-          const T* PR = lev.panel.get() + poff[f] + P.fN[f];
-          const int K = P.prow[f] - P.fN[f];
-          gd.push_back({PR, PR, G.get() + goff[f], P.fN[f], P.fN[f], K, pld[f], pld[f], gld[f]});
-          flops += 2.0 * K * P.fN[f] * (double)P.fN[f];
-        }
-        run_gemms<T, double>("gemm_gram", OP_T, OP_N, GF_C_LOWER | GF_C_MIRROR, gd, 1.0, 0.0, s,
-                             GC_GRAM);
-        DevBuf<int64_t> d_goff = to_dev(goff, s);
-        DevBuf<int> d_gld = to_dev(gld, s);
-        {
-          dim3 g((unsigned)ceil_div(std::max(1, lev.maxF), NT), (unsigned)P.nface);
-          hipLaunchKernelGGL(k_gram_edges, g, dim3(NT), 0, s, A->stencil(), P.w, lev.fpts.get(),
-                             lev.fpt_off.get(), lev.fN.get(), G.get(), d_goff.get(), d_gld.get());
-          HIF_LAUNCH_CHECK();
-        }
-        DevBuf<int> d_k(P.nface);
-        std::vector<int64_t> hpoff(P.fpt_off.begin(), P.fpt_off.end() - 1);
-        pivoted_cholesky(G.get(), Lp.get(), d_goff.get(), lev.fN.get(), d_gld.get(),
-                         lev.fpt_off.get(), d_perm.get(), d_k.get(), P.nface, o.eps, P.fN, goff,
-                         gld, hpoff, s);
-        HIF_HIP(hipMemcpyAsync(lev.hk.data(), d_k.get(), sizeof(int) * P.nface,
-                               hipMemcpyDeviceToHost, s));
-        HIF_HIP(hipMemcpyAsync(hperm.data(), d_perm.get(), sizeof(int) * hperm.size(),
-                               hipMemcpyDeviceToHost, s));
-        check_errors();  // synchronizes: ranks, pivots and flags are on the host
-        staging_synced(s);
-        G.release();
-
-        // skeleton descriptors and arena
+      // skeleton descriptors and arenas; T = R11^{-1} R12 = L11^{-T} L21^T (FP64)
+      std::vector<FrontDesc> tri;
+      for (int j : below) {
+        Job<T>& J = jobs[j];
+        Level<T>& lev = J.impl->levels[level];
+        const LevelPlan& P = *lev.plan;
         int64_t ssz = 0, s11 = 0, s21 = 0, shh = 0, shc = 0;
-        std::vector<int64_t> o11, o21, ohh, ohc;
+        J.o11.clear();
+        J.o21.clear();
+        J.ohh.clear();
+        J.ohc.clear();
         for (int f = 0; f < P.nface; ++f) {
           const int k = lev.hk[f], r = P.fN[f] - k;
-          flops += (double)P.fN[f] * k * k;
+          J.flops += (double)P.fN[f] * k * k;
           if (r == 0) continue;
           SkelDesc d{};
           d.face = f;
@@ -639,173 +794,226 @@ void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, h
           lev.ksum += k;
           lev.rsum += r;
           lev.hsk.push_back(d);
-          o11.push_back(s11);
+          J.o11.push_back(s11);
           s11 += (int64_t)k * k;
-          o21.push_back(s21);
+          J.o21.push_back(s21);
           s21 += (int64_t)r * k;
-          ohh.push_back(shh);
+          J.ohh.push_back(shh);
           shh += (int64_t)k * k;
-          ohc.push_back(shc);
+          J.ohc.push_back(shc);
           shc += (int64_t)k * r;
           lev.maxk = std::max(lev.maxk, k);
           lev.maxr = std::max(lev.maxr, r);
           lev.redundant += r;
           const double kk = k, rr = r;
-          flops += 2 * kk * kk * kk / 3 + kk * kk * rr + 2 * rr * rr * kk + 2 * kk * kk * rr +
-                   2 * rr * rr * kk + 2 * rr * rr * rr / 3 + rr * rr * kk + 2 * kk * kk * rr;
+          J.flops += 2 * kk * kk * kk / 3 + kk * kk * rr + 2 * rr * rr * kk + 2 * kk * kk * rr +
+                     2 * rr * rr * kk + 2 * rr * rr * rr / 3 + rr * rr * kk + 2 * kk * kk * rr;
         }
         const int nsk = (int)lev.hsk.size();
+        J.ssz = ssz;
         lev.sk = to_dev(lev.hsk, s);
         lev.skel.alloc(std::max<int64_t>(ssz, 1));
-        if (nsk > 0) {
-          // T = R11^{-1} R12 = L11^{-T} L21^T (FP64)
-          DevBuf<double> L11(std::max<int64_t>(s11, 1)), L21(std::max<int64_t>(s21, 1));
-          DevBuf<int64_t> d_o11 = to_dev(o11, s), d_o21 = to_dev(o21, s);
-          {
-            dim3 g((unsigned)std::max(1, lev.maxk), (unsigned)nsk);
-            hipLaunchKernelGGL(k_split_L, g, dim3(NT), 0, s, Lp.get(), d_goff.get(), d_gld.get(),
-                               d_perm.get(), lev.fpt_off.get(), lev.sk.get(), L11.get(),
-                               d_o11.get(), L21.get(), d_o21.get(), lev.fN.get());
-            HIF_LAUNCH_CHECK();
-          }
-          std::vector<FrontDesc> tri;
-          for (int i = 0; i < nsk; ++i)
-            if (lev.hsk[i].k > 0) tri.push_back({o11[i], lev.hsk[i].k, lev.hsk[i].k, lev.hsk[i].k, 0});
-          if (!tri.empty()) {
-            DevBuf<FrontDesc> d_tri = to_dev(tri, s);
-            // L11 holds zeros above the diagonal (rows pivoted earlier)
-            front_invert<double>(L11.get(), d_tri.get(), tri, s, true);
-          }
-          DevBuf<double> Td;
-          if (!std::is_same<T, double>::value) Td.alloc(std::max<int64_t>(ssz, 1));
-          double* Tdst = std::is_same<T, double>::value ? (double*)lev.skel.get() : Td.get();
-          std::vector<GemmDesc> tg;
-          for (int i = 0; i < nsk; ++i) {
-            const SkelDesc& d = lev.hsk[i];
-            if (d.k == 0) continue;
-            tg.push_back({L11.get() + o11[i], L21.get() + o21[i], Tdst + d.offT, d.k, d.r, d.k,
-                          d.k, d.r, d.k});
-          }
-          run_gemms<double, double>("gemm_interp", OP_T, OP_T, GF_A_UPPER, tg, 1.0, 0.0, s);
-          if (!std::is_same<T, double>::value && ssz > 0) {
-            ProfScope ps("convert_T", s);
-            hipLaunchKernelGGL((k_convert<T>),
-                               dim3((unsigned)std::min<int64_t>(ceil_div(ssz, NT), 8192)),
-                               dim3(NT), 0, s, Td.get(), lev.skel.get(), ssz);
-            HIF_LAUNCH_CHECK();
-          }
-          L11.release();
-          L21.release();
-          Lp.release();
-
-          // ---- skeleton update (Section 2.3, B blocks) -----------------
-          DevBuf<T> Ahh(std::max<int64_t>(shh, 1)), Ahc(std::max<int64_t>(shc, 1));
-          DevBuf<int64_t> d_ohh = to_dev(ohh, s), d_ohc = to_dev(ohc, s);
-          {
-            dim3 g((unsigned)std::max(1, lev.maxF), (unsigned)nsk);
-            hipLaunchKernelGGL((k_skel_gather<T>), g, dim3(NT), 0, s, lev.panel.get(),
-                               lev.panel_off.get(), lev.panel_ld.get(), d_perm.get(),
-                               lev.fpt_off.get(), lev.sk.get(), Ahh.get(), d_ohh.get(), Ahc.get(),
-                               d_ohc.get(), lev.skel.get());
-            HIF_LAUNCH_CHECK();
-          }
-          T* SK = lev.skel.get();
-          std::vector<GemmDesc> g1, g2, g3, g4, g5;
-          for (int i = 0; i < nsk; ++i) {
-            const SkelDesc& d = lev.hsk[i];
-            T* Tm = SK + d.offT;
-            T* Acc = SK + d.offL;
-            T* Hh = Ahh.get() + ohh[i];
-            T* Hc = Ahc.get() + ohc[i];
-            const int k = std::max(d.k, 1), r = d.r;
-            g1.push_back({Tm, Hc, Acc, d.r, d.r, d.k, k, k, r});        // Acc -= T^T A_hc
-            g2.push_back({Hh, Tm, Hc, d.k, d.r, d.k, k, k, k});         // A_hc -= A_hh T  (= B_hc)
-            g3.push_back({Hc, Tm, Acc, d.r, d.r, d.k, k, k, r});        // Acc -= B_hc^T T (= B_cc)
-            g4.push_back({Acc, Hc, SK + d.offY, d.r, d.k, d.r, r, k, r});  // Y = Lc^{-1} B_hc^T
-            g5.push_back({SK + d.offY, SK + d.offY, Hh, d.k, d.k, d.r, r, r, k});  // A_hh -= Y^T Y
-          }
-          run_gemms<T, T>("gemm_skel", OP_T, OP_N, 0, g1, T(-1), T(1), s);
-          run_gemms<T, T>("gemm_skel", OP_N, OP_N, 0, g2, T(-1), T(1), s);
-          run_gemms<T, T>("gemm_skel", OP_T, OP_N, 0, g3, T(-1), T(1), s);
-          std::vector<FrontDesc> cfd;
-          for (int i = 0; i < nsk; ++i)
-            cfd.push_back({lev.hsk[i].offL, lev.hsk[i].r, lev.hsk[i].r, lev.hsk[i].r, 0});
-          {
-            DevBuf<FrontDesc> d_cfd = to_dev(cfd, s);
-            front_factor<T>(SK, d_cfd.get(), cfd, d_err.get() + 2 * level + 1, s, false);
-          }
-          run_gemms<T, T>("gemm_skel", OP_N, OP_T, GF_A_LOWER, g4, T(1), T(0), s);
-          run_gemms<T, T>("gemm_skel", OP_T, OP_N, 0, g5, T(-1), T(1), s);
-          {
-            dim3 g((unsigned)std::max(1, lev.maxk), (unsigned)nsk);
-            hipLaunchKernelGGL((k_skel_writeback<T>), g, dim3(NT), 0, s, lev.panel.get(),
-                               lev.panel_off.get(), lev.panel_ld.get(), d_perm.get(),
-                               lev.fpt_off.get(), lev.sk.get(), Ahh.get(), d_ohh.get());
-            HIF_LAUNCH_CHECK();
-          }
+        if (nsk == 0) continue;
+        J.L11.alloc(std::max<int64_t>(s11, 1));
+        J.L21.alloc(std::max<int64_t>(s21, 1));
+        J.Ahh.alloc(std::max<int64_t>(shh, 1));
+        J.Ahc.alloc(std::max<int64_t>(shc, 1));
+        J.d_o11 = to_dev(J.o11, s);
+        J.d_o21 = to_dev(J.o21, s);
+        J.d_ohh = to_dev(J.ohh, s);
+        J.d_ohc = to_dev(J.ohc, s);
+        {
+          dim3 g((unsigned)std::max(1, lev.maxk), (unsigned)nsk);
+          hipLaunchKernelGGL(k_split_L, g, dim3(NT), 0, s, Lp.get(), d_goff.get() + J.face0,
+                             d_gld.get() + J.face0, d_perm.get() + J.pt0, lev.fpt_off.get(),
+                             lev.sk.get(), J.L11.get(), J.d_o11.get(), J.L21.get(),
+                             J.d_o21.get(), lev.fN.get());
+          HIF_LAUNCH_CHECK();
         }
-      } else {
+        for (int i = 0; i < nsk; ++i) {
+          const int k = lev.hsk[i].k;
+          if (k > 0) tri.push_back({J.L11.get() + J.o11[i], k, k, k, 0});
+        }
+      }
+      if (!tri.empty()) {
+        DevBuf<FrontDesc> d_tri = to_dev(tri, s);
+        // L11 holds zeros above the diagonal (rows pivoted earlier)
+        front_invert<double>(d_tri.get(), tri, s, true);
+      }
+      std::vector<GemmDesc> tg;
+      for (int j : below) {
+        Job<T>& J = jobs[j];
+        Level<T>& lev = J.impl->levels[level];
+        if (lev.hsk.empty()) continue;
+        double* Tdst = (double*)lev.skel.get();
+        if (!std::is_same<T, double>::value) {
+          J.Td.alloc(std::max<int64_t>(J.ssz, 1));
+          Tdst = J.Td.get();
+        }
+        for (size_t i = 0; i < lev.hsk.size(); ++i) {
+          const SkelDesc& d = lev.hsk[i];
+          if (d.k == 0) continue;
+          tg.push_back({J.L11.get() + J.o11[i], J.L21.get() + J.o21[i], Tdst + d.offT, d.k, d.r,
+                        d.k, d.k, d.r, d.k});
+        }
+      }
+      run_gemms<double, double>("gemm_interp", OP_T, OP_T, GF_A_UPPER, tg, 1.0, 0.0, s);
+      for (int j : below) {
+        Job<T>& J = jobs[j];
+        Level<T>& lev = J.impl->levels[level];
+        if (!std::is_same<T, double>::value && !lev.hsk.empty() && J.ssz > 0) {
+          ProfScope ps("convert_T", s);
+          hipLaunchKernelGGL((k_convert<T>),
+                             dim3((unsigned)std::min<int64_t>(ceil_div(J.ssz, NT), 8192)),
+                             dim3(NT), 0, s, J.Td.get(), lev.skel.get(), J.ssz);
+          HIF_LAUNCH_CHECK();
+        }
+        J.L11.release();
+        J.L21.release();
+        J.Td.release();
+      }
+      Lp.release();
+
+      // ---- skeleton update (Section 2.3, B blocks) -----------------------
+      std::vector<GemmDesc> g1, g2, g3, g4, g5;
+      std::vector<FrontDesc> cfd;
+      for (int j : below) {
+        Job<T>& J = jobs[j];
+        Level<T>& lev = J.impl->levels[level];
+        const int nsk = (int)lev.hsk.size();
+        if (nsk == 0) continue;
+        {
+          dim3 g((unsigned)std::max(1, lev.maxF), (unsigned)nsk);
+          hipLaunchKernelGGL((k_skel_gather<T>), g, dim3(NT), 0, s, lev.panel.get(),
+                             lev.panel_off.get(), lev.panel_ld.get(), d_perm.get() + J.pt0,
+                             lev.fpt_off.get(), lev.sk.get(), J.Ahh.get(), J.d_ohh.get(),
+                             J.Ahc.get(), J.d_ohc.get(), lev.skel.get());
+          HIF_LAUNCH_CHECK();
+        }
+        T* SK = lev.skel.get();
+        for (int i = 0; i < nsk; ++i) {
+          const SkelDesc& d = lev.hsk[i];
+          T* Tm = SK + d.offT;
+          T* Acc = SK + d.offL;
+          T* Hh = J.Ahh.get() + J.ohh[i];
+          T* Hc = J.Ahc.get() + J.ohc[i];
+          const int k = std::max(d.k, 1), r = d.r;
+          g1.push_back({Tm, Hc, Acc, d.r, d.r, d.k, k, k, r});        // Acc -= T^T A_hc
+          g2.push_back({Hh, Tm, Hc, d.k, d.r, d.k, k, k, k});         // A_hc -= A_hh T  (= B_hc)
+          g3.push_back({Hc, Tm, Acc, d.r, d.r, d.k, k, k, r});        // Acc -= B_hc^T T (= B_cc)
+          g4.push_back({Acc, Hc, SK + d.offY, d.r, d.k, d.r, r, k, r});  // Y = Lc^{-1} B_hc^T
+          g5.push_back({SK + d.offY, SK + d.offY, Hh, d.k, d.k, d.r, r, r, k});  // A_hh -= Y^T Y
+          cfd.push_back({Acc, d.r, d.r, d.r, (int)own_skel[level].size()});
+          own_skel[level].push_back({j, i});
+        }
+      }
+      run_gemms<T, T>("gemm_skel", OP_T, OP_N, 0, g1, T(-1), T(1), s);
+      run_gemms<T, T>("gemm_skel", OP_N, OP_N, 0, g2, T(-1), T(1), s);
+      run_gemms<T, T>("gemm_skel", OP_T, OP_N, 0, g3, T(-1), T(1), s);
+      if (!cfd.empty()) {
+        DevBuf<FrontDesc> d_cfd = to_dev(cfd, s);
+        front_factor<T>(d_cfd.get(), cfd, d_err.get() + 2 * level + 1, s, false);
+      }
+      run_gemms<T, T>("gemm_skel", OP_N, OP_T, GF_A_LOWER, g4, T(1), T(0), s);
+      run_gemms<T, T>("gemm_skel", OP_T, OP_N, 0, g5, T(-1), T(1), s);
+      for (int j : below) {
+        Job<T>& J = jobs[j];
+        Level<T>& lev = J.impl->levels[level];
+        const int nsk = (int)lev.hsk.size();
+        if (nsk > 0) {
+          dim3 g((unsigned)std::max(1, lev.maxk), (unsigned)nsk);
+          hipLaunchKernelGGL((k_skel_writeback<T>), g, dim3(NT), 0, s, lev.panel.get(),
+                             lev.panel_off.get(), lev.panel_ld.get(), d_perm.get() + J.pt0,
+                             lev.fpt_off.get(), lev.sk.get(), J.Ahh.get(), J.d_ohh.get());
+          HIF_LAUNCH_CHECK();
+        }
+        J.Ahh.release();
+        J.Ahc.release();
+      }
+    } else {
+      // eps = 0: no ID, every face point is a skeleton point
+      std::vector<int> perm_all((size_t)std::max<int64_t>(npt_all, 1), 0);
+      for (int j : below) {
+        Job<T>& J = jobs[j];
+        Level<T>& lev = J.impl->levels[level];
+        const LevelPlan& P = *lev.plan;
         for (int f = 0; f < P.nface; ++f) {
           lev.hk[f] = P.fN[f];
-          for (int j = 0; j < P.fN[f]; ++j) hperm[P.fpt_off[f] + j] = j;
+          for (int q = 0; q < P.fN[f]; ++q) {
+            J.hperm[P.fpt_off[f] + q] = q;
+            perm_all[J.pt0 + P.fpt_off[f] + q] = q;
+          }
         }
-        d_perm.upload(hperm, s);
       }
+      d_perm.upload(perm_all, s);
+    }
+
+    for (int j : below) {
+      Job<T>& J = jobs[j];
+      hif_stats& st = J.F->stats;
+      Level<T>& lev = J.impl->levels[level];
+      const LevelPlan& P = *lev.plan;
       // face points in pivot order for the apply
       lev.skpts.alloc(std::max<size_t>(P.fpts.size(), 1));
       if (P.nface > 0) {
         dim3 g((unsigned)ceil_div(std::max(1, lev.maxF), NT), (unsigned)P.nface);
-        hipLaunchKernelGGL(k_perm_points, g, dim3(NT), 0, s, lev.fpts.get(), d_perm.get(),
+        hipLaunchKernelGGL(k_perm_points, g, dim3(NT), 0, s, lev.fpts.get(), d_perm.get() + J.pt0,
                            lev.fpt_off.get(), lev.fN.get(), lev.skpts.get());
         HIF_LAUNCH_CHECK();
       }
       st.redundant[level] = lev.redundant;
 
-      // ---- next level's active set and lookup maps --------------------
-      {
-        hipLaunchKernelGGL(k_fill_int, dim3((unsigned)std::min<int64_t>(ceil_div(N, NT), 8192)),
-                           dim3(NT), 0, s, d_pface.get(), N, -1);
+      // ---- next level's active set and lookup maps ------------------------
+      hipLaunchKernelGGL(k_fill_int, dim3((unsigned)std::min<int64_t>(ceil_div(J.N, NT), 8192)),
+                         dim3(NT), 0, s, J.d_pface.get(), J.N, -1);
+      HIF_LAUNCH_CHECK();
+      if (P.nface > 0) {
+        dim3 g((unsigned)ceil_div(std::max(1, lev.maxF), NT), (unsigned)P.nface);
+        hipLaunchKernelGGL(k_face_map, g, dim3(NT), 0, s, lev.fpts.get(), lev.fpt_off.get(),
+                           lev.fN.get(), J.d_pface.get(), J.d_ploc.get());
         HIF_LAUNCH_CHECK();
-        if (P.nface > 0) {
-          dim3 g((unsigned)ceil_div(std::max(1, lev.maxF), NT), (unsigned)P.nface);
-          hipLaunchKernelGGL(k_face_map, g, dim3(NT), 0, s, lev.fpts.get(), lev.fpt_off.get(),
-                             lev.fN.get(), d_pface.get(), d_ploc.get());
-          HIF_LAUNCH_CHECK();
-        }
       }
       std::vector<int> red;
       red.reserve(lev.redundant);
       for (int f = 0; f < P.nface; ++f) {
         const int64_t o0 = P.fpt_off[f];
-        for (int j = lev.hk[f]; j < P.fN[f]; ++j) {
-          const int p = P.fpts[o0 + hperm[o0 + j]];
-          active[p] = 0;
+        for (int q = lev.hk[f]; q < P.fN[f]; ++q) {
+          const int p = P.fpts[o0 + J.hperm[o0 + q]];
+          J.active[p] = 0;
           red.push_back(p);
         }
       }
-      F->redundant_pts.push_back(std::move(red));
-      F->ranks.push_back(lev.hk);
-      F->sizes.push_back(P.fN);
-    } else {
-      st.root_size = lev.ysum;
-      if (prev) prev->panel.release();
+      J.F->redundant_pts.push_back(std::move(red));
+      J.F->ranks.push_back(lev.hk);
+      J.F->sizes.push_back(P.fN);
     }
   }
-  HIF_HIP(hipEventRecord(ev.e[L + 1], s));
-  Fi.prepare(s);
+  HIF_HIP(hipEventRecord(ev.e[maxL + 1], s));
+  for (auto& J : jobs) J.impl->prepare(s);
   check_errors();
   staging_synced(s);
-  for (int level = 0; level <= L; ++level) {
+  std::vector<double> level_s(maxL + 1);
+  for (int level = 0; level <= maxL; ++level) {
     float ms = 0.f;
     HIF_HIP(hipEventElapsedTime(&ms, ev.e[level], ev.e[level + 1]));
-    st.level_seconds[level] = 1e-3 * ms;
+    level_s[level] = 1e-3 * ms;
   }
   profiler().level = -1;
-  st.factor_flops = flops;
-  st.build_seconds = now_s() - t_begin;
-  st.peak_bytes = mem_stats().peak - mem0;
-  F->impl = std::move(impl);
-  st.factor_bytes = F->impl->stored_bytes();
+  const double t_end = now_s();
+  for (auto& J : jobs) {
+    hif_stats& st = J.F->stats;
+    for (int level = 0; level <= J.L; ++level) st.level_seconds[level] = level_s[level];
+    st.factor_flops = J.flops;
+    st.build_seconds = t_end - t_begin;
+    st.peak_bytes = mem_stats().peak - mem0;
+    J.F->impl = std::move(J.impl);
+    st.factor_bytes = J.F->impl->stored_bytes();
+  }
+}
+
+template <typename T>
+void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, hif_factor_s* F) {
+  build_factors<T>({BuildRequest{A, o, F}}, s);
 }
 
 template <typename T>
@@ -815,6 +1023,8 @@ int64_t FactorImpl<T>::stored_bytes() const {
   return b;
 }
 
+template void build_factors<double>(const std::vector<BuildRequest>&, hipStream_t);
+template void build_factors<float>(const std::vector<BuildRequest>&, hipStream_t);
 template void build_factor<double>(const hif_problem_s*, const hif_options&, hipStream_t,
                                    hif_factor_s*);
 template void build_factor<float>(const hif_problem_s*, const hif_options&, hipStream_t,

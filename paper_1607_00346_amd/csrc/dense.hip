@@ -36,6 +36,7 @@ struct Mfma<float> {
 constexpr int BM = 64, BN = 64, KC = 16, NTHR = 256;
 // Fronts of at most this many interior columns are factored one per workgroup.
 constexpr int kSmallFront = 512;
+constexpr int kMaxGridY = 65535;  // largest y or z dimension of a launch grid
 
 // LDS staging of one K chunk: As[k][m], Bs[k][n], rows padded by one element
 // so that stores along k (transposed operands) do not collide in banks.
@@ -257,14 +258,14 @@ __global__ __launch_bounds__(NTHR) void k_gemm_desc(int flags, const GemmDesc* _
 // place (the step kernel cannot write it: its workgroups read the block
 // unfactored); launched with a (1, 1, batch) grid it does only that.
 template <typename T, int TS>
-__global__ __launch_bounds__(NTHR) void k_front_trailing(T* arena, const FrontDesc* __restrict__ fd,
+__global__ __launch_bounds__(NTHR) void k_front_trailing(const FrontDesc* __restrict__ fd,
                                                          int j0, int p0, int pw, int c0, int cw,
                                                          const T* __restrict__ dblk) {
   __shared__ TileSmem<T, TS, TS> sm;
   unsigned bx, by, bz;
   xcd_remap(bx, by, bz);
   const FrontDesc f = fd[bz];
-  T* base = arena + f.off;
+  T* base = static_cast<T*>(f.ptr);
   if (j0 >= 0 && j0 < f.nI && bx == 0 && by == 0) {
     const int nb = min(kPanel, f.nI - j0);
     const T* D = dblk + (int64_t)bz * kPanel * kPanel;
@@ -452,7 +453,7 @@ __device__ __forceinline__ void panel_row_light(T* row, int64_t ld, int nb,
 // kernel puts it in place).  Then each thread solves one panel row below the
 // block by forward substitution.
 template <typename T>
-__global__ __launch_bounds__(NTHR) void k_front_step(T* arena, const FrontDesc* __restrict__ fd,
+__global__ __launch_bounds__(NTHR) void k_front_step(const FrontDesc* __restrict__ fd,
                                                      int j0, T* __restrict__ dblk, int* err) {
   __shared__ StepSmem<T> ss;
   const FrontDesc f = fd[blockIdx.y];
@@ -462,11 +463,11 @@ __global__ __launch_bounds__(NTHR) void k_front_step(T* arena, const FrontDesc* 
   const int m = f.nR - j1;
   const int r0 = blockIdx.x * NTHR;
   if (blockIdx.x > 0 && r0 >= m) return;
-  T* col0 = arena + f.off + (int64_t)f.ld * j0;  // column j0 of the front
+  T* col0 = static_cast<T*>(f.ptr) + (int64_t)f.ld * j0;  // column j0 of the front
   const int tid = threadIdx.x;
   const bool bad = diag_factor<T>(col0, f.ld, j0, nb, ss);
   if (blockIdx.x == 0) {
-    if (bad && (tid & 63) == 0) atomicMin(err, (int)blockIdx.y);
+    if (bad && (tid & 63) == 0) atomicMin(err, f.id);
     T* D = dblk + (int64_t)blockIdx.y * kPanel * kPanel;
     for (int e = tid; e < kPanel * kPanel; e += NTHR) {
       const int c = e >> 6, r = e & 63;
@@ -482,7 +483,7 @@ __global__ __launch_bounds__(NTHR) void k_front_step(T* arena, const FrontDesc* 
 // small fronts of the lowest level, where per-step launches would leave the
 // chip waiting on latency.  The step buffers and the GEMM tile share LDS.
 template <typename T>
-__global__ __launch_bounds__(NTHR, 8 / sizeof(T)) void k_front_small(T* arena,
+__global__ __launch_bounds__(NTHR, 8 / sizeof(T)) void k_front_small(
                                                          const FrontDesc* __restrict__ fd,
                                                          int* err) {
   constexpr size_t kBytes = sizeof(StepSmem<T>) > sizeof(TileSmem<T, 64, 64>)
@@ -492,7 +493,7 @@ __global__ __launch_bounds__(NTHR, 8 / sizeof(T)) void k_front_small(T* arena,
   StepSmem<T>& ss = *reinterpret_cast<StepSmem<T>*>(smem);
   TileSmem<T, 64, 64>& ts = *reinterpret_cast<TileSmem<T, 64, 64>*>(smem);
   const FrontDesc f = fd[blockIdx.x];
-  T* base = arena + f.off;
+  T* base = static_cast<T*>(f.ptr);
   const int tid = threadIdx.x;
   bool bad_any = false;
   for (int j0 = 0; j0 < f.nI; j0 += kPanel) {
@@ -515,7 +516,7 @@ __global__ __launch_bounds__(NTHR, 8 / sizeof(T)) void k_front_small(T* arena,
                                               n0, T(-1), T(1), ts);
     __syncthreads();
   }
-  if (bad_any && (tid & 63) == 0) atomicMin(err, (int)blockIdx.x);
+  if (bad_any && (tid & 63) == 0) atomicMin(err, f.id);
 }
 
 // In-place inverse of every 64 x 64 diagonal block of the factored L_I, one
@@ -524,7 +525,7 @@ __global__ __launch_bounds__(NTHR, 8 / sizeof(T)) void k_front_small(T* arena,
 // of one step are independent), with the columns of L read as LDS
 // broadcasts.  Rows and columns past nb are padded with the identity.
 template <typename T>
-__global__ __launch_bounds__(64) void k_diag_inv(T* arena, const FrontDesc* __restrict__ fd) {
+__global__ __launch_bounds__(64) void k_diag_inv(const FrontDesc* __restrict__ fd) {
   // Lc[t][i] = L(i, t) while the inverse is formed, then Xs[c][i] = L^{-1}(i, c)
   // in the same storage (one wave: its LDS accesses complete in issue order),
   // which doubles the waves per CU of this latency-bound kernel
@@ -537,7 +538,7 @@ __global__ __launch_bounds__(64) void k_diag_inv(T* arena, const FrontDesc* __re
   if (j0 >= f.nI) return;
   const int nb = min(kPanel, f.nI - j0);
   const int lane = threadIdx.x;
-  T* base = arena + f.off + j0 + (int64_t)f.ld * j0;
+  T* base = static_cast<T*>(f.ptr) + j0 + (int64_t)f.ld * j0;
   // one wave: its LDS accesses complete in issue order, no barriers needed
 #pragma unroll 4
   for (int e = lane; e < kPanel * kPanel; e += 64) {
@@ -728,8 +729,8 @@ __global__ __launch_bounds__(64) void k_pchol_tail(const int* __restrict__ nFa,
 template <typename TIn, typename TC, int OPA, int OPB, int TS, int CLS>
 void launch_gemm(int flags, const GemmDesc* d_desc, int batch, int max_m, int max_n, TC alpha,
                  TC beta, hipStream_t s) {
-  for (int b0 = 0; b0 < batch; b0 += 65535) {
-    const int nb = std::min(batch - b0, 65535);
+  for (int b0 = 0; b0 < batch; b0 += kMaxGridY) {
+    const int nb = std::min(batch - b0, kMaxGridY);
     dim3 grid((unsigned)ceil_div(max_n, TS), (unsigned)ceil_div(max_m, TS), (unsigned)nb);
     hipLaunchKernelGGL((k_gemm_desc<TIn, TC, OPA, OPB, TS, TS, CLS>), grid, dim3(NTHR), 0, s,
                        flags, d_desc + b0, alpha, beta);
@@ -773,8 +774,8 @@ void transpose_batched(const TransDesc* d_desc, int batch, int max_rows, int max
                        hipStream_t s, const char* name) {
   if (batch <= 0 || max_rows <= 0 || max_cols <= 0) return;
   ProfScope ps(name, s);
-  for (int b0 = 0; b0 < batch; b0 += 65535) {
-    const int nb = std::min(batch - b0, 65535);
+  for (int b0 = 0; b0 < batch; b0 += kMaxGridY) {
+    const int nb = std::min(batch - b0, kMaxGridY);
     dim3 g((unsigned)ceil_div(max_cols, 32), (unsigned)ceil_div(max_rows, 32), (unsigned)nb);
     hipLaunchKernelGGL((k_transpose<T>), g, dim3(NTHR), 0, s, d_desc + b0);
     HIF_LAUNCH_CHECK();
@@ -811,11 +812,18 @@ double gemm_flops(const GemmDesc& d, int flags) {
 }
 
 template <typename T>
-void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
+void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
                   int* err, hipStream_t s, bool upper_zero) {
   const int batch = (int)h_fronts.size();
   if (batch == 0) return;
-  HIF_REQUIRE(batch <= 65535, HIF_EINVAL, "too many fronts in one launch");
+  if (batch > kMaxGridY) {  // the per-front grid dimension is limited
+    for (int b0 = 0; b0 < batch; b0 += kMaxGridY) {
+      const int nb = std::min(kMaxGridY, batch - b0);
+      std::vector<FrontDesc> sub(h_fronts.begin() + b0, h_fronts.begin() + b0 + nb);
+      front_factor<T>(d_fronts + b0, sub, err, s, upper_zero);
+    }
+    return;
+  }
   int maxI = 0;
   for (auto& f : h_fronts) maxI = std::max(maxI, f.nI);
   if (maxI <= kSmallFront) {
@@ -826,11 +834,11 @@ void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
     }
     {
       ProfScope ps("potrf_small", s, fl);
-      hipLaunchKernelGGL((k_front_small<T>), dim3((unsigned)batch), dim3(NTHR), 0, s, arena,
+      hipLaunchKernelGGL((k_front_small<T>), dim3((unsigned)batch), dim3(NTHR), 0, s,
                          d_fronts, err);
       HIF_LAUNCH_CHECK();
     }
-    front_invert<T>(arena, d_fronts, h_fronts, s, upper_zero);
+    front_invert<T>(d_fronts, h_fronts, s, upper_zero);
     return;
   }
   DevBuf<T> dblk((size_t)batch * kPanel * kPanel);
@@ -852,13 +860,13 @@ void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
     const T* D = dblk.get();
     if (sizeof(T) == 4 && max_n >= 1024) {
       dim3 gt((unsigned)ceil_div(max_n, 128), (unsigned)ceil_div(max_m, 128), (unsigned)batch);
-      hipLaunchKernelGGL((k_front_trailing<T, 128>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0,
-                         p0, pw, c0, cw, D);
+      hipLaunchKernelGGL((k_front_trailing<T, 128>), gt, dim3(NTHR), 0, s, d_fronts, j0, p0,
+                         pw, c0, cw, D);
     } else {
       dim3 gt((unsigned)std::max<int64_t>(1, ceil_div(max_n, 64)),
               (unsigned)std::max<int64_t>(1, ceil_div(max_m, 64)), (unsigned)batch);
-      hipLaunchKernelGGL((k_front_trailing<T, 64>), gt, dim3(NTHR), 0, s, arena, d_fronts, j0,
-                         p0, pw, c0, cw, D);
+      hipLaunchKernelGGL((k_front_trailing<T, 64>), gt, dim3(NTHR), 0, s, d_fronts, j0, p0,
+                         pw, c0, cw, D);
     }
     HIF_LAUNCH_CHECK();
   };
@@ -882,8 +890,8 @@ void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
       {
         ProfScope ps("potrf_step", s, fl_step);
         dim3 g((unsigned)std::max<int64_t>(1, ceil_div(max_m, NTHR)), (unsigned)batch);
-        hipLaunchKernelGGL((k_front_step<T>), g, dim3(NTHR), 0, s, arena, d_fronts, j0,
-                           dblk.get(), err);
+        hipLaunchKernelGGL((k_front_step<T>), g, dim3(NTHR), 0, s, d_fronts, j0, dblk.get(),
+                           err);
         HIF_LAUNCH_CHECK();
       }
       // always launched: it also puts the factored diagonal blocks in place
@@ -891,25 +899,32 @@ void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
     }
     if (J + kSuper < maxI) trailing(-1, J, kSuper, J + kSuper, maxI);
   }
-  front_invert<T>(arena, d_fronts, h_fronts, s, upper_zero);
+  front_invert<T>(d_fronts, h_fronts, s, upper_zero);
 }
 
 // In-place inverse of the lower-triangular L_I of every front, bottom-up over
 // doubling block sizes: with the two diagonal halves already inverted,
 // inv([[A, 0], [B, C]]) = [[A^-1, 0], [-C^-1 B A^-1, C^-1]].
 template <typename T>
-void front_invert(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
+void front_invert(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
                   hipStream_t s, bool upper_zero) {
   const int zf = upper_zero ? GF_TRI_ZEROS : 0;
   const int batch = (int)h_fronts.size();
   if (batch == 0) return;
-  HIF_REQUIRE(batch <= 65535, HIF_EINVAL, "too many fronts in one launch");
+  if (batch > kMaxGridY) {
+    for (int b0 = 0; b0 < batch; b0 += kMaxGridY) {
+      const int nb = std::min(kMaxGridY, batch - b0);
+      std::vector<FrontDesc> sub(h_fronts.begin() + b0, h_fronts.begin() + b0 + nb);
+      front_invert<T>(d_fronts + b0, sub, s, upper_zero);
+    }
+    return;
+  }
   int maxI = 0;
   for (auto& f : h_fronts) maxI = std::max(maxI, f.nI);
   {
     ProfScope ps("trtri_diag", s);
     dim3 g((unsigned)ceil_div(maxI, kPanel), (unsigned)batch);
-    hipLaunchKernelGGL((k_diag_inv<T>), g, dim3(64), 0, s, arena, d_fronts);
+    hipLaunchKernelGGL((k_diag_inv<T>), g, dim3(64), 0, s, d_fronts);
     HIF_LAUNCH_CHECK();
   }
   int64_t wmax = 0;
@@ -930,7 +945,7 @@ void front_invert(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDe
     int mm = 0, mk = 0;
     double f1 = 0.0, f2 = 0.0;
     for (auto& f : h_fronts) {
-      T* base = arena + f.off;
+      T* base = static_cast<T*>(f.ptr);
       for (int o = 0; o + sz < f.nI; o += 2 * sz) {
         const int nc = std::min(sz, f.nI - o - sz);
         T* Bp = base + (o + sz) + (int64_t)f.ld * o;
@@ -1015,13 +1030,13 @@ template void gemm_batched<float, float>(int, int, int, const GemmDesc*, int, in
                                          float, hipStream_t, const char*, double, int);
 template void gemm_batched<float, double>(int, int, int, const GemmDesc*, int, int, int, double,
                                           double, hipStream_t, const char*, double, int);
-template void front_factor<double>(double*, const FrontDesc*, const std::vector<FrontDesc>&,
-                                   int*, hipStream_t, bool);
-template void front_factor<float>(float*, const FrontDesc*, const std::vector<FrontDesc>&, int*,
-                                  hipStream_t, bool);
-template void front_invert<double>(double*, const FrontDesc*, const std::vector<FrontDesc>&,
+template void front_factor<double>(const FrontDesc*, const std::vector<FrontDesc>&, int*,
                                    hipStream_t, bool);
-template void front_invert<float>(float*, const FrontDesc*, const std::vector<FrontDesc>&,
+template void front_factor<float>(const FrontDesc*, const std::vector<FrontDesc>&, int*,
                                   hipStream_t, bool);
+template void front_invert<double>(const FrontDesc*, const std::vector<FrontDesc>&, hipStream_t,
+                                   bool);
+template void front_invert<float>(const FrontDesc*, const std::vector<FrontDesc>&, hipStream_t,
+                                  bool);
 
 }  // namespace hif

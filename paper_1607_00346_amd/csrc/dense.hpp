@@ -61,28 +61,30 @@ template <typename T>
 void transpose_batched(const TransDesc* d_desc, int batch, int max_rows, int max_cols,
                        hipStream_t s, const char* name = "transpose");
 
-// One front: element offset of its column-major block in the arena, interior
-// count nI, total rows nR = nI + nS, leading dimension ld >= nR.
+// One front: device address of its column-major block, interior count nI,
+// total rows nR = nI + nS, leading dimension ld >= nR, and the id that a
+// failed factorization reports.  Fronts of one batch may live in different
+// allocations (for instance, of different problems).
 struct FrontDesc {
-  int64_t off;
+  void* ptr;
   int nI, nR, ld;
-  int pad_;
+  int id;
 };
 
 constexpr int kPanel = 64;  // block width of the blocked factorizations
 
 // Partial Cholesky of the first nI columns of every front (rows nI..nR-1 get
 // A_SI L_I^{-T}), then L_I <- L_I^{-1} in place.  err[0] receives the smallest
-// batch index with a non-positive pivot (untouched otherwise).  upper_zero:
+// id of a front with a non-positive pivot (untouched otherwise).  upper_zero:
 // the strict upper triangle of every nI x nI block is stored as zeros (the
 // factorization keeps it so, and the inverse can then skip its masks).
 template <typename T>
-void front_factor(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
+void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
                   int* err, hipStream_t s, bool upper_zero);
 
 // Only the in-place inverse of an already factored lower-triangular L_I.
 template <typename T>
-void front_invert(T* arena, const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
+void front_invert(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
                   hipStream_t s, bool upper_zero);
 
 // Pivoted Cholesky of each symmetric G_b (nF x nF, FP64, offset goff[b], ld

@@ -138,6 +138,18 @@ void stencil_matvec(const Stencil& st, const double* x, double* y, hipStream_t s
 template <typename T>
 void build_factor(const hif_problem_s* A, const hif_options& o, hipStream_t s, hif_factor_s* F);
 
+// One problem of a batched build: its operator, options and the factor to fill.
+struct BuildRequest {
+  const hif_problem_s* A;
+  hif_options o;
+  hif_factor_s* F;
+};
+
+// Factors every request (same precision T and eps; grids and leaf sizes may
+// differ) with joint launches per level.
+template <typename T>
+void build_factors(const std::vector<BuildRequest>& req, hipStream_t s);
+
 void pcg_solve(const hif_problem_s* A, hif_factor_s* F, const double* f, double* u, double tol,
                int maxit, hif_pcg_info* info, hipStream_t s);
 

@@ -439,7 +439,7 @@ void FactorImpl<T>::prepare(hipStream_t s) {
     }
     for (int c = 0; c < lv.plan->ncell; ++c) {
       const FrontDesc& d = lv.hfd[c];
-      const T* base = lv.front.get() + d.off;
+      const T* base = static_cast<const T*>(d.ptr);
       gl.push_back({base, d.nI, d.nI, d.ld, 1, yoff[c], yoff[c]});
       if (((uintptr_t)base % 16) != 0 || d.ld % Vec16<T>::N != 0) lv.gv_L_vec = false;
       if (d.nR > d.nI) gs.push_back({base + d.nI, d.nR - d.nI, d.nI, d.ld, 0, zoff[c], yoff[c]});

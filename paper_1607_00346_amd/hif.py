@@ -19,7 +19,7 @@ HIF_DIRICHLET = 0
 HIF_MAX_LEVELS = 16
 
 EXPORTED = [
-    "hif_problem_create", "hif_build", "hif_apply", "hif_matvec", "hif_pcg",
+    "hif_problem_create", "hif_build", "hif_build_batched", "hif_apply", "hif_matvec", "hif_pcg",
     "hif_factor_stats", "hif_factor_ranks", "hif_factor_active", "hif_factor_destroy",
     "hif_problem_destroy", "hif_status_string", "hif_last_error", "hif_profile_begin",
     "hif_profile_end",
@@ -89,6 +89,8 @@ def lib():
         L.hif_problem_create.argtypes = [ctypes.POINTER(hif_options), vp, vp, vp,
                                          ctypes.POINTER(vp)]
         L.hif_build.argtypes = [vp, ctypes.POINTER(hif_options), vp, ctypes.POINTER(vp)]
+        L.hif_build_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(hif_options), vp,
+                                        ctypes.POINTER(vp)]
         L.hif_apply.argtypes = [vp, vp, vp, i32, vp]
         L.hif_matvec.argtypes = [vp, vp, vp, i32, vp]
         L.hif_pcg.argtypes = [vp, vp, vp, vp, i32, f64, i32, ctypes.POINTER(hif_pcg_info), vp]
@@ -102,8 +104,8 @@ def lib():
         L.hif_status_string.argtypes = [i32]
         L.hif_status_string.restype = ctypes.c_char_p
         L.hif_last_error.restype = ctypes.c_char_p
-        for name in ("hif_problem_create", "hif_build", "hif_apply", "hif_matvec", "hif_pcg",
-                     "hif_factor_stats", "hif_factor_ranks", "hif_factor_active",
+        for name in ("hif_problem_create", "hif_build", "hif_build_batched", "hif_apply",
+                     "hif_matvec", "hif_pcg", "hif_factor_stats", "hif_factor_ranks", "hif_factor_active",
                      "hif_profile_begin", "hif_profile_end"):
             getattr(L, name).restype = ctypes.c_int
         L.hif_factor_destroy.restype = None
@@ -147,6 +149,18 @@ def hif_build(A, opts: hif_options, stream=None):
     h = ctypes.c_void_p()
     _check(lib().hif_build(A, ctypes.byref(opts), _stream(stream), ctypes.byref(h)), "hif_build")
     return h
+
+
+def hif_build_batched(problems, opts, stream=None):
+    """Factor several problems with joint launches per level; opts[i] describes problems[i]."""
+    count = len(problems)
+    assert len(opts) == count and count >= 1
+    A = (ctypes.c_void_p * count)(*[p.value if isinstance(p, ctypes.c_void_p) else p
+                                    for p in problems])
+    O = (hif_options * count)(*opts)
+    out = (ctypes.c_void_p * count)()
+    _check(lib().hif_build_batched(count, A, O, _stream(stream), out), "hif_build_batched")
+    return [ctypes.c_void_p(out[i]) for i in range(count)]
 
 
 def hif_apply(F, f, u, nrhs: int = 1, stream=None):

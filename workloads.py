@@ -89,3 +89,24 @@ WORKLOADS = {
     "c32_contrast": Workload("c32_contrast", 32, 8, 1e-6, "logu", (-2.0, 2.0, 211),
                              "const", (0.0,), 212),
 }
+
+
+def batched_leaf(n: int) -> int:
+    """Leaf width for a batched problem: the largest m <= 8 with n / m a power of two."""
+    for m in range(8, 1, -1):
+        q, r = divmod(n, m)
+        if r == 0 and q >= 1 and (q & (q - 1)) == 0:
+            return m
+    raise ValueError(f"no leaf width <= 8 divides {n} into a power of two")
+
+
+def batched_workloads(count: int = 48, seed: int = 400,
+                      sizes: tuple = (32, 48, 64, 96), eps: float = 1e-4) -> list:
+    """Independent problems of a batched build: grid n drawn uniformly from `sizes`
+    (seed `seed`), problem i with log10 a ~ U(-1, 1) (seed 1000 + i), b ~ U(0, 1)
+    (seed 2000 + i) and f ~ N(0, 1) (seed 3000 + i); FP32 factor at `eps`."""
+    ns = _gen(seed).choice(np.asarray(sizes), size=count)
+    return [Workload(f"batch{i}_n{int(n)}", int(n), batched_leaf(int(n)), eps, "logu",
+                     (-1.0, 1.0, 1000 + i), "unif", (0.0, 1.0, 2000 + i), 3000 + i,
+                     precision="mixed")
+            for i, n in enumerate(ns)]
