@@ -1,7 +1,9 @@
 // Device memory cache with stream-ordered reuse, and pinned staging of uploads.
 #include <algorithm>
 #include <cstring>
+#include <iterator>
 #include <map>
+#include <unordered_map>
 #include <mutex>
 
 #include "common.hpp"
@@ -24,7 +26,8 @@ struct Block {
 
 struct Pool {
   std::mutex mu;
-  std::multimap<size_t, Block> free_blocks;
+  std::multimap<size_t, Block> free_blocks;  // keyed by block size
+  std::unordered_map<void*, size_t> live;    // size of every block handed out
   int64_t cached = 0;
   ~Pool() {
     for (auto& kv : free_blocks) (void)hipFree(kv.second.p);
@@ -61,59 +64,87 @@ size_t pool_round(size_t bytes) {
   return (bytes + g - 1) / g * g;
 }
 
+namespace {
+
+// Frees cached blocks, largest first, until at least `target` bytes are gone
+// (after one device synchronization, so no freed block is still in use).
+void trim_locked(Pool& P, int64_t target) {
+  (void)hipDeviceSynchronize();
+  int64_t freed = 0;
+  while (freed < target && !P.free_blocks.empty()) {
+    auto it = std::prev(P.free_blocks.end());
+    (void)hipFree(it->second.p);
+    freed += (int64_t)it->first;
+    P.cached -= (int64_t)it->first;
+    P.free_blocks.erase(it);
+  }
+  for (auto& kv : P.free_blocks) kv.second.tag = Tag::kClean;
+}
+
+}  // namespace
+
 void* pool_alloc(size_t bytes) {
   const size_t r = pool_round(bytes);
+  // best fit among cached blocks at most a quarter (or 2 MiB) larger
+  const size_t slack = std::max(r / 4, size_t(2) << 20);
   Pool& P = pool();
   std::lock_guard<std::mutex> lock(P.mu);
-  auto range = P.free_blocks.equal_range(r);
+  auto lo = P.free_blocks.lower_bound(r);
+  auto hi = P.free_blocks.upper_bound(r + slack);
   auto take = P.free_blocks.end();
-  for (auto it = range.first; it != range.second; ++it) {
+  for (auto it = lo; it != hi; ++it) {
     const Block& b = it->second;
     if (b.tag == Tag::kClean || (b.tag == Tag::kStream && t_stream_set && b.s == t_stream)) {
       take = it;
       break;
     }
   }
-  if (take == P.free_blocks.end() && range.first != range.second) {
+  if (take == P.free_blocks.end() && lo != hi) {
     // only blocks that other streams (or unknown work) may still use: wait for
     // the device, after which every cached block is free for anyone
     HIF_HIP(hipDeviceSynchronize());
     for (auto& kv : P.free_blocks) kv.second.tag = Tag::kClean;
-    take = range.first;
+    take = lo;
   }
   if (take != P.free_blocks.end()) {
     void* p = take->second.p;
+    const size_t sz = take->first;
     P.free_blocks.erase(take);
-    P.cached -= (int64_t)r;
+    P.cached -= (int64_t)sz;
+    P.live[p] = sz;
     return p;
   }
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, r);
   if (e == hipErrorOutOfMemory && !P.free_blocks.empty()) {
     (void)hipGetLastError();
-    HIF_HIP(hipDeviceSynchronize());
-    for (auto& kv : P.free_blocks) (void)hipFree(kv.second.p);
-    P.free_blocks.clear();
-    P.cached = 0;
+    trim_locked(P, P.cached);
     e = hipMalloc(&p, r);
   }
   if (e != hipSuccess)
     throw Error(e == hipErrorOutOfMemory ? HIF_ENOMEM : HIF_EDEVICE,
                 std::string("hipMalloc: ") + hipGetErrorString(e));
+  P.live[p] = r;
   return p;
 }
 
 void pool_free(void* p, size_t bytes) {
-  const size_t r = pool_round(bytes);
   Pool& P = pool();
   std::lock_guard<std::mutex> lock(P.mu);
-  if (P.cached + (int64_t)r > kPoolCap) {
-    (void)hipFree(p);  // hipFree waits for the device
-    return;
+  size_t sz = pool_round(bytes);
+  auto it = P.live.find(p);
+  if (it != P.live.end()) {
+    sz = it->second;
+    P.live.erase(it);
+  }
+  if (P.cached + (int64_t)sz > kPoolCap) {
+    // make room for a quarter of the cache at once, so that a build that
+    // overflows it synchronizes once rather than at every release
+    trim_locked(P, P.cached + (int64_t)sz - kPoolCap + kPoolCap / 4);
   }
   Block b{p, t_stream_set ? Tag::kStream : Tag::kUnknown, t_stream};
-  P.free_blocks.emplace(r, b);
-  P.cached += (int64_t)r;
+  P.free_blocks.emplace(sz, b);
+  P.cached += (int64_t)sz;
 }
 
 StreamScope::StreamScope(hipStream_t s) : prev_(t_stream), prev_set_(t_stream_set) {
