@@ -112,9 +112,12 @@ hif_status hif_build_batched(int32_t count, const hif_problem_t* A, const hif_op
                              void* stream, hif_factor_t* out);
 
 /* u = F^{-1} f for nrhs column-major vectors (paper, Section 2.4: the
- * product W^0..W^L D^{-1} W^L^T..W^0^T).  FP64 in and out (the mixed factor
- * is read in FP32, accumulated in FP64).  u may alias f.  Asynchronous on
- * `stream`.  nrhs = 0 is a no-op. */
+ * product W^0..W^L D^{-1} W^L^T..W^0^T).  FP64 in and out.  One vector: the
+ * sweeps are batched matrix-vector products, and the mixed factor is read in
+ * FP32 and accumulated in FP64.  Several vectors: the sweeps are batched GEMMs
+ * over up to 32 vectors at a time, computed in the factor's precision (the
+ * mixed factor's block apply rounds to about 1e-7 relative).  u may alias f
+ * (exactly, not partly).  Asynchronous on `stream`.  nrhs = 0 is a no-op. */
 hif_status hif_apply(hif_factor_t F, const double* f, double* u, int32_t nrhs, void* stream);
 
 /* y = A x for nrhs column-major vectors, FP64.  Asynchronous. */
@@ -122,8 +125,11 @@ hif_status hif_matvec(hif_problem_t A, const double* x, double* y, int32_t nrhs,
 
 /* Solve A u = f by preconditioned CG with F^{-1} as the preconditioner,
  * FP64 residuals, matvecs and inner products, from u = 0; stops when the
- * true relative residual is <= tol.  info has nrhs entries (host memory).
- * Returns HIF_ENOCONV if any column hit maxit.  Blocks the calling thread. */
+ * true relative residual is <= tol.  nrhs > 1: one CG per column, all
+ * columns sharing each block application of F^{-1} (see hif_apply); a
+ * column stops on its own.  info has nrhs entries (host memory).  f and u
+ * must not alias.  Returns HIF_ENOCONV if any column hit maxit.  Blocks the
+ * calling thread. */
 hif_status hif_pcg(hif_problem_t A, hif_factor_t F, const double* f, double* u, int32_t nrhs,
                    double tol, int32_t maxit, hif_pcg_info* info, void* stream);
 

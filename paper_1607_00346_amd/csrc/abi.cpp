@@ -155,7 +155,10 @@ hif_status hif_apply(hif_factor_t F, const double* f, double* u, int32_t nrhs, v
     HIF_REQUIRE(f != nullptr && u != nullptr, HIF_EINVAL, "NULL vector");
     const int64_t N = F->stats.n_dof;
     hif::StreamScope scope(as_stream(stream));
-    for (int c = 0; c < nrhs; ++c) F->impl->apply(f + c * N, u + c * N, as_stream(stream));
+    if (nrhs == 1)
+      F->impl->apply(f, u, as_stream(stream));
+    else
+      F->impl->apply_block(f, u, nrhs, as_stream(stream));
   });
 }
 
@@ -182,11 +185,12 @@ hif_status hif_pcg(hif_problem_t A, hif_factor_t F, const double* f, double* u, 
     HIF_REQUIRE(f != nullptr && u != nullptr && info != nullptr && f != u, HIF_EINVAL,
                 "bad vectors");
     hif::StreamScope scope(as_stream(stream));
+    if (nrhs == 1)
+      hif::pcg_solve(A, F, f, u, tol, maxit, info, as_stream(stream));
+    else
+      hif::pcg_solve_block(A, F, f, u, nrhs, tol, maxit, info, as_stream(stream));
     bool all = true;
-    for (int c = 0; c < nrhs; ++c) {
-      hif::pcg_solve(A, F, f + c * A->N, u + c * A->N, tol, maxit, &info[c], as_stream(stream));
-      all = all && info[c].converged;
-    }
+    for (int c = 0; c < nrhs; ++c) all = all && info[c].converged;
     if (!all) throw hif::Error(HIF_ENOCONV, "PCG did not reach tol within maxit");
   });
 }

@@ -536,6 +536,8 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
       lev.fd = to_dev(lev.hfd, s);
       lev.yoff = to_dev(yoff, s);
       lev.zoff = to_dev(zoff, s);
+      lev.hyoff = std::move(yoff);
+      lev.hzoff = std::move(zoff);
       st.cells[level] = P.ncell;
       st.eliminated[level] = lev.ysum;
       if (P.ncell == 0) continue;

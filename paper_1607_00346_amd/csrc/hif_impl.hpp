@@ -51,6 +51,7 @@ struct Level {
   DevBuf<FrontDesc> fd;
   DevBuf<T> front;  // per cell [L_I^{-1}; L_SI], (nI+nS) x nI column-major
   DevBuf<int64_t> yoff, zoff;  // per cell offsets into the apply scratch vectors
+  std::vector<int64_t> hyoff, hzoff;
   int64_t ysum = 0, zsum = 0;
   int maxI = 0, maxS = 0;
   // faces
@@ -82,6 +83,8 @@ struct Level {
 struct FactorBase {
   virtual ~FactorBase() = default;
   virtual void apply(const double* f, double* u, hipStream_t s) = 0;
+  // u = F^{-1} f for nrhs column-major vectors (leading dimension N) at once.
+  virtual void apply_block(const double* f, double* u, int nrhs, hipStream_t s) = 0;
   virtual int64_t stored_bytes() const = 0;
   virtual const LevelPlan& level_plan(int level) const = 0;
 };
@@ -95,9 +98,24 @@ struct FactorImpl : FactorBase {
   DevBuf<double> sbuf;            // skeleton scratch (x_F̂, x_F̌, L_F̌^{-1} x_F̌)
   int64_t ymax = 1, zmax = 1, kmax = 1, rmax = 1;  // scratch segment sizes
   bool prepared = false;
+  // Block apply: scratch blocks in the factor's precision (segment sizes as
+  // above, one column per right-hand side) and the GEMM descriptors of every
+  // sweep step, built once per block width.
+  DevBuf<T> mbuf;
+  int mbuf_cols = 0;
+  struct BlockStep {
+    DevBuf<GemmDesc> d;
+    int count = 0, max_m = 0, max_n = 0;
+    double flops = 0.0;
+  };
+  enum { kStepL, kStepS, kStepT1, kStepLc1, kStepY1, kStepY2, kStepLc2, kStepT2, kStepS2,
+         kStepL2, kSteps };
+  std::vector<std::vector<BlockStep>> bsteps;  // [level][step], for bsteps_cols columns
+  int bsteps_cols = 0;
   // Sweep descriptors and scratch of the apply (idempotent).
   void prepare(hipStream_t s);
   void apply(const double* f, double* u, hipStream_t s) override;
+  void apply_block(const double* f, double* u, int nrhs, hipStream_t s) override;
   int64_t stored_bytes() const override;
   const LevelPlan& level_plan(int level) const override { return *levels[level].plan; }
 };
@@ -152,5 +170,7 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s);
 
 void pcg_solve(const hif_problem_s* A, hif_factor_s* F, const double* f, double* u, double tol,
                int maxit, hif_pcg_info* info, hipStream_t s);
+void pcg_solve_block(const hif_problem_s* A, hif_factor_s* F, const double* f, double* u, int nrhs,
+                     double tol, int maxit, hif_pcg_info* info, hipStream_t s);
 
 }  // namespace hif

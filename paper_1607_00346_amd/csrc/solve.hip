@@ -295,6 +295,73 @@ __global__ __launch_bounds__(NT) void k_skel_move(double* u, const int* __restri
   else *s = u[p];
 }
 
+// ---- block apply (several right-hand sides) --------------------------------
+// Vector blocks: column z of u at u + z * N; column z of a scratch segment of
+// length ld at base + z * ld (scratch in the factor's precision T).
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_gather_cell_b(const double* __restrict__ u, int64_t N,
+                                                      const int* __restrict__ rows,
+                                                      const int64_t* __restrict__ crow_off,
+                                                      const FrontDesc* __restrict__ fd,
+                                                      const int64_t* __restrict__ yoff,
+                                                      const int64_t* __restrict__ zoff, T* xi,
+                                                      int64_t ldy, T* xs, int64_t ldz,
+                                                      int with_s) {
+  const int c = blockIdx.y;
+  const FrontDesc f = fd[c];
+  const int i = blockIdx.x * NT + threadIdx.x;
+  const int64_t z = blockIdx.z;
+  const int* r = rows + crow_off[c];
+  if (i < f.nI) xi[z * ldy + yoff[c] + i] = (T)u[z * N + r[i]];
+  else if (with_s && i < f.nR) xs[z * ldz + zoff[c] + i - f.nI] = (T)u[z * N + r[i]];
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_scatter_I_b(double* u, int64_t N,
+                                                    const int* __restrict__ rows,
+                                                    const int64_t* __restrict__ crow_off,
+                                                    const FrontDesc* __restrict__ fd,
+                                                    const int64_t* __restrict__ yoff,
+                                                    const T* __restrict__ y, int64_t ldy) {
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= fd[c].nI) return;
+  const int64_t z = blockIdx.z;
+  u[z * N + rows[crow_off[c] + i]] = (double)y[z * ldy + yoff[c] + i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_face_sub_b(
+    double* u, int64_t N, const int* __restrict__ fpts, const int64_t* __restrict__ fpt_off,
+    const int* __restrict__ fN, const int* __restrict__ fcellA, const int* __restrict__ fcellB,
+    const int* __restrict__ rb_sa, const int* __restrict__ rb_sb,
+    const int64_t* __restrict__ zoff, const T* __restrict__ zv, int64_t ldz) {
+  const int f = blockIdx.y;
+  const int j = blockIdx.x * NT + threadIdx.x;
+  if (j >= fN[f]) return;
+  const int64_t z = blockIdx.z;
+  const T* zc = zv + z * ldz;
+  const double za = (double)zc[zoff[fcellA[f]] + rb_sa[(size_t)f * kRowBlocks] + j];
+  const double zb = (double)zc[zoff[fcellB[f]] + rb_sb[(size_t)f * kRowBlocks] + j];
+  u[z * N + fpts[fpt_off[f] + j]] -= za + zb;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_skel_move_b(double* u, int64_t N,
+                                                    const int* __restrict__ skpts,
+                                                    const SkelDesc* __restrict__ sk, T* xh,
+                                                    int64_t ldk, T* xc, int64_t ldr, int to_u) {
+  const SkelDesc d = sk[blockIdx.y];
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= d.k + d.r) return;
+  const int64_t z = blockIdx.z;
+  const int64_t p = z * N + skpts[d.pts_off + i];
+  T* s = i < d.k ? xh + z * ldk + d.kofs + i : xc + z * ldr + d.rofs + (i - d.k);
+  if (to_u) u[p] = (double)*s;
+  else *s = (T)u[p];
+}
+
 // ---- PCG vector kernels --------------------------------------------------
 
 constexpr int kDotBlocks = 1024;
@@ -567,10 +634,190 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   profiler().level = -1;
 }
 
+// The sweeps of apply() on a block of nb vectors: every matrix-vector product
+// of a level becomes one batched GEMM (MFMA) whose N dimension is the block,
+// so each stored factor word is read once per sweep for the whole block.
+// Scratch blocks are in the factor's precision T (FP32 for the mixed factor:
+// the block apply of that factor rounds like the factor itself).
+template <typename T>
+void FactorImpl<T>::apply_block(const double* f, double* u, int nrhs, hipStream_t s) {
+  prepare(s);
+  constexpr int kCols = 32;  // right-hand sides per pass
+  if (u != f)
+    HIF_HIP(hipMemcpyAsync(u, f, sizeof(double) * N * nrhs, hipMemcpyDeviceToDevice, s));
+  const int nb = std::min(nrhs, kCols);
+  // segment layout of the scratch: XI, YV (ymax), ZV, XS (zmax), SH (kmax), SC, SC2 (rmax)
+  const int64_t seg = 2 * ymax + 2 * zmax + kmax + 2 * rmax;
+  if (mbuf_cols < nb) {
+    mbuf.alloc(seg * nb);
+    mbuf_cols = nb;
+  }
+  T* XI = mbuf.get();
+  T* YV = XI + ymax * nb;
+  T* ZV = YV + ymax * nb;
+  T* XS = ZV + zmax * nb;
+  T* SH = XS + zmax * nb;
+  T* SC = SH + kmax * nb;
+  T* SC2 = SC + rmax * nb;
+  if (bsteps_cols != nb) {
+    bsteps.clear();
+    bsteps.resize(levels.size());
+    for (size_t l = 0; l < levels.size(); ++l) {
+      Level<T>& lv = levels[l];
+      std::vector<std::vector<GemmDesc>> g(kSteps);
+      for (int c = 0; c < lv.plan->ncell; ++c) {
+        const FrontDesc& d = lv.hfd[c];
+        if (d.nI == 0) continue;
+        T* L = static_cast<T*>(d.ptr);
+        const int nS = d.nR - d.nI;
+        const int64_t yo = lv.hyoff[c], zo = lv.hzoff[c];
+        g[kStepL].push_back({L, XI + yo, YV + yo, d.nI, nb, d.nI, d.ld, (int)ymax, (int)ymax});
+        g[kStepL2].push_back({L, XI + yo, YV + yo, d.nI, nb, d.nI, d.ld, (int)ymax, (int)ymax});
+        if (nS > 0) {
+          g[kStepS].push_back({L + d.nI, YV + yo, ZV + zo, nS, nb, d.nI, d.ld, (int)ymax,
+                               (int)zmax});
+          g[kStepS2].push_back({L + d.nI, XS + zo, XI + yo, d.nI, nb, nS, d.ld, (int)zmax,
+                                (int)ymax});
+        }
+      }
+      T* sk = lv.skel.get();
+      for (const SkelDesc& d : lv.hsk) {
+        T* Tm = sk + d.offT;
+        T* Lc = sk + d.offL;
+        T* Y = sk + d.offY;
+        const int k = d.k, r = d.r, ldt = std::max(1, k);
+        const int ldk = (int)kmax, ldr = (int)rmax;
+        g[kStepLc1].push_back({Lc, SC + d.rofs, SC2 + d.rofs, r, nb, r, r, ldr, ldr});
+        g[kStepLc2].push_back({Lc, SC + d.rofs, SC2 + d.rofs, r, nb, r, r, ldr, ldr});
+        if (k == 0) continue;
+        g[kStepT1].push_back({Tm, SH + d.kofs, SC + d.rofs, r, nb, k, ldt, ldk, ldr});
+        g[kStepY1].push_back({Y, SC2 + d.rofs, SH + d.kofs, k, nb, r, r, ldr, ldk});
+        g[kStepY2].push_back({Y, SH + d.kofs, SC + d.rofs, r, nb, k, r, ldk, ldr});
+        g[kStepT2].push_back({Tm, SC2 + d.rofs, SH + d.kofs, k, nb, r, ldt, ldr, ldk});
+      }
+      bsteps[l].resize(kSteps);
+      for (int q = 0; q < kSteps; ++q) {
+        BlockStep& b = bsteps[l][q];
+        b.count = (int)g[q].size();
+        for (const GemmDesc& d : g[q]) {
+          b.max_m = std::max(b.max_m, d.m);
+          b.max_n = std::max(b.max_n, d.n);
+          b.flops += 2.0 * d.m * d.n * (double)d.k;
+        }
+        if (b.count > 0) b.d.upload(g[q], s);
+      }
+    }
+    bsteps_cols = nb;
+  }
+  // op(A), triangular structure and (alpha, beta) of each step
+  struct StepKind {
+    int opa, flags;
+    T alpha, beta;
+  };
+  const StepKind kind[kSteps] = {
+      {OP_N, GF_A_LOWER | GF_TRI_ZEROS, T(1), T(0)},  // YV = L_I^{-1} XI
+      {OP_N, 0, T(1), T(0)},                          // ZV = L_SI YV
+      {OP_T, 0, T(-1), T(1)},                         // SC -= T^T SH
+      {OP_N, GF_A_LOWER, T(1), T(0)},                 // SC2 = L_F̌^{-1} SC
+      {OP_T, 0, T(-1), T(1)},                         // SH -= Y^T SC2
+      {OP_N, 0, T(-1), T(1)},                         // SC -= Y SH
+      {OP_T, GF_A_UPPER, T(1), T(0)},                 // SC2 = L_F̌^{-T} SC
+      {OP_N, 0, T(-1), T(1)},                         // SH -= T SC2
+      {OP_T, 0, T(-1), T(1)},                         // XI -= L_SI^T XS
+      {OP_T, GF_A_UPPER | GF_TRI_ZEROS, T(1), T(0)},  // YV = L_I^{-T} XI
+  };
+  auto gemm = [&](size_t l, int q, int nc) {
+    const BlockStep& b = bsteps[l][q];
+    if (b.count == 0) return;
+    gemm_batched<T, T>(kind[q].opa, OP_N, kind[q].flags, b.d.get(), b.count, b.max_m, b.max_n,
+                       kind[q].alpha, kind[q].beta, s, "apply_block",
+                       b.flops * nc / (double)nb);
+  };
+  const int nlev = (int)levels.size();
+  for (int c0 = 0; c0 < nrhs; c0 += nb) {
+    const int nc = std::min(nb, nrhs - c0);
+    double* U = u + (int64_t)c0 * N;
+    // a short last pass still runs nb columns of GEMM work on scratch; only its
+    // nc columns are gathered from and scattered to u
+    for (int l = 0; l < nlev; ++l) {
+      Level<T>& lv = levels[l];
+      profiler().level = l;
+      const int ncell = lv.plan->ncell;
+      if (ncell > 0) {
+        dim3 gI((unsigned)ceil_div(std::max(1, lv.maxI), NT), (unsigned)ncell, (unsigned)nc);
+        hipLaunchKernelGGL((k_gather_cell_b<T>), gI, dim3(NT), 0, s, U, N, lv.rows.get(),
+                           lv.crow_off.get(), lv.fd.get(), lv.yoff.get(), lv.zoff.get(), XI,
+                           ymax, XS, zmax, 0);
+        HIF_LAUNCH_CHECK();
+        gemm(l, kStepL, nc);
+        gemm(l, kStepS, nc);
+        hipLaunchKernelGGL((k_scatter_I_b<T>), gI, dim3(NT), 0, s, U, N, lv.rows.get(),
+                           lv.crow_off.get(), lv.fd.get(), lv.yoff.get(), (const T*)YV, ymax);
+        HIF_LAUNCH_CHECK();
+      }
+      if (!lv.plan->root && lv.plan->nface > 0) {
+        dim3 gF((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)lv.plan->nface,
+                (unsigned)nc);
+        hipLaunchKernelGGL((k_face_sub_b<T>), gF, dim3(NT), 0, s, U, N, lv.fpts.get(),
+                           lv.fpt_off.get(), lv.fN.get(), lv.fcellA.get(), lv.fcellB.get(),
+                           lv.rb_sa.get(), lv.rb_sb.get(), lv.zoff.get(), (const T*)ZV, zmax);
+        HIF_LAUNCH_CHECK();
+        const int ns = (int)lv.hsk.size();
+        if (ns > 0) {
+          dim3 gM((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)ns, (unsigned)nc);
+          hipLaunchKernelGGL((k_skel_move_b<T>), gM, dim3(NT), 0, s, U, N, lv.skpts.get(),
+                             lv.sk.get(), SH, kmax, SC, rmax, 0);
+          HIF_LAUNCH_CHECK();
+          gemm(l, kStepT1, nc);
+          gemm(l, kStepLc1, nc);
+          gemm(l, kStepY1, nc);
+          hipLaunchKernelGGL((k_skel_move_b<T>), gM, dim3(NT), 0, s, U, N, lv.skpts.get(),
+                             lv.sk.get(), SH, kmax, SC2, rmax, 1);
+          HIF_LAUNCH_CHECK();
+        }
+      }
+    }
+    for (int l = nlev - 1; l >= 0; --l) {
+      Level<T>& lv = levels[l];
+      profiler().level = l;
+      const int ns = (int)lv.hsk.size();
+      if (!lv.plan->root && ns > 0) {
+        dim3 gM((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)ns, (unsigned)nc);
+        hipLaunchKernelGGL((k_skel_move_b<T>), gM, dim3(NT), 0, s, U, N, lv.skpts.get(),
+                           lv.sk.get(), SH, kmax, SC, rmax, 0);
+        HIF_LAUNCH_CHECK();
+        gemm(l, kStepY2, nc);
+        gemm(l, kStepLc2, nc);
+        gemm(l, kStepT2, nc);
+        hipLaunchKernelGGL((k_skel_move_b<T>), gM, dim3(NT), 0, s, U, N, lv.skpts.get(),
+                           lv.sk.get(), SH, kmax, SC2, rmax, 1);
+        HIF_LAUNCH_CHECK();
+      }
+      const int ncell = lv.plan->ncell;
+      if (ncell == 0) continue;
+      const int gmax = std::max(lv.maxI, lv.maxI + lv.maxS);
+      dim3 gG((unsigned)ceil_div(std::max(1, gmax), NT), (unsigned)ncell, (unsigned)nc);
+      dim3 gI((unsigned)ceil_div(std::max(1, lv.maxI), NT), (unsigned)ncell, (unsigned)nc);
+      hipLaunchKernelGGL((k_gather_cell_b<T>), gG, dim3(NT), 0, s, U, N, lv.rows.get(),
+                         lv.crow_off.get(), lv.fd.get(), lv.yoff.get(), lv.zoff.get(), XI, ymax,
+                         XS, zmax, 1);
+      HIF_LAUNCH_CHECK();
+      gemm(l, kStepS2, nc);
+      gemm(l, kStepL2, nc);
+      hipLaunchKernelGGL((k_scatter_I_b<T>), gI, dim3(NT), 0, s, U, N, lv.rows.get(),
+                         lv.crow_off.get(), lv.fd.get(), lv.yoff.get(), (const T*)YV, ymax);
+      HIF_LAUNCH_CHECK();
+    }
+  }
+  profiler().level = -1;
+}
+
 template void FactorImpl<double>::prepare(hipStream_t);
 template void FactorImpl<float>::prepare(hipStream_t);
 template void FactorImpl<double>::apply(const double*, double*, hipStream_t);
 template void FactorImpl<float>::apply(const double*, double*, hipStream_t);
+template void FactorImpl<double>::apply_block(const double*, double*, int, hipStream_t);
+template void FactorImpl<float>::apply_block(const double*, double*, int, hipStream_t);
 
 namespace {
 
@@ -650,6 +897,117 @@ void pcg_solve(const hif_problem_s* A, hif_factor_s* F, const double* f, double*
   fetch();
   info->relres = std::sqrt(h[6]) / fn;
   info->converged = info->relres <= tol;
+}
+
+// nrhs > 1: independent PCG runs, one per column, sharing each preconditioner
+// application (apply_block).  Vector operations and inner products run per
+// live column; a column leaves when its true residual reaches tol or on
+// breakdown, and the others go on.
+void pcg_solve_block(const hif_problem_s* A, hif_factor_s* F, const double* f, double* u, int nrhs,
+                     double tol, int maxit, hif_pcg_info* info, hipStream_t s) {
+  const int64_t N = A->N;
+  const int64_t NB = N * nrhs;
+  const Stencil st = A->stencil();
+  DevBuf<double> r(NB), rold(NB), z(NB), p(NB), q(NB), sc(8 * (size_t)nrhs);
+  Dot dot;
+  std::vector<double> h(8 * (size_t)nrhs);
+  auto fetch = [&]() {
+    HIF_HIP(hipMemcpyAsync(h.data(), sc.get(), sizeof(double) * h.size(), hipMemcpyDeviceToHost,
+                           s));
+    HIF_HIP(hipStreamSynchronize(s));
+  };
+  auto at = [&](double* b, int j) { return b + (int64_t)j * N; };
+  auto cat = [&](const double* b, int j) { return b + (int64_t)j * N; };
+  const unsigned g = grid_for(N);
+  HIF_HIP(hipMemsetAsync(u, 0, sizeof(double) * NB, s));
+  HIF_HIP(hipMemcpyAsync(r.get(), f, sizeof(double) * NB, hipMemcpyDeviceToDevice, s));
+  for (int j = 0; j < nrhs; ++j) dot.run(cat(f, j), cat(f, j), nullptr, N, sc.get() + 8 * j + 5, s);
+  fetch();
+  std::vector<double> fn(nrhs);
+  std::vector<char> live(nrhs, 0);
+  int nlive = 0;
+  for (int j = 0; j < nrhs; ++j) {
+    fn[j] = std::sqrt(h[8 * j + 5]);
+    info[j].iters = 0;
+    info[j].converged = fn[j] == 0.0;
+    info[j].relres = fn[j] == 0.0 ? 0.0 : 1.0;
+    live[j] = fn[j] > 0.0;
+    nlive += live[j];
+  }
+  if (nlive == 0) return;
+  F->impl->apply_block(r.get(), z.get(), nrhs, s);
+  HIF_HIP(hipMemcpyAsync(p.get(), z.get(), sizeof(double) * NB, hipMemcpyDeviceToDevice, s));
+  for (int j = 0; j < nrhs; ++j)
+    if (live[j]) dot.run(at(r.get(), j), at(z.get(), j), nullptr, N, sc.get() + 8 * j, s);
+  for (int it = 1; it <= maxit && nlive > 0; ++it) {
+    for (int j = 0; j < nrhs; ++j) {
+      if (!live[j]) continue;
+      double* scj = sc.get() + 8 * j;
+      stencil_matvec(st, at(p.get(), j), at(q.get(), j), s);
+      dot.run(at(p.get(), j), at(q.get(), j), nullptr, N, scj + 1, s);
+      hipLaunchKernelGGL(k_cg_step, dim3(g), dim3(NT), 0, s, at(u, j), at(r.get(), j),
+                         at(rold.get(), j), (const double*)at(p.get(), j),
+                         (const double*)at(q.get(), j), (const double*)scj, N);
+      dot.run(at(r.get(), j), at(r.get(), j), nullptr, N, scj + 4, s);
+    }
+    fetch();
+    std::vector<int> check;
+    for (int j = 0; j < nrhs; ++j) {
+      if (!live[j]) continue;
+      info[j].iters = it;
+      if (!(h[8 * j + 1] > 0.0) || !std::isfinite(h[8 * j + 4])) {  // breakdown
+        live[j] = 0;
+        --nlive;
+        continue;
+      }
+      if (std::sqrt(h[8 * j + 4]) <= tol * fn[j]) check.push_back(j);
+    }
+    if (!check.empty()) {
+      for (int j : check) {
+        stencil_matvec(st, at(u, j), at(q.get(), j), s);
+        hipLaunchKernelGGL(k_residual, dim3(g), dim3(NT), 0, s, cat(f, j), at(q.get(), j), N);
+        dot.run(at(q.get(), j), at(q.get(), j), nullptr, N, sc.get() + 8 * j + 6, s);
+      }
+      fetch();
+      for (int j : check) {
+        info[j].relres = std::sqrt(h[8 * j + 6]) / fn[j];
+        if (info[j].relres <= tol) {
+          info[j].converged = 1;
+          live[j] = 0;
+          --nlive;
+        } else {
+          HIF_HIP(hipMemcpyAsync(at(r.get(), j), at(q.get(), j), sizeof(double) * N,
+                                 hipMemcpyDeviceToDevice, s));
+        }
+      }
+    }
+    if (nlive == 0) break;
+    F->impl->apply_block(r.get(), z.get(), nrhs, s);
+    for (int j = 0; j < nrhs; ++j) {
+      if (!live[j]) continue;
+      double* scj = sc.get() + 8 * j;
+      dot.run(at(z.get(), j), at(r.get(), j), at(rold.get(), j), N, scj + 2, s);
+      dot.run(at(r.get(), j), at(z.get(), j), nullptr, N, scj + 3, s);
+      hipLaunchKernelGGL(k_cg_dir, dim3(g), dim3(NT), 0, s, at(p.get(), j),
+                         (const double*)at(z.get(), j), (const double*)scj, N);
+      hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, scj, 0, 3);
+      HIF_LAUNCH_CHECK();
+    }
+  }
+  std::vector<int> rest;
+  for (int j = 0; j < nrhs; ++j)
+    if (!info[j].converged && fn[j] > 0.0) rest.push_back(j);
+  if (rest.empty()) return;
+  for (int j : rest) {
+    stencil_matvec(st, at(u, j), at(q.get(), j), s);
+    hipLaunchKernelGGL(k_residual, dim3(g), dim3(NT), 0, s, cat(f, j), at(q.get(), j), N);
+    dot.run(at(q.get(), j), at(q.get(), j), nullptr, N, sc.get() + 8 * j + 6, s);
+  }
+  fetch();
+  for (int j : rest) {
+    info[j].relres = std::sqrt(h[8 * j + 6]) / fn[j];
+    info[j].converged = info[j].relres <= tol;
+  }
 }
 
 }  // namespace hif

@@ -225,19 +225,61 @@ def test_empty_rhs_and_zero_rhs(gpu_lib):
     g.close()
 
 
-def test_multi_rhs_apply(gpu_lib):
+@pytest.mark.parametrize("prec,nrhs", [(0, 3), (0, 40), (1, 5)])
+def test_multi_rhs_apply(gpu_lib, prec, nrhs):
+    """Block apply (batched GEMM sweeps, 32 columns per pass) = one apply per
+    column.  FP64 factor: the same products summed in another order (1e-12
+    relative).  Mixed factor: the block path computes in FP32, the column path
+    accumulates in FP64 (1e-5 relative, far below eps)."""
     import torch
     n, leaf = 16, 4
     a = log_uniform_field(n, -1, 1, 151)
-    g = GpuHif(gpu_lib, n, leaf, 1e-4, a, const_field(n, 0.0))
-    F = normal_rhs(n, 152, nrhs=3)
+    g = GpuHif(gpu_lib, n, leaf, 1e-4, a, const_field(n, 0.0), precision=prec)
+    F = normal_rhs(n, 152, nrhs=nrhs)
     tf = _t(F)
     tu = torch.empty_like(tf)
-    gpu_lib.hif_apply(g.F, tf, tu, nrhs=3)
+    gpu_lib.hif_apply(g.F, tf, tu, nrhs=nrhs)
     torch.cuda.synchronize()
     U = tu.cpu().numpy()
-    for i in range(3):
-        assert np.allclose(U[i], g.apply(F[i]), rtol=0, atol=1e-14 * np.abs(U[i]).max())
+    tol = 1e-12 if prec == 0 else 1e-5
+    for i in range(nrhs):
+        ref = g.apply(F[i])
+        assert np.linalg.norm(U[i] - ref) <= tol * np.linalg.norm(ref), i
+    # in place (u = f)
+    gpu_lib.hif_apply(g.F, tf, tf, nrhs=nrhs)
+    torch.cuda.synchronize()
+    assert np.array_equal(tf.cpu().numpy(), U)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_multi_rhs_pcg(gpu_lib, prec):
+    """Block PCG (one shared block apply per iteration): every column reaches a
+    true residual of 1e-10 (oracle operator) and matches its single-RHS solve;
+    a zero column stays zero."""
+    import torch
+    n, leaf, nrhs = 24, 6, 4
+    a = log_uniform_field(n, -2, 2, 171)
+    b = const_field(n, 0.0)
+    g = GpuHif(gpu_lib, n, leaf, 1e-4, a, b, precision=prec)
+    A = O.assemble(n, a, b)
+    F = normal_rhs(n, 172, nrhs=nrhs)
+    F[2] = 0.0
+    tf = _t(F)
+    tu = torch.empty_like(tf)
+    st, info = gpu_lib.hif_pcg(g.A, g.F, tf, tu, nrhs=nrhs, tol=1e-10, maxit=100)
+    torch.cuda.synchronize()
+    U = tu.cpu().numpy()
+    assert st == 0
+    for i in range(nrhs):
+        assert info[i].converged
+        if i == 2:
+            assert np.all(U[i] == 0) and info[i].iters == 0
+            continue
+        assert np.linalg.norm(F[i] - A @ U[i]) <= 1e-10 * np.linalg.norm(F[i])
+        st1, info1, u1 = g.pcg(F[i], 1e-10)
+        assert st1 == 0 and info1.converged
+        assert np.linalg.norm(U[i] - u1) <= 1e-8 * np.linalg.norm(u1)
     g.close()
 
 
