@@ -85,6 +85,9 @@ WORKLOADS = {
                            "const", (0.0,), 302, precision="mixed"),
     "c128_fp64": Workload("c128_fp64", 128, 8, 1e-6, "logu", (-2.0, 2.0, 301),
                           "const", (0.0,), 302, precision="fp64"),
+    # 256^3 high-contrast field, FP32 factor at eps 1e-4, 32 right-hand sides.
+    "c256_mixed": Workload("c256_mixed", 256, 8, 1e-4, "logu", (-2.0, 2.0, 701),
+                           "const", (0.0,), 702, precision="mixed", extra={"nrhs": 32}),
     # 32^3 high-contrast field used for mid-size parity and the CPU baseline sample.
     "c32_contrast": Workload("c32_contrast", 32, 8, 1e-6, "logu", (-2.0, 2.0, 211),
                              "const", (0.0,), 212),
