@@ -166,6 +166,22 @@ typedef struct {
 hif_status hif_profile_begin(void);
 hif_status hif_profile_end(hif_kernel_stat* out, int32_t cap, int32_t* count);
 
+/* Tile autotuning (tune_tiles.py drives it; not needed to factor or solve).
+ * The batched GEMMs of the library run square tiles of 32, 64 or (FP32
+ * accumulation only) 128, chosen per key (operand bytes, accumulator bytes,
+ * transposes, triangular flags, size bucket = smallest power of two >= the
+ * batch's largest m or n) from the table file tiles.tsv beside the library,
+ * else by a built-in rule (128 for FP32 outputs of at least 1024 x 1024, else
+ * 64).
+ * hif_tune_begin: from now on every batched GEMM that overwrites its output
+ * is run and timed with each candidate tile (results are unchanged: all tiles
+ * take K in the same order).  Run the builds and solves to tune on.
+ * hif_tune_end: pick the fastest tile per key, write the table to `path`
+ * (NULL or "": do not write), use it from now on, and return the number of
+ * keys in *keys (may be NULL).  Process-wide; not thread safe. */
+hif_status hif_tune_begin(void);
+hif_status hif_tune_end(const char* path, int32_t* keys);
+
 void hif_factor_destroy(hif_factor_t F);
 void hif_problem_destroy(hif_problem_t A);
 

@@ -147,6 +147,17 @@ hif_status hif_build_batched(int32_t count, const hif_problem_t* A, const hif_op
   });
 }
 
+hif_status hif_tune_begin(void) {
+  return guarded([&] { hif::tune_begin(); });
+}
+
+hif_status hif_tune_end(const char* path, int32_t* keys) {
+  return guarded([&] {
+    const int n = hif::tune_end(path);
+    if (keys) *keys = n;
+  });
+}
+
 hif_status hif_apply(hif_factor_t F, const double* f, double* u, int32_t nrhs, void* stream) {
   return guarded([&] {
     HIF_REQUIRE(F != nullptr && F->impl, HIF_EINVAL, "NULL factor");

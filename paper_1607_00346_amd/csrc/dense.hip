@@ -3,6 +3,15 @@
 #include <cfloat>
 
 #include "dense.hpp"
+
+#include <dlfcn.h>
+
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
 #include "prof.hpp"
 
 namespace hif {
@@ -757,16 +766,186 @@ void dispatch_gemm(int opa, int opb, int flags, int cls, const GemmDesc* d_desc,
     launch_gemm<TIn, TC, OP_T, OP_T, TS, 0>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
 }
 
+// ---- tile shapes --------------------------------------------------------
+// A batched GEMM runs square TS x TS tiles, TS in {32, 64, 128} (128 only for
+// FP32 accumulation, whose tile fits the register file).  The shape comes from
+// a table keyed by the operand and accumulator types, the two transposes, the
+// triangular flags and the size bucket (the smallest power of two >= the
+// largest m or n of the batch), written by the autotuner (tune_tiles.py) into
+// tiles.tsv beside the library.  Keys it does not hold fall back to the
+// built-in rule: 128 for FP32 outputs of at least 1024 x 1024, else 64.
+
+namespace {
+
+struct TileKey {
+  int in_bytes, acc_bytes, opa, opb, flags, bucket;
+  bool operator<(const TileKey& o) const {
+    return std::tie(in_bytes, acc_bytes, opa, opb, flags, bucket) <
+           std::tie(o.in_bytes, o.acc_bytes, o.opa, o.opb, o.flags, o.bucket);
+  }
+};
+
+constexpr int kTileFlags = GF_A_LOWER | GF_A_UPPER | GF_B_LOWER | GF_B_UPPER | GF_C_LOWER |
+                           GF_C_MIRROR | GF_TRI_ZEROS;
+
+int size_bucket(int max_m, int max_n) {
+  const int v = std::max(max_m, max_n);
+  int b = 32;
+  while (b < v && b < 8192) b *= 2;
+  return b;
+}
+
+struct TileTable {
+  std::mutex mu;
+  bool loaded = false;
+  std::map<TileKey, int> tiles;
+  // tuning mode: device time per key and candidate tile, summed over launches
+  bool tuning = false;
+  std::map<TileKey, std::map<int, double>> timed;
+};
+
+TileTable& tile_table() {
+  static TileTable t;
+  return t;
+}
+
+std::string library_dir() {
+  Dl_info info;
+  if (dladdr((const void*)&library_dir, &info) && info.dli_fname) {
+    std::string p(info.dli_fname);
+    const size_t k = p.rfind('/');
+    return k == std::string::npos ? std::string(".") : p.substr(0, k);
+  }
+  return ".";
+}
+
+void load_tiles_locked(TileTable& T) {
+  T.loaded = true;
+  std::ifstream in(library_dir() + "/tiles.tsv");
+  std::string line;
+  while (std::getline(in, line)) {
+    const size_t hash = line.find('#');
+    if (hash != std::string::npos) line.resize(hash);
+    std::istringstream ss(line);
+    TileKey k{};
+    int tile = 0;
+    if (!(ss >> k.in_bytes >> k.acc_bytes >> k.opa >> k.opb >> k.flags >> k.bucket >> tile))
+      continue;
+    if (tile == 32 || tile == 64 || (tile == 128 && k.acc_bytes == 4)) T.tiles[k] = tile;
+  }
+}
+
+template <typename TIn, typename TC>
+TileKey tile_key(int opa, int opb, int flags, int max_m, int max_n) {
+  return {(int)sizeof(TIn), (int)sizeof(TC), opa, opb, flags & kTileFlags,
+          size_bucket(max_m, max_n)};
+}
+
+template <typename TIn, typename TC>
+int pick_tile(const TileKey& k, int max_m, int max_n) {
+  TileTable& T = tile_table();
+  std::lock_guard<std::mutex> lock(T.mu);
+  if (!T.loaded) load_tiles_locked(T);
+  auto it = T.tiles.find(k);
+  if (it != T.tiles.end()) return it->second;
+  return (sizeof(TC) == 4 && max_m >= 1024 && max_n >= 1024) ? 128 : 64;
+}
+
+template <typename TIn, typename TC>
+void launch_tile(int ts, int opa, int opb, int flags, int cls, const GemmDesc* d_desc, int batch,
+                 int max_m, int max_n, TC alpha, TC beta, hipStream_t s) {
+  if (sizeof(TC) == 4 && ts == 128)
+    dispatch_gemm<TIn, TC, 128>(opa, opb, flags, cls, d_desc, batch, max_m, max_n, alpha, beta, s);
+  else if (ts == 32)
+    dispatch_gemm<TIn, TC, 32>(opa, opb, flags, cls, d_desc, batch, max_m, max_n, alpha, beta, s);
+  else
+    dispatch_gemm<TIn, TC, 64>(opa, opb, flags, cls, d_desc, batch, max_m, max_n, alpha, beta, s);
+}
+
+}  // namespace
+
 template <typename TIn, typename TC>
 void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch, int max_m,
                   int max_n, TC alpha, TC beta, hipStream_t s, const char* name, double flops,
                   int cls) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
+  const TileKey key = tile_key<TIn, TC>(opa, opb, flags, max_m, max_n);
+  bool tuning;
+  {
+    TileTable& T = tile_table();
+    std::lock_guard<std::mutex> lock(T.mu);
+    tuning = T.tuning;
+  }
+  // Tuning: a product that overwrites C (beta = 0; no library GEMM with
+  // beta = 0 reads C or lets it overlap A or B) is run with every candidate
+  // tile and each run timed.  All tile sizes take K in the same chunk order,
+  // so every run writes the same C.
+  if (tuning && beta == TC(0)) {
+    std::vector<int> cands = {32, 64};
+    if (sizeof(TC) == 4) cands.push_back(128);
+    hipEvent_t e0, e1;
+    HIF_HIP(hipEventCreate(&e0));
+    HIF_HIP(hipEventCreate(&e1));
+    std::vector<float> ms(cands.size(), 0.f);
+    for (size_t c = 0; c < cands.size(); ++c) {
+      HIF_HIP(hipEventRecord(e0, s));
+      launch_tile<TIn, TC>(cands[c], opa, opb, flags, cls, d_desc, batch, max_m, max_n, alpha,
+                           beta, s);
+      HIF_HIP(hipEventRecord(e1, s));
+      HIF_HIP(hipEventSynchronize(e1));
+      HIF_HIP(hipEventElapsedTime(&ms[c], e0, e1));
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    TileTable& T = tile_table();
+    std::lock_guard<std::mutex> lock(T.mu);
+    for (size_t c = 0; c < cands.size(); ++c) T.timed[key][cands[c]] += ms[c];
+    return;
+  }
   ProfScope ps(name, s, flops);
-  if (sizeof(TC) == 4 && max_m >= 1024 && max_n >= 1024)
-    dispatch_gemm<TIn, TC, 128>(opa, opb, flags, cls, d_desc, batch, max_m, max_n, alpha, beta, s);
-  else
-    dispatch_gemm<TIn, TC, 64>(opa, opb, flags, cls, d_desc, batch, max_m, max_n, alpha, beta, s);
+  launch_tile<TIn, TC>(pick_tile<TIn, TC>(key, max_m, max_n), opa, opb, flags, cls, d_desc,
+                       batch, max_m, max_n, alpha, beta, s);
+}
+
+void tune_begin() {
+  TileTable& T = tile_table();
+  std::lock_guard<std::mutex> lock(T.mu);
+  T.timed.clear();
+  T.tuning = true;
+}
+
+int tune_end(const char* path) {
+  TileTable& T = tile_table();
+  std::lock_guard<std::mutex> lock(T.mu);
+  T.tuning = false;
+  std::map<TileKey, int> best;
+  for (auto& kv : T.timed) {
+    int bt = 0;
+    double bm = 0.0;
+    for (auto& tm : kv.second)
+      if (bt == 0 || tm.second < bm) {
+        bt = tm.first;
+        bm = tm.second;
+      }
+    best[kv.first] = bt;
+  }
+  if (path && *path) {
+    std::ofstream out(path);
+    HIF_REQUIRE(out.good(), HIF_EINVAL, std::string("cannot write ") + path);
+    out << "# in_bytes acc_bytes opa opb flags bucket tile   device ms per candidate tile "
+           "(summed over the tuning run)\n";
+    for (auto& kv : best) {
+      const TileKey& k = kv.first;
+      out << k.in_bytes << ' ' << k.acc_bytes << ' ' << k.opa << ' ' << k.opb << ' ' << k.flags
+          << ' ' << k.bucket << ' ' << kv.second << "   #";
+      for (auto& tm : T.timed[k]) out << ' ' << tm.first << ':' << tm.second;
+      out << '\n';
+    }
+  }
+  T.tiles = best;
+  T.loaded = true;
+  T.timed.clear();
+  return (int)best.size();
 }
 
 template <typename T>

@@ -50,6 +50,14 @@ void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch
 // Algorithmic flops of one descriptor under the triangular flags (one flag class).
 double gemm_flops(const GemmDesc& d, int flags);
 
+// Tile autotuning on a real workload: between tune_begin() and tune_end(),
+// every batched GEMM that overwrites its output is run and timed with each
+// candidate tile; tune_end() picks the fastest tile per key (summed device
+// time), writes the table to `path` (if not empty), makes it the table in use
+// and returns the number of keys.
+void tune_begin();
+int tune_end(const char* path);
+
 // Batched out-of-place transpose: dst (cols x rows, leading dimension ldd) =
 // src (rows x cols, leading dimension lds)^T, column-major.
 struct TransDesc {

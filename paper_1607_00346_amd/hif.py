@@ -22,7 +22,7 @@ EXPORTED = [
     "hif_problem_create", "hif_build", "hif_build_batched", "hif_apply", "hif_matvec", "hif_pcg",
     "hif_factor_stats", "hif_factor_ranks", "hif_factor_active", "hif_factor_destroy",
     "hif_problem_destroy", "hif_status_string", "hif_last_error", "hif_profile_begin",
-    "hif_profile_end",
+    "hif_profile_end", "hif_tune_begin", "hif_tune_end",
 ]
 
 
@@ -101,12 +101,14 @@ def lib():
         L.hif_problem_destroy.argtypes = [vp]
         L.hif_profile_begin.argtypes = []
         L.hif_profile_end.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.hif_tune_begin.argtypes = []
+        L.hif_tune_end.argtypes = [ctypes.c_char_p, ctypes.POINTER(i32)]
         L.hif_status_string.argtypes = [i32]
         L.hif_status_string.restype = ctypes.c_char_p
         L.hif_last_error.restype = ctypes.c_char_p
         for name in ("hif_problem_create", "hif_build", "hif_build_batched", "hif_apply",
                      "hif_matvec", "hif_pcg", "hif_factor_stats", "hif_factor_ranks", "hif_factor_active",
-                     "hif_profile_begin", "hif_profile_end"):
+                     "hif_profile_begin", "hif_profile_end", "hif_tune_begin", "hif_tune_end"):
             getattr(L, name).restype = ctypes.c_int
         L.hif_factor_destroy.restype = None
         L.hif_problem_destroy.restype = None
@@ -223,6 +225,19 @@ def hif_profile_end():
         out[k.name.decode()] = {"launches": k.launches, "seconds": k.seconds, "flops": k.flops,
                                 "bytes": k.bytes}
     return out
+
+
+def hif_tune_begin():
+    """Tile tuning mode: every output-overwriting batched GEMM is timed with each tile."""
+    _check(lib().hif_tune_begin(), "hif_tune_begin")
+
+
+def hif_tune_end(path: str | None = None) -> int:
+    """Pick the fastest tile per key, write the table to path (if given), use it; returns keys."""
+    keys = ctypes.c_int32()
+    _check(lib().hif_tune_end(path.encode() if path else None, ctypes.byref(keys)),
+           "hif_tune_end")
+    return keys.value
 
 
 def hif_factor_destroy(F):
