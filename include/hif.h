@@ -22,6 +22,11 @@
  *   - Array arguments named a, b, f, u, x, y are DEVICE pointers to doubles
  *     owned by the caller; the library copies what it keeps.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   - Calls that use the same factor must not overlap in time, from several
+ *     threads or on several streams: they share its scratch vectors.  The
+ *     single-vector preconditioner application inside hif_pcg is captured
+ *     into a HIP graph at the second solve with a factor and replayed from
+ *     then on (HIF_APPLY_GRAPH=0 in the environment launches it directly).
  *   - Every call returns a status; nothing throws or aborts across the ABI.
  *     On error an output handle is set to NULL and nothing leaks;
  *     hif_last_error() gives a thread-local description.

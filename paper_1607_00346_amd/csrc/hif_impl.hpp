@@ -80,11 +80,17 @@ struct Level {
   int64_t ksum = 0, rsum = 0;
 };
 
+struct PcgCache;  // the single-vector PCG's workspace and captured apply graph
+
+// Calls on one factor must not overlap (they share its scratch vectors).
 struct FactorBase {
   virtual ~FactorBase() = default;
+  std::shared_ptr<PcgCache> pcg;
   virtual void apply(const double* f, double* u, hipStream_t s) = 0;
   // u = F^{-1} f for nrhs column-major vectors (leading dimension N) at once.
   virtual void apply_block(const double* f, double* u, int nrhs, hipStream_t s) = 0;
+  // algorithmic HBM bytes of one single-vector apply (profiler)
+  virtual double apply_bytes() const = 0;
   virtual int64_t stored_bytes() const = 0;
   virtual const LevelPlan& level_plan(int level) const = 0;
 };
@@ -116,6 +122,7 @@ struct FactorImpl : FactorBase {
   void prepare(hipStream_t s);
   void apply(const double* f, double* u, hipStream_t s) override;
   void apply_block(const double* f, double* u, int nrhs, hipStream_t s) override;
+  double apply_bytes() const override;
   int64_t stored_bytes() const override;
   const LevelPlan& level_plan(int level) const override { return *levels[level].plan; }
 };

@@ -2,6 +2,7 @@
 // application of F^{-1} by level-wise sweeps (Section 2.4, product form of
 // F^{-1}), and the FP64 preconditioned CG driver.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "hif_impl.hpp"
@@ -424,6 +425,12 @@ __global__ __launch_bounds__(NT) void k_cg_dir(double* p, const double* __restri
 
 __global__ void k_copy_scalar(double* sc, int dst, int src) { sc[dst] = sc[src]; }
 
+__global__ __launch_bounds__(NT) void k_copy(const double* __restrict__ src, double* dst,
+                                             int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+    dst[i] = src[i];
+}
+
 // y = f - y
 __global__ __launch_bounds__(NT) void k_residual(const double* __restrict__ f, double* y, int64_t N) {
   for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < N; i += (int64_t)gridDim.x * NT)
@@ -535,7 +542,10 @@ void FactorImpl<T>::prepare(hipStream_t s) {
 template <typename T>
 void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   prepare(s);
-  if (u != f) HIF_HIP(hipMemcpyAsync(u, f, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  if (u != f) {  // a kernel, not a copy node, so that the sweep can be captured in a graph
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(N)), dim3(NT), 0, s, f, u, N);
+    HIF_LAUNCH_CHECK();
+  }
   double* xi = ybuf.get();
   double* yv = ybuf.get() + ymax;
   double* zv = zbuf.get();
@@ -640,11 +650,20 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
 // Scratch blocks are in the factor's precision T (FP32 for the mixed factor:
 // the block apply of that factor rounds like the factor itself).
 template <typename T>
+double FactorImpl<T>::apply_bytes() const {
+  double b = 0.0;
+  for (const auto& lv : levels) b += 2.0 * (lv.bytes_L + lv.bytes_S + lv.bytes_skel);
+  return b;
+}
+
+template <typename T>
 void FactorImpl<T>::apply_block(const double* f, double* u, int nrhs, hipStream_t s) {
   prepare(s);
   constexpr int kCols = 32;  // right-hand sides per pass
-  if (u != f)
-    HIF_HIP(hipMemcpyAsync(u, f, sizeof(double) * N * nrhs, hipMemcpyDeviceToDevice, s));
+  if (u != f) {
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(N * nrhs)), dim3(NT), 0, s, f, u, N * nrhs);
+    HIF_LAUNCH_CHECK();
+  }
   const int nb = std::min(nrhs, kCols);
   // segment layout of the scratch: XI, YV (ymax), ZV, XS (zmax), SH (kmax), SC, SC2 (rmax)
   const int64_t seg = 2 * ymax + 2 * zmax + kmax + 2 * rmax;
@@ -817,6 +836,8 @@ template void FactorImpl<float>::prepare(hipStream_t);
 template void FactorImpl<double>::apply(const double*, double*, hipStream_t);
 template void FactorImpl<float>::apply(const double*, double*, hipStream_t);
 template void FactorImpl<double>::apply_block(const double*, double*, int, hipStream_t);
+template double FactorImpl<double>::apply_bytes() const;
+template double FactorImpl<float>::apply_bytes() const;
 template void FactorImpl<float>::apply_block(const double*, double*, int, hipStream_t);
 
 namespace {
@@ -835,11 +856,106 @@ struct Dot {
 
 }  // namespace
 
+// A preconditioner application captured once into a HIP graph (on a private
+// stream: the caller's may be the legacy stream, which cannot be captured) and
+// replayed on the caller's stream, which replaces its ~10 launches per level by
+// one graph launch.  The captured work is kernels only (no memset or copy
+// nodes).  HIF_APPLY_GRAPH=0 in the environment (read at every use) launches
+// the sweeps directly instead; a capture the runtime refuses falls back to the
+// same direct launches.
+struct ApplyGraph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  hipStream_t cs = nullptr;
+  bool failed = false;
+  double bytes = 0.0;  // algorithmic bytes of one application (profiler)
+
+  explicit ApplyGraph(double b) : bytes(b) {}
+  ~ApplyGraph() {
+    if (x) (void)hipGraphExecDestroy(x);
+    if (g) (void)hipGraphDestroy(g);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+  ApplyGraph(const ApplyGraph&) = delete;
+  ApplyGraph& operator=(const ApplyGraph&) = delete;
+  static bool env_off() {
+    const char* e = std::getenv("HIF_APPLY_GRAPH");
+    return e && e[0] == '0';
+  }
+  template <typename Fn>
+  void run(Fn&& fn, hipStream_t s) {
+    if (env_off() || failed) {
+      fn(s);
+      return;
+    }
+    if (!x) capture(fn);
+    if (!x) {
+      fn(s);
+      return;
+    }
+    ProfScope ps("apply_graph", s, 0.0, bytes);
+    HIF_HIP(hipGraphLaunch(x, s));
+  }
+
+ private:
+  template <typename Fn>
+  void capture(Fn& fn) {
+    if (!cs) HIF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    Profiler& P = profiler();
+    const bool was = P.on;
+    P.on = false;  // no event records inside the graph
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      try {
+        fn(cs);
+      } catch (...) {
+        hipGraph_t t = nullptr;
+        (void)hipStreamEndCapture(cs, &t);
+        if (t) (void)hipGraphDestroy(t);
+        P.on = was;
+        throw;
+      }
+      e = hipStreamEndCapture(cs, &g);
+      if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    }
+    P.on = was;
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      if (x) (void)hipGraphExecDestroy(x);
+      if (g) (void)hipGraphDestroy(g);
+      x = nullptr;
+      g = nullptr;
+      failed = true;
+    }
+  }
+};
+
+// Workspace of the single-vector PCG kept with the factor: its residual and
+// preconditioned residual vectors and the graph of F^{-1} applied from one to
+// the other.  The first solve with a factor launches the sweeps directly (a
+// capture costs about as much as it saves over one solve); the second captures
+// the graph, and it and every later solve replay it.
+struct PcgCache {
+  DevBuf<double> r, z;
+  std::unique_ptr<ApplyGraph> graph;
+  int solves = 0;
+};
+
 void pcg_solve(const hif_problem_s* A, hif_factor_s* F, const double* f, double* u, double tol,
                int maxit, hif_pcg_info* info, hipStream_t s) {
   const int64_t N = A->N;
   const Stencil st = A->stencil();
-  DevBuf<double> r(N), rold(N), z(N), p(N), q(N), sc(8);
+  if (!F->impl->pcg) F->impl->pcg = std::make_shared<PcgCache>();
+  PcgCache& C = *F->impl->pcg;
+  if ((int64_t)C.r.size() != N) {
+    C.r.alloc(N);
+    C.z.alloc(N);
+    C.graph.reset();
+  }
+  if (!C.graph) C.graph = std::make_unique<ApplyGraph>(F->impl->apply_bytes());
+  DevBuf<double>& r = C.r;
+  DevBuf<double>& z = C.z;
+  DevBuf<double> rold(N), p(N), q(N), sc(8);
   Dot dot;
   double h[8];
   auto fetch = [&]() {
@@ -858,7 +974,14 @@ void pcg_solve(const hif_problem_s* A, hif_factor_s* F, const double* f, double*
     info->converged = 1;
     return;
   }
-  F->impl->apply(r.get(), z.get(), s);
+  ApplyGraph& ag = *C.graph;
+  const bool replay = ++C.solves >= 2;
+  auto precondition = [&](hipStream_t q) { F->impl->apply(r.get(), z.get(), q); };
+  auto apply_z = [&]() {
+    if (replay) ag.run(precondition, s);
+    else precondition(s);
+  };
+  apply_z();
   HIF_HIP(hipMemcpyAsync(p.get(), z.get(), sizeof(double) * N, hipMemcpyDeviceToDevice, s));
   dot.run(r.get(), z.get(), nullptr, N, sc.get() + 0, s);
   const unsigned g = grid_for(N);
@@ -883,7 +1006,7 @@ void pcg_solve(const hif_problem_s* A, hif_factor_s* F, const double* f, double*
       }
       HIF_HIP(hipMemcpyAsync(r.get(), q.get(), sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     }
-    F->impl->apply(r.get(), z.get(), s);
+    apply_z();
     dot.run(z.get(), r.get(), rold.get(), N, sc.get() + 2, s);
     dot.run(r.get(), z.get(), nullptr, N, sc.get() + 3, s);
     hipLaunchKernelGGL(k_cg_dir, dim3(g), dim3(NT), 0, s, p.get(), (const double*)z.get(),
