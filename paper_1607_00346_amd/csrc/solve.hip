@@ -202,14 +202,26 @@ __global__ __launch_bounds__(NT) void k_gemv_t(const GemvDesc* __restrict__ dd,
       const int ib = i0 + head;
       const int nv = (d.m - ib) / VN;
       const auto cv = as_global((const V*)(col + ib));
-      for (int v = l; v < nv; v += 16) {
-        const V a = cv[v];
+      auto madd = [&](const V a, int v) {
         const int i = ib + VN * v;
 #pragma unroll
         for (int e = 0; e < VN; e += 2) {
           s0 += (double)a[e] * xv[i + e];
           s1 += (double)a[e + 1] * xv[i + e + 1];
         }
+      };
+      int v = l;
+      // four loads in flight per lane before their products
+      for (; v + 48 < nv; v += 64) {
+        const V a0 = cv[v], a1 = cv[v + 16], a2 = cv[v + 32], a3 = cv[v + 48];
+        madd(a0, v);
+        madd(a1, v + 16);
+        madd(a2, v + 32);
+        madd(a3, v + 48);
+      }
+      for (; v < nv; v += 16) {
+        const V a = cv[v];
+        madd(a, v);
       }
       const int it = ib + VN * nv + l;
       if (it < d.m) s0 += (double)as_global(col)[it] * xv[it];
@@ -294,6 +306,168 @@ __global__ __launch_bounds__(NT) void k_skel_move(double* u, const int* __restri
   double* s = i < d.k ? xh + d.kofs + i : xc + d.rofs + (i - d.k);
   if (to_u) u[p] = *s;
   else *s = u[p];
+}
+
+// ---- fused per-front sweeps (levels of many small fronts) -------------------
+// One workgroup per cell gathers the cell's vector entries into LDS, applies
+// its factor blocks reading each stored word once, and scatters the result:
+// one launch per level and sweep instead of a gather, two matrix-vector
+// launches and a scatter.  Factor columns are read as 16-byte vectors from
+// quads of rows aligned to the column start (the front base is 16-byte
+// aligned and ld a multiple of the quad), so a quad may reach past the rows
+// wanted: those entries lie inside the column's padded ld rows and are
+// dropped.
+
+// out[r - r0] = sum_t A(r, t) x[t] for r in [r0, r1), t < ncol (tri: only
+// t < the end of r's quad; the stored upper triangle is zero).
+template <typename T>
+__device__ __forceinline__ void fused_gemv_n(const T* A, int ld, int r0, int r1, int ncol,
+                                             bool tri, const double* x, double* out,
+                                             double* part) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::N;
+  const int q0 = r0 / VN, q1 = (r1 + VN - 1) / VN, nq = q1 - q0;
+  if (nq <= 0) return;  // uniform over the workgroup
+  const int tid = threadIdx.x;
+  const int G = nq >= NT ? 1 : NT / nq;  // column groups
+  const int busy = nq >= NT ? NT : nq * G;
+  const int g = tid / (nq >= NT ? NT : nq);
+  for (int qq = tid % (nq >= NT ? NT : nq); qq < nq && tid < busy; qq += (nq >= NT ? NT : nq)) {
+    const int q = q0 + qq;
+    const int tend = tri ? min(ncol, VN * q + VN) : ncol;
+    double acc[VN];
+#pragma unroll
+    for (int e = 0; e < VN; ++e) acc[e] = 0.0;
+    const auto col = as_global((const V*)(A + VN * q));
+    const int64_t ldv = ld / VN;
+    int t = g;
+    for (; t + 3 * G < tend; t += 4 * G) {
+      const V a0 = col[ldv * t], a1 = col[ldv * (t + G)], a2 = col[ldv * (t + 2 * G)],
+              a3 = col[ldv * (t + 3 * G)];
+#pragma unroll
+      for (int e = 0; e < VN; ++e)
+        acc[e] += (double)a0[e] * x[t] + (double)a1[e] * x[t + G] + (double)a2[e] * x[t + 2 * G] +
+                  (double)a3[e] * x[t + 3 * G];
+    }
+    for (; t < tend; t += G) {
+      const V a = col[ldv * t];
+#pragma unroll
+      for (int e = 0; e < VN; ++e) acc[e] += (double)a[e] * x[t];
+    }
+    if (G == 1) {
+#pragma unroll
+      for (int e = 0; e < VN; ++e) {
+        const int r = VN * q + e;
+        if (r >= r0 && r < r1) out[r - r0] = acc[e];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < VN; ++e) part[g * (nq * VN) + qq * VN + e] = acc[e];
+    }
+  }
+  if (G > 1) {
+    __syncthreads();
+    for (int i = tid; i < nq * VN; i += NT) {
+      const int r = VN * q0 + i;
+      if (r < r0 || r >= r1) continue;
+      double v = 0.0;
+      for (int k = 0; k < G; ++k) v += part[k * (nq * VN) + i];
+      out[r - r0] = v;
+    }
+  }
+  __syncthreads();
+}
+
+// out[t] = sum_{r in [r0, r1)} A(r, t) x[r - r0] for t < ncol (tri: r >= t):
+// 16 lanes per column, the columns dealt to the 16 groups of the workgroup.
+template <typename T>
+__device__ __forceinline__ void fused_gemv_t(const T* A, int ld, int r0, int r1, int ncol,
+                                             bool tri, const double* x, double* out) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::N;
+  const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
+  for (int tb = 0; tb < ncol; tb += NT / 16) {
+    const int t = tb + g;
+    double s = 0.0;
+    if (t < ncol) {
+      const int rs = tri ? max(r0, t) : r0;
+      const int qb = rs / VN, qe = (r1 + VN - 1) / VN;
+      const auto col = as_global((const V*)(A + (int64_t)ld * t));
+      int q = qb + l;
+      for (; q + 16 < qe; q += 32) {
+        const V a0 = col[q], a1 = col[q + 16];
+#pragma unroll
+        for (int e = 0; e < VN; ++e) {
+          const int r = VN * q + e, r2 = r + 16 * VN;
+          s += (r >= rs && r < r1) ? (double)a0[e] * x[r - r0] : 0.0;
+          s += (r2 >= rs && r2 < r1) ? (double)a1[e] * x[r2 - r0] : 0.0;
+        }
+      }
+      for (; q < qe; q += 16) {
+        const V a = col[q];
+#pragma unroll
+        for (int e = 0; e < VN; ++e) {
+          const int r = VN * q + e;
+          s += (r >= rs && r < r1) ? (double)a[e] * x[r - r0] : 0.0;
+        }
+      }
+    }
+    s += __shfl_xor(s, 8, 16);
+    s += __shfl_xor(s, 4, 16);
+    s += __shfl_xor(s, 2, 16);
+    s += __shfl_xor(s, 1, 16);
+    if (t < ncol && l == 0) out[t] = s;
+  }
+  __syncthreads();
+}
+
+// Up sweep of one level: x_I <- L_I^{-1} x_I (scattered into u) and
+// z = L_SI x_I for the face update.  Dynamic LDS: 2 maxI + 4 NT doubles.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_up_fused(double* u, const int* __restrict__ rows,
+                                                 const int64_t* __restrict__ crow_off,
+                                                 const FrontDesc* __restrict__ fd, int maxI,
+                                                 const int64_t* __restrict__ zoff, double* zv) {
+  extern __shared__ double lds[];
+  double* xs = lds;
+  double* ys = lds + maxI;
+  double* part = lds + 2 * maxI;
+  const FrontDesc f = fd[blockIdx.x];
+  const int* r = rows + crow_off[blockIdx.x];
+  const T* L = static_cast<const T*>(f.ptr);
+  for (int i = threadIdx.x; i < f.nI; i += NT) xs[i] = u[r[i]];
+  __syncthreads();
+  fused_gemv_n<T>(L, f.ld, 0, f.nI, f.nI, true, xs, ys, part);
+  for (int i = threadIdx.x; i < f.nI; i += NT) u[r[i]] = ys[i];
+  if (f.nR > f.nI) fused_gemv_n<T>(L, f.ld, f.nI, f.nR, f.nI, false, ys, zv + zoff[blockIdx.x], part);
+}
+
+// Down sweep of one level: x_I <- L_I^{-T} (x_I - L_SI^T x_S), scattered into
+// u.  Dynamic LDS: 2 maxI + maxS doubles.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_down_fused(double* u, const int* __restrict__ rows,
+                                                   const int64_t* __restrict__ crow_off,
+                                                   const FrontDesc* __restrict__ fd, int maxI) {
+  extern __shared__ double lds[];
+  double* xi = lds;
+  double* ys = lds + maxI;
+  double* xsv = lds + 2 * maxI;
+  const FrontDesc f = fd[blockIdx.x];
+  const int* r = rows + crow_off[blockIdx.x];
+  const T* L = static_cast<const T*>(f.ptr);
+  for (int i = threadIdx.x; i < f.nR; i += NT) {
+    const double v = u[r[i]];
+    if (i < f.nI) xi[i] = v;
+    else xsv[i - f.nI] = v;
+  }
+  __syncthreads();
+  if (f.nR > f.nI) {
+    fused_gemv_t<T>(L, f.ld, f.nI, f.nR, f.nI, false, xsv, ys);
+    for (int i = threadIdx.x; i < f.nI; i += NT) xi[i] -= ys[i];
+    __syncthreads();
+  }
+  fused_gemv_t<T>(L, f.ld, 0, f.nI, f.nI, true, xi, ys);
+  for (int i = threadIdx.x; i < f.nI; i += NT) u[r[i]] = ys[i];
 }
 
 // ---- block apply (several right-hand sides) --------------------------------
@@ -539,6 +713,19 @@ void FactorImpl<T>::prepare(hipStream_t s) {
   prepared = true;
 }
 
+// Levels of many small fronts take the fused per-front sweeps (one workgroup
+// per cell; their vectors must fit in LDS and the factor columns must start
+// 16-byte aligned).  HIF_APPLY_FUSED=0 in the environment turns them off.
+constexpr int kFuseMinCells = 1024, kFuseMaxI = 2048, kFuseMaxS = 4096;
+
+template <typename T>
+bool fused_level(const Level<T>& lv) {
+  const char* e = std::getenv("HIF_APPLY_FUSED");
+  const bool off = e && e[0] == '0';
+  return !off && lv.plan->ncell >= kFuseMinCells && lv.maxI <= kFuseMaxI &&
+         lv.maxS <= kFuseMaxS && lv.gv_L_vec;
+}
+
 template <typename T>
 void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   prepare(s);
@@ -559,7 +746,13 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
     Level<T>& lv = levels[l];
     profiler().level = l;
     const int nc = lv.plan->ncell;
-    if (nc > 0) {
+    if (nc > 0 && fused_level(lv)) {
+      ProfScope ps("apply_up_fused", s, 0.0, lv.bytes_L + lv.bytes_S);
+      const size_t lds = sizeof(double) * (2 * (size_t)lv.maxI + 4 * NT);
+      hipLaunchKernelGGL((k_up_fused<T>), dim3((unsigned)nc), dim3(NT), lds, s, u, lv.rows.get(),
+                         lv.crow_off.get(), lv.fd.get(), lv.maxI, lv.zoff.get(), zv);
+      HIF_LAUNCH_CHECK();
+    } else if (nc > 0) {
       dim3 gI((unsigned)ceil_div(std::max(1, lv.maxI), NT), (unsigned)nc);
       {
         ProfScope ps("apply_up_L", s, 0.0, lv.bytes_L);
@@ -623,6 +816,14 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
     }
     const int nc = lv.plan->ncell;
     if (nc == 0) continue;
+    if (fused_level(lv)) {
+      ProfScope ps("apply_down_fused", s, 0.0, lv.bytes_L + lv.bytes_S);
+      const size_t lds = sizeof(double) * (2 * (size_t)lv.maxI + lv.maxS);
+      hipLaunchKernelGGL((k_down_fused<T>), dim3((unsigned)nc), dim3(NT), lds, s, u,
+                         lv.rows.get(), lv.crow_off.get(), lv.fd.get(), lv.maxI);
+      HIF_LAUNCH_CHECK();
+      continue;
+    }
     const int gmax = std::max(lv.maxI, lv.maxI + lv.maxS);
     dim3 gG((unsigned)ceil_div(std::max(1, gmax), NT), (unsigned)nc);
     dim3 gI((unsigned)ceil_div(std::max(1, lv.maxI), NT), (unsigned)nc);

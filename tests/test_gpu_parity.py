@@ -293,3 +293,69 @@ def test_deterministic_factor(gpu_lib):
     assert np.array_equal(g1.apply(f), g2.apply(f))
     g1.close()
     g2.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_coarse_eps_degenerate_skeletons(gpu_lib, prec):
+    """eps = 0.5: almost every face point is redundant (ranks 1-4 of up to
+    49 points at level 0: skeleton blocks far narrower than the redundant
+    ones).  Ranks match the oracle face by face and the weak preconditioner
+    still drives PCG to 1e-10."""
+    n, leaf, eps = 16, 4, 0.5
+    a = log_uniform_field(n, -1, 1, 211)
+    b = uniform_field(n, 0, 1, 212)
+    fac = O.build(n, leaf, a, b, eps)
+    g = GpuHif(gpu_lib, n, leaf, eps, a, b, precision=prec)
+    total, bad = 0, 0
+    for level, lev in enumerate(fac.levels):
+        ranks, sizes = gpu_lib.hif_factor_ranks(g.F, level)
+        r_gpu, r_orc = np.array(ranks), np.array(lev.face_ranks)
+        total += len(ranks)
+        bad += int(np.sum(np.abs(r_gpu - r_orc) > 1))
+    assert bad <= max(1, total // 50), (bad, total)
+    f = normal_rhs(n, 213)
+    st, info, u = g.pcg(f, 1e-10, maxit=300)
+    assert st == 0 and info.converged
+    A = O.assemble(n, a, b)
+    assert np.linalg.norm(f - A @ u) <= 1e-10 * np.linalg.norm(f)
+    g.close()
+
+
+def test_fused_sweeps_exact_at_eps0(gpu_lib):
+    """32^3 with 2^3 leaves: 4096 level-0 cells of 1 to 8 interior points, so
+    the fused per-front sweeps run on the smallest fronts there are; at eps = 0
+    the apply is a direct solve (1e-11 against a sparse solve)."""
+    n, leaf = 32, 2
+    a = log_uniform_field(n, -2, 2, 221)
+    b = const_field(n, 0.0)
+    f = normal_rhs(n, 222)
+    ref = spla.spsolve(O.assemble(n, a, b).tocsc(), f)
+    g = GpuHif(gpu_lib, n, leaf, 0.0, a, b)
+    u = g.apply(f)
+    assert np.linalg.norm(u - ref) <= 1e-11 * np.linalg.norm(ref)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fused_sweeps_match_general_path(gpu_lib, prec):
+    """64^3 with 4^3 leaves (4096 level-0 fronts of 27-64 interior points):
+    the fused per-front sweeps equal the gather / matrix-vector / scatter path
+    up to the order of the FP64 sums (1e-12 relative)."""
+    import os
+    n, leaf = 64, 4
+    a = log_uniform_field(n, -2, 2, 231)
+    f = normal_rhs(n, 232)
+    g = GpuHif(gpu_lib, n, leaf, 1e-4, a, const_field(n, 0.0), precision=prec)
+    old = os.environ.get("HIF_APPLY_FUSED")
+    try:
+        os.environ["HIF_APPLY_FUSED"] = "0"
+        u0 = g.apply(f)
+        os.environ["HIF_APPLY_FUSED"] = "1"
+        u1 = g.apply(f)
+    finally:
+        if old is None:
+            os.environ.pop("HIF_APPLY_FUSED", None)
+        else:
+            os.environ["HIF_APPLY_FUSED"] = old
+    assert np.linalg.norm(u1 - u0) <= 1e-12 * np.linalg.norm(u0)
+    g.close()
