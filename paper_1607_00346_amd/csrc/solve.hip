@@ -470,6 +470,70 @@ __global__ __launch_bounds__(NT) void k_down_fused(double* u, const int* __restr
   for (int i = threadIdx.x; i < f.nI; i += NT) u[r[i]] = ys[i];
 }
 
+// Skeleton step of one face in one wave (levels of many small faces): the
+// face's x_F̂ (k) and x_F̌ (r) are gathered into LDS and the three small
+// products run there.  Up: x_F̌ -= T^T x_F̂, x_F̌ <- L_F̌^{-1} x_F̌,
+// x_F̂ -= Y^T x_F̌.  Down: x_F̌ -= Y x_F̂, x_F̌ <- L_F̌^{-T} x_F̌, x_F̂ -= T x_F̌.
+// L_F̌^{-1}'s stored upper triangle is not zero, so its loops stop at the
+// diagonal.  Dynamic LDS: maxF + maxr doubles.
+template <typename T>
+__global__ __launch_bounds__(64) void k_skel_fused(double* u, const int* __restrict__ skpts,
+                                                   const SkelDesc* __restrict__ sk,
+                                                   const T* __restrict__ skel, int maxF, int down) {
+  extern __shared__ double lds[];
+  const SkelDesc d = sk[blockIdx.x];
+  const int k = d.k, r = d.r, lane = threadIdx.x;
+  double* xh = lds;
+  double* xc = lds + k;
+  double* yc = lds + maxF;
+  const int* pts = skpts + d.pts_off;
+  const auto Tm = as_global(skel + d.offT);
+  const auto Lc = as_global(skel + d.offL);
+  const auto Y = as_global(skel + d.offY);
+  for (int i = lane; i < k + r; i += 64) lds[i] = u[pts[i]];
+  __syncthreads();
+  if (!down) {
+    for (int b = lane; b < r; b += 64) {
+      double s = 0.0;
+      for (int i = 0; i < k; ++i) s += (double)Tm[i + (int64_t)k * b] * xh[i];
+      xc[b] -= s;
+    }
+    __syncthreads();
+    for (int b = lane; b < r; b += 64) {
+      double s = 0.0;
+      for (int t = 0; t <= b; ++t) s += (double)Lc[b + (int64_t)r * t] * xc[t];
+      yc[b] = s;
+    }
+    __syncthreads();
+    for (int i = lane; i < k; i += 64) {
+      double s = 0.0;
+      for (int b = 0; b < r; ++b) s += (double)Y[b + (int64_t)r * i] * yc[b];
+      xh[i] -= s;
+    }
+  } else {
+    for (int b = lane; b < r; b += 64) {
+      double s = 0.0;
+      for (int i = 0; i < k; ++i) s += (double)Y[b + (int64_t)r * i] * xh[i];
+      xc[b] -= s;
+    }
+    __syncthreads();
+    for (int b = lane; b < r; b += 64) {
+      double s = 0.0;
+      for (int t = b; t < r; ++t) s += (double)Lc[t + (int64_t)r * b] * xc[t];
+      yc[b] = s;
+    }
+    __syncthreads();
+    for (int i = lane; i < k; i += 64) {
+      double s = 0.0;
+      for (int b = 0; b < r; ++b) s += (double)Tm[i + (int64_t)k * b] * yc[b];
+      xh[i] -= s;
+    }
+  }
+  __syncthreads();
+  for (int i = lane; i < k; i += 64) u[pts[i]] = xh[i];
+  for (int b = lane; b < r; b += 64) u[pts[k + b]] = yc[b];
+}
+
 // ---- block apply (several right-hand sides) --------------------------------
 // Vector blocks: column z of u at u + z * N; column z of a scratch segment of
 // length ld at base + z * ld (scratch in the factor's precision T).
@@ -726,6 +790,16 @@ bool fused_level(const Level<T>& lv) {
          lv.maxS <= kFuseMaxS && lv.gv_L_vec;
 }
 
+// Levels of many small faces take the one-wave skeleton step (same switch).
+constexpr int kSkelFuseMinFaces = 1024, kSkelFuseMaxF = 1024;
+
+template <typename T>
+bool fused_skel(const Level<T>& lv) {
+  const char* e = std::getenv("HIF_APPLY_FUSED");
+  const bool off = e && e[0] == '0';
+  return !off && lv.hsk.size() >= (size_t)kSkelFuseMinFaces && lv.maxF <= kSkelFuseMaxF;
+}
+
 template <typename T>
 void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   prepare(s);
@@ -782,7 +856,13 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
         HIF_LAUNCH_CHECK();
       }
       const int ns = (int)lv.hsk.size();
-      if (ns > 0) {
+      if (ns > 0 && fused_skel(lv)) {
+        ProfScope ps("apply_skel_fused", s, 0.0, lv.bytes_skel);
+        hipLaunchKernelGGL((k_skel_fused<T>), dim3((unsigned)ns), dim3(64),
+                           sizeof(double) * (size_t)(lv.maxF + lv.maxr), s, u, lv.skpts.get(),
+                           lv.sk.get(), (const T*)lv.skel.get(), lv.maxF, 0);
+        HIF_LAUNCH_CHECK();
+      } else if (ns > 0) {
         ProfScope ps("apply_skel", s, 0.0, lv.bytes_skel);
         dim3 gM((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)ns);
         hipLaunchKernelGGL(k_skel_move, gM, dim3(NT), 0, s, u, lv.skpts.get(), lv.sk.get(), sh, sc,
@@ -802,7 +882,13 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
     Level<T>& lv = levels[l];
     profiler().level = l;
     const int ns = (int)lv.hsk.size();
-    if (!lv.plan->root && ns > 0) {
+    if (!lv.plan->root && ns > 0 && fused_skel(lv)) {
+      ProfScope ps("apply_skel_fused", s, 0.0, lv.bytes_skel);
+      hipLaunchKernelGGL((k_skel_fused<T>), dim3((unsigned)ns), dim3(64),
+                         sizeof(double) * (size_t)(lv.maxF + lv.maxr), s, u, lv.skpts.get(),
+                         lv.sk.get(), (const T*)lv.skel.get(), lv.maxF, 1);
+      HIF_LAUNCH_CHECK();
+    } else if (!lv.plan->root && ns > 0) {
       ProfScope ps("apply_skel", s, 0.0, lv.bytes_skel);
       dim3 gM((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)ns);
       hipLaunchKernelGGL(k_skel_move, gM, dim3(NT), 0, s, u, lv.skpts.get(), lv.sk.get(), sh, sc, 0);
