@@ -81,14 +81,27 @@ def run_gpu(args):
         prof = H.hif_profile_end()
         return (t1 - t0) / args.steps, rec, stats, prof
 
+    def solve_error(opts):
+        """e_s = |x - F^{-1} A x| / |x| for one seeded Gaussian x (the paper's
+        relative solve error), on a factor built outside the timed region."""
+        g = torch.Generator(device="cpu").manual_seed(7)
+        x = torch.randn(N, generator=g, dtype=torch.float64).to(dev)
+        y, z = torch.empty_like(x), torch.empty_like(x)
+        F = H.hif_build(A, opts)
+        H.hif_matvec(A, x, y)
+        H.hif_apply(F, y, z)
+        torch.cuda.synchronize()
+        H.hif_factor_destroy(F)
+        return float(torch.linalg.norm(x - z) / torch.linalg.norm(x))
+
     ms_m, rec_m, stats_m, prof_m = timed(opt_m, "mixed")
     u_m = tu.cpu().numpy().copy()
     out = {"mixed": {"s_per_step": ms_m, "rec": rec_m, "stats": stats_m, "u": u_m,
-                     "prof": prof_m}}
+                     "prof": prof_m, "e_s": solve_error(opt_m)}}
     if not args.skip_fp64:
         ms_d, rec_d, stats_d, prof_d = timed(opt_d, "fp64")
         out["fp64"] = {"s_per_step": ms_d, "rec": rec_d, "stats": stats_d,
-                       "u": tu.cpu().numpy().copy(), "prof": prof_d}
+                       "u": tu.cpu().numpy().copy(), "prof": prof_d, "e_s": solve_error(opt_d)}
     H.hif_problem_destroy(A)
     out["N"] = N
     out["a"], out["b"], out["f"] = a, b, f
@@ -386,6 +399,7 @@ def main():
     res_m = float(np.linalg.norm(r["f"] - A @ mixed["u"]) / fn)
     extra = {"mixed_relres_oracle_matvec": res_m,
              "mixed_pcg_iters": mixed["rec"][-1][1],
+             "mixed_solve_error_e_s": mixed["e_s"],
              "mixed_t_factor_s": float(np.mean([x[4] for x in mixed["rec"]])),
              "mixed_t_pcg_s": float(np.mean([x[5] for x in mixed["rec"]])),
              "mixed_root_size": mixed["stats"]["root_size"],
@@ -396,6 +410,7 @@ def main():
         extra.update({
             "fp64_value": N / d["s_per_step"],
             "fp64_pcg_iters": d["rec"][-1][1],
+            "fp64_solve_error_e_s": d["e_s"],
             "fp64_t_factor_s": float(np.mean([x[4] for x in d["rec"]])),
             "fp64_t_pcg_s": float(np.mean([x[5] for x in d["rec"]])),
             "fp64_relres_oracle_matvec": float(np.linalg.norm(r["f"] - A @ d["u"]) / fn),
