@@ -587,14 +587,16 @@ constexpr int kPivPanel = 64;
 
 // NTP threads per face: 1024 for large faces (few faces, each pivot's column
 // spread over more lanes), 64 for faces of at most 64 points, 256 otherwise.
-template <int NTP>
+template <int NTP, int MAXF>
 __global__ __launch_bounds__(NTP) void k_pchol_panel(
     const double* __restrict__ G, double* __restrict__ L, const int64_t* __restrict__ goff,
     const int* __restrict__ nFa, const int* __restrict__ ldga, const int64_t* __restrict__ poff,
     int* __restrict__ perm, double* __restrict__ dbuf, int* __restrict__ pivbuf,
     int* __restrict__ kst, double* __restrict__ r11, double eps, int j0) {
-  __shared__ double d[kPcholMax];
-  __shared__ unsigned char piv[kPcholMax];
+  // sized for the largest face of the launch, so that small faces keep many
+  // workgroups resident per CU
+  __shared__ double d[MAXF];
+  __shared__ unsigned char piv[MAXF];
   __shared__ double lp[kPivPanel];
   __shared__ double rv[NTP / 64];
   __shared__ int ri[NTP / 64];
@@ -1166,17 +1168,21 @@ void pivoted_cholesky(double* G, double* L, const int64_t* goff, const int* nF, 
   for (int j0 = 0; j0 < maxF; j0 += kPivPanel) {
     {
       ProfScope ps("pivoted_cholesky", s);
-      if (maxF > 256)
-        hipLaunchKernelGGL(k_pchol_panel<1024>, dim3((unsigned)batch), dim3(1024), 0, s, G, L,
-                           goff, nF, ldg, poff, perm, dbuf.get(), pivbuf.get(), kst.get(),
+      if (maxF > 1024)
+        hipLaunchKernelGGL((k_pchol_panel<1024, kPcholMax>), dim3((unsigned)batch), dim3(1024),
+                           0, s, G, L, goff, nF, ldg, poff, perm, dbuf.get(), pivbuf.get(),
+                           kst.get(), r11.get(), eps, j0);
+      else if (maxF > 256)
+        hipLaunchKernelGGL((k_pchol_panel<1024, 1024>), dim3((unsigned)batch), dim3(1024), 0, s,
+                           G, L, goff, nF, ldg, poff, perm, dbuf.get(), pivbuf.get(), kst.get(),
                            r11.get(), eps, j0);
       else if (maxF <= 64)
-        hipLaunchKernelGGL(k_pchol_panel<64>, dim3((unsigned)batch), dim3(64), 0, s, G, L, goff,
-                           nF, ldg, poff, perm, dbuf.get(), pivbuf.get(), kst.get(), r11.get(),
-                           eps, j0);
-      else
-        hipLaunchKernelGGL(k_pchol_panel<NTHR>, dim3((unsigned)batch), dim3(NTHR), 0, s, G, L,
+        hipLaunchKernelGGL((k_pchol_panel<64, 64>), dim3((unsigned)batch), dim3(64), 0, s, G, L,
                            goff, nF, ldg, poff, perm, dbuf.get(), pivbuf.get(), kst.get(),
+                           r11.get(), eps, j0);
+      else
+        hipLaunchKernelGGL((k_pchol_panel<NTHR, 256>), dim3((unsigned)batch), dim3(NTHR), 0, s,
+                           G, L, goff, nF, ldg, poff, perm, dbuf.get(), pivbuf.get(), kst.get(),
                            r11.get(), eps, j0);
       HIF_LAUNCH_CHECK();
     }
