@@ -64,7 +64,7 @@ struct TileSmem {
 template <typename TIn, typename TC, int OPA, int OPB, int TM, int TN>
 __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, const TIn* __restrict__ B, int ldb,
                             TC* C, int ldc, int m, int n, int k, int m0, int n0, TC alpha, TC beta,
-                            TileSmem<TC, TM, TN>& sm) {
+                            TileSmem<TIn, TM, TN>& sm) {
   const auto gA = as_global(A);
   const auto gB = as_global(B);
   const auto gC = as_global(C);
@@ -128,16 +128,16 @@ __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, co
     return c;
   };
 
-  TC ra[LA], rb[LB];
+  TIn ra[LA], rb[LB];  // operands stay in their own type until the MFMA reads them
   auto load = [&](int c) {
     const int t0 = kb + c * KC;
     if (clean(t0)) {
       const TIn* ca = OPA == OP_N ? A + m0 + (int64_t)lda * t0 : A + t0 + (int64_t)lda * m0;
       const TIn* cb = OPB == OP_N ? B + t0 + (int64_t)ldb * n0 : B + n0 + (int64_t)ldb * t0;
 #pragma unroll
-      for (int r = 0; r < LA; ++r) ra[r] = (TC)load_global(ca, oa[r]);
+      for (int r = 0; r < LA; ++r) ra[r] = load_global(ca, oa[r]);
 #pragma unroll
-      for (int r = 0; r < LB; ++r) rb[r] = (TC)load_global(cb, ob[r]);
+      for (int r = 0; r < LB; ++r) rb[r] = load_global(cb, ob[r]);
       return;
     }
 #pragma unroll
@@ -146,8 +146,8 @@ __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, co
       bool ok = gi < m && gt < ke;
       if (flags & GF_A_LOWER) ok = ok && gt <= gi;
       if (flags & GF_A_UPPER) ok = ok && gt >= gi;
-      TC v = TC(0);
-      if (ok) v = (TC)(OPA == OP_N ? gA[gi + (int64_t)lda * gt] : gA[gt + (int64_t)lda * gi]);
+      TIn v = TIn(0);
+      if (ok) v = OPA == OP_N ? gA[gi + (int64_t)lda * gt] : gA[gt + (int64_t)lda * gi];
       ra[r] = v;
     }
 #pragma unroll
@@ -156,8 +156,8 @@ __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, co
       bool ok = gj < n && gt < ke;
       if (flags & GF_B_LOWER) ok = ok && gt >= gj;
       if (flags & GF_B_UPPER) ok = ok && gt <= gj;
-      TC v = TC(0);
-      if (ok) v = (TC)(OPB == OP_N ? gB[gt + (int64_t)ldb * gj] : gB[gj + (int64_t)ldb * gt]);
+      TIn v = TIn(0);
+      if (ok) v = OPB == OP_N ? gB[gt + (int64_t)ldb * gj] : gB[gj + (int64_t)ldb * gt];
       rb[r] = v;
     }
   };
@@ -173,9 +173,9 @@ __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, co
       const int kk = 4 * s + (lane >> 4);
       TC av[FM], bv[FN];
 #pragma unroll
-      for (int x = 0; x < FM; ++x) av[x] = sm.As[buf][kk][wm * (TM / 2) + 16 * x + (lane & 15)];
+      for (int x = 0; x < FM; ++x) av[x] = (TC)sm.As[buf][kk][wm * (TM / 2) + 16 * x + (lane & 15)];
 #pragma unroll
-      for (int y = 0; y < FN; ++y) bv[y] = sm.Bs[buf][kk][wn * (TN / 2) + 16 * y + (lane & 15)];
+      for (int y = 0; y < FN; ++y) bv[y] = (TC)sm.Bs[buf][kk][wn * (TN / 2) + 16 * y + (lane & 15)];
 #pragma unroll
       for (int x = 0; x < FM; ++x)
 #pragma unroll
@@ -184,7 +184,7 @@ __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, co
   };
 
   if (nchunk > 0) {
-    if constexpr (TileSmem<TC, TM, TN>::NBUF == 2) {
+    if constexpr (TileSmem<TIn, TM, TN>::NBUF == 2) {
       load(0);
       store(0);
       __syncthreads();
@@ -248,7 +248,7 @@ __device__ __forceinline__ void xcd_remap(unsigned& bx, unsigned& by, unsigned& 
 template <typename TIn, typename TC, int OPA, int OPB, int TM, int TN, int CLS>
 __global__ __launch_bounds__(NTHR) void k_gemm_desc(int flags, const GemmDesc* __restrict__ desc,
                                                     TC alpha, TC beta) {
-  __shared__ TileSmem<TC, TM, TN> sm;
+  __shared__ TileSmem<TIn, TM, TN> sm;
   unsigned bx, by, bz;
   xcd_remap(bx, by, bz);
   const GemmDesc d = desc[bz];
