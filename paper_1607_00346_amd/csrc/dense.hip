@@ -191,9 +191,13 @@ __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, co
       for (int c = 0; c < nchunk; ++c) {
         const int buf = c & 1;
         if (c + 1 < nchunk) load(c + 1);
-        // keep the next chunk's global loads issued ahead of this chunk's MFMAs
+        // keep the next chunk's global loads issued ahead of this chunk's MFMAs,
+        // and let this wave's MFMA phase take issue priority over the other
+        // waves' load and store phases
         __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_setprio(1);
         compute(buf);
+        __builtin_amdgcn_s_setprio(0);
         __builtin_amdgcn_sched_barrier(0);
         if (c + 1 < nchunk) store(buf ^ 1);
         __syncthreads();
