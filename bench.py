@@ -111,7 +111,8 @@ def run_gpu(args):
 def run_batched(args):
     """48 independent problems (n drawn from 32^3..96^3, leaf per size, log10 a ~
     U(-1,1), b ~ U(0,1)), FP32 factor at eps 1e-4 + FP64 PCG to 1e-10 each:
-    one joint build (hif_build_batched) against one hif_build per problem."""
+    one joint build (hif_build_batched) and one joint solve (hif_pcg_batched)
+    against one hif_build and one hif_pcg per problem."""
     import torch
     from paper_1607_00346_amd import hif as H
     from workloads import batched_workloads
@@ -127,14 +128,22 @@ def run_batched(args):
     torch.cuda.synchronize()
     total = sum(w.n ** 3 for w in wl)
 
-    def solve_all(F):
+    def solve_all(F, together):
         its, worst = [], 0.0
-        for i in range(len(wl)):
-            st, info = H.hif_pcg(A[i], F[i], ins[i][2], outs[i], tol=args.tol, maxit=args.maxit)
-            if st != 0 or not info[0].converged:
+        if together:  # one call: the solves overlap on the library's streams
+            st, infos = H.hif_pcg_batched(A, F, [x[2] for x in ins], outs, tol=args.tol,
+                                          maxit=args.maxit)
+        else:
+            infos = []
+            for i in range(len(wl)):
+                st, info = H.hif_pcg(A[i], F[i], ins[i][2], outs[i], tol=args.tol,
+                                     maxit=args.maxit)
+                infos.append(info[0])
+        for i, info in enumerate(infos):
+            if not info.converged:
                 raise RuntimeError(f"problem {i} did not converge")
-            its.append(info[0].iters)
-            worst = max(worst, info[0].relres)
+            its.append(info.iters)
+            worst = max(worst, info.relres)
         torch.cuda.synchronize()
         return its, worst
 
@@ -145,7 +154,7 @@ def run_batched(args):
         F = H.hif_build_batched(A, opts)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        its, worst = solve_all(F)
+        its, worst = solve_all(F, True)
         t2 = time.perf_counter()
         peak["joint_gb"] = H.hif_factor_stats(F[0]).peak_bytes / 1e9
         peak["factor_gb"] = sum(H.hif_factor_stats(x).factor_bytes for x in F) / 1e9
@@ -159,7 +168,7 @@ def run_batched(args):
         F = [H.hif_build(A[i], opts[i]) for i in range(len(wl))]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        its, worst = solve_all(F)
+        its, worst = solve_all(F, False)
         t2 = time.perf_counter()
         for x in F:
             H.hif_factor_destroy(x)

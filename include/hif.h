@@ -138,6 +138,17 @@ hif_status hif_matvec(hif_problem_t A, const double* x, double* y, int32_t nrhs,
 hif_status hif_pcg(hif_problem_t A, hif_factor_t F, const double* f, double* u, int32_t nrhs,
                    double tol, int32_t maxit, hif_pcg_info* info, void* stream);
 
+/* hif_pcg for several problems at once: for each i, one single-vector PCG
+ * solve of A[i] u[i] = f[i] with F[i] (as hif_pcg with nrhs = 1).  The solves
+ * run concurrently on library-owned streams (ordered after `stream`, which
+ * then waits for all of them), so that the latency-bound iterations of small
+ * problems overlap.  A, F, f, u and info are host arrays of `count` entries;
+ * f[i] and u[i] are device pointers; no factor may appear twice.  Returns
+ * HIF_ENOCONV if any solve hit maxit.  Blocks the calling thread. */
+hif_status hif_pcg_batched(int32_t count, const hif_problem_t* A, const hif_factor_t* F,
+                           const double* const* f, double* const* u, double tol, int32_t maxit,
+                           hif_pcg_info* info, void* stream);
+
 /* Sizes, ranks, flops, bytes and times of a factor (host struct). */
 hif_status hif_factor_stats(hif_factor_t F, hif_stats* out);
 

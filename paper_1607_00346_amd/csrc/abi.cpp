@@ -206,6 +206,29 @@ hif_status hif_pcg(hif_problem_t A, hif_factor_t F, const double* f, double* u, 
   });
 }
 
+hif_status hif_pcg_batched(int32_t count, const hif_problem_t* A, const hif_factor_t* F,
+                           const double* const* f, double* const* u, double tol, int32_t maxit,
+                           hif_pcg_info* info, void* stream) {
+  return guarded([&] {
+    HIF_REQUIRE(count >= 1 && A != nullptr && F != nullptr && f != nullptr && u != nullptr &&
+                    info != nullptr,
+                HIF_EINVAL, "NULL array or count < 1");
+    HIF_REQUIRE(maxit >= 1 && std::isfinite(tol) && tol > 0.0, HIF_EINVAL,
+                "need maxit >= 1, tol > 0");
+    for (int32_t i = 0; i < count; ++i) {
+      HIF_REQUIRE(A[i] != nullptr && F[i] != nullptr && F[i]->impl, HIF_EINVAL, "NULL handle");
+      HIF_REQUIRE(F[i]->stats.n_dof == A[i]->N, HIF_EINVAL, "factor and problem sizes differ");
+      HIF_REQUIRE(f[i] != nullptr && u[i] != nullptr && f[i] != u[i], HIF_EINVAL, "bad vectors");
+      for (int32_t j = 0; j < i; ++j)
+        HIF_REQUIRE(F[j] != F[i], HIF_EINVAL, "a factor listed twice (its calls would overlap)");
+    }
+    hif::pcg_solve_batched(count, A, F, f, u, tol, maxit, info, as_stream(stream));
+    bool all = true;
+    for (int32_t i = 0; i < count; ++i) all = all && info[i].converged;
+    if (!all) throw hif::Error(HIF_ENOCONV, "PCG did not reach tol within maxit");
+  });
+}
+
 hif_status hif_factor_stats(hif_factor_t F, hif_stats* out) {
   return guarded([&] {
     HIF_REQUIRE(F != nullptr && out != nullptr, HIF_EINVAL, "NULL argument");

@@ -482,7 +482,7 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
 
   for (int level = 0; level <= maxL; ++level) {
     HIF_HIP(hipEventRecord(ev.e[level], s));
-    profiler().level = level;
+    prof_level() = level;
     std::vector<int> here, below;  // problems with this level; those for which it is not the root
     for (int j = 0; j < nj; ++j) {
       if (level <= jobs[j].L) here.push_back(j);
@@ -1000,7 +1000,7 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
     HIF_HIP(hipEventElapsedTime(&ms, ev.e[level], ev.e[level + 1]));
     level_s[level] = 1e-3 * ms;
   }
-  profiler().level = -1;
+  prof_level() = -1;
   const double t_end = now_s();
   for (auto& J : jobs) {
     hif_stats& st = J.F->stats;

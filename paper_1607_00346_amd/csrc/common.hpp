@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <atomic>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -41,8 +42,8 @@ void set_last_error(const std::string& msg);
 
 // Bytes of device memory held by the library (per process) and their peak.
 struct MemStats {
-  int64_t live = 0;
-  int64_t peak = 0;
+  std::atomic<int64_t> live{0};
+  std::atomic<int64_t> peak{0};
 };
 MemStats& mem_stats();
 
@@ -57,7 +58,8 @@ MemStats& mem_stats();
 // is active on this thread is handed out again, without any synchronization,
 // to an allocation made under a scope for the same s (later work on s runs
 // after the work that used the block).  Blocks released outside any scope, or
-// wanted by another stream, are reused only after a device synchronization.
+// wanted by another stream, are reused only after a device synchronization,
+// and only when a fresh allocation fails.
 constexpr int64_t kPoolCap = int64_t(48) << 30;
 void* pool_alloc(size_t bytes);
 void pool_free(void* p, size_t bytes);
@@ -131,8 +133,10 @@ class DevBuf {
     p_ = static_cast<T*>(pool_alloc(count * sizeof(T)));
     n_ = count;
     auto& ms = mem_stats();
-    ms.live += (int64_t)(count * sizeof(T));
-    if (ms.live > ms.peak) ms.peak = ms.live;
+    const int64_t now = ms.live.fetch_add((int64_t)(count * sizeof(T))) + (int64_t)(count * sizeof(T));
+    int64_t pk = ms.peak.load();
+    while (now > pk && !ms.peak.compare_exchange_weak(pk, now)) {
+    }
   }
   void release() {
     if (p_) {

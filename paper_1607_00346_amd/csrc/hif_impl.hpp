@@ -179,5 +179,10 @@ void pcg_solve(const hif_problem_s* A, hif_factor_s* F, const double* f, double*
                int maxit, hif_pcg_info* info, hipStream_t s);
 void pcg_solve_block(const hif_problem_s* A, hif_factor_s* F, const double* f, double* u, int nrhs,
                      double tol, int maxit, hif_pcg_info* info, hipStream_t s);
+// One single-vector PCG per problem, run concurrently by host worker threads,
+// each on a stream of its own ordered after s; s waits for all of them.
+void pcg_solve_batched(int count, hif_problem_s* const* A, hif_factor_s* const* F,
+                       const double* const* f, double* const* u, double tol, int maxit,
+                       hif_pcg_info* info, hipStream_t s);
 
 }  // namespace hif

@@ -100,8 +100,15 @@ void* pool_alloc(size_t bytes) {
     }
   }
   if (take == P.free_blocks.end() && lo != hi) {
-    // only blocks that other streams (or unknown work) may still use: wait for
-    // the device, after which every cached block is free for anyone
+    // only blocks that other streams (or unknown work) may still use: allocate
+    // afresh if the device has room (a wait for the device would stall every
+    // stream), else wait for it, after which every cached block is free
+    void* p = nullptr;
+    if (hipMalloc(&p, r) == hipSuccess) {
+      P.live[p] = r;
+      return p;
+    }
+    (void)hipGetLastError();
     HIF_HIP(hipDeviceSynchronize());
     for (auto& kv : P.free_blocks) kv.second.tag = Tag::kClean;
     take = lo;

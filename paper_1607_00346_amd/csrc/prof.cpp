@@ -11,6 +11,11 @@ Profiler& profiler() {
   return p;
 }
 
+int& prof_level() {
+  thread_local int level = -1;
+  return level;
+}
+
 int Profiler::class_id(const char* name) {
   for (size_t i = 0; i < names.size(); ++i)
     if (names[i] == name) return (int)i;
@@ -32,9 +37,9 @@ hipEvent_t Profiler::event() {
 ProfScope::ProfScope(const char* name, hipStream_t s, double flops, double bytes) {
   Profiler& p = profiler();
   if (!p.on) return;
-  if (p.level >= 0) {
+  if (prof_level() >= 0) {
     char buf[64];
-    snprintf(buf, sizeof(buf), "%s@%d", name, p.level);
+    snprintf(buf, sizeof(buf), "%s@%d", name, prof_level());
     rec_.cls = p.class_id(buf);
   } else {
     rec_.cls = p.class_id(name);

@@ -19,7 +19,6 @@ class Profiler {
     double flops, bytes;
   };
   bool on = false;
-  int level = -1;  // appended to class names as "@level" when >= 0
   std::vector<std::string> names;
   std::vector<Rec> recs;
 
@@ -32,6 +31,10 @@ class Profiler {
 };
 
 Profiler& profiler();
+
+// The factorization level of the calling thread's launches, appended to class
+// names as "@level" when >= 0.
+int& prof_level();
 
 // RAII: records a start event now and an end event when it goes out of scope.
 class ProfScope {

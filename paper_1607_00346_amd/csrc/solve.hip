@@ -2,6 +2,10 @@
 // application of F^{-1} by level-wise sweeps (Section 2.4, product form of
 // F^{-1}), and the FP64 preconditioned CG driver.
 #include <cmath>
+#include <thread>
+#include <mutex>
+#include <exception>
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 
@@ -818,7 +822,7 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   // W^l^T for l = 0..L (level L: L_Sigma^{-1})
   for (int l = 0; l < nlev; ++l) {
     Level<T>& lv = levels[l];
-    profiler().level = l;
+    prof_level() = l;
     const int nc = lv.plan->ncell;
     if (nc > 0 && fused_level(lv)) {
       ProfScope ps("apply_up_fused", s, 0.0, lv.bytes_L + lv.bytes_S);
@@ -880,7 +884,7 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   // W^l for l = L..0
   for (int l = nlev - 1; l >= 0; --l) {
     Level<T>& lv = levels[l];
-    profiler().level = l;
+    prof_level() = l;
     const int ns = (int)lv.hsk.size();
     if (!lv.plan->root && ns > 0 && fused_skel(lv)) {
       ProfScope ps("apply_skel_fused", s, 0.0, lv.bytes_skel);
@@ -928,7 +932,7 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
     }
     HIF_LAUNCH_CHECK();
   }
-  profiler().level = -1;
+  prof_level() = -1;
 }
 
 // The sweeps of apply() on a block of nb vectors: every matrix-vector product
@@ -1047,7 +1051,7 @@ void FactorImpl<T>::apply_block(const double* f, double* u, int nrhs, hipStream_
     // nc columns are gathered from and scattered to u
     for (int l = 0; l < nlev; ++l) {
       Level<T>& lv = levels[l];
-      profiler().level = l;
+      prof_level() = l;
       const int ncell = lv.plan->ncell;
       if (ncell > 0) {
         dim3 gI((unsigned)ceil_div(std::max(1, lv.maxI), NT), (unsigned)ncell, (unsigned)nc);
@@ -1085,7 +1089,7 @@ void FactorImpl<T>::apply_block(const double* f, double* u, int nrhs, hipStream_
     }
     for (int l = nlev - 1; l >= 0; --l) {
       Level<T>& lv = levels[l];
-      profiler().level = l;
+      prof_level() = l;
       const int ns = (int)lv.hsk.size();
       if (!lv.plan->root && ns > 0) {
         dim3 gM((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)ns, (unsigned)nc);
@@ -1115,7 +1119,7 @@ void FactorImpl<T>::apply_block(const double* f, double* u, int nrhs, hipStream_
       HIF_LAUNCH_CHECK();
     }
   }
-  profiler().level = -1;
+  prof_level() = -1;
 }
 
 template void FactorImpl<double>::prepare(hipStream_t);
@@ -1190,7 +1194,7 @@ struct ApplyGraph {
     if (!cs) HIF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     Profiler& P = profiler();
     const bool was = P.on;
-    P.on = false;  // no event records inside the graph
+    if (was) P.on = false;  // no event records inside the graph
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       try {
@@ -1199,13 +1203,13 @@ struct ApplyGraph {
         hipGraph_t t = nullptr;
         (void)hipStreamEndCapture(cs, &t);
         if (t) (void)hipGraphDestroy(t);
-        P.on = was;
+        if (was) P.on = true;
         throw;
       }
       e = hipStreamEndCapture(cs, &g);
       if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     }
-    P.on = was;
+    if (was) P.on = true;
     if (e != hipSuccess) {
       (void)hipGetLastError();
       if (x) (void)hipGraphExecDestroy(x);
@@ -1418,6 +1422,63 @@ void pcg_solve_block(const hif_problem_s* A, hif_factor_s* F, const double* f, d
     info[j].relres = std::sqrt(h[8 * j + 6]) / fn[j];
     info[j].converged = info[j].relres <= tol;
   }
+}
+
+void pcg_solve_batched(int count, hif_problem_s* const* A, hif_factor_s* const* F,
+                       const double* const* f, double* const* u, double tol, int maxit,
+                       hif_pcg_info* info, hipStream_t s) {
+  // Each solve is latency-bound on small problems (a host round trip per
+  // iteration); a few solves in flight on separate streams keep the GPU busy.
+  constexpr int kWorkers = 4;
+  // profiling records are not thread safe: a profiled run solves in turn
+  const int workers = profiler().on ? 1 : std::min(count, kWorkers);
+  if (workers <= 1) {
+    for (int i = 0; i < count; ++i) pcg_solve(A[i], F[i], f[i], u[i], tol, maxit, &info[i], s);
+    return;
+  }
+  struct Streams {
+    std::vector<hipStream_t> st;
+    std::vector<hipEvent_t> ev;
+    ~Streams() {
+      for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+      for (hipStream_t q : st)
+        if (q) (void)hipStreamDestroy(q);
+    }
+  } R;
+  R.st.assign(workers, nullptr);
+  R.ev.assign(workers + 1, nullptr);
+  for (auto& e : R.ev) HIF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  HIF_HIP(hipEventRecord(R.ev[workers], s));  // the inputs are ready on s
+  for (int w = 0; w < workers; ++w) {
+    HIF_HIP(hipStreamCreateWithFlags(&R.st[w], hipStreamNonBlocking));
+    HIF_HIP(hipStreamWaitEvent(R.st[w], R.ev[workers], 0));
+  }
+  std::atomic<int> next{0};
+  std::mutex emu;
+  std::exception_ptr first;
+  auto work = [&](int w) {
+    try {
+      StreamScope scope(R.st[w]);
+      for (;;) {
+        const int i = next.fetch_add(1);
+        if (i >= count) break;
+        pcg_solve(A[i], F[i], f[i], u[i], tol, maxit, &info[i], R.st[w]);
+      }
+    } catch (...) {
+      std::lock_guard<std::mutex> lock(emu);
+      if (!first) first = std::current_exception();
+      next.store(count);
+    }
+  };
+  std::vector<std::thread> th;
+  for (int w = 0; w < workers; ++w) th.emplace_back(work, w);
+  for (auto& t : th) t.join();
+  for (int w = 0; w < workers; ++w) {  // s waits for every worker stream
+    HIF_HIP(hipEventRecord(R.ev[w], R.st[w]));
+    HIF_HIP(hipStreamWaitEvent(s, R.ev[w], 0));
+  }
+  if (first) std::rethrow_exception(first);
 }
 
 }  // namespace hif

@@ -20,6 +20,7 @@ HIF_MAX_LEVELS = 16
 
 EXPORTED = [
     "hif_problem_create", "hif_build", "hif_build_batched", "hif_apply", "hif_matvec", "hif_pcg",
+    "hif_pcg_batched",
     "hif_factor_stats", "hif_factor_ranks", "hif_factor_active", "hif_factor_destroy",
     "hif_problem_destroy", "hif_status_string", "hif_last_error", "hif_profile_begin",
     "hif_profile_end", "hif_tune_begin", "hif_tune_end",
@@ -94,6 +95,9 @@ def lib():
         L.hif_apply.argtypes = [vp, vp, vp, i32, vp]
         L.hif_matvec.argtypes = [vp, vp, vp, i32, vp]
         L.hif_pcg.argtypes = [vp, vp, vp, vp, i32, f64, i32, ctypes.POINTER(hif_pcg_info), vp]
+        L.hif_pcg_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(vp), ctypes.POINTER(vp), f64, i32,
+                                      ctypes.POINTER(hif_pcg_info), vp]
         L.hif_factor_stats.argtypes = [vp, ctypes.POINTER(hif_stats)]
         L.hif_factor_ranks.argtypes = [vp, i32, vp, vp, i32, ctypes.POINTER(i32)]
         L.hif_factor_active.argtypes = [vp, i32, vp]
@@ -107,7 +111,7 @@ def lib():
         L.hif_status_string.restype = ctypes.c_char_p
         L.hif_last_error.restype = ctypes.c_char_p
         for name in ("hif_problem_create", "hif_build", "hif_build_batched", "hif_apply",
-                     "hif_matvec", "hif_pcg", "hif_factor_stats", "hif_factor_ranks", "hif_factor_active",
+                     "hif_matvec", "hif_pcg", "hif_pcg_batched", "hif_factor_stats", "hif_factor_ranks", "hif_factor_active",
                      "hif_profile_begin", "hif_profile_end", "hif_tune_begin", "hif_tune_end"):
             getattr(L, name).restype = ctypes.c_int
         L.hif_factor_destroy.restype = None
@@ -179,6 +183,22 @@ def hif_pcg(A, F, f, u, nrhs: int = 1, tol: float = 1e-10, maxit: int = 500, str
     st = _check(lib().hif_pcg(A, F, _dptr(f), _dptr(u), int(nrhs), float(tol), int(maxit),
                               info, _stream(stream)), "hif_pcg", allow=(HIF_ENOCONV,))
     return st, [info[i] for i in range(nrhs)]
+
+
+def hif_pcg_batched(problems, factors, fs, us, tol: float = 1e-10, maxit: int = 500, stream=None):
+    """One single-vector PCG per problem, run concurrently; returns (status, [hif_pcg_info])."""
+    count = len(problems)
+    assert len(factors) == count and len(fs) == count and len(us) == count and count >= 1
+    def arr(hs):
+        return (ctypes.c_void_p * count)(*[h.value if isinstance(h, ctypes.c_void_p) else h
+                                           for h in hs])
+    F = (ctypes.c_void_p * count)(*[_dptr(t).value for t in fs])
+    U = (ctypes.c_void_p * count)(*[_dptr(t).value for t in us])
+    info = (hif_pcg_info * count)()
+    st = _check(lib().hif_pcg_batched(count, arr(problems), arr(factors), F, U, float(tol),
+                                      int(maxit), info, _stream(stream)),
+                "hif_pcg_batched", allow=(HIF_ENOCONV,))
+    return st, [info[i] for i in range(count)]
 
 
 def hif_factor_stats(F) -> hif_stats:

@@ -214,3 +214,27 @@ def test_full_batched_workload(gpu_lib):
         H.hif_factor_destroy(Fi)
     for a in A:
         H.hif_problem_destroy(a)
+
+
+def test_batched_pcg_equals_single_solves(gpu_lib):
+    """hif_pcg_batched runs one PCG per problem on concurrent streams: every
+    solve does the same kernels in the same order as hif_pcg, so the solutions,
+    iteration counts and residuals are identical bit for bit."""
+    import torch
+    H = gpu_lib
+    grid = [(16, 4), (24, 6), (32, 8), (12, 3), (16, 8), (24, 3), (8, 2)]
+    specs = [(n, leaf, log_uniform_field(n, -1, 1, 620 + k), const_field(n, 0.0))
+             for k, (n, leaf) in enumerate(grid)]
+    bt = Batch(H, specs, 1e-4, 1)
+    fs = [_t(normal_rhs(n, 640 + i)) for i, (n, _, _, _) in enumerate(specs)]
+    us = [torch.empty_like(f) for f in fs]
+    st, info = H.hif_pcg_batched(bt.A, bt.F, fs, us, tol=1e-10, maxit=100)
+    torch.cuda.synchronize()
+    assert st == 0
+    for i in range(len(specs)):
+        u1 = torch.empty_like(fs[i])
+        st1, info1 = H.hif_pcg(bt.A[i], bt.F[i], fs[i], u1, tol=1e-10, maxit=100)
+        torch.cuda.synchronize()
+        assert st1 == 0 and info1[0].iters == info[i].iters and info1[0].relres == info[i].relres
+        assert torch.equal(u1, us[i])
+    bt.close()
