@@ -63,3 +63,20 @@ def test_null_arguments_rejected(L):
     assert L.hif_pcg(None, None, None, None, 1, 1e-10, 10, None, None) == H.HIF_EINVAL
     cnt = ctypes.c_int32()
     assert L.hif_factor_ranks(None, 0, None, None, 0, ctypes.byref(cnt)) == H.HIF_EINVAL
+
+
+def test_batched_calls_reject_bad_arguments(L):
+    """The batched entry points check counts and arrays before any device work."""
+    out = (ctypes.c_void_p * 2)()
+    opts = (H.hif_options * 2)(H.make_options(16, 4, 1e-6), H.make_options(16, 4, 1e-6))
+    probs = (ctypes.c_void_p * 2)(None, None)
+    assert L.hif_build_batched(0, probs, opts, None, out) == H.HIF_EINVAL
+    assert L.hif_build_batched(2, None, opts, None, out) == H.HIF_EINVAL
+    assert L.hif_build_batched(2, probs, opts, None, out) == H.HIF_EINVAL  # NULL handles
+    assert out[0] is None and out[1] is None
+    vecs = (ctypes.c_void_p * 2)(None, None)
+    info = (H.hif_pcg_info * 2)()
+    assert L.hif_pcg_batched(0, probs, probs, vecs, vecs, 1e-10, 10, info, None) == H.HIF_EINVAL
+    assert L.hif_pcg_batched(2, probs, probs, vecs, vecs, 1e-10, 10, info, None) == H.HIF_EINVAL
+    assert L.hif_pcg_batched(2, probs, probs, vecs, vecs, -1.0, 10, info, None) == H.HIF_EINVAL
+    assert len(H.hif_last_error()) > 0

@@ -237,4 +237,12 @@ def test_batched_pcg_equals_single_solves(gpu_lib):
         torch.cuda.synchronize()
         assert st1 == 0 and info1[0].iters == info[i].iters and info1[0].relres == info[i].relres
         assert torch.equal(u1, us[i])
+    # a factor listed twice would share its scratch between two solves in flight
+    with pytest.raises(H.HifError) as ei:
+        H.hif_pcg_batched([bt.A[0], bt.A[0]], [bt.F[0], bt.F[0]], [fs[0], fs[0]],
+                          [us[0], torch.empty_like(us[0])])
+    assert ei.value.status == H.HIF_EINVAL
+    # maxit = 1: every solve stops early and the call reports it
+    st, info = H.hif_pcg_batched(bt.A, bt.F, fs, us, tol=1e-14, maxit=1)
+    assert st == H.HIF_ENOCONV and all(x.iters == 1 and not x.converged for x in info)
     bt.close()
