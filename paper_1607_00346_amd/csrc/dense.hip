@@ -1009,6 +1009,20 @@ void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
     }
     return;
   }
+  int nsmall = 0;
+  for (auto& f : h_fronts) nsmall += f.nI <= kSmallFront;
+  if (nsmall > 0 && nsmall < batch) {
+    // two size buckets (fronts of several problems or levels): one workgroup
+    // per small front, blocked steps only for the large ones
+    std::vector<FrontDesc> small, large;
+    for (auto& f : h_fronts) (f.nI <= kSmallFront ? small : large).push_back(f);
+    DevBuf<FrontDesc> ds, dl;
+    ds.upload(small, s);
+    dl.upload(large, s);
+    front_factor<T>(ds.get(), small, err, s, upper_zero);
+    front_factor<T>(dl.get(), large, err, s, upper_zero);
+    return;
+  }
   int maxI = 0;
   for (auto& f : h_fronts) maxI = std::max(maxI, f.nI);
   if (maxI <= kSmallFront) {
