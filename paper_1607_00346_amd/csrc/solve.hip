@@ -1428,8 +1428,9 @@ void pcg_solve_batched(int count, hif_problem_s* const* A, hif_factor_s* const* 
                        const double* const* f, double* const* u, double tol, int maxit,
                        hif_pcg_info* info, hipStream_t s) {
   // Each solve is latency-bound on small problems (a host round trip per
-  // iteration); a few solves in flight on separate streams keep the GPU busy.
-  constexpr int kWorkers = 4;
+  // iteration); a few solves in flight on separate streams keep the GPU busy
+  // (8 measured best for the 48-problem workload; 4 and 16 were slower).
+  constexpr int kWorkers = 8;
   // profiling records are not thread safe: a profiled run solves in turn
   const int workers = profiler().on ? 1 : std::min(count, kWorkers);
   if (workers <= 1) {
