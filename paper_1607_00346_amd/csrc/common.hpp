@@ -57,9 +57,9 @@ MemStats& mem_stats();
 // Reuse is stream ordered: a block released while a StreamScope for stream s
 // is active on this thread is handed out again, without any synchronization,
 // to an allocation made under a scope for the same s (later work on s runs
-// after the work that used the block).  Blocks released outside any scope, or
-// wanted by another stream, are reused only after a device synchronization,
-// and only when a fresh allocation fails.
+// after the work that used the block).  Blocks released outside any scope are
+// reused after a device synchronization; blocks wanted by another stream only
+// when a fresh allocation fails (a device-wide wait would stall that stream).
 constexpr int64_t kPoolCap = int64_t(48) << 30;
 void* pool_alloc(size_t bytes);
 void pool_free(void* p, size_t bytes);

@@ -100,15 +100,21 @@ void* pool_alloc(size_t bytes) {
     }
   }
   if (take == P.free_blocks.end() && lo != hi) {
-    // only blocks that other streams (or unknown work) may still use: allocate
-    // afresh if the device has room (a wait for the device would stall every
-    // stream), else wait for it, after which every cached block is free
-    void* p = nullptr;
-    if (hipMalloc(&p, r) == hipSuccess) {
-      P.live[p] = r;
-      return p;
+    // Only blocks that other streams or unknown work (a release outside any
+    // call) may still use.  Blocks of other streams: allocate afresh if the
+    // device has room, since a wait for the device would stall the other
+    // streams.  Otherwise (or without room) wait for the device, after which
+    // every cached block is free for anyone.
+    bool unknown = false;
+    for (auto it = lo; it != hi; ++it) unknown = unknown || it->second.tag == Tag::kUnknown;
+    if (!unknown) {
+      void* p = nullptr;
+      if (hipMalloc(&p, r) == hipSuccess) {
+        P.live[p] = r;
+        return p;
+      }
+      (void)hipGetLastError();
     }
-    (void)hipGetLastError();
     HIF_HIP(hipDeviceSynchronize());
     for (auto& kv : P.free_blocks) kv.second.tag = Tag::kClean;
     take = lo;
