@@ -372,6 +372,9 @@ def main():
     p.add_argument("--maxit", type=int, default=500)
     p.add_argument("--skip-fp64", action="store_true")
     p.add_argument("--skip-cpu", action="store_true")
+    p.add_argument("--skip-extra", action="store_true",
+                   help="leave out the batched and 256^3 workloads reported beside the headline "
+                        "(also left out by --skip-cpu or --skip-fp64)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 256 MiB device copy three times (scales the HBM "
                         "byte counters of a profiler run)")
@@ -455,6 +458,23 @@ def main():
     line["extra"]["stats_mixed"] = {k: mixed["stats"][k] for k in (
         "cells", "faces", "eliminated", "face_dofs", "redundant", "max_front", "level_seconds",
         "factor_flops")}
+    if not (args.skip_extra or args.skip_cpu or args.skip_fp64):
+        # full runs only: the batched and large workloads, one warm-up and one
+        # timed step each, reported beside the headline (a failure there does
+        # not void it)
+        sub = argparse.Namespace(**vars(args))
+        sub.steps, sub.warmup = 1, 1
+        from paper_1607_00346_amd import hif as H
+        for key, fn in (("batched", run_batched), ("c256", run_large)):
+            try:
+                # blocks cached for the previous workload's sizes would not fit this one
+                H.hif_release_cached_memory()
+                r = fn(sub)
+                line["extra"]["workload_" + key] = {
+                    "metric": r["metric"], "value": r["value"], "unit": r["unit"],
+                    "ms_per_step": r["ms_per_step"], "config": r["config"], "extra": r["extra"]}
+            except Exception as e:  # noqa: BLE001
+                line["extra"]["workload_" + key] = {"error": repr(e)}
     if not args.skip_cpu:
         line["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(line))

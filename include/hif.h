@@ -182,6 +182,12 @@ typedef struct {
 hif_status hif_profile_begin(void);
 hif_status hif_profile_end(hif_kernel_stat* out, int32_t cap, int32_t* count);
 
+/* Device memory the library released is kept in a process-wide cache for
+ * reuse by later calls (up to 48 GB).  This returns all of it to the device
+ * after a device synchronization, e.g. between workloads of very different
+ * sizes.  Memory held by live problems and factors is not touched. */
+hif_status hif_release_cached_memory(void);
+
 /* Tile autotuning (tune_tiles.py drives it; not needed to factor or solve).
  * The batched GEMMs of the library run square tiles of 32, 64 or (FP32
  * accumulation only) 128, chosen per key (operand bytes, accumulator bytes,

@@ -147,6 +147,10 @@ hif_status hif_build_batched(int32_t count, const hif_problem_t* A, const hif_op
   });
 }
 
+hif_status hif_release_cached_memory(void) {
+  return guarded([&] { hif::pool_release_cached(); });
+}
+
 hif_status hif_tune_begin(void) {
   return guarded([&] { hif::tune_begin(); });
 }

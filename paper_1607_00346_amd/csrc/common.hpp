@@ -63,6 +63,8 @@ MemStats& mem_stats();
 constexpr int64_t kPoolCap = int64_t(48) << 30;
 void* pool_alloc(size_t bytes);
 void pool_free(void* p, size_t bytes);
+// Returns every cached block to the device (after a device synchronization).
+void pool_release_cached();
 size_t pool_round(size_t bytes);
 
 // The stream that all device work of the current library call is ordered on.

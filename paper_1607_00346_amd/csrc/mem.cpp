@@ -141,6 +141,12 @@ void* pool_alloc(size_t bytes) {
   return p;
 }
 
+void pool_release_cached() {
+  Pool& P = pool();
+  std::lock_guard<std::mutex> lock(P.mu);
+  trim_locked(P, P.cached);
+}
+
 void pool_free(void* p, size_t bytes) {
   Pool& P = pool();
   std::lock_guard<std::mutex> lock(P.mu);

@@ -23,7 +23,7 @@ EXPORTED = [
     "hif_pcg_batched",
     "hif_factor_stats", "hif_factor_ranks", "hif_factor_active", "hif_factor_destroy",
     "hif_problem_destroy", "hif_status_string", "hif_last_error", "hif_profile_begin",
-    "hif_profile_end", "hif_tune_begin", "hif_tune_end",
+    "hif_profile_end", "hif_tune_begin", "hif_tune_end", "hif_release_cached_memory",
 ]
 
 
@@ -105,6 +105,8 @@ def lib():
         L.hif_problem_destroy.argtypes = [vp]
         L.hif_profile_begin.argtypes = []
         L.hif_profile_end.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.hif_release_cached_memory.argtypes = []
+        L.hif_release_cached_memory.restype = ctypes.c_int
         L.hif_tune_begin.argtypes = []
         L.hif_tune_end.argtypes = [ctypes.c_char_p, ctypes.POINTER(i32)]
         L.hif_status_string.argtypes = [i32]
@@ -245,6 +247,11 @@ def hif_profile_end():
         out[k.name.decode()] = {"launches": k.launches, "seconds": k.seconds, "flops": k.flops,
                                 "bytes": k.bytes}
     return out
+
+
+def hif_release_cached_memory():
+    """Return the library's cached device memory to the device."""
+    _check(lib().hif_release_cached_memory(), "hif_release_cached_memory")
 
 
 def hif_tune_begin():
