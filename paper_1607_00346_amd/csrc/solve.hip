@@ -117,15 +117,17 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // y[roff + i] (+)= alpha sum_t A(i, t) x[coff + t] (tri: t <= i only): 64
-// rows per workgroup, the columns split over the four waves in groups of 8
-// (independent loads in flight), partial sums reduced through LDS.  Groups
-// that straddle the diagonal load all 8 columns (the stored upper triangle
-// is in bounds) and drop the entries above it by selects.
-template <typename T>
-__global__ __launch_bounds__(NT) void k_gemv_n(const GemvDesc* __restrict__ dd,
-                                               const double* __restrict__ x, double* y,
-                                               double alpha, int accumulate) {
-  __shared__ double part[NT / 64][64];
+// rows per workgroup, the columns split over the NW waves in groups of 8
+// (independent loads in flight), partial sums reduced through LDS in wave
+// order.  Groups that straddle the diagonal load all 8 columns (the stored
+// upper triangle is in bounds) and drop the entries above it by selects.
+// Launches of few row blocks take NW = 16, so that each workgroup keeps
+// enough loads in flight to stream its long rows.
+template <typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void k_gemv_n(const GemvDesc* __restrict__ dd,
+                                                    const double* __restrict__ x, double* y,
+                                                    double alpha, int accumulate) {
+  __shared__ double part[NW][64];
   const GemvDesc d = dd[blockIdx.y];
   const int r0 = blockIdx.x * 64;
   if (r0 >= d.m) return;
@@ -136,7 +138,7 @@ __global__ __launch_bounds__(NT) void k_gemv_n(const GemvDesc* __restrict__ dd,
   const auto A = as_global((const T*)d.A + (row_ok ? i : 0));
   const auto xv = as_global(x + d.coff);
   double s0 = 0.0, s1 = 0.0;
-  for (int t0 = wave * 8; t0 < tend; t0 += 32) {
+  for (int t0 = wave * 8; t0 < tend; t0 += 8 * NW) {
     if (t0 + 8 <= tend) {
       double a[8];
 #pragma unroll
@@ -159,7 +161,10 @@ __global__ __launch_bounds__(NT) void k_gemv_n(const GemvDesc* __restrict__ dd,
   part[wave][lane] = row_ok ? s0 + s1 : 0.0;
   __syncthreads();
   if (wave == 0 && row_ok) {
-    const double v = alpha * (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
+    double sum = part[0][lane];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) sum += part[w][lane];
+    const double v = alpha * sum;
     const auto yo = as_global(y + d.roff + i);
     *yo = accumulate ? *yo + v : v;
   }
@@ -244,17 +249,20 @@ __global__ __launch_bounds__(NT) void k_gemv_t(const GemvDesc* __restrict__ dd,
 
 // y[roff + i] (+)= alpha sum_t A(i, t) x[coff + t] (tri: t <= i only) for
 // matrices whose columns start 16-byte aligned: lane l of group g reads VN
-// consecutive rows as one 16-byte vector, the 16 groups take every 16th
-// column, partial sums are reduced through LDS.  Rows past m are read only
-// by the lanes that hold both valid and invalid rows, element by element.
-template <typename T>
-__global__ __launch_bounds__(NT) void k_gemv_nv(const GemvDesc* __restrict__ dd,
-                                                const double* __restrict__ x, double* y,
-                                                double alpha, int accumulate) {
+// consecutive rows as one 16-byte vector, the NG groups take every NG-th
+// column, partial sums are reduced through LDS in group order.  Rows past m
+// are read only by the lanes that hold both valid and invalid rows, element
+// by element.  Launches of few row blocks (the top levels' few large
+// triangles, where one workgroup streams a whole row block of up to several
+// thousand columns) take NG = 64.
+template <typename T, int NG>
+__global__ __launch_bounds__(16 * NG) void k_gemv_nv(const GemvDesc* __restrict__ dd,
+                                                     const double* __restrict__ x, double* y,
+                                                     double alpha, int accumulate) {
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::N;
   constexpr int R = 16 * VN;  // rows per workgroup
-  __shared__ double part[16][R + 1];
+  __shared__ double part[NG][R + 1];
   const GemvDesc d = dd[blockIdx.y];
   const int r0 = blockIdx.x * R;
   if (r0 >= d.m) return;
@@ -267,7 +275,7 @@ __global__ __launch_bounds__(NT) void k_gemv_nv(const GemvDesc* __restrict__ dd,
 #pragma unroll
   for (int e = 0; e < VN; ++e) acc[e] = 0.0;
 #pragma unroll 4
-  for (int t = g; t < tend; t += 16) {
+  for (int t = g; t < tend; t += NG) {
     const double xt = xv[t];
     const T* col = (const T*)d.A + (int64_t)d.lda * t;
     T a[VN];
@@ -290,7 +298,7 @@ __global__ __launch_bounds__(NT) void k_gemv_nv(const GemvDesc* __restrict__ dd,
     if (row < d.m) {
       double sum = 0.0;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) sum += part[q][threadIdx.x];
+      for (int q = 0; q < NG; ++q) sum += part[q][threadIdx.x];
       const double v = alpha * sum;
       const auto yo = as_global(y + d.roff + row);
       *yo = accumulate ? *yo + v : v;
@@ -713,15 +721,24 @@ template <typename T>
 void gemv_launch(bool trans, const GemvDesc* d, int batch, int maxm, int maxn, const double* x,
                  double* y, double alpha, int acc, hipStream_t s, bool aligned = false) {
   if (batch <= 0 || maxm <= 0 || maxn <= 0) return;
+  // few row blocks over long rows (the last row block of a large triangle
+  // streams the whole matrix width): wide workgroups
+  auto wide = [&](int64_t blocks) { return blocks < 2048 && maxn >= 256; };
   if (!trans && aligned) {
     dim3 g((unsigned)ceil_div(maxm, 16 * Vec16<T>::N), (unsigned)batch);
-    hipLaunchKernelGGL((k_gemv_nv<T>), g, dim3(NT), 0, s, d, x, y, alpha, acc);
+    if (wide((int64_t)g.x * batch))
+      hipLaunchKernelGGL((k_gemv_nv<T, 64>), g, dim3(1024), 0, s, d, x, y, alpha, acc);
+    else
+      hipLaunchKernelGGL((k_gemv_nv<T, 16>), g, dim3(NT), 0, s, d, x, y, alpha, acc);
   } else if (trans) {
     dim3 g((unsigned)ceil_div(maxn, kGemvTCols), (unsigned)batch);
     hipLaunchKernelGGL((k_gemv_t<T>), g, dim3(NT), 0, s, d, x, y, alpha, acc);
   } else {
     dim3 g((unsigned)ceil_div(maxm, 64), (unsigned)batch);
-    hipLaunchKernelGGL((k_gemv_n<T>), g, dim3(NT), 0, s, d, x, y, alpha, acc);
+    if (wide((int64_t)g.x * batch))
+      hipLaunchKernelGGL((k_gemv_n<T, 16>), g, dim3(1024), 0, s, d, x, y, alpha, acc);
+    else
+      hipLaunchKernelGGL((k_gemv_n<T, 4>), g, dim3(NT), 0, s, d, x, y, alpha, acc);
   }
   HIF_LAUNCH_CHECK();
 }
