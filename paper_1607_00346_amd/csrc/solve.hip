@@ -546,6 +546,105 @@ __global__ __launch_bounds__(64) void k_skel_fused(double* u, const int* __restr
   for (int b = lane; b < r; b += 64) u[pts[k + b]] = yc[b];
 }
 
+// The same three products for faces of more than 64 points, one workgroup
+// per face.  Products with a transposed factor (a dot product per column)
+// give each column 16 lanes reading along it; the others give each row a
+// lane and deal the columns to the four waves in turn, partial sums through
+// LDS in wave order.  Every word of T, L_F̌^{-1} and Y is then read in
+// contiguous runs, where the one-wave kernel walks them with a stride of a
+// column per lane.  Dynamic LDS: maxF + maxr + NT doubles.
+
+// out[c] (-)= sum_{i in [lo, n)} A(i, c) x[i] for c < ncols, lo = c if tri
+// else 0; ends with a barrier.
+template <typename T>
+__device__ __forceinline__ void wg_col_dots(const T* __restrict__ A, int ld, int n, int ncols,
+                                            bool tri, const double* x, double* out, bool sub) {
+  const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
+  for (int c0 = 0; c0 < ncols; c0 += NT / 16) {
+    const int c = c0 + g;
+    double s0 = 0.0, s1 = 0.0;
+    if (c < ncols) {
+      const auto col = as_global(A + (int64_t)ld * c);
+      int i = (tri ? c : 0) + l;
+      for (; i + 16 < n; i += 32) {
+        const double a0 = (double)col[i], a1 = (double)col[i + 16];
+        s0 += a0 * x[i];
+        s1 += a1 * x[i + 16];
+      }
+      if (i < n) s0 += (double)col[i] * x[i];
+    }
+    double v = s0 + s1;
+    v += __shfl_xor(v, 8, 16);
+    v += __shfl_xor(v, 4, 16);
+    v += __shfl_xor(v, 2, 16);
+    v += __shfl_xor(v, 1, 16);
+    if (c < ncols && l == 0) out[c] = sub ? out[c] - v : v;
+  }
+  __syncthreads();
+}
+
+// out[r] (-)= sum_{c < cend} A(r, c) x[c] for r < nrows, cend = r + 1 if tri
+// (the stored upper triangle is in bounds and dropped by selects) else
+// ncols; part holds NT doubles; ends with a barrier.
+template <typename T>
+__device__ __forceinline__ void wg_row_dots(const T* __restrict__ A, int ld, int nrows, int ncols,
+                                            bool tri, const double* x, double* out, bool sub,
+                                            double* part) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int r0 = 0; r0 < nrows; r0 += 64) {
+    const int r = r0 + lane;
+    const bool ok = r < nrows;
+    const int cend = tri ? min(ncols, r0 + 64) : ncols;
+    const auto a = as_global(A + (ok ? r : 0));
+    double s0 = 0.0, s1 = 0.0;
+    int c = w;
+    for (; c + 4 < cend; c += 8) {
+      const double a0 = (double)a[(int64_t)ld * c], a1 = (double)a[(int64_t)ld * (c + 4)];
+      s0 += (!tri || c <= r) ? a0 * x[c] : 0.0;
+      s1 += (!tri || c + 4 <= r) ? a1 * x[c + 4] : 0.0;
+    }
+    if (c < cend && (!tri || c <= r)) s0 += (double)a[(int64_t)ld * c] * x[c];
+    part[threadIdx.x] = s0 + s1;
+    __syncthreads();
+    if (w == 0 && ok) {
+      const double v = part[lane] + part[64 + lane] + part[128 + lane] + part[192 + lane];
+      out[r] = sub ? out[r] - v : v;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_skel_fused_wg(double* u, const int* __restrict__ skpts,
+                                                      const SkelDesc* __restrict__ sk,
+                                                      const T* __restrict__ skel, int maxF,
+                                                      int maxr, int down) {
+  extern __shared__ double lds[];
+  const SkelDesc d = sk[blockIdx.x];
+  const int k = d.k, r = d.r;
+  double* xh = lds;
+  double* xc = lds + k;
+  double* yc = lds + maxF;
+  double* part = lds + maxF + maxr;
+  const int* pts = skpts + d.pts_off;
+  const T* Tm = skel + d.offT;
+  const T* Lc = skel + d.offL;
+  const T* Y = skel + d.offY;
+  for (int i = threadIdx.x; i < k + r; i += NT) lds[i] = u[pts[i]];
+  __syncthreads();
+  if (!down) {
+    wg_col_dots<T>(Tm, k, k, r, false, xh, xc, true);        // x_F̌ -= T^T x_F̂
+    wg_row_dots<T>(Lc, r, r, r, true, xc, yc, false, part);  // y = L_F̌^{-1} x_F̌
+    wg_col_dots<T>(Y, r, r, k, false, yc, xh, true);         // x_F̂ -= Y^T y
+  } else {
+    wg_row_dots<T>(Y, r, r, k, false, xh, xc, true, part);   // x_F̌ -= Y x_F̂
+    wg_col_dots<T>(Lc, r, r, r, true, xc, yc, false);        // y = L_F̌^{-T} x_F̌
+    wg_row_dots<T>(Tm, k, k, r, false, yc, xh, true, part);  // x_F̂ -= T y
+  }
+  for (int i = threadIdx.x; i < k; i += NT) u[pts[i]] = xh[i];
+  for (int b = threadIdx.x; b < r; b += NT) u[pts[k + b]] = yc[b];
+}
+
 // ---- block apply (several right-hand sides) --------------------------------
 // Vector blocks: column z of u at u + z * N; column z of a scratch segment of
 // length ld at base + z * ld (scratch in the factor's precision T).
@@ -811,14 +910,34 @@ bool fused_level(const Level<T>& lv) {
          lv.maxS <= kFuseMaxS && lv.gv_L_vec;
 }
 
-// Levels of many small faces take the one-wave skeleton step (same switch).
-constexpr int kSkelFuseMinFaces = 1024, kSkelFuseMaxF = 1024;
+// Skeleton step of a level (same switch).  Levels of many faces take a fused
+// kernel: 1 = one wave per face (faces of at most 64 points), 2 = one
+// workgroup per face (up to 1024 points).  0 = gather, three batched
+// matrix-vector launches, scatter: for levels of few faces, whose
+// workgroups would leave most of the chip idle.
+constexpr int kSkelFuseMinFaces = 1024, kSkelWaveMaxF = 64, kSkelFuseMaxF = 1024;
 
 template <typename T>
-bool fused_skel(const Level<T>& lv) {
+int fused_skel(const Level<T>& lv) {
   const char* e = std::getenv("HIF_APPLY_FUSED");
-  const bool off = e && e[0] == '0';
-  return !off && lv.hsk.size() >= (size_t)kSkelFuseMinFaces && lv.maxF <= kSkelFuseMaxF;
+  if ((e && e[0] == '0') || lv.hsk.size() < (size_t)kSkelFuseMinFaces) return 0;
+  if (lv.maxF <= kSkelWaveMaxF) return 1;
+  return lv.maxF <= kSkelFuseMaxF ? 2 : 0;
+}
+
+template <typename T>
+void launch_skel_fused(const Level<T>& lv, int mode, double* u, int down, hipStream_t s) {
+  const unsigned ns = (unsigned)lv.hsk.size();
+  if (mode == 1) {
+    hipLaunchKernelGGL((k_skel_fused<T>), dim3(ns), dim3(64),
+                       sizeof(double) * (size_t)(lv.maxF + lv.maxr), s, u, lv.skpts.get(),
+                       lv.sk.get(), (const T*)lv.skel.get(), lv.maxF, down);
+  } else {
+    hipLaunchKernelGGL((k_skel_fused_wg<T>), dim3(ns), dim3(NT),
+                       sizeof(double) * (size_t)(lv.maxF + lv.maxr + NT), s, u, lv.skpts.get(),
+                       lv.sk.get(), (const T*)lv.skel.get(), lv.maxF, lv.maxr, down);
+  }
+  HIF_LAUNCH_CHECK();
 }
 
 template <typename T>
@@ -877,12 +996,10 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
         HIF_LAUNCH_CHECK();
       }
       const int ns = (int)lv.hsk.size();
-      if (ns > 0 && fused_skel(lv)) {
+      const int fm = ns > 0 ? fused_skel(lv) : 0;
+      if (fm) {
         ProfScope ps("apply_skel_fused", s, 0.0, lv.bytes_skel);
-        hipLaunchKernelGGL((k_skel_fused<T>), dim3((unsigned)ns), dim3(64),
-                           sizeof(double) * (size_t)(lv.maxF + lv.maxr), s, u, lv.skpts.get(),
-                           lv.sk.get(), (const T*)lv.skel.get(), lv.maxF, 0);
-        HIF_LAUNCH_CHECK();
+        launch_skel_fused(lv, fm, u, 0, s);
       } else if (ns > 0) {
         ProfScope ps("apply_skel", s, 0.0, lv.bytes_skel);
         dim3 gM((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)ns);
@@ -903,12 +1020,10 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
     Level<T>& lv = levels[l];
     prof_level() = l;
     const int ns = (int)lv.hsk.size();
-    if (!lv.plan->root && ns > 0 && fused_skel(lv)) {
+    const int fm = !lv.plan->root && ns > 0 ? fused_skel(lv) : 0;
+    if (fm) {
       ProfScope ps("apply_skel_fused", s, 0.0, lv.bytes_skel);
-      hipLaunchKernelGGL((k_skel_fused<T>), dim3((unsigned)ns), dim3(64),
-                         sizeof(double) * (size_t)(lv.maxF + lv.maxr), s, u, lv.skpts.get(),
-                         lv.sk.get(), (const T*)lv.skel.get(), lv.maxF, 1);
-      HIF_LAUNCH_CHECK();
+      launch_skel_fused(lv, fm, u, 1, s);
     } else if (!lv.plan->root && ns > 0) {
       ProfScope ps("apply_skel", s, 0.0, lv.bytes_skel);
       dim3 gM((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)ns);

@@ -337,12 +337,15 @@ def test_fused_sweeps_exact_at_eps0(gpu_lib):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_fused_sweeps_match_general_path(gpu_lib, prec):
-    """64^3 with 4^3 leaves (4096 level-0 fronts of 27-64 interior points):
-    the fused per-front sweeps equal the gather / matrix-vector / scatter path
-    up to the order of the FP64 sums (1e-12 relative)."""
+@pytest.mark.parametrize("n,leaf", [(64, 4), (128, 8)])
+def test_fused_sweeps_match_general_path(gpu_lib, prec, n, leaf):
+    """The fused per-front and per-face sweeps equal the gather / matrix-vector
+    / scatter path up to the order of the FP64 sums (1e-12 relative).  64^3
+    with 4^3 leaves: 4096 level-0 fronts of 27-64 interior points and faces
+    of at most 49 points (one wave per face).  128^3 with 8^3 leaves: the
+    1344 level-1 faces hold up to a few hundred points (one workgroup per
+    face)."""
     import os
-    n, leaf = 64, 4
     a = log_uniform_field(n, -2, 2, 231)
     f = normal_rhs(n, 232)
     g = GpuHif(gpu_lib, n, leaf, 1e-4, a, const_field(n, 0.0), precision=prec)
