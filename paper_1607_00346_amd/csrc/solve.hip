@@ -185,22 +185,23 @@ struct Vec16<double> {
 };
 
 // y[coff + j] (+)= alpha sum_i A(i, j) x[roff + i] (tri: i >= j only): 16
-// lanes per column, 16 columns at a time, 64 columns per workgroup.  Each
+// lanes per column, NG columns at a time, 64 columns per workgroup.  Each
 // column is read as 16-byte vectors (two full cache lines per load across its
 // 16 lanes) after a scalar head up to the first aligned row, then a scalar
-// tail.
+// tail.  Launches of few column blocks over long columns take NG = 64 (all 64
+// columns at once); a column's sum is the same either way.
 constexpr int kGemvTCols = 64;
-template <typename T>
-__global__ __launch_bounds__(NT) void k_gemv_t(const GemvDesc* __restrict__ dd,
-                                               const double* __restrict__ x, double* y,
-                                               double alpha, int accumulate) {
+template <typename T, int NG>
+__global__ __launch_bounds__(16 * NG) void k_gemv_t(const GemvDesc* __restrict__ dd,
+                                                    const double* __restrict__ x, double* y,
+                                                    double alpha, int accumulate) {
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::N;
   const GemvDesc d = dd[blockIdx.y];
   const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
   const auto xv = as_global(x + d.roff);
   const int jend = min(d.n, (int)(blockIdx.x + 1) * kGemvTCols);
-  for (int jb = blockIdx.x * kGemvTCols; jb < jend; jb += NT / 16) {
+  for (int jb = blockIdx.x * kGemvTCols; jb < jend; jb += NG) {
     const int j = jb + g;
     double s0 = 0.0, s1 = 0.0;
     if (j < jend) {
@@ -820,21 +821,24 @@ template <typename T>
 void gemv_launch(bool trans, const GemvDesc* d, int batch, int maxm, int maxn, const double* x,
                  double* y, double alpha, int acc, hipStream_t s, bool aligned = false) {
   if (batch <= 0 || maxm <= 0 || maxn <= 0) return;
-  // few row blocks over long rows (the last row block of a large triangle
-  // streams the whole matrix width): wide workgroups
-  auto wide = [&](int64_t blocks) { return blocks < 2048 && maxn >= 256; };
+  // few row (column) blocks over long rows (columns): the last row block of a
+  // large triangle streams the whole matrix width: wide workgroups
+  auto wide = [&](int64_t blocks, int len) { return blocks < 2048 && len >= 256; };
   if (!trans && aligned) {
     dim3 g((unsigned)ceil_div(maxm, 16 * Vec16<T>::N), (unsigned)batch);
-    if (wide((int64_t)g.x * batch))
+    if (wide((int64_t)g.x * batch, maxn))
       hipLaunchKernelGGL((k_gemv_nv<T, 64>), g, dim3(1024), 0, s, d, x, y, alpha, acc);
     else
       hipLaunchKernelGGL((k_gemv_nv<T, 16>), g, dim3(NT), 0, s, d, x, y, alpha, acc);
   } else if (trans) {
     dim3 g((unsigned)ceil_div(maxn, kGemvTCols), (unsigned)batch);
-    hipLaunchKernelGGL((k_gemv_t<T>), g, dim3(NT), 0, s, d, x, y, alpha, acc);
+    if (wide((int64_t)g.x * batch, maxm))
+      hipLaunchKernelGGL((k_gemv_t<T, 64>), g, dim3(1024), 0, s, d, x, y, alpha, acc);
+    else
+      hipLaunchKernelGGL((k_gemv_t<T, 16>), g, dim3(NT), 0, s, d, x, y, alpha, acc);
   } else {
     dim3 g((unsigned)ceil_div(maxm, 64), (unsigned)batch);
-    if (wide((int64_t)g.x * batch))
+    if (wide((int64_t)g.x * batch, maxn))
       hipLaunchKernelGGL((k_gemv_n<T, 16>), g, dim3(1024), 0, s, d, x, y, alpha, acc);
     else
       hipLaunchKernelGGL((k_gemv_n<T, 4>), g, dim3(NT), 0, s, d, x, y, alpha, acc);
