@@ -581,7 +581,8 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
     }
     if (!tops.empty()) {
       DevBuf<FrontDesc> d_top = to_dev(tops, s);
-      front_factor<T>(d_top.get(), tops, d_err.get() + 2 * level, s, true);
+      front_factor<T>(d_top.get(), tops, d_err.get() + 2 * level, s, true,
+                      level == 0 ? kSmallFrontLeaf : kSmallFrontUpper);
     }
     run_gemms<T, T>("gemm_lsi", OP_N, OP_T, GF_B_UPPER | GF_TRI_ZEROS, g_lsi, T(1), T(0), s,
                     GC_LSI);
@@ -914,7 +915,7 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
       run_gemms<T, T>("gemm_skel", OP_T, OP_N, 0, g3, T(-1), T(1), s);
       if (!cfd.empty()) {
         DevBuf<FrontDesc> d_cfd = to_dev(cfd, s);
-        front_factor<T>(d_cfd.get(), cfd, d_err.get() + 2 * level + 1, s, false);
+        front_factor<T>(d_cfd.get(), cfd, d_err.get() + 2 * level + 1, s, false, kSmallFrontLeaf);
       }
       run_gemms<T, T>("gemm_skel", OP_N, OP_T, GF_A_LOWER, g4, T(1), T(0), s);
       run_gemms<T, T>("gemm_skel", OP_T, OP_N, 0, g5, T(-1), T(1), s);

@@ -43,8 +43,6 @@ struct Mfma<float> {
 };
 
 constexpr int BM = 64, BN = 64, KC = 16, NTHR = 256;
-// Fronts of at most this many interior columns are factored one per workgroup.
-constexpr int kSmallFront = 512;
 constexpr int kMaxGridY = 65535;  // largest y or z dimension of a launch grid
 
 // LDS staging of one K chunk: As[k][m], Bs[k][n], rows padded by one element
@@ -998,34 +996,34 @@ double gemm_flops(const GemmDesc& d, int flags) {
 
 template <typename T>
 void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  int* err, hipStream_t s, bool upper_zero) {
+                  int* err, hipStream_t s, bool upper_zero, int small_limit) {
   const int batch = (int)h_fronts.size();
   if (batch == 0) return;
   if (batch > kMaxGridY) {  // the per-front grid dimension is limited
     for (int b0 = 0; b0 < batch; b0 += kMaxGridY) {
       const int nb = std::min(kMaxGridY, batch - b0);
       std::vector<FrontDesc> sub(h_fronts.begin() + b0, h_fronts.begin() + b0 + nb);
-      front_factor<T>(d_fronts + b0, sub, err, s, upper_zero);
+      front_factor<T>(d_fronts + b0, sub, err, s, upper_zero, small_limit);
     }
     return;
   }
   int nsmall = 0;
-  for (auto& f : h_fronts) nsmall += f.nI <= kSmallFront;
+  for (auto& f : h_fronts) nsmall += f.nI <= small_limit;
   if (nsmall > 0 && nsmall < batch) {
     // two size buckets (fronts of several problems or levels): one workgroup
     // per small front, blocked steps only for the large ones
     std::vector<FrontDesc> small, large;
-    for (auto& f : h_fronts) (f.nI <= kSmallFront ? small : large).push_back(f);
+    for (auto& f : h_fronts) (f.nI <= small_limit ? small : large).push_back(f);
     DevBuf<FrontDesc> ds, dl;
     ds.upload(small, s);
     dl.upload(large, s);
-    front_factor<T>(ds.get(), small, err, s, upper_zero);
-    front_factor<T>(dl.get(), large, err, s, upper_zero);
+    front_factor<T>(ds.get(), small, err, s, upper_zero, small_limit);
+    front_factor<T>(dl.get(), large, err, s, upper_zero, small_limit);
     return;
   }
   int maxI = 0;
   for (auto& f : h_fronts) maxI = std::max(maxI, f.nI);
-  if (maxI <= kSmallFront) {
+  if (maxI <= small_limit) {
     double fl = 0.0;
     for (auto& f : h_fronts) {
       const double nI = f.nI, nS = f.nR - f.nI;
@@ -1234,9 +1232,9 @@ template void gemm_batched<float, float>(int, int, int, const GemmDesc*, int, in
 template void gemm_batched<float, double>(int, int, int, const GemmDesc*, int, int, int, double,
                                           double, hipStream_t, const char*, double, int);
 template void front_factor<double>(const FrontDesc*, const std::vector<FrontDesc>&, int*,
-                                   hipStream_t, bool);
+                                   hipStream_t, bool, int);
 template void front_factor<float>(const FrontDesc*, const std::vector<FrontDesc>&, int*,
-                                  hipStream_t, bool);
+                                  hipStream_t, bool, int);
 template void front_invert<double>(const FrontDesc*, const std::vector<FrontDesc>&, hipStream_t,
                                    bool);
 template void front_invert<float>(const FrontDesc*, const std::vector<FrontDesc>&, hipStream_t,

@@ -86,9 +86,18 @@ constexpr int kPanel = 64;  // block width of the blocked factorizations
 // id of a front with a non-positive pivot (untouched otherwise).  upper_zero:
 // the strict upper triangle of every nI x nI block is stored as zeros (the
 // factorization keeps it so, and the inverse can then skip its masks).
+// small_limit: fronts of at most this many interior columns are factored one
+// per workgroup (one launch), larger ones by blocked steps batched over the
+// fronts.  One workgroup per front pays off for the thousands of cell fronts
+// of the leaf level and for the redundant blocks of faces; the few hundred
+// cell fronts of 300-800 columns one level up leave most of the chip idle
+// that way.  The limit depends on the level and the kind of front only, so a
+// front takes the same kernels in a single and in a batched build.
+constexpr int kSmallFrontLeaf = 512, kSmallFrontUpper = 256;
+
 template <typename T>
 void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  int* err, hipStream_t s, bool upper_zero);
+                  int* err, hipStream_t s, bool upper_zero, int small_limit);
 
 // Only the in-place inverse of an already factored lower-triangular L_I.
 template <typename T>
