@@ -27,6 +27,11 @@
  *     single-vector preconditioner application inside hif_pcg is captured
  *     into a HIP graph at the second solve with a factor and replayed from
  *     then on (HIF_APPLY_GRAPH=0 in the environment launches it directly).
+ *   - Levels of many fronts or faces apply their factor blocks with fused
+ *     per-front and per-face kernels; HIF_APPLY_FUSED=0 in the environment
+ *     (read at every application) selects the gather / batched matrix-vector
+ *     / scatter sweeps instead.  Both give the same result up to the order of
+ *     the FP64 sums.
  *   - Every call returns a status; nothing throws or aborts across the ABI.
  *     On error an output handle is set to NULL and nothing leaks;
  *     hif_last_error() gives a thread-local description.
