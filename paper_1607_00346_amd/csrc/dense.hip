@@ -550,12 +550,20 @@ __global__ __launch_bounds__(64) void k_diag_inv(const FrontDesc* __restrict__ f
   const int nb = min(kPanel, f.nI - j0);
   const int lane = threadIdx.x;
   T* base = static_cast<T*>(f.ptr) + j0 + (int64_t)f.ld * j0;
-  // one wave: its LDS accesses complete in issue order, no barriers needed
-#pragma unroll 4
-  for (int e = lane; e < kPanel * kPanel; e += 64) {
-    const int c = e >> 6, r = e & 63;
+  // one wave: its LDS accesses complete in issue order, no barriers needed.
+  // Lane r reads row r of every column, all 64 loads issued before the first
+  // is used (clamped to the block; entries outside it are replaced below):
+  // the block comes from HBM, and batches of a few loads each waited out the
+  // memory latency in turn.
+  T g[kPanel];
+  const int rl = min(lane, nb - 1);
+#pragma unroll
+  for (int c = 0; c < kPanel; ++c) g[c] = base[(int64_t)f.ld * min(c, nb - 1) + rl];
+#pragma unroll
+  for (int c = 0; c < kPanel; ++c) {
+    const int r = lane;
     T v = r == c ? T(1) : T(0);
-    if (r < nb && c < nb && c <= r) v = base[(int64_t)f.ld * c + r];
+    if (r < nb && c < nb && c <= r) v = g[c];
     Lc[c][r] = v;
     if (r == c) rd[c] = T(1) / v;
   }
