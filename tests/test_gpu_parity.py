@@ -345,10 +345,18 @@ def test_fused_sweeps_match_general_path(gpu_lib, prec, n, leaf):
     of at most 49 points (one wave per face).  128^3 with 8^3 leaves: the
     1344 level-1 faces hold up to a few hundred points (one workgroup per
     face)."""
-    import os
     a = log_uniform_field(n, -2, 2, 231)
     f = normal_rhs(n, 232)
     g = GpuHif(gpu_lib, n, leaf, 1e-4, a, const_field(n, 0.0), precision=prec)
+    u0, u1 = _general_and_fused(g, f)
+    assert np.linalg.norm(u1 - u0) <= 1e-12 * np.linalg.norm(u0)
+    g.close()
+
+
+def _general_and_fused(g, f):
+    """F^{-1} f by the gather / matrix-vector / scatter sweeps, then by the
+    fused ones (the library reads HIF_APPLY_FUSED at every application)."""
+    import os
     old = os.environ.get("HIF_APPLY_FUSED")
     try:
         os.environ["HIF_APPLY_FUSED"] = "0"
@@ -360,5 +368,25 @@ def test_fused_sweeps_match_general_path(gpu_lib, prec, n, leaf):
             os.environ.pop("HIF_APPLY_FUSED", None)
         else:
             os.environ["HIF_APPLY_FUSED"] = old
+    return u0, u1
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-6])
+def test_fused_face_sweeps_at_other_skeleton_widths(gpu_lib, eps):
+    """128^3 with 8^3 leaves, FP32 factor: at eps = 1e-2 the level-1 faces
+    keep few skeleton points (narrow T and Y, a wide L_F̌^{-1}), at 1e-6 many
+    (the reverse).  The level still has at least 1024 faces of more than 64
+    points on average, so its skeleton step runs one workgroup per face, and
+    the fused sweeps equal the general path to 1e-12."""
+    n, leaf = 128, 8
+    a = log_uniform_field(n, -2, 2, 241)
+    g = GpuHif(gpu_lib, n, leaf, eps, a, const_field(n, 0.0), precision=1)
+    st = gpu_lib.hif_factor_stats(g.F).as_dict()
+    assert st["faces"][1] >= 1024 and st["face_dofs"][1] > 64 * st["faces"][1]
+    ranks, sizes = gpu_lib.hif_factor_ranks(g.F, 1)
+    k_med = float(np.median(np.array(ranks) / np.array(sizes)))
+    assert (k_med < 0.5) if eps == 1e-2 else (k_med > 0.5), k_med
+    f = normal_rhs(n, 242)
+    u0, u1 = _general_and_fused(g, f)
     assert np.linalg.norm(u1 - u0) <= 1e-12 * np.linalg.norm(u0)
     g.close()
