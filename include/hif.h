@@ -29,9 +29,11 @@
  *     then on (HIF_APPLY_GRAPH=0 in the environment launches it directly).
  *   - Levels of many fronts or faces apply their factor blocks with fused
  *     per-front and per-face kernels; HIF_APPLY_FUSED=0 in the environment
- *     (read at every application) selects the gather / batched matrix-vector
- *     / scatter sweeps instead.  Both give the same result up to the order of
- *     the FP64 sums.
+ *     selects the gather / batched matrix-vector / scatter sweeps instead.
+ *     Both give the same result up to the order of the FP64 sums.  The
+ *     variable is read at every direct application (hif_apply, and the first
+ *     PCG solve with a factor); the HIP graph that later hif_pcg solves
+ *     replay keeps the choice made when it was captured.
  *   - Every call returns a status; nothing throws or aborts across the ABI.
  *     On error an output handle is set to NULL and nothing leaks;
  *     hif_last_error() gives a thread-local description.
@@ -65,7 +67,12 @@ enum { HIF_DIRICHLET = 0 };            /* boundary condition                    
 typedef struct {
   int32_t n;         /* grid points per dimension; n = leaf * 2^L, L >= 0         */
   int32_t leaf;      /* leaf cell width m >= 2 (paper: m, Section 2.1)             */
-  double eps;        /* ID relative precision; 0 = no ID (exact nested dissection) */
+  double eps;        /* ID relative precision; 0 = no ID (exact nested dissection).
+                        Otherwise 1e-7 <= eps < 1 (HIF_EINVAL outside): the ID's
+                        rank test compares the FP64 Gram matrix's downdated
+                        diagonal with eps^2 times its largest entry, which
+                        resolves only while eps^2 is far above the FP64 unit
+                        roundoff (1.1e-16).                                      */
   int32_t precision; /* HIF_FP64: all front work in FP64.  HIF_MIXED: fronts,
                         Schur updates and skeleton algebra in FP32; ID pivot
                         decisions (Gram + pivoted Cholesky) in FP64.             */
@@ -94,6 +101,14 @@ typedef struct {
   int64_t factor_bytes;                    /* bytes of stored factor blocks        */
   int64_t peak_bytes;                      /* device high-water mark of the library */
   double build_seconds;                    /* wall time of hif_build               */
+  /* Appended after the fields above (their layout is unchanged): */
+  double level_flops[HIF_MAX_LEVELS + 1];  /* algorithmic flops counted per level  */
+  int64_t level_bytes[HIF_MAX_LEVELS + 1]; /* stored factor bytes per level        */
+  double e_s;       /* relative solve error ||x - F^{-1}A x|| / ||x|| of the last
+                       hif_factor_error call (paper, Section 4, result metrics);
+                       NaN until then                                          */
+  double err_norm;  /* ||I - F^{-1}A||_2 estimated by power iteration in the last
+                       hif_factor_error call with power_iters > 0; NaN until then */
 } hif_stats;
 
 /* Create the operator A from coefficient fields a (> 0, finite) and b
@@ -104,7 +119,9 @@ hif_status hif_problem_create(const hif_options* opts, const double* a, const do
 
 /* Factor A ~= F (paper, Sections 2.2-2.4 and 3.2).  Blocks the calling
  * thread: ranks of each level are read back before the next level is
- * planned.  The factor keeps no reference to caller memory. */
+ * planned.  The factor keeps no reference to caller memory.  The ID of a
+ * face runs on at most 4096 active points: a level with a larger face
+ * (e.g. n = 512, or 256^3 with eps <= 1e-6) returns HIF_EINVAL. */
 hif_status hif_build(hif_problem_t A, const hif_options* opts, void* stream,
                      hif_factor_t* out);
 
@@ -130,12 +147,18 @@ hif_status hif_build_batched(int32_t count, const hif_problem_t* A, const hif_op
  * (exactly, not partly).  Asynchronous on `stream`.  nrhs = 0 is a no-op. */
 hif_status hif_apply(hif_factor_t F, const double* f, double* u, int32_t nrhs, void* stream);
 
-/* y = A x for nrhs column-major vectors, FP64.  Asynchronous. */
+/* y = A x for nrhs column-major vectors, FP64: the 7-point operator of
+ * hif_problem_create (paper, Section 2.4, seven-point stencil), one thread
+ * per grid point.  x and y must not alias.  Asynchronous. */
 hif_status hif_matvec(hif_problem_t A, const double* x, double* y, int32_t nrhs, void* stream);
 
 /* Solve A u = f by preconditioned CG with F^{-1} as the preconditioner,
  * FP64 residuals, matvecs and inner products, from u = 0; stops when the
- * true relative residual is <= tol.  nrhs > 1: one CG per column, all
+ * true relative residual is <= tol.  The paper (Section 4) uses the HIF as
+ * the preconditioner of GMRES; A and F^{-1} are symmetric positive definite
+ * here, so CG is the Krylov method used for the timed solve (with the
+ * Polak-Ribiere form of beta, which tolerates the slightly non-symmetric
+ * FP32 preconditioner).  nrhs > 1: one CG per column, all
  * columns sharing each block application of F^{-1} (see hif_apply); a
  * column stops on its own.  info has nrhs entries (host memory).  f and u
  * must not alias.  Returns HIF_ENOCONV if any column hit maxit.  Blocks the
@@ -154,7 +177,10 @@ hif_status hif_pcg_batched(int32_t count, const hif_problem_t* A, const hif_fact
                            const double* const* f, double* const* u, double tol, int32_t maxit,
                            hif_pcg_info* info, void* stream);
 
-/* Sizes, ranks, flops, bytes and times of a factor (host struct). */
+/* Sizes, ranks, flops, bytes and times of a factor (host struct): the
+ * result metrics of the paper's Section 4 (|Sigma_L| = root_size, factor
+ * time t_f = build_seconds, memory m_f = peak_bytes / factor_bytes, e_s and
+ * ||I - F^{-1}A|| after hif_factor_error) plus per-level counts. */
 hif_status hif_factor_stats(hif_factor_t F, hif_stats* out);
 
 /* Rank k of every face of `level` in face order (faces enumerated by
@@ -167,6 +193,17 @@ hif_status hif_factor_ranks(hif_factor_t F, int32_t level, int32_t* ranks, int32
 /* Active-DOF mask after `level` (0..L-1): mask[p] = 1 if grid point p is
  * still active in A^{level+1} (host array of N bytes). */
 hif_status hif_factor_active(hif_factor_t F, int32_t level, uint8_t* mask);
+
+/* Accuracy of F as an approximation of A (paper, Section 4, result
+ * metrics): *e_s = ||x - F^{-1} A x||_2 / ||x||_2 for the caller's device
+ * vector x (N doubles, e.g. i.i.d. Gaussian), and, if power_iters > 0,
+ * *err_norm = an estimate of ||I - F^{-1} A||_2 from power_iters steps of
+ * the power method on B^T B, B = I - F^{-1} A, B^T = I - A F^{-1}, started
+ * at x (either output pointer may be NULL; *err_norm is NaN when
+ * power_iters = 0).  Both are also stored in the factor's hif_stats.  FP64
+ * vectors; single-vector applies of F^{-1}.  Blocks the calling thread. */
+hif_status hif_factor_error(hif_problem_t A, hif_factor_t F, const double* x, int32_t power_iters,
+                            double* e_s, double* err_norm, void* stream);
 
 /* Per-kernel-class device timing.  hif_profile_begin() clears and starts
  * recording: every library kernel launch made afterwards (on any stream)
@@ -186,6 +223,13 @@ typedef struct {
 
 hif_status hif_profile_begin(void);
 hif_status hif_profile_end(hif_kernel_stat* out, int32_t cap, int32_t* count);
+
+/* Restrict the recording of hif_profile_begin to the kernel classes named in
+ * `classes`, a comma-separated list of class names without the "@level"
+ * suffix (e.g. "gemm_syrk"), so that a timed region carries event pairs
+ * around those launches only.  NULL or "" records every class again.  Takes
+ * effect for launches made after the call; process-wide, not thread safe. */
+hif_status hif_profile_select(const char* classes);
 
 /* Device memory the library released is kept in a process-wide cache for
  * reuse by later calls (up to 48 GB).  This returns all of it to the device

@@ -331,6 +331,20 @@ def apply_inverse(fac: Factor, f: np.ndarray) -> np.ndarray:
 # Diagnostics (Section 4, result metrics) and the Krylov driver
 # ---------------------------------------------------------------------------
 
+def active_after(fac: Factor, level: int) -> np.ndarray:
+    """Mask of the points still active in A^{level+1}: every interior
+    eliminated and every redundant face point left out at levels 0..level
+    is inactive (Section 2.4, the sets Sigma^l)."""
+    N = fac.n ** 3
+    active = np.ones(N, dtype=bool)
+    for lev in fac.levels[:level + 1]:
+        for cf in lev.cells:
+            active[cf.I] = False
+        for ff in lev.faces:
+            active[ff.chk] = False
+    return active
+
+
 def relative_solve_error(fac: Factor, A, x: np.ndarray) -> float:
     """e_s = ||(I - F^{-1} A) x|| / ||x||."""
     return float(np.linalg.norm(x - apply_inverse(fac, A @ x)) / np.linalg.norm(x))

@@ -51,8 +51,8 @@ void check_options(const hif_options* o) {
   HIF_REQUIRE(o->n >= 2 && o->n <= 1024, HIF_EINVAL, "n must be in [2, 1024]");
   HIF_REQUIRE(hif::levels_for(o->n, o->leaf) >= 0, HIF_EINVAL,
               "n must equal leaf * 2^L with leaf >= 2");
-  HIF_REQUIRE(std::isfinite(o->eps) && o->eps >= 0.0 && o->eps < 1.0, HIF_EINVAL,
-              "eps must be in [0, 1)");
+  HIF_REQUIRE(std::isfinite(o->eps) && (o->eps == 0.0 || (o->eps >= hif::kEpsMin && o->eps < 1.0)),
+              HIF_EINVAL, "eps must be 0 or in [1e-7, 1)");
   HIF_REQUIRE(o->precision == HIF_FP64 || o->precision == HIF_MIXED, HIF_EINVAL,
               "precision must be HIF_FP64 or HIF_MIXED");
   HIF_REQUIRE(o->bc == HIF_DIRICHLET, HIF_EINVAL, "only HIF_DIRICHLET is implemented");
@@ -254,6 +254,23 @@ hif_status hif_factor_ranks(hif_factor_t F, int32_t level, int32_t* ranks, int32
   });
 }
 
+hif_status hif_factor_error(hif_problem_t A, hif_factor_t F, const double* x, int32_t power_iters,
+                            double* e_s, double* err_norm, void* stream) {
+  return guarded([&] {
+    HIF_REQUIRE(A != nullptr && F != nullptr && F->impl && x != nullptr, HIF_EINVAL,
+                "NULL argument");
+    HIF_REQUIRE(F->stats.n_dof == A->N, HIF_EINVAL, "factor and problem sizes differ");
+    HIF_REQUIRE(power_iters >= 0, HIF_EINVAL, "power_iters must be >= 0");
+    hif::StreamScope scope(as_stream(stream));
+    double es = 0.0, nrm = 0.0;
+    hif::factor_error(A, F, x, power_iters, &es, &nrm, as_stream(stream));
+    F->stats.e_s = es;
+    F->stats.err_norm = nrm;
+    if (e_s) *e_s = es;
+    if (err_norm) *err_norm = nrm;
+  });
+}
+
 hif_status hif_factor_active(hif_factor_t F, int32_t level, uint8_t* mask) {
   return guarded([&] {
     HIF_REQUIRE(F != nullptr && mask != nullptr, HIF_EINVAL, "NULL argument");
@@ -279,6 +296,24 @@ hif_status hif_profile_begin(void) {
     }
     p.recs.clear();
     p.on = true;
+  });
+}
+
+hif_status hif_profile_select(const char* classes) {
+  return guarded([&] {
+    hif::Profiler& p = hif::profiler();
+    p.only.clear();
+    if (!classes) return;
+    std::string cur;
+    for (const char* c = classes;; ++c) {
+      if (*c == ',' || *c == '\0') {
+        if (!cur.empty()) p.only.push_back(cur);
+        cur.clear();
+        if (*c == '\0') break;
+      } else if (*c != ' ') {
+        cur.push_back(*c);
+      }
+    }
   });
 }
 

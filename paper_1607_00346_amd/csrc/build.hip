@@ -3,6 +3,7 @@
 // form the Schur updates, assemble face panels, interpolative decomposition
 // of every face, skeleton update; a host round trip reads the ranks back.
 #include <chrono>
+#include <cmath>
 #include <climits>
 #include <cstring>
 
@@ -379,6 +380,7 @@ struct Job {
   int64_t face0 = 0;  // first face of this problem in the level's joint ID arrays
   int64_t pt0 = 0;    // first face point of this problem in the joint pivot order
   int64_t ssz = 0;    // skeleton arena size of the level
+  std::vector<double> flops_mark;  // flops counted before each level
 };
 
 // The problem and the cell (or skeleton) that a front id of a joint launch names.
@@ -483,6 +485,7 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
   for (int level = 0; level <= maxL; ++level) {
     HIF_HIP(hipEventRecord(ev.e[level], s));
     prof_level() = level;
+    for (auto& J : jobs) J.flops_mark.push_back(J.flops);
     std::vector<int> here, below;  // problems with this level; those for which it is not the root
     for (int j = 0; j < nj; ++j) {
       if (level <= jobs[j].L) here.push_back(j);
@@ -1005,7 +1008,15 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
   const double t_end = now_s();
   for (auto& J : jobs) {
     hif_stats& st = J.F->stats;
-    for (int level = 0; level <= J.L; ++level) st.level_seconds[level] = level_s[level];
+    J.flops_mark.push_back(J.flops);
+    for (int level = 0; level <= J.L; ++level) {
+      st.level_seconds[level] = level_s[level];
+      st.level_flops[level] = J.flops_mark[level + 1] - J.flops_mark[level];
+      st.level_bytes[level] = (int64_t)(J.impl->levels[level].front.bytes() +
+                                        J.impl->levels[level].skel.bytes());
+    }
+    st.e_s = std::nan("");
+    st.err_norm = std::nan("");
     st.factor_flops = J.flops;
     st.build_seconds = t_end - t_begin;
     st.peak_bytes = mem_stats().peak - mem0;

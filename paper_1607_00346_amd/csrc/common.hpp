@@ -61,6 +61,10 @@ MemStats& mem_stats();
 // reused after a device synchronization; blocks wanted by another stream only
 // when a fresh allocation fails (a device-wide wait would stall that stream).
 constexpr int64_t kPoolCap = int64_t(48) << 30;
+
+// Smallest eps > 0 accepted: the ID's rank test on the FP64 Gram diagonal
+// needs eps^2 well above the FP64 unit roundoff.
+constexpr double kEpsMin = 1e-7;
 void* pool_alloc(size_t bytes);
 void pool_free(void* p, size_t bytes);
 // Returns every cached block to the device (after a device synchronization).

@@ -175,6 +175,16 @@ struct BuildRequest {
 template <typename T>
 void build_factors(const std::vector<BuildRequest>& req, hipStream_t s);
 
+// e_s = ||x - F^{-1}A x|| / ||x|| and, for power_iters > 0, the power-method
+// estimate of ||I - F^{-1}A||_2 started at x (NaN for power_iters = 0).
+void factor_error(const hif_problem_s* A, hif_factor_s* F, const double* x, int power_iters,
+                  double* e_s, double* err_norm, hipStream_t s);
+
+// Device inner product a.(b - c) (c may be null) into *out (device), FP64,
+// in a fixed reduction order.
+void device_dot(const double* a, const double* b, const double* c, int64_t N, double* out,
+                hipStream_t s);
+
 void pcg_solve(const hif_problem_s* A, hif_factor_s* F, const double* f, double* u, double tol,
                int maxit, hif_pcg_info* info, hipStream_t s);
 void pcg_solve_block(const hif_problem_s* A, hif_factor_s* F, const double* f, double* u, int nrhs,

@@ -23,6 +23,13 @@ int Profiler::class_id(const char* name) {
   return (int)names.size() - 1;
 }
 
+bool Profiler::selected(const char* name) const {
+  if (only.empty()) return true;
+  for (const std::string& o : only)
+    if (o == name) return true;
+  return false;
+}
+
 hipEvent_t Profiler::event() {
   if (!pool_.empty()) {
     hipEvent_t e = pool_.back();
@@ -36,7 +43,7 @@ hipEvent_t Profiler::event() {
 
 ProfScope::ProfScope(const char* name, hipStream_t s, double flops, double bytes) {
   Profiler& p = profiler();
-  if (!p.on) return;
+  if (!p.on || !p.selected(name)) return;
   if (prof_level() >= 0) {
     char buf[64];
     snprintf(buf, sizeof(buf), "%s@%d", name, prof_level());

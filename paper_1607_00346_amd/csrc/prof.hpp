@@ -19,10 +19,14 @@ class Profiler {
     double flops, bytes;
   };
   bool on = false;
+  // When non-empty, only kernel classes whose name (before any "@level")
+  // equals one of these are recorded.
+  std::vector<std::string> only;
   std::vector<std::string> names;
   std::vector<Rec> recs;
 
   int class_id(const char* name);
+  bool selected(const char* name) const;
   hipEvent_t event();
   void recycle(hipEvent_t e) { pool_.push_back(e); }
 

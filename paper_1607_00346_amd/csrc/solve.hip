@@ -1283,6 +1283,12 @@ struct Dot {
 
 }  // namespace
 
+void device_dot(const double* a, const double* b, const double* c, int64_t N, double* out,
+                hipStream_t s) {
+  Dot d;
+  d.run(a, b, c, N, out, s);
+}
+
 // A preconditioner application captured once into a HIP graph (on a private
 // stream: the caller's may be the legacy stream, which cannot be captured) and
 // replayed on the caller's stream, which replaces its ~10 launches per level by

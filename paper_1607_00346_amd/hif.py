@@ -21,9 +21,10 @@ HIF_MAX_LEVELS = 16
 EXPORTED = [
     "hif_problem_create", "hif_build", "hif_build_batched", "hif_apply", "hif_matvec", "hif_pcg",
     "hif_pcg_batched",
-    "hif_factor_stats", "hif_factor_ranks", "hif_factor_active", "hif_factor_destroy",
+    "hif_factor_stats", "hif_factor_ranks", "hif_factor_active", "hif_factor_error",
+    "hif_factor_destroy",
     "hif_problem_destroy", "hif_status_string", "hif_last_error", "hif_profile_begin",
-    "hif_profile_end", "hif_tune_begin", "hif_tune_end", "hif_release_cached_memory",
+    "hif_profile_end", "hif_profile_select", "hif_tune_begin", "hif_tune_end", "hif_release_cached_memory",
 ]
 
 
@@ -48,7 +49,10 @@ class hif_stats(ctypes.Structure):
                 ("redundant", ctypes.c_int64 * _M), ("max_front", ctypes.c_int64 * (_M + 1)),
                 ("level_seconds", ctypes.c_double * (_M + 1)), ("factor_flops", ctypes.c_double),
                 ("factor_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
-                ("build_seconds", ctypes.c_double)]
+                ("build_seconds", ctypes.c_double),
+                ("level_flops", ctypes.c_double * (_M + 1)),
+                ("level_bytes", ctypes.c_int64 * (_M + 1)),
+                ("e_s", ctypes.c_double), ("err_norm", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         L = self.levels
@@ -61,6 +65,9 @@ class hif_stats(ctypes.Structure):
             "level_seconds": list(self.level_seconds[:L + 1]),
             "factor_flops": self.factor_flops, "factor_bytes": self.factor_bytes,
             "peak_bytes": self.peak_bytes, "build_seconds": self.build_seconds,
+            "level_flops": list(self.level_flops[:L + 1]),
+            "level_bytes": list(self.level_bytes[:L + 1]),
+            "e_s": self.e_s, "err_norm": self.err_norm,
         }
 
 
@@ -101,10 +108,13 @@ def lib():
         L.hif_factor_stats.argtypes = [vp, ctypes.POINTER(hif_stats)]
         L.hif_factor_ranks.argtypes = [vp, i32, vp, vp, i32, ctypes.POINTER(i32)]
         L.hif_factor_active.argtypes = [vp, i32, vp]
+        L.hif_factor_error.argtypes = [vp, vp, vp, i32, ctypes.POINTER(f64),
+                                       ctypes.POINTER(f64), vp]
         L.hif_factor_destroy.argtypes = [vp]
         L.hif_problem_destroy.argtypes = [vp]
         L.hif_profile_begin.argtypes = []
         L.hif_profile_end.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.hif_profile_select.argtypes = [ctypes.c_char_p]
         L.hif_release_cached_memory.argtypes = []
         L.hif_release_cached_memory.restype = ctypes.c_int
         L.hif_tune_begin.argtypes = []
@@ -113,8 +123,10 @@ def lib():
         L.hif_status_string.restype = ctypes.c_char_p
         L.hif_last_error.restype = ctypes.c_char_p
         for name in ("hif_problem_create", "hif_build", "hif_build_batched", "hif_apply",
-                     "hif_matvec", "hif_pcg", "hif_pcg_batched", "hif_factor_stats", "hif_factor_ranks", "hif_factor_active",
-                     "hif_profile_begin", "hif_profile_end", "hif_tune_begin", "hif_tune_end"):
+                     "hif_matvec", "hif_pcg", "hif_pcg_batched", "hif_factor_stats",
+                     "hif_factor_ranks", "hif_factor_active", "hif_factor_error",
+                     "hif_profile_begin", "hif_profile_end", "hif_profile_select",
+                     "hif_tune_begin", "hif_tune_end"):
             getattr(L, name).restype = ctypes.c_int
         L.hif_factor_destroy.restype = None
         L.hif_problem_destroy.restype = None
@@ -230,8 +242,23 @@ def hif_factor_active(F, level: int, n_dof: int):
     return m
 
 
+def hif_factor_error(A, F, x, power_iters: int = 0, stream=None):
+    """(e_s, ||I - F^{-1}A|| estimate or nan) for the device vector x."""
+    es, nrm = ctypes.c_double(), ctypes.c_double()
+    _check(lib().hif_factor_error(A, F, _dptr(x), int(power_iters), ctypes.byref(es),
+                                  ctypes.byref(nrm), _stream(stream)), "hif_factor_error")
+    return es.value, nrm.value
+
+
 def hif_profile_begin():
     _check(lib().hif_profile_begin(), "hif_profile_begin")
+
+
+def hif_profile_select(classes=None):
+    """Record only these kernel classes (list or comma-separated string); None: all."""
+    if classes is not None and not isinstance(classes, str):
+        classes = ",".join(classes)
+    _check(lib().hif_profile_select(classes.encode() if classes else None), "hif_profile_select")
 
 
 def hif_profile_end():
