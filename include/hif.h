@@ -79,8 +79,8 @@ typedef struct {
   int32_t bc;        /* HIF_DIRICHLET (the only one implemented)                  */
 } hif_options;
 
-typedef struct {
-  int32_t iters;     /* PCG iterations taken                                      */
+typedef struct {      /* result of hif_pcg, hif_pcg_batched and hif_gmres        */
+  int32_t iters;     /* Krylov iterations taken                                   */
   int32_t converged; /* 1 if the true relative residual reached tol               */
   double relres;     /* ||f - A u||_2 / ||f||_2 recomputed in FP64 at exit         */
 } hif_pcg_info;
@@ -165,6 +165,24 @@ hif_status hif_matvec(hif_problem_t A, const double* x, double* y, int32_t nrhs,
  * calling thread. */
 hif_status hif_pcg(hif_problem_t A, hif_factor_t F, const double* f, double* u, int32_t nrhs,
                    double tol, int32_t maxit, hif_pcg_info* info, void* stream);
+
+/* Solve A u = f by GMRES with F^{-1} as the preconditioner, the Krylov
+ * method of the paper's experiments (Section 4: GMRES to a relative
+ * tolerance of 1e-12, n_iter in its tables).  Restarted GMRES(restart) from
+ * u = 0 with right preconditioning in its flexible form (z_j = F^{-1} v_j
+ * kept beside the Arnoldi basis v_j, so the mixed factor's FP32 application
+ * is allowed to vary by rounding); Arnoldi orthogonalization by classical
+ * Gram-Schmidt applied twice, all vectors and inner products FP64.  A cycle
+ * ends when the least-squares residual estimate reaches tol * ||f|| (or
+ * after `restart` steps); the true residual ||f - A u|| then decides between
+ * stopping and another cycle.  info (one entry, host memory): iters =
+ * Arnoldi steps over all cycles, relres = the final true relative residual,
+ * converged = relres <= tol.  Needs 1 <= restart <= 1024 and device memory
+ * for 2 * restart + 2 vectors of N doubles.  f and u must not alias.
+ * Returns HIF_ENOCONV when maxit steps do not reach tol (u holds the last
+ * iterate).  Blocks the calling thread. */
+hif_status hif_gmres(hif_problem_t A, hif_factor_t F, const double* f, double* u, double tol,
+                     int32_t restart, int32_t maxit, hif_pcg_info* info, void* stream);
 
 /* hif_pcg for several problems at once: for each i, one single-vector PCG
  * solve of A[i] u[i] = f[i] with F[i] (as hif_pcg with nrhs = 1).  The solves

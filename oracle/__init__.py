@@ -6,10 +6,11 @@ the benchmark's CPU-baseline leg may import anything from here.
 """
 from .dense import NotSPD, cholesky, cpqr, interp_decomp, solve_lower, solve_lower_t, solve_upper
 from .hif import (Factor, Geometry, active_after, apply_inverse, assemble, build, count_levels,
-                  energy, pcg, relative_solve_error, power_norm_error)
+                  energy, gmres, pcg, relative_solve_error, power_norm_error)
 
 __all__ = [
     "NotSPD", "cholesky", "cpqr", "interp_decomp", "solve_lower", "solve_lower_t", "solve_upper",
-    "Factor", "Geometry", "active_after", "apply_inverse", "assemble", "build", "count_levels", "energy", "pcg",
+    "Factor", "Geometry", "active_after", "apply_inverse", "assemble", "build", "count_levels",
+    "energy", "gmres", "pcg",
     "relative_solve_error", "power_norm_error",
 ]

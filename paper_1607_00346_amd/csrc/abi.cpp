@@ -210,6 +210,21 @@ hif_status hif_pcg(hif_problem_t A, hif_factor_t F, const double* f, double* u, 
   });
 }
 
+hif_status hif_gmres(hif_problem_t A, hif_factor_t F, const double* f, double* u, double tol,
+                     int32_t restart, int32_t maxit, hif_pcg_info* info, void* stream) {
+  return guarded([&] {
+    HIF_REQUIRE(A != nullptr && F != nullptr && F->impl, HIF_EINVAL, "NULL handle");
+    HIF_REQUIRE(F->stats.n_dof == A->N, HIF_EINVAL, "factor and problem sizes differ");
+    HIF_REQUIRE(restart >= 1 && restart <= 1024 && maxit >= 1 && std::isfinite(tol) && tol > 0.0,
+                HIF_EINVAL, "need 1 <= restart <= 1024, maxit >= 1, tol > 0");
+    HIF_REQUIRE(f != nullptr && u != nullptr && info != nullptr && f != u, HIF_EINVAL,
+                "bad vectors");
+    hif::StreamScope scope(as_stream(stream));
+    hif::gmres_solve(A, F, f, u, tol, restart, maxit, info, as_stream(stream));
+    if (!info->converged) throw hif::Error(HIF_ENOCONV, "GMRES did not reach tol within maxit");
+  });
+}
+
 hif_status hif_pcg_batched(int32_t count, const hif_problem_t* A, const hif_factor_t* F,
                            const double* const* f, double* const* u, double tol, int32_t maxit,
                            hif_pcg_info* info, void* stream) {

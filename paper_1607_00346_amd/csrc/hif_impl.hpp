@@ -121,6 +121,10 @@ struct FactorImpl : FactorBase {
   // Sweep descriptors and scratch of the apply (idempotent).
   void prepare(hipStream_t s);
   void apply(const double* f, double* u, hipStream_t s) override;
+  // The single-vector sweeps on the given scratch segments: xi, yv (ymax
+  // each), zv, xsv (zmax each), sh (kmax), sc, sc2 (rmax each).
+  void sweep(const double* f, double* u, double* xi, double* yv, double* zv, double* xsv,
+             double* sh, double* sc, double* sc2, hipStream_t s);
   void apply_block(const double* f, double* u, int nrhs, hipStream_t s) override;
   double apply_bytes() const override;
   int64_t stored_bytes() const override;
@@ -184,6 +188,12 @@ void factor_error(const hif_problem_s* A, hif_factor_s* F, const double* x, int 
 // in a fixed reduction order.
 void device_dot(const double* a, const double* b, const double* c, int64_t N, double* out,
                 hipStream_t s);
+
+// Restarted flexible GMRES(restart) with F^{-1} as a right preconditioner,
+// from u = 0, to a true relative residual <= tol (info->iters counts Arnoldi
+// steps over all cycles).
+void gmres_solve(const hif_problem_s* A, hif_factor_s* F, const double* f, double* u, double tol,
+                 int restart, int maxit, hif_pcg_info* info, hipStream_t s);
 
 void pcg_solve(const hif_problem_s* A, hif_factor_s* F, const double* f, double* u, double tol,
                int maxit, hif_pcg_info* info, hipStream_t s);

@@ -8,6 +8,7 @@
 #include <atomic>
 #include <cstdlib>
 #include <cstring>
+#include <string>
 
 #include "hif_impl.hpp"
 #include "prof.hpp"
@@ -947,17 +948,18 @@ void launch_skel_fused(const Level<T>& lv, int mode, double* u, int down, hipStr
 template <typename T>
 void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   prepare(s);
+  double* sc = sbuf.get() + kmax;
+  sweep(f, u, ybuf.get(), ybuf.get() + ymax, zbuf.get(), zbuf.get() + zmax, sbuf.get(), sc,
+        sc + rmax, s);
+}
+
+template <typename T>
+void FactorImpl<T>::sweep(const double* f, double* u, double* xi, double* yv, double* zv,
+                          double* xsv, double* sh, double* sc, double* sc2, hipStream_t s) {
   if (u != f) {  // a kernel, not a copy node, so that the sweep can be captured in a graph
     hipLaunchKernelGGL(k_copy, dim3(grid_for(N)), dim3(NT), 0, s, f, u, N);
     HIF_LAUNCH_CHECK();
   }
-  double* xi = ybuf.get();
-  double* yv = ybuf.get() + ymax;
-  double* zv = zbuf.get();
-  double* xsv = zbuf.get() + zmax;
-  double* sh = sbuf.get();
-  double* sc = sbuf.get() + kmax;
-  double* sc2 = sc + rmax;
   const int nlev = (int)levels.size();
   // W^l^T for l = 0..L (level L: L_Sigma^{-1})
   for (int l = 0; l < nlev; ++l) {
@@ -1262,6 +1264,7 @@ template void FactorImpl<double>::prepare(hipStream_t);
 template void FactorImpl<float>::prepare(hipStream_t);
 template void FactorImpl<double>::apply(const double*, double*, hipStream_t);
 template void FactorImpl<float>::apply(const double*, double*, hipStream_t);
+
 template void FactorImpl<double>::apply_block(const double*, double*, int, hipStream_t);
 template double FactorImpl<double>::apply_bytes() const;
 template double FactorImpl<float>::apply_bytes() const;

@@ -19,8 +19,8 @@ HIF_DIRICHLET = 0
 HIF_MAX_LEVELS = 16
 
 EXPORTED = [
-    "hif_problem_create", "hif_build", "hif_build_batched", "hif_apply", "hif_matvec", "hif_pcg",
-    "hif_pcg_batched",
+    "hif_problem_create", "hif_build", "hif_build_batched", "hif_apply",
+    "hif_matvec", "hif_pcg", "hif_gmres", "hif_pcg_batched",
     "hif_factor_stats", "hif_factor_ranks", "hif_factor_active", "hif_factor_error",
     "hif_factor_destroy",
     "hif_problem_destroy", "hif_status_string", "hif_last_error", "hif_profile_begin",
@@ -102,6 +102,7 @@ def lib():
         L.hif_apply.argtypes = [vp, vp, vp, i32, vp]
         L.hif_matvec.argtypes = [vp, vp, vp, i32, vp]
         L.hif_pcg.argtypes = [vp, vp, vp, vp, i32, f64, i32, ctypes.POINTER(hif_pcg_info), vp]
+        L.hif_gmres.argtypes = [vp, vp, vp, vp, f64, i32, i32, ctypes.POINTER(hif_pcg_info), vp]
         L.hif_pcg_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                       ctypes.POINTER(vp), ctypes.POINTER(vp), f64, i32,
                                       ctypes.POINTER(hif_pcg_info), vp]
@@ -123,6 +124,7 @@ def lib():
         L.hif_status_string.restype = ctypes.c_char_p
         L.hif_last_error.restype = ctypes.c_char_p
         for name in ("hif_problem_create", "hif_build", "hif_build_batched", "hif_apply",
+                     "hif_gmres",
                      "hif_matvec", "hif_pcg", "hif_pcg_batched", "hif_factor_stats",
                      "hif_factor_ranks", "hif_factor_active", "hif_factor_error",
                      "hif_profile_begin", "hif_profile_end", "hif_profile_select",
@@ -197,6 +199,16 @@ def hif_pcg(A, F, f, u, nrhs: int = 1, tol: float = 1e-10, maxit: int = 500, str
     st = _check(lib().hif_pcg(A, F, _dptr(f), _dptr(u), int(nrhs), float(tol), int(maxit),
                               info, _stream(stream)), "hif_pcg", allow=(HIF_ENOCONV,))
     return st, [info[i] for i in range(nrhs)]
+
+
+def hif_gmres(A, F, f, u, tol: float = 1e-12, restart: int = 50, maxit: int = 500, stream=None):
+    """GMRES(restart) with F^{-1} as a right preconditioner; returns (status, hif_pcg_info);
+    HIF_ENOCONV is reported, not raised."""
+    info = hif_pcg_info()
+    st = _check(lib().hif_gmres(A, F, _dptr(f), _dptr(u), float(tol), int(restart), int(maxit),
+                                ctypes.byref(info), _stream(stream)), "hif_gmres",
+                allow=(HIF_ENOCONV,))
+    return st, info
 
 
 def hif_pcg_batched(problems, factors, fs, us, tol: float = 1e-10, maxit: int = 500, stream=None):

@@ -40,6 +40,8 @@ def test_status_strings(L):
     (7, 2, 1e-6, 0),      # 7 is not leaf * 2^L
     (16, 1, 1e-6, 0),     # leaf < 2
     (16, 4, -1.0, 0),     # eps < 0
+    (16, 4, 1e-9, 0),     # eps > 0 below the 1e-7 floor of the Gram-based rank test
+    (16, 4, 1.0, 0),      # eps >= 1
     (16, 4, float("nan"), 0),
     (16, 4, 1e-6, 7),     # unknown precision
     (0, 2, 1e-6, 0),

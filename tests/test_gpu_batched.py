@@ -8,7 +8,7 @@
     to 1e-11 relative (FP64), and the eliminated counts per level are the
     oracle planner's.
   * At eps > 0 the ranks of a mixed batch are compared with the oracle face
-    by face (near ties may differ, as for single builds), and PCG reaches a
+    by face (every differing face counted; at least 98% must match), and PCG reaches a
     true residual of 1e-10 measured with the oracle's operator.
   * The full batched workload (48 problems of 32^3..96^3, FP32 factor at
     eps = 1e-4) is checked by properties that hold at any size: every PCG
@@ -154,13 +154,13 @@ def test_mixed_sizes_eps_ranks_and_pcg(gpu_lib, prec):
             ranks, sizes = H.hif_factor_ranks(bt.F[i], level)
             assert list(sizes) == lev.face_sizes
             total += len(ranks)
-            bad += int(np.sum(np.abs(np.array(ranks) - np.array(lev.face_ranks)) > 1))
+            bad += int(np.sum(np.array(ranks) != np.array(lev.face_ranks)))
         A = O.assemble(n, a, b)
         f = normal_rhs(n, 600 + i)
         st, info, u = bt.pcg(i, f, 1e-10)
         assert st == 0 and info.converged
         assert np.linalg.norm(f - A @ u) / np.linalg.norm(f) <= 1e-10
-    assert bad <= max(1, total // 50), (bad, total)
+    assert bad <= total // 50, (bad, total)
     bt.close()
 
 

@@ -6,10 +6,12 @@ Tolerances:
     kappa <= 1e5 on these grids, u = 1.1e-16).
   * Mixed precision at eps = 0: the factor is an FP32 Cholesky, error ~
     kappa(A) * u32 * growth; bound 2e-3 on the small grids used here.
-  * eps > 0: skeleton sets can differ on near ties (several answers are
-    correct), so ranks are compared face by face with a small allowed
-    fraction of mismatches, and the preconditioned solves are compared after
-    PCG to 1e-12 (|u - u_oracle| / |u_oracle| <= 1e-9).
+  * eps > 0: skeleton sets could differ on near ties (several answers are
+    correct), so every face whose rank differs from the oracle's is counted
+    and at least 98% must match exactly (on these tie-free inputs all do);
+    where the skeletons coincide the applies agree element by element (FP64:
+    1e-11 relative to max |F^{-1} f|), and PCG solutions driven to 1e-13
+    agree to 1e-10.
 """
 import numpy as np
 import pytest
@@ -129,17 +131,18 @@ def test_eps_ranks_match_oracle(gpu_lib, n, leaf, eps):
         ranks, sizes = gpu_lib.hif_factor_ranks(g.F, level)
         assert list(sizes) == lev.face_sizes
         total += len(ranks)
-        bad += int(np.sum(np.abs(np.array(ranks) - np.array(lev.face_ranks)) > 1))
-    assert bad <= max(1, total // 50), (bad, total)
+        bad += int(np.sum(np.array(ranks) != np.array(lev.face_ranks)))
+    assert bad <= total // 50, (bad, total)
     st = g.stats()
-    assert abs(st["root_size"] - fac.root_size) <= max(3, fac.root_size // 50)
+    assert abs(st["root_size"] - fac.root_size) <= fac.root_size // 50
     g.close()
 
 
 @pytest.mark.parametrize("n,leaf,eps", [(16, 4, 1e-6), (32, 8, 1e-4)])
 def test_apply_close_to_oracle(gpu_lib, n, leaf, eps):
-    """eps > 0: both F^{-1} approximate A^{-1} to O(eps); they agree far better
-    than that when the skeletons coincide."""
+    """eps > 0: both F^{-1} approximate A^{-1} to O(eps); with the same
+    skeletons they agree element by element to rounding (1e-11 relative to
+    max |F^{-1} f|), and the GPU's e_s is the oracle's."""
     a = log_uniform_field(n, -1, 1, 121)
     b = const_field(n, 0.0)
     f = normal_rhs(n, 122)
@@ -147,13 +150,13 @@ def test_apply_close_to_oracle(gpu_lib, n, leaf, eps):
     g = GpuHif(gpu_lib, n, leaf, eps, a, b)
     u = g.apply(f)
     uo = O.apply_inverse(fac, f)
-    d = np.linalg.norm(u - uo) / np.linalg.norm(uo)
+    d = np.abs(u - uo).max() / np.abs(uo).max()
     A = O.assemble(n, a, b)
     x = normal_rhs(n, 123)
     es_gpu = np.linalg.norm(x - g.apply(A @ x)) / np.linalg.norm(x)
     es_or = O.relative_solve_error(fac, A, x)
-    assert d <= 50 * eps, d
-    assert es_gpu <= 3 * es_or + 1e-12, (es_gpu, es_or)
+    assert d <= 1e-11, d
+    assert abs(es_gpu - es_or) <= 1e-6 * es_or, (es_gpu, es_or)
     g.close()
 
 
@@ -311,8 +314,8 @@ def test_coarse_eps_degenerate_skeletons(gpu_lib, prec):
         ranks, sizes = gpu_lib.hif_factor_ranks(g.F, level)
         r_gpu, r_orc = np.array(ranks), np.array(lev.face_ranks)
         total += len(ranks)
-        bad += int(np.sum(np.abs(r_gpu - r_orc) > 1))
-    assert bad <= max(1, total // 50), (bad, total)
+        bad += int(np.sum(r_gpu != r_orc))
+    assert bad <= total // 50, (bad, total)
     f = normal_rhs(n, 213)
     st, info, u = g.pcg(f, 1e-10, maxit=300)
     assert st == 0 and info.converged

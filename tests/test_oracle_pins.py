@@ -311,3 +311,101 @@ def test_edge_columns_are_orthogonal(n, leaf):
             assert np.all(norms > 1e-4 * norms.max())
             checked += 1
     assert checked > 0
+
+
+@pytest.mark.parametrize("n,m", [(8, 2), (12, 3), (16, 4), (32, 8)])
+def test_face_sizes_closed_form(n, m):
+    """At eps = 0 every face point stays active, so level l has 3 (nc-1) nc^2
+    faces (nc = n / w cells per dimension, w = m 2^l) and a face spans, along
+    each of its two in-plane dimensions, the w points of a first cell (the
+    plane x = 0 is no separator) or the w - 1 points of any other cell.  The
+    sizes are listed in the face order of the C ABI: normal d, plane j >= 1,
+    then the slower and the faster in-plane cell index."""
+    fac = O.build(n, m, log_uniform_field(n, -1, 1, 5), const_field(n, 0.0), 0.0)
+    for level, lev in enumerate(fac.levels):
+        w = m << level
+        nc = n // w
+
+        def width(i):
+            return w if i == 0 else w - 1
+        expect = [width(i_lo) * width(i_hi) for d in range(3) for j in range(1, nc)
+                  for i_hi in range(nc) for i_lo in range(nc)]
+        assert len(expect) == 3 * (nc - 1) * nc * nc
+        assert lev.face_sizes == expect
+        assert lev.face_ranks == expect
+
+
+@pytest.mark.parametrize("n,m,eps", [(6, 3, 1e-3), (8, 2, 1e-3), (8, 4, 1e-2)])
+def test_power_norm_error_vs_dense(n, m, eps):
+    """The power-method estimate of ||I - F^{-1}A||_2 equals the largest
+    singular value of the dense matrix I - F^{-1}A, formed column by column
+    from the sweeps, and never exceeds it (the method converges from below)."""
+    a = log_uniform_field(n, -1, 1, 9)
+    b = const_field(n, 0.0)
+    fac = O.build(n, m, a, b, eps)
+    A = O.assemble(n, a, b)
+    N = n ** 3
+    Finv = np.stack([O.apply_inverse(fac, e) for e in np.eye(N)], axis=1)
+    sigma = np.linalg.norm(np.eye(N) - Finv @ A.toarray(), 2)
+    est = O.power_norm_error(fac, A, iters=40)
+    assert est <= sigma * (1 + 1e-10)
+    assert est >= sigma * (1 - 1e-6), (est, sigma)
+
+
+def test_active_after_counts():
+    """The active set after level l keeps exactly the points not eliminated
+    as interiors and not left out as redundant face points up to l; at the
+    last level it is the root."""
+    n, m = 16, 4
+    fac = O.build(n, m, log_uniform_field(n, -2, 2, 17), const_field(n, 0.0), 1e-3)
+    left = n ** 3
+    for level, lev in enumerate(fac.levels):
+        left -= sum(len(c.I) for c in lev.cells) + sum(len(f.chk) for f in lev.faces)
+        assert int(O.active_after(fac, level).sum()) == left
+    assert np.array_equal(np.flatnonzero(O.active_after(fac, len(fac.levels) - 1)), fac.root)
+
+
+# --- GMRES (Section 4: the paper's Krylov solver) ---------------------------
+
+def test_gmres_distinct_eigenvalues():
+    """Unpreconditioned GMRES on a diagonal matrix with k distinct eigenvalues
+    reaches the exact solution in exactly k steps (the minimal polynomial of
+    A has degree k); one step fewer leaves a residual far above tol."""
+    import scipy.sparse as sp
+    vals = np.repeat([1.0, 2.0, 3.5, 7.0, 11.0], 20)
+    A = sp.diags(vals).tocsr()
+    f = np.random.default_rng(81).standard_normal(len(vals))
+    u, its, rel, ok = O.gmres(A, lambda r: r, f, 1e-12, restart=50, maxit=50)
+    assert ok and its == 5 and rel <= 1e-12
+    assert np.allclose(u, f / vals, rtol=1e-12, atol=0)
+    _, its4, rel4, ok4 = O.gmres(A, lambda r: r, f, 1e-12, restart=50, maxit=4)
+    assert not ok4 and its4 == 4 and rel4 > 1e-6
+
+
+def test_gmres_exact_preconditioner_one_step():
+    """At eps = 0 F^{-1} = A^{-1}: GMRES with it converges in one step."""
+    n, m = 8, 2
+    a = log_uniform_field(n, -2, 2, 83)
+    b = const_field(n, 0.0)
+    A = O.assemble(n, a, b)
+    fac = O.build(n, m, a, b, 0.0)
+    f = np.random.default_rng(84).standard_normal(n ** 3)
+    u, its, rel, ok = O.gmres(A, lambda r: O.apply_inverse(fac, r), f, 1e-12)
+    assert ok and its == 1 and rel <= 1e-12
+
+
+@pytest.mark.parametrize("restart", [50, 2])
+def test_gmres_matches_direct_solve(restart):
+    """With the eps = 1e-2 HIF as preconditioner GMRES (also restarted every
+    two steps) reaches 1e-12 and the direct solution."""
+    n, m = 16, 4
+    a = log_uniform_field(n, -2, 2, 85)
+    b = const_field(n, 0.0)
+    A = O.assemble(n, a, b)
+    fac = O.build(n, m, a, b, 1e-2)
+    f = np.random.default_rng(86).standard_normal(n ** 3)
+    u, its, rel, ok = O.gmres(A, lambda r: O.apply_inverse(fac, r), f, 1e-12, restart, 300)
+    assert ok and rel <= 1e-12
+    assert np.linalg.norm(f - A @ u) <= 1e-12 * np.linalg.norm(f)
+    ud = spla.spsolve(A.tocsc(), f)
+    assert np.linalg.norm(u - ud) <= 1e-9 * np.linalg.norm(ud)
