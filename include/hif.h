@@ -147,6 +147,22 @@ hif_status hif_build_batched(int32_t count, const hif_problem_t* A, const hif_op
  * (exactly, not partly).  Asynchronous on `stream`.  nrhs = 0 is a no-op. */
 hif_status hif_apply(hif_factor_t F, const double* f, double* u, int32_t nrhs, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): u = F^{-1} f
+ * for one vector, exactly as hif_apply with nrhs = 1 (same kernels, same
+ * result bit for bit), but with every scratch vector of the sweeps in a
+ * static device array of the library (64 MiB per GPU, held from the first
+ * call on a GPU until the process ends) instead of the factor's own buffers.
+ * No device memory is allocated or freed.  The scratch needed is at most
+ * about 26 bytes per unknown (the 128^3 problem with 8^3 leaves needs at
+ * most 53 MiB); a factor that needs more than 64 MiB returns HIF_EINVAL,
+ * with the size it needs in hif_last_error(), and nothing is launched.  Every
+ * call on a GPU shares that GPU's array: calls that overlap in time on one
+ * GPU (several streams or threads) race and give wrong results.  The array
+ * keeps the last call's contents; the sweeps write every entry before they
+ * read it.  u may alias f (exactly).  Asynchronous on `stream`. */
+hif_status hif_apply_noalloc(hif_factor_t F, const double* f, double* u, void* stream);
+
 /* y = A x for nrhs column-major vectors, FP64: the 7-point operator of
  * hif_problem_create (paper, Section 2.4, seven-point stencil), one thread
  * per grid point.  x and y must not alias.  Asynchronous. */

@@ -177,6 +177,14 @@ hif_status hif_apply(hif_factor_t F, const double* f, double* u, int32_t nrhs, v
   });
 }
 
+hif_status hif_apply_noalloc(hif_factor_t F, const double* f, double* u, void* stream) {
+  return guarded([&] {
+    HIF_REQUIRE(F != nullptr && F->impl, HIF_EINVAL, "NULL factor");
+    HIF_REQUIRE(f != nullptr && u != nullptr, HIF_EINVAL, "NULL vector");
+    hif::apply_noalloc(F, f, u, as_stream(stream));
+  });
+}
+
 hif_status hif_matvec(hif_problem_t A, const double* x, double* y, int32_t nrhs, void* stream) {
   return guarded([&] {
     HIF_REQUIRE(A != nullptr, HIF_EINVAL, "NULL problem");

@@ -87,6 +87,12 @@ struct FactorBase {
   virtual ~FactorBase() = default;
   std::shared_ptr<PcgCache> pcg;
   virtual void apply(const double* f, double* u, hipStream_t s) = 0;
+  // apply() with its scratch vectors carved out of `scratch` (cap doubles,
+  // 256-byte aligned) instead of the factor's own; allocates nothing.
+  virtual void apply_scratch(const double* f, double* u, double* scratch, int64_t cap,
+                             hipStream_t s) = 0;
+  // doubles of scratch apply_scratch needs
+  virtual int64_t scratch_doubles() const = 0;
   // u = F^{-1} f for nrhs column-major vectors (leading dimension N) at once.
   virtual void apply_block(const double* f, double* u, int nrhs, hipStream_t s) = 0;
   // algorithmic HBM bytes of one single-vector apply (profiler)
@@ -121,6 +127,9 @@ struct FactorImpl : FactorBase {
   // Sweep descriptors and scratch of the apply (idempotent).
   void prepare(hipStream_t s);
   void apply(const double* f, double* u, hipStream_t s) override;
+  void apply_scratch(const double* f, double* u, double* scratch, int64_t cap,
+                     hipStream_t s) override;
+  int64_t scratch_doubles() const override;
   // The single-vector sweeps on the given scratch segments: xi, yv (ymax
   // each), zv, xsv (zmax each), sh (kmax), sc, sc2 (rmax each).
   void sweep(const double* f, double* u, double* xi, double* yv, double* zv, double* xsv,
@@ -188,6 +197,11 @@ void factor_error(const hif_problem_s* A, hif_factor_s* F, const double* x, int 
 // in a fixed reduction order.
 void device_dot(const double* a, const double* b, const double* c, int64_t N, double* out,
                 hipStream_t s);
+
+// u = F^{-1} f with every scratch vector in the library's static device
+// array (one per GPU, kNoAllocScratchBytes); allocates nothing.
+void apply_noalloc(hif_factor_s* F, const double* f, double* u, hipStream_t s);
+constexpr int64_t kNoAllocScratchBytes = int64_t(64) << 20;
 
 // Restarted flexible GMRES(restart) with F^{-1} as a right preconditioner,
 // from u = 0, to a true relative residual <= tol (info->iters counts Arnoldi

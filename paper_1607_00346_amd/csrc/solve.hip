@@ -953,6 +953,39 @@ void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
         sc + rmax, s);
 }
 
+// Scratch segments of apply_scratch, each starting on a 256-byte boundary.
+inline int64_t seg_round(int64_t n) { return (n + 31) / 32 * 32; }
+
+template <typename T>
+int64_t FactorImpl<T>::scratch_doubles() const {
+  return 2 * seg_round(ymax) + 2 * seg_round(zmax) + seg_round(kmax) + 2 * seg_round(rmax);
+}
+
+template <typename T>
+void FactorImpl<T>::apply_scratch(const double* f, double* u, double* scratch, int64_t cap,
+                                  hipStream_t s) {
+  HIF_REQUIRE(prepared, HIF_EINVAL, "factor has no sweep descriptors");
+  const int64_t need = scratch_doubles();
+  HIF_REQUIRE(need <= cap, HIF_EINVAL,
+              "this factor's apply needs " + std::to_string((need * 8 + (1 << 20) - 1) >> 20) +
+                  " MiB of scratch, more than the " + std::to_string((cap * 8) >> 20) +
+                  " MiB available without allocation");
+  double* p = scratch;
+  auto take = [&](int64_t n) {
+    double* q = p;
+    p += seg_round(n);
+    return q;
+  };
+  double* xi = take(ymax);
+  double* yv = take(ymax);
+  double* zv = take(zmax);
+  double* xsv = take(zmax);
+  double* sh = take(kmax);
+  double* sc = take(rmax);
+  double* sc2 = take(rmax);
+  sweep(f, u, xi, yv, zv, xsv, sh, sc, sc2, s);
+}
+
 template <typename T>
 void FactorImpl<T>::sweep(const double* f, double* u, double* xi, double* yv, double* zv,
                           double* xsv, double* sh, double* sc, double* sc2, hipStream_t s) {
@@ -1264,7 +1297,44 @@ template void FactorImpl<double>::prepare(hipStream_t);
 template void FactorImpl<float>::prepare(hipStream_t);
 template void FactorImpl<double>::apply(const double*, double*, hipStream_t);
 template void FactorImpl<float>::apply(const double*, double*, hipStream_t);
+template void FactorImpl<double>::apply_scratch(const double*, double*, double*, int64_t,
+                                                hipStream_t);
+template void FactorImpl<float>::apply_scratch(const double*, double*, double*, int64_t,
+                                               hipStream_t);
+template int64_t FactorImpl<double>::scratch_doubles() const;
+template int64_t FactorImpl<float>::scratch_doubles() const;
 
+// Scratch of apply_noalloc: every GPU the library runs on holds its own copy
+// of this array until the process ends.  Host code never passes the array's
+// name to a kernel (on the host it is a stand-in, not a device address): the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+namespace {
+
+double* scratch_on_current_device() {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* ptr[kMaxDevices] = {};
+  int dev = 0;
+  HIF_HIP(hipGetDevice(&dev));
+  HIF_REQUIRE(dev >= 0 && dev < kMaxDevices, HIF_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    HIF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    HIF_REQUIRE(p != nullptr, HIF_EDEVICE, "no device address for the scratch array");
+    ptr[dev] = static_cast<double*>(p);
+  }
+  return ptr[dev];
+}
+
+}  // namespace
+
+void apply_noalloc(hif_factor_s* F, const double* f, double* u, hipStream_t s) {
+  double* p = scratch_on_current_device();
+  F->impl->apply_scratch(f, u, p, kNoAllocScratchBytes / (int64_t)sizeof(double), s);
+}
 template void FactorImpl<double>::apply_block(const double*, double*, int, hipStream_t);
 template double FactorImpl<double>::apply_bytes() const;
 template double FactorImpl<float>::apply_bytes() const;

@@ -19,7 +19,7 @@ HIF_DIRICHLET = 0
 HIF_MAX_LEVELS = 16
 
 EXPORTED = [
-    "hif_problem_create", "hif_build", "hif_build_batched", "hif_apply",
+    "hif_problem_create", "hif_build", "hif_build_batched", "hif_apply", "hif_apply_noalloc",
     "hif_matvec", "hif_pcg", "hif_gmres", "hif_pcg_batched",
     "hif_factor_stats", "hif_factor_ranks", "hif_factor_active", "hif_factor_error",
     "hif_factor_destroy",
@@ -100,6 +100,7 @@ def lib():
         L.hif_build_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(hif_options), vp,
                                         ctypes.POINTER(vp)]
         L.hif_apply.argtypes = [vp, vp, vp, i32, vp]
+        L.hif_apply_noalloc.argtypes = [vp, vp, vp, vp]
         L.hif_matvec.argtypes = [vp, vp, vp, i32, vp]
         L.hif_pcg.argtypes = [vp, vp, vp, vp, i32, f64, i32, ctypes.POINTER(hif_pcg_info), vp]
         L.hif_gmres.argtypes = [vp, vp, vp, vp, f64, i32, i32, ctypes.POINTER(hif_pcg_info), vp]
@@ -124,7 +125,7 @@ def lib():
         L.hif_status_string.restype = ctypes.c_char_p
         L.hif_last_error.restype = ctypes.c_char_p
         for name in ("hif_problem_create", "hif_build", "hif_build_batched", "hif_apply",
-                     "hif_gmres",
+                     "hif_apply_noalloc", "hif_gmres",
                      "hif_matvec", "hif_pcg", "hif_pcg_batched", "hif_factor_stats",
                      "hif_factor_ranks", "hif_factor_active", "hif_factor_error",
                      "hif_profile_begin", "hif_profile_end", "hif_profile_select",
@@ -187,6 +188,11 @@ def hif_build_batched(problems, opts, stream=None):
 
 def hif_apply(F, f, u, nrhs: int = 1, stream=None):
     _check(lib().hif_apply(F, _dptr(f), _dptr(u), int(nrhs), _stream(stream)), "hif_apply")
+
+
+def hif_apply_noalloc(F, f, u, stream=None):
+    """u = F^{-1} f (one vector) with the library's static scratch: no allocation."""
+    _check(lib().hif_apply_noalloc(F, _dptr(f), _dptr(u), _stream(stream)), "hif_apply_noalloc")
 
 
 def hif_matvec(A, x, y, nrhs: int = 1, stream=None):
