@@ -4,9 +4,11 @@
  *
  *     -div(a(x) grad u(x)) + b(x) u(x) = f(x)          (paper, eq. 1.1)
  *
- * discretized by the 7-point stencil on an n x n x n interior grid
- * (paper, Section 2.4, "seven-point stencil") with zero Dirichlet values
- * outside, grid spacing h = 1/(n+1) and harmonic-mean edge coefficients.
+ * discretized by the 7-point stencil (paper, Section 2.4, "seven-point
+ * stencil") with harmonic-mean edge coefficients on an n x n x n grid,
+ * either with zero Dirichlet values outside an interior grid (h = 1/(n+1))
+ * or periodic on [0,1)^3 as in the paper (Section 2.1: h = 1/n, indices
+ * wrap around).
  *
  * The factorization follows the paper's sequential HIF (Section 2.4) with
  * the distributed version's face snapshot (Section 3.2): for each level
@@ -60,7 +62,7 @@ typedef enum {
 } hif_status;
 
 enum { HIF_FP64 = 0, HIF_MIXED = 1 };  /* factor precision                        */
-enum { HIF_DIRICHLET = 0 };            /* boundary condition                      */
+enum { HIF_DIRICHLET = 0, HIF_PERIODIC = 1 };  /* boundary condition           */
 
 #define HIF_MAX_LEVELS 16
 
@@ -76,7 +78,12 @@ typedef struct {
   int32_t precision; /* HIF_FP64: all front work in FP64.  HIF_MIXED: fronts,
                         Schur updates and skeleton algebra in FP32; ID pivot
                         decisions (Gram + pivoted Cholesky) in FP64.             */
-  int32_t bc;        /* HIF_DIRICHLET (the only one implemented)                  */
+  int32_t bc;        /* HIF_DIRICHLET: zero values outside the grid; separators of
+                        level l are the planes x_d = w j, j >= 1 (w = leaf 2^l).
+                        HIF_PERIODIC (n >= 4): the paper's setting; every plane
+                        x_d = w j, j >= 0, below the root is a separator, the
+                        faces on x_d = 0 joining the last and the first cell.
+                        A must be positive definite (periodic: b > 0 somewhere). */
 } hif_options;
 
 typedef struct {      /* result of hif_pcg, hif_pcg_batched and hif_gmres        */
@@ -218,8 +225,8 @@ hif_status hif_pcg_batched(int32_t count, const hif_problem_t* A, const hif_fact
 hif_status hif_factor_stats(hif_factor_t F, hif_stats* out);
 
 /* Rank k of every face of `level` in face order (faces enumerated by
- * (normal d, plane j_d >= 1, then the other two cell indices, slowest
- * first)), and the face sizes |F| (host arrays of `cap` entries; either
+ * (normal d, plane j_d (>= 1 Dirichlet, >= 0 periodic), then the other two
+ * cell indices, slowest first)), and the face sizes |F| (host arrays of `cap` entries; either
  * may be NULL).  *count receives the number of faces. */
 hif_status hif_factor_ranks(hif_factor_t F, int32_t level, int32_t* ranks, int32_t* sizes,
                             int32_t cap, int32_t* count);

@@ -45,6 +45,33 @@ def cholesky(A: np.ndarray) -> np.ndarray:
     return L
 
 
+def ldl_signed(A: np.ndarray):
+    """Unpivoted symmetric factorization A = L S L^T of a symmetric A whose
+    leading principal minors are nonzero: S = diag(+-1), L lower triangular
+    with a positive diagonal.  This is the LDL^T factorization the paper
+    uses (unit-diagonal factor times D, Section 2.2), stored as
+    L = L_unit |D|^{1/2} and S = sign(D).  Column j from the definition:
+        d_j    = A[j,j] - sum_{t<j} L[j,t]^2 S[t]
+        S[j]   = sign(d_j),  L[j,j] = sqrt(|d_j|)
+        L[i,j] = (A[i,j] - sum_{t<j} L[i,t] S[t] L[j,t]) / (S[j] L[j,j]),  i > j.
+    Only the lower triangle of A is read.  Raises NotSPD (naming the column)
+    on a zero pivot.  For a positive definite A it is the Cholesky factor
+    (every S[j] = +1)."""
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    L = np.zeros((n, n))
+    S = np.zeros(n)
+    for j in range(n):
+        d = A[j, j] - (L[j, :j] * S[:j]) @ L[j, :j]
+        if d == 0.0 or not np.isfinite(d):
+            raise NotSPD(j, float(d))
+        S[j] = 1.0 if d > 0.0 else -1.0
+        L[j, j] = np.sqrt(abs(d))
+        if j + 1 < n:
+            L[j + 1:, j] = (A[j + 1:, j] - L[j + 1:, :j] @ (S[:j] * L[j, :j])) / (S[j] * L[j, j])
+    return L, S
+
+
 def _as2d(B):
     B = np.asarray(B, dtype=np.float64)
     return (B[:, None], True) if B.ndim == 1 else (B, False)

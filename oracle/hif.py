@@ -9,8 +9,10 @@ DHIF reading of skeletonization (Section 3.2: every face of a level is
 skeletonized from the same matrix after all sparse eliminations):
 
   * the operator A is the 7-point discretization of -div(a grad u) + b u
-    (eq. "seven-point stencil"), here with zero Dirichlet values outside an
-    n^3 interior grid, h = 1/(n+1) and harmonic-mean edge coefficients;
+    (eq. "seven-point stencil") with harmonic-mean edge coefficients, either
+    with zero Dirichlet values outside an n^3 interior grid (h = 1/(n+1)) or
+    periodic on [0,1)^3 as in the paper (Section 2.1: h = 1/n, indices
+    wrap around);
   * level l = 0..L-1: sparse elimination of every cell interior I (Section
     2.2), giving Ã^l; then skeletonization of every face F by an
     interpolative decomposition of Ã^l(R, F) (Section 2.3);
@@ -21,9 +23,15 @@ inactive points are empty; the shells S of interiors and the row sets R of
 faces are read off its sparsity structure rather than from geometry.
 
 Readings where the paper is silent (all listed in the design notes):
-  - LDL^T is replaced by Cholesky (D = I); F^{-1} is unchanged.
+  - LDL^T is replaced by Cholesky (D = I); F^{-1} is unchanged.  The one
+    exception is the root of a periodic problem: there the compressed
+    matrix can lose definiteness along the near-null (constant) mode, and
+    the root keeps the paper's LDL^T, stored as L S L^T with S = sign(D).
   - Dirichlet layout: the plane x_d = 0 is not a separator; separators of
     level l are the coordinates x_d = w j with j >= 1, w = leaf * 2^l.
+    Periodic layout (the paper's, Section 2.1): every x_d = w j, j >= 0, is
+    a separator, and the face on x_d = 0 lies between the last and the
+    first cell along d.
   - "relative precision eps" of the ID: k = #{i : |R_ii| > eps |R_11|} from
     column-pivoted QR; eps = 0 skips the ID (exact nested dissection).
   - W^l = (prod_I S_I)(prod_F Q_F S_F̌), F^{-1} = W^0 ... W^L W^L^T ... W^0^T.
@@ -35,21 +43,26 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.sparse as sp
 
-from .dense import cholesky, interp_decomp, solve_lower, solve_lower_t
+from .dense import cholesky, interp_decomp, ldl_signed, solve_lower, solve_lower_t
 
 
 # ---------------------------------------------------------------------------
 # Operator (Section 2.4, seven-point stencil)
 # ---------------------------------------------------------------------------
 
-def assemble(n: int, a: np.ndarray, b: np.ndarray) -> sp.csr_matrix:
-    """7-point operator on the n^3 interior grid, natural order x1 fastest.
+def assemble(n: int, a: np.ndarray, b: np.ndarray, bc: str = "dirichlet") -> sp.csr_matrix:
+    """7-point operator on the n^3 grid, natural order x1 fastest.
 
     Row j: (1/h^2) sum_e a_e (u_j - u_k) + b_j u_j over the six neighbours k,
-    where a_e is the harmonic mean 2 a_j a_k / (a_j + a_k) for a neighbour
-    inside the grid, and a_j for an edge to the zero Dirichlet ghost outside.
-    h = 1/(n+1).
+    where a_e is the harmonic mean 2 a_j a_k / (a_j + a_k).
+    bc = "dirichlet": h = 1/(n+1); an edge to the zero ghost outside the grid
+    uses a_j.  bc = "periodic": h = 1/n and neighbour indices wrap around
+    (x = n-1 couples to x = 0).
     """
+    if bc == "periodic":
+        return _assemble_periodic(n, a, b)
+    if bc != "dirichlet":
+        raise ValueError(f"unknown boundary condition {bc!r}")
     N = n ** 3
     a = np.asarray(a, dtype=np.float64).reshape(n, n, n)  # axes (x3, x2, x1)
     b = np.asarray(b, dtype=np.float64).reshape(n, n, n)
@@ -84,6 +97,35 @@ def assemble(n: int, a: np.ndarray, b: np.ndarray) -> sp.csr_matrix:
     return A.tocsr()
 
 
+def _assemble_periodic(n: int, a: np.ndarray, b: np.ndarray) -> sp.csr_matrix:
+    """The periodic operator: every grid point has six neighbours, the edge
+    between j and its wrapped neighbour k carrying 2 a_j a_k / (a_j + a_k) / h^2
+    with h = 1/n.  Duplicate entries (n = 2: both neighbours along a
+    dimension are the same point) are summed."""
+    N = n ** 3
+    a = np.asarray(a, dtype=np.float64).reshape(n, n, n)
+    b = np.asarray(b, dtype=np.float64).reshape(n, n, n)
+    h2 = 1.0 / n ** 2
+    idx = np.arange(N).reshape(n, n, n)
+    diag = b.copy()
+    rows, cols, vals = [], [], []
+    for axis in (2, 1, 0):
+        ak = np.roll(a, -1, axis=axis)        # the +1 neighbour along axis, wrapped
+        kk = np.roll(idx, -1, axis=axis)
+        ae = 2.0 * a * ak / (a + ak) / h2
+        diag += ae
+        diag += np.roll(ae, 1, axis=axis)     # the edge to the -1 neighbour
+        rows += [idx.ravel(), kk.ravel()]
+        cols += [kk.ravel(), idx.ravel()]
+        vals += [-ae.ravel(), -ae.ravel()]
+    rows.append(idx.ravel())
+    cols.append(idx.ravel())
+    vals.append(diag.ravel())
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(N, N))
+    return A.tocsr()
+
+
 def energy(n: int, a: np.ndarray, b: np.ndarray, x: np.ndarray) -> float:
     """x^T A x written as a sum over grid edges (used as an independent check)."""
     a = np.asarray(a, dtype=np.float64).reshape(n, n, n)
@@ -106,9 +148,16 @@ def energy(n: int, a: np.ndarray, b: np.ndarray, x: np.ndarray) -> float:
 # ---------------------------------------------------------------------------
 
 class Geometry:
-    """n = leaf * 2^L grid with level-l cells of width w = leaf * 2^l."""
+    """n = leaf * 2^L grid with level-l cells of width w = leaf * 2^l.
 
-    def __init__(self, n: int, leaf: int):
+    Dirichlet: the separators of level l are x_d = w j with j >= 1.
+    Periodic: every x_d = w j (j >= 0) is a separator, and the face on the
+    plane j lies between cell j - 1 (mod n / w) and cell j."""
+
+    def __init__(self, n: int, leaf: int, bc: str = "dirichlet"):
+        if bc not in ("dirichlet", "periodic"):
+            raise ValueError(f"unknown boundary condition {bc!r}")
+        self.periodic = bc == "periodic"
         if leaf < 2 or n < leaf:
             raise ValueError("need leaf >= 2 and n >= leaf")
         L = 0
@@ -129,7 +178,12 @@ class Geometry:
         interior point, and the id of the face holding a face point."""
         w = self.width(level)
         nc = self.n // w
-        sep = [(x % w == 0) & (x != 0) for x in self.coords]
+        if self.periodic:
+            sep = [(x % w == 0) for x in self.coords]
+            planes, first = nc, 0
+        else:
+            sep = [(x % w == 0) & (x != 0) for x in self.coords]
+            planes, first = nc - 1, 1
         c = sep[0].astype(np.int64) + sep[1] + sep[2]
         cidx = [x // w for x in self.coords]
         cell = (cidx[2] * nc + cidx[1]) * nc + cidx[0]
@@ -137,15 +191,15 @@ class Geometry:
         for d in range(3):
             o1, o2 = [e for e in range(3) if e != d]
             on = sep[d] & (c == 1)
-            fid = ((d * (nc - 1) + (cidx[d] - 1)) * nc + cidx[o2]) * nc + cidx[o1]
+            fid = ((d * planes + (cidx[d] - first)) * nc + cidx[o2]) * nc + cidx[o1]
             face[on] = fid[on]
         return c, cell, face
 
 
-def count_levels(n: int, leaf: int):
+def count_levels(n: int, leaf: int, bc: str = "dirichlet"):
     """Points that first become interior at each level, and the points left
     for the root, read off the classification (eps = 0 elimination counts)."""
-    g = Geometry(n, leaf)
+    g = Geometry(n, leaf, bc)
     seen = np.zeros(n ** 3, dtype=bool)
     out = []
     for level in range(g.L):
@@ -197,6 +251,8 @@ class Factor:
     levels: list
     root: np.ndarray
     Lroot: np.ndarray
+    bc: str = "dirichlet"
+    Sroot: np.ndarray = None   # signs of the root's LDL^T (None: Cholesky, all +1)
 
     @property
     def root_size(self) -> int:
@@ -240,11 +296,12 @@ def _groups(ids: np.ndarray, mask: np.ndarray):
             if len(p)]
 
 
-def build(n: int, leaf: int, a: np.ndarray, b: np.ndarray, eps: float) -> Factor:
+def build(n: int, leaf: int, a: np.ndarray, b: np.ndarray, eps: float,
+          bc: str = "dirichlet") -> Factor:
     """Factor A ~= F level by level (Section 2.4 with the Section 3.2 face snapshot)."""
-    geo = Geometry(n, leaf)
+    geo = Geometry(n, leaf, bc)
     N = n ** 3
-    A = assemble(n, a, b)
+    A = assemble(n, a, b, bc)
     active = np.ones(N, dtype=bool)
     levels = []
     for level in range(geo.L):
@@ -299,8 +356,12 @@ def build(n: int, leaf: int, a: np.ndarray, b: np.ndarray, eps: float) -> Factor
         A = (_restrict(At, active) + _blocks_to_csr(N, replace)).tocsr()
         levels.append(lev)
     root = np.nonzero(active)[0]
-    Lroot = cholesky(A.tocsr()[root][:, root].toarray())
-    return Factor(n, leaf, eps, levels, root, Lroot)
+    Aroot = A.tocsr()[root][:, root].toarray()
+    if bc == "periodic":
+        Lroot, Sroot = ldl_signed(Aroot)
+    else:
+        Lroot, Sroot = cholesky(Aroot), None
+    return Factor(n, leaf, eps, levels, root, Lroot, bc, Sroot)
 
 
 # ---------------------------------------------------------------------------
@@ -317,7 +378,10 @@ def apply_inverse(fac: Factor, f: np.ndarray) -> np.ndarray:
             x[ff.chk] -= ff.T.T @ x[ff.hat]
             x[ff.chk] = solve_lower(ff.Lc, x[ff.chk])
             x[ff.hat] -= ff.Y.T @ x[ff.chk]
-    x[fac.root] = solve_lower_t(fac.Lroot, solve_lower(fac.Lroot, x[fac.root]))
+    y = solve_lower(fac.Lroot, x[fac.root])                # W^L^T (then D^{-1} = S)
+    if fac.Sroot is not None:
+        y = fac.Sroot * y
+    x[fac.root] = solve_lower_t(fac.Lroot, y)
     for lev in reversed(fac.levels):                        # W^l, l = L-1..0
         for ff in lev.faces:                                # Q_F S_F̌
             x[ff.chk] = solve_lower_t(ff.Lc, x[ff.chk] - ff.Y @ x[ff.hat])

@@ -55,7 +55,9 @@ void check_options(const hif_options* o) {
               HIF_EINVAL, "eps must be 0 or in [1e-7, 1)");
   HIF_REQUIRE(o->precision == HIF_FP64 || o->precision == HIF_MIXED, HIF_EINVAL,
               "precision must be HIF_FP64 or HIF_MIXED");
-  HIF_REQUIRE(o->bc == HIF_DIRICHLET, HIF_EINVAL, "only HIF_DIRICHLET is implemented");
+  HIF_REQUIRE(o->bc == HIF_DIRICHLET || o->bc == HIF_PERIODIC, HIF_EINVAL,
+              "bc must be HIF_DIRICHLET or HIF_PERIODIC");
+  HIF_REQUIRE(o->bc != HIF_PERIODIC || o->n >= 4, HIF_EINVAL, "periodic grids need n >= 4");
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -91,7 +93,8 @@ hif_status hif_build(hif_problem_t A, const hif_options* opts, void* stream, hif
   return guarded([&] {
     HIF_REQUIRE(out != nullptr && A != nullptr, HIF_EINVAL, "NULL handle");
     check_options(opts);
-    HIF_REQUIRE(opts->n == A->n, HIF_EINVAL, "options describe another grid than the problem");
+    HIF_REQUIRE(opts->n == A->n && opts->bc == A->opts.bc, HIF_EINVAL,
+                "options describe another grid than the problem");
     hif::StreamScope scope(as_stream(stream));
     hif::Staging staging(as_stream(stream));  // synchronizes the stream when the build ends
     auto* F = new hif_factor_s();
@@ -120,7 +123,7 @@ hif_status hif_build_batched(int32_t count, const hif_problem_t* A, const hif_op
     for (int32_t i = 0; i < count; ++i) {
       HIF_REQUIRE(A[i] != nullptr, HIF_EINVAL, "NULL problem handle");
       check_options(&opts[i]);
-      HIF_REQUIRE(opts[i].n == A[i]->n, HIF_EINVAL,
+      HIF_REQUIRE(opts[i].n == A[i]->n && opts[i].bc == A[i]->opts.bc, HIF_EINVAL,
                   "options describe another grid than the problem");
       HIF_REQUIRE(opts[i].precision == opts[0].precision && opts[i].eps == opts[0].eps,
                   HIF_EINVAL, "the problems of a batch must share precision and eps");

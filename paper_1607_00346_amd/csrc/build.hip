@@ -38,6 +38,7 @@ struct Src {
 template <typename T>
 struct ColLookup {
   int q, fq;
+  int qx, qy, qz;  // grid coordinates of q (periodic stencil lookups)
   const T* pcol;
   int gface[kRowBlocks], goff[kRowBlocks];
 };
@@ -47,6 +48,10 @@ __device__ __forceinline__ ColLookup<T> col_lookup(const Src<T>& s, int q) {
   ColLookup<T> c;
   c.q = q;
   c.fq = s.has_prev ? s.pface[q] : -1;
+  const int n = s.st.n;
+  c.qx = q % n;
+  c.qy = (q / n) % n;
+  c.qz = q / (n * n);
   c.pcol = nullptr;
 #pragma unroll
   for (int t = 0; t < kRowBlocks; ++t) {
@@ -83,9 +88,20 @@ __device__ __forceinline__ T row_lookup(const Src<T>& s, const ColLookup<T>& c, 
   }
   const int q = c.q;
   if (p == q) return (T)s.st.diag[p];
+  const int n = s.st.n;
+  if (s.st.periodic) {
+    // neighbours along one dimension, the index wrapping around (n >= 4)
+    const int dx = c.qx - p % n, dy = c.qy - (p / n) % n, dz = c.qz - p / (n * n);
+    const double* cd = dy == 0 && dz == 0 ? s.st.cx
+                       : (dx == 0 && dz == 0 ? s.st.cy : (dx == 0 && dy == 0 ? s.st.cz : nullptr));
+    const int dd = cd == s.st.cx ? dx : (cd == s.st.cy ? dy : dz);
+    if (cd == nullptr) return T(0);
+    if (dd == 1 || dd == -(n - 1)) return (T)(-cd[p]);  // q is p's + neighbour
+    if (dd == -1 || dd == n - 1) return (T)(-cd[q]);    // p is q's + neighbour
+    return T(0);
+  }
   const int dl = q - p;
   const int lo = p < q ? p : q;
-  const int n = s.st.n;
   if (dl == 1 || dl == -1) return (T)(-s.st.cx[lo]);
   if (dl == n || dl == -n) return (T)(-s.st.cy[lo]);
   if (dl == n * n || dl == -n * n) return (T)(-s.st.cz[lo]);
@@ -175,8 +191,9 @@ __global__ __launch_bounds__(NT) void k_gather_panel(
   }
 }
 
-__device__ __forceinline__ int nsep(int x, int y, int z, int w) {
-  return (x % w == 0 && x != 0) + (y % w == 0 && y != 0) + (z % w == 0 && z != 0);
+__device__ __forceinline__ int nsep(int x, int y, int z, int w, int periodic) {
+  return (x % w == 0 && (periodic || x != 0)) + (y % w == 0 && (periodic || y != 0)) +
+         (z % w == 0 && (periodic || z != 0));
 }
 
 // Rows of edge points in Ã^l(R, F) hold one stencil coupling each, so they add
@@ -189,16 +206,25 @@ __global__ __launch_bounds__(NT) void k_gram_edges(Stencil st, int w, const int*
   const int f = blockIdx.y;
   const int j = blockIdx.x * NT + threadIdx.x;
   if (j >= fN[f]) return;
-  const int n = st.n;
+  const int n = st.n, per = st.periodic;
   const int q = fpts[fpt_off[f] + j];
-  const int x = q % n, y = (q / n) % n, z = q / (n * n);
+  const int c3[3] = {q % n, (q / n) % n, q / (n * n)};
+  const double* cd[3] = {st.cx, st.cy, st.cz};
   double add = 0.0;
-  if (x > 0 && nsep(x - 1, y, z, w) == 2) add += st.cx[q - 1] * st.cx[q - 1];
-  if (x < n - 1 && nsep(x + 1, y, z, w) == 2) add += st.cx[q] * st.cx[q];
-  if (y > 0 && nsep(x, y - 1, z, w) == 2) add += st.cy[q - n] * st.cy[q - n];
-  if (y < n - 1 && nsep(x, y + 1, z, w) == 2) add += st.cy[q] * st.cy[q];
-  if (z > 0 && nsep(x, y, z - 1, w) == 2) add += st.cz[q - n * n] * st.cz[q - n * n];
-  if (z < n - 1 && nsep(x, y, z + 1, w) == 2) add += st.cz[q] * st.cz[q];
+  for (int d = 0; d < 3; ++d) {
+    for (int dir = -1; dir <= 1; dir += 2) {
+      int nb[3] = {c3[0], c3[1], c3[2]};
+      nb[d] += dir;
+      if (nb[d] < 0 || nb[d] >= n) {
+        if (!per) continue;  // the Dirichlet ghost
+        nb[d] = (nb[d] + n) % n;
+      }
+      if (nsep(nb[0], nb[1], nb[2], w, per) != 2) continue;
+      const int r = nb[0] + n * nb[1] + n * n * nb[2];
+      const double v = dir > 0 ? cd[d][q] : cd[d][r];  // the coupling lives at the lower point
+      add += v * v;
+    }
+  }
   G[goff[f] + j + (int64_t)gld[f] * j] += add;
 }
 
@@ -430,7 +456,7 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
     st.n_dof = J.N;
     const hif_problem_s* A = J.A;
     if (A->geom_leaf != J.o.leaf) {
-      A->geom = plan_geometry(n, J.o.leaf);
+      A->geom = plan_geometry(n, J.o.leaf, A->opts.bc == HIF_PERIODIC);
       A->plan0 = std::make_shared<const LevelPlan>(
           plan_level(A->geom[0], std::vector<uint8_t>((size_t)J.N, 1)));
       A->dev0 = {};

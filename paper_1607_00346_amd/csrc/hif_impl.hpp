@@ -11,10 +11,13 @@
 
 namespace hif {
 
-// 7-point operator: A(p,p) = diag[p]; A(p, p+e_d) = -c_d[p] (c_d = 0 past the
-// last grid line, so the coupling across a wrapped index is always zero).
+// 7-point operator: A(p,p) = diag[p]; A(p, p+e_d) = -c_d[p].  Dirichlet:
+// c_d = 0 past the last grid line, so the coupling across a wrapped index is
+// always zero.  Periodic (n >= 4): at x_d = n-1, c_d[p] couples p to the
+// point with x_d = 0 on the same line.
 struct Stencil {
   int n;
+  int periodic;
   const double* diag;
   const double* cx;
   const double* cy;
@@ -157,7 +160,9 @@ struct hif_problem_s {
     hif::DevArr<int64_t> crow_off, fpt_off;
   };
   mutable Level0Arrays dev0;
-  hif::Stencil stencil() const { return {n, diag.get(), cx.get(), cy.get(), cz.get()}; }
+  hif::Stencil stencil() const {
+    return {n, opts.bc == HIF_PERIODIC ? 1 : 0, diag.get(), cx.get(), cy.get(), cz.get()};
+  }
 };
 
 struct hif_factor_s {

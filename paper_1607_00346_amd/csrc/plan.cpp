@@ -28,16 +28,25 @@ int64_t LevelPlan::sum_S() const {
 
 namespace {
 
-inline int face_id(int nc, int d, int plane, int i_lo, int i_hi) {
+// Faces per dimension: nc - 1 interior planes (Dirichlet: planes 1..nc-1) or
+// nc planes (periodic: planes 0..nc-1, plane 0 between cells nc-1 and 0).
+struct Planes {
+  int count, first;
+};
+inline Planes planes_of(int nc, bool periodic) {
+  return periodic ? Planes{nc, 0} : Planes{nc - 1, 1};
+}
+
+inline int face_id(const Planes& pl, int nc, int d, int plane, int i_lo, int i_hi) {
   // i_lo: cell index along the faster of the two other dimensions.
-  return ((d * (nc - 1) + (plane - 1)) * nc + i_hi) * nc + i_lo;
+  return ((d * pl.count + (plane - pl.first)) * nc + i_hi) * nc + i_lo;
 }
 
 inline int cell_id(int nc, int cx, int cy, int cz) { return (cz * nc + cy) * nc + cx; }
 
 }  // namespace
 
-std::vector<LevelGeom> plan_geometry(int n, int leaf) {
+std::vector<LevelGeom> plan_geometry(int n, int leaf, bool periodic) {
   const int L = levels_for(n, leaf);
   if (L < 0) throw std::invalid_argument("n must be leaf * 2^L");
   const int64_t N = (int64_t)n * n * n;
@@ -51,10 +60,13 @@ std::vector<LevelGeom> plan_geometry(int n, int leaf) {
     G.nc = n / G.w;
     G.root = level == L;
     const int w = G.w, nc = G.nc;
+    // the root level (one cell) has no separators in either layout
+    const bool per = periodic && !G.root;
+    const Planes pl = planes_of(nc, per);
     G.ncell = nc * nc * nc;
-    G.nface = 3 * (nc - 1) * nc * nc;
+    G.nface = G.root ? 0 : 3 * pl.count * nc * nc;
     for (int x = 0; x < n; ++x) {
-      sep[x] = (x % w == 0 && x != 0);
+      sep[x] = G.root ? 0 : (x % w == 0 && (per || x != 0));
       cidx[x] = x / w;
     }
     // candidates: points with no separator coordinate at any earlier level
@@ -68,8 +80,9 @@ std::vector<LevelGeom> plan_geometry(int n, int leaf) {
           const int64_t p = row + x;
           owner[p] = -1;
           if (level > 0) {
-            const bool sp = (x % wp == 0 && x != 0) || (y % wp == 0 && y != 0) ||
-                            (z % wp == 0 && z != 0);
+            const bool sp = (x % wp == 0 && (periodic || x != 0)) ||
+                            (y % wp == 0 && (periodic || y != 0)) ||
+                            (z % wp == 0 && (periodic || z != 0));
             if (!sp) continue;  // eliminated as an interior point at an earlier level
           }
           const int ns = sep[x] + sep[y] + sep[z];
@@ -81,7 +94,7 @@ std::vector<LevelGeom> plan_geometry(int n, int leaf) {
             const int c3[3] = {x, y, z};
             const int d = sep[x] ? 0 : (sep[y] ? 1 : 2);
             const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
-            const int id = face_id(nc, d, cidx[c3[d]], cidx[c3[o1]], cidx[c3[o2]]);
+            const int id = face_id(pl, nc, d, cidx[c3[d]], cidx[c3[o1]], cidx[c3[o2]]);
             owner[p] = -id - 2;
             ++cntF[id];
           }
@@ -111,9 +124,10 @@ std::vector<LevelGeom> plan_geometry(int n, int leaf) {
           for (int d = 0; d < 3; ++d) {
             const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
             for (int up = 0; up < 2; ++up) {
-              const int plane = cc[d] + up;
-              if (plane < 1 || plane > nc - 1) continue;
-              G.cface[(size_t)id * 6 + 2 * d + up] = face_id(nc, d, plane, cc[o1], cc[o2]);
+              int plane = cc[d] + up;
+              if (per) plane %= nc;
+              else if (G.root || plane < 1 || plane > nc - 1) continue;
+              G.cface[(size_t)id * 6 + 2 * d + up] = face_id(pl, nc, d, plane, cc[o1], cc[o2]);
             }
           }
         }
@@ -122,14 +136,14 @@ std::vector<LevelGeom> plan_geometry(int n, int leaf) {
     G.rb_face.assign((size_t)G.nface * kRowBlocks, -1);
     G.rb_slotA.assign((size_t)G.nface * kRowBlocks, -1);
     G.rb_slotB.assign((size_t)G.nface * kRowBlocks, -1);
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 0; d < 3 && !G.root; ++d) {
       const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
-      for (int plane = 1; plane < nc; ++plane)
+      for (int plane = pl.first; plane < pl.first + pl.count; ++plane)
         for (int ihi = 0; ihi < nc; ++ihi)
           for (int ilo = 0; ilo < nc; ++ilo) {
-            const int f = face_id(nc, d, plane, ilo, ihi);
+            const int f = face_id(pl, nc, d, plane, ilo, ihi);
             int ca[3], cb[3];
-            ca[d] = plane - 1;
+            ca[d] = (plane - 1 + nc) % nc;  // lower neighbour (wraps for plane 0)
             cb[d] = plane;
             ca[o1] = cb[o1] = ilo;
             ca[o2] = cb[o2] = ihi;
@@ -150,10 +164,18 @@ std::vector<LevelGeom> plan_geometry(int n, int leaf) {
               for (int s = 0; s < 6; ++s) {
                 const int g = G.cface[(size_t)cell * 6 + s];
                 if (s == skip || g < 0) continue;
-                G.rb_face[base + t] = g;
-                if (side == 0) G.rb_slotA[base + t] = s;
-                else G.rb_slotB[base + t] = s;
-                ++t;
+                // a face of both cells (periodic with two cells along d: the
+                // other plane between them) is one row block fed by both
+                int at = -1;
+                for (int u = 0; u < t; ++u)
+                  if (G.rb_face[base + u] == g) at = u;
+                if (at < 0) {
+                  at = t++;
+                  if (t > kRowBlocks) throw std::logic_error("face panel row blocks overflow");
+                  G.rb_face[base + at] = g;
+                }
+                if (side == 0) G.rb_slotA[base + at] = s;
+                else G.rb_slotB[base + at] = s;
               }
             }
           }
@@ -233,9 +255,10 @@ LevelPlan plan_level(const LevelGeom& G, const std::vector<uint8_t>& active) {
   return P;
 }
 
-LevelPlan plan_level(int n, int leaf, int level, int L, const std::vector<uint8_t>& active) {
+LevelPlan plan_level(int n, int leaf, int level, int L, const std::vector<uint8_t>& active,
+                     bool periodic) {
   (void)L;
-  const std::vector<LevelGeom> G = plan_geometry(n, leaf);
+  const std::vector<LevelGeom> G = plan_geometry(n, leaf, periodic);
   return plan_level(G[level], active);
 }
 

@@ -3,7 +3,10 @@
 // Level l cells have width w = leaf * 2^l (paper, Section 2.1).  With zero
 // Dirichlet values outside the grid, the separators of level l are the grid
 // planes x_d = w * j with j >= 1 (the plane x_d = 0 is not a separator and
-// there is none at x_d = n), so every face borders exactly two cells.  A point
+// there is none at x_d = n), so every face borders exactly two cells.  With
+// periodic boundaries (the paper's setting) every plane x_d = w * j, j >= 0,
+// is a separator; the face on x_d = 0 lies between the last and the first
+// cell along d, so again every face borders exactly two cells.  A point
 // with c separator coordinates is a cell interior point (c = 0), a face point
 // (c = 1), an edge point (c = 2) or a corner (c = 3).
 //
@@ -36,7 +39,7 @@ struct LevelPlan {
   std::vector<int> cface;      // ncell * 6: face id per slot or -1
   std::vector<int> cface_off;  // ncell * 6: offset of that face inside S or -1
 
-  // Faces enumerated by (normal d, plane j_d >= 1, index of the slower other
+  // Faces enumerated by (normal d, plane j_d (>= 1; periodic: >= 0), index of the slower other
   // dimension, index of the faster one).  fpts lists a face's active points
   // ascending.  Cell A is the lower neighbour along d, cell B the upper.
   int nface = 0;
@@ -67,15 +70,18 @@ struct LevelGeom {
   std::vector<int> rb_slotA, rb_slotB;  // slot of the block's face in cell A / B, or -1
 };
 
-// Geometry of every level 0..L of an n^3 grid with leaf width `leaf`.
-std::vector<LevelGeom> plan_geometry(int n, int leaf);
+// Geometry of every level 0..L of an n^3 grid with leaf width `leaf`;
+// periodic: every plane x_d = w j (j >= 0) below the root is a separator and
+// the faces on x_d = 0 join the last and the first cell along d.
+std::vector<LevelGeom> plan_geometry(int n, int leaf, bool periodic);
 
 // Plan level `level` from its geometry and the current active mask (1 byte per
 // grid point): the candidates that are still active.
 LevelPlan plan_level(const LevelGeom& G, const std::vector<uint8_t>& active);
 
 // Plan level `level` of an n^3 grid directly (geometry + filter).
-LevelPlan plan_level(int n, int leaf, int level, int L, const std::vector<uint8_t>& active);
+LevelPlan plan_level(int n, int leaf, int level, int L, const std::vector<uint8_t>& active,
+                     bool periodic);
 
 // Number of levels L with n = leaf * 2^L, or -1 if n is not of that form.
 int levels_for(int n, int leaf);

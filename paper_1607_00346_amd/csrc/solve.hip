@@ -20,6 +20,35 @@ constexpr int NT = 256;
 
 __device__ __forceinline__ double harmonic(double u, double v) { return 2.0 * u * v / (u + v); }
 
+// Periodic variant of k_assemble: every point has six neighbours, indices wrap.
+__global__ __launch_bounds__(NT) void k_assemble_periodic(int n, double h2inv,
+                                                          const double* __restrict__ a,
+                                                          const double* __restrict__ b,
+                                                          double* diag, double* cx, double* cy,
+                                                          double* cz, int* bad) {
+  const int64_t N = (int64_t)n * n * n;
+  const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
+  if (p >= N) return;
+  const int x = (int)(p % n), y = (int)((p / n) % n), z = (int)(p / ((int64_t)n * n));
+  const double ap = a[p], bp = b[p];
+  if (!(ap > 0.0) || !isfinite(ap) || !isfinite(bp)) atomicOr(bad, 1);
+  const int64_t sy = n, sz = (int64_t)n * n;
+  const int64_t xp = x < n - 1 ? p + 1 : p - (n - 1), xm = x > 0 ? p - 1 : p + (n - 1);
+  const int64_t yp = y < n - 1 ? p + sy : p - (n - 1) * sy, ym = y > 0 ? p - sy : p + (n - 1) * sy;
+  const int64_t zp = z < n - 1 ? p + sz : p - (n - 1) * sz, zm = z > 0 ? p - sz : p + (n - 1) * sz;
+  double d = bp;
+  double c = harmonic(ap, a[xp]) * h2inv;
+  cx[p] = c;
+  d += c + harmonic(ap, a[xm]) * h2inv;
+  c = harmonic(ap, a[yp]) * h2inv;
+  cy[p] = c;
+  d += c + harmonic(ap, a[ym]) * h2inv;
+  c = harmonic(ap, a[zp]) * h2inv;
+  cz[p] = c;
+  d += c + harmonic(ap, a[zm]) * h2inv;
+  diag[p] = d;
+}
+
 __global__ __launch_bounds__(NT) void k_assemble(int n, double h2inv, const double* __restrict__ a,
                                                  const double* __restrict__ b, double* diag,
                                                  double* cx, double* cy, double* cz, int* bad) {
@@ -56,12 +85,23 @@ __global__ __launch_bounds__(NT) void k_matvec(Stencil st, const double* __restr
   const int64_t sy = n, sz = (int64_t)n * n;
   const int xx = (int)(p % n), yy = (int)((p / n) % n), zz = (int)(p / sz);
   double v = st.diag[p] * x[p];
-  if (xx < n - 1) v -= st.cx[p] * x[p + 1];
-  if (xx > 0) v -= st.cx[p - 1] * x[p - 1];
-  if (yy < n - 1) v -= st.cy[p] * x[p + sy];
-  if (yy > 0) v -= st.cy[p - sy] * x[p - sy];
-  if (zz < n - 1) v -= st.cz[p] * x[p + sz];
-  if (zz > 0) v -= st.cz[p - sz] * x[p - sz];
+  if (!st.periodic) {
+    if (xx < n - 1) v -= st.cx[p] * x[p + 1];
+    if (xx > 0) v -= st.cx[p - 1] * x[p - 1];
+    if (yy < n - 1) v -= st.cy[p] * x[p + sy];
+    if (yy > 0) v -= st.cy[p - sy] * x[p - sy];
+    if (zz < n - 1) v -= st.cz[p] * x[p + sz];
+    if (zz > 0) v -= st.cz[p - sz] * x[p - sz];
+  } else {
+    const int64_t xp = xx < n - 1 ? p + 1 : p - (n - 1), xm = xx > 0 ? p - 1 : p + (n - 1);
+    const int64_t yp = yy < n - 1 ? p + sy : p - (n - 1) * sy;
+    const int64_t ym = yy > 0 ? p - sy : p + (n - 1) * sy;
+    const int64_t zp = zz < n - 1 ? p + sz : p - (n - 1) * sz;
+    const int64_t zm = zz > 0 ? p - sz : p + (n - 1) * sz;
+    v -= st.cx[p] * x[xp] + st.cx[xm] * x[xm];
+    v -= st.cy[p] * x[yp] + st.cy[ym] * x[ym];
+    v -= st.cz[p] * x[zp] + st.cz[zm] * x[zm];
+  }
   y[p] = v;
 }
 
@@ -801,9 +841,16 @@ void problem_assemble(hif_problem_s* A, const double* a, const double* b, hipStr
   A->cz.alloc(N);
   DevBuf<int> bad(1);
   HIF_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), s));
-  const double h2inv = (double)(n + 1) * (double)(n + 1);
-  hipLaunchKernelGGL(k_assemble, dim3((unsigned)ceil_div(N, NT)), dim3(NT), 0, s, n, h2inv, a, b,
-                     A->diag.get(), A->cx.get(), A->cy.get(), A->cz.get(), bad.get());
+  if (A->opts.bc == HIF_PERIODIC) {  // h = 1/n
+    const double h2inv = (double)n * (double)n;
+    hipLaunchKernelGGL(k_assemble_periodic, dim3((unsigned)ceil_div(N, NT)), dim3(NT), 0, s, n,
+                       h2inv, a, b, A->diag.get(), A->cx.get(), A->cy.get(), A->cz.get(),
+                       bad.get());
+  } else {  // h = 1/(n+1)
+    const double h2inv = (double)(n + 1) * (double)(n + 1);
+    hipLaunchKernelGGL(k_assemble, dim3((unsigned)ceil_div(N, NT)), dim3(NT), 0, s, n, h2inv, a,
+                       b, A->diag.get(), A->cx.get(), A->cy.get(), A->cz.get(), bad.get());
+  }
   HIF_LAUNCH_CHECK();
   int h = 0;
   HIF_HIP(hipMemcpyAsync(&h, bad.get(), sizeof(int), hipMemcpyDeviceToHost, s));

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libhif.so")
 
 HIF_OK, HIF_EINVAL, HIF_ENOMEM, HIF_ENOTSPD, HIF_ENOCONV, HIF_EDEVICE = 0, -1, -2, -3, -4, -5
 HIF_FP64, HIF_MIXED = 0, 1
-HIF_DIRICHLET = 0
+HIF_DIRICHLET, HIF_PERIODIC = 0, 1
 HIF_MAX_LEVELS = 16
 
 EXPORTED = [

@@ -82,3 +82,13 @@ def test_batched_calls_reject_bad_arguments(L):
     assert L.hif_pcg_batched(2, probs, probs, vecs, vecs, 1e-10, 10, info, None) == H.HIF_EINVAL
     assert L.hif_pcg_batched(2, probs, probs, vecs, vecs, -1.0, 10, info, None) == H.HIF_EINVAL
     assert len(H.hif_last_error()) > 0
+
+
+def test_periodic_options_checked(L):
+    """Periodic grids need n >= 4; unknown boundary conditions are refused."""
+    h = ctypes.c_void_p(123)
+    dummy = ctypes.c_void_p(16)
+    for opts in (H.make_options(2, 2, 0.0, 0, bc=H.HIF_PERIODIC),
+                 H.make_options(16, 4, 1e-6, 0, bc=7)):
+        st = L.hif_problem_create(ctypes.byref(opts), dummy, dummy, None, ctypes.byref(h))
+        assert st == H.HIF_EINVAL and h.value is None

@@ -44,6 +44,32 @@ def normal_rhs(n: int, seed: int, nrhs: int = 1) -> np.ndarray:
     return g.standard_normal((nrhs, n ** 3))
 
 
+def smoothed_binary_field(n: int, seed: int, lo: float = 0.1, hi: float = 1000.0,
+                          sigma: float = 1.0) -> np.ndarray:
+    """The high-contrast random field of the paper's Example 2 (Section 4): a
+    uniform value in [0, 1) per grid point (x1 fastest), convolved
+    periodically with an isotropic Gaussian of standard deviation `sigma` grid
+    spacings (kernel normalised to sum 1, applied by FFT), then `lo` where
+    the result is <= 0.5 and `hi` where it is above."""
+    u = _gen(seed).uniform(0.0, 1.0, n ** 3).reshape(n, n, n)
+    d = np.minimum(np.arange(n), n - np.arange(n)).astype(np.float64)  # periodic distance
+    g1 = np.exp(-0.5 * (d / sigma) ** 2)
+    ker = g1[:, None, None] * g1[None, :, None] * g1[None, None, :]
+    ker /= ker.sum()
+    sm = np.real(np.fft.ifftn(np.fft.fftn(u) * np.fft.fftn(ker)))
+    return np.where(sm <= 0.5, lo, hi).ravel()
+
+
+def checkerboard_field(n: int, block: int = 7, even: float = 1000.0,
+                       odd: float = 0.1) -> np.ndarray:
+    """The field of the paper's Example 3 (Section 4): `even` where
+    floor(j1/block) + floor(j2/block) + floor(j3/block) is even (grid point
+    j = (j1, j2, j3), x_i = j_i / n), `odd` elsewhere; x1 fastest."""
+    j = np.arange(n) // block
+    par = (j[:, None, None] + j[None, :, None] + j[None, None, :]) % 2
+    return np.where(par == 0, even, odd).ravel()
+
+
 @dataclass
 class Workload:
     """One synthetic problem: grid n^3, leaf width m, coefficient recipe, ID tolerance."""
@@ -51,17 +77,22 @@ class Workload:
     n: int
     leaf: int
     eps: float
-    a_kind: str            # "const" | "logu"
+    a_kind: str            # "const" | "logu" | "smooth01" | "checker"
     a_args: tuple
     b_kind: str            # "const" | "unif"
     b_args: tuple
     f_seed: int
     precision: str = "fp64"  # "fp64" | "mixed"
     extra: dict = field(default_factory=dict)
+    bc: str = "dirichlet"    # "dirichlet" | "periodic"
 
     def a(self) -> np.ndarray:
         if self.a_kind == "const":
             return const_field(self.n, *self.a_args)
+        if self.a_kind == "smooth01":
+            return smoothed_binary_field(self.n, *self.a_args)
+        if self.a_kind == "checker":
+            return checkerboard_field(self.n, *self.a_args)
         return log_uniform_field(self.n, *self.a_args)
 
     def b(self) -> np.ndarray:
@@ -91,6 +122,25 @@ WORKLOADS = {
     # 32^3 high-contrast field used for mid-size parity and the CPU baseline sample.
     "c32_contrast": Workload("c32_contrast", 32, 8, 1e-6, "logu", (-2.0, 2.0, 211),
                              "const", (0.0,), 212),
+    # The paper's three examples (Section 4): periodic on [0,1)^3, leaf 4^3 (blocks of
+    # at most 64 points), b = 0.1 relative to the stencil taken without its 1/h^2
+    # factor, i.e. b = 0.1 n^2 beside the 1/h^2 = n^2 stencil assembled here (the
+    # reading under which the paper's 32^3 Example 1 figures are reproduced:
+    # |Sigma_L| = 3440 and 6 GMRES steps).  Example 1: a = 1, eps 1e-3.
+    "ex1_32": Workload("ex1_32", 32, 4, 1e-3, "const", (1.0,), "const", (0.1 * 32 ** 2,), 801,
+                       bc="periodic"),
+    # Example 2: smoothed, quantized random field a in {0.1, 1000}, eps 1e-5.
+    "ex2_32": Workload("ex2_32", 32, 4, 1e-5, "smooth01", (802,), "const", (0.1 * 32 ** 2,),
+                       803, bc="periodic"),
+    # Example 3: checkerboard of 7-point blocks, a in {1000, 0.1}, eps 1e-4.
+    "ex3_64": Workload("ex3_64", 64, 4, 1e-4, "checker", (7,), "const", (0.1 * 64 ** 2,), 804,
+                       bc="periodic"),
+    "ex1_128": Workload("ex1_128", 128, 4, 1e-3, "const", (1.0,), "const", (0.1 * 128 ** 2,),
+                        805, bc="periodic"),
+    "ex2_128": Workload("ex2_128", 128, 4, 1e-5, "smooth01", (806,), "const",
+                        (0.1 * 128 ** 2,), 807, bc="periodic"),
+    "ex3_128": Workload("ex3_128", 128, 4, 1e-4, "checker", (7,), "const", (0.1 * 128 ** 2,),
+                        808, bc="periodic"),
 }
 
 
