@@ -154,6 +154,19 @@ hif_status hif_build_batched(int32_t count, const hif_problem_t* A, const hif_op
  * (exactly, not partly).  Asynchronous on `stream`.  nrhs = 0 is a no-op. */
 hif_status hif_apply(hif_factor_t F, const double* f, double* u, int32_t nrhs, void* stream);
 
+/* y = F x for one vector: the factorization itself, F = W^0^{-T} ... W^L^{-T}
+ * D W^L^{-1} ... W^0^{-1} (paper, Section 2.4, the product form of F), which
+ * approximates A (F = A up to rounding at eps = 0).  Every elementary step
+ * of hif_apply is inverted, in the reverse order; the products with the
+ * triangular factors L_I, L_F̌ and L_Sigma, which the factor stores as
+ * explicit inverses, are triangular solves with those blocks (one
+ * workgroup per block, one step per row: far slower than hif_apply, and
+ * meant for checks such as ||(A - F) x|| and F F^{-1} x = x).  FP64 in and
+ * out; the mixed factor's blocks are read in FP32.  y may alias x
+ * (exactly).  The first call on a factor builds and keeps its block lists.
+ * Asynchronous on `stream`. */
+hif_status hif_apply_forward(hif_factor_t F, const double* x, double* y, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): u = F^{-1} f
  * for one vector, exactly as hif_apply with nrhs = 1 (same kernels, same
@@ -234,6 +247,23 @@ hif_status hif_factor_ranks(hif_factor_t F, int32_t level, int32_t* ranks, int32
 /* Active-DOF mask after `level` (0..L-1): mask[p] = 1 if grid point p is
  * still active in A^{level+1} (host array of N bytes). */
 hif_status hif_factor_active(hif_factor_t F, int32_t level, uint8_t* mask);
+
+/* Write the factorization to the file `path` (created or truncated): the
+ * stored blocks of F (paper, Section 2.4: the factors of every S_I, Q_F,
+ * S_F̌ and of the root, in the factor's precision) with the options,
+ * statistics, ranks and skeleton choices, so that hif_factor_load can
+ * rebuild it without the problem.  A 128^3 mixed factor takes about 8 GB.
+ * Blocks the calling thread (device blocks are copied to the host first).
+ * HIF_EINVAL if the file cannot be written. */
+hif_status hif_factor_save(hif_factor_t F, const char* path, void* stream);
+
+/* Read a file written by hif_factor_save into a new factor on the current
+ * device (used and destroyed like one from hif_build; hif_pcg and
+ * hif_gmres need a problem of the same grid and boundary condition).
+ * Applications of the loaded factor equal those of the saved one bit for
+ * bit.  HIF_EINVAL for a missing, truncated or foreign file (*out = NULL,
+ * nothing leaks).  Blocks the calling thread. */
+hif_status hif_factor_load(const char* path, void* stream, hif_factor_t* out);
 
 /* Accuracy of F as an approximation of A (paper, Section 4, result
  * metrics): *e_s = ||x - F^{-1} A x||_2 / ||x||_2 for the caller's device

@@ -6,12 +6,12 @@ the benchmark's CPU-baseline leg may import anything from here.
 """
 from .dense import (NotSPD, cholesky, cpqr, interp_decomp, ldl_signed, solve_lower, solve_lower_t,
                     solve_upper)
-from .hif import (Factor, Geometry, active_after, apply_inverse, assemble, build, count_levels,
+from .hif import (Factor, Geometry, active_after, apply_forward, apply_inverse, assemble, build, count_levels,
                   energy, gmres, pcg, relative_solve_error, power_norm_error)
 
 __all__ = [
     "NotSPD", "cholesky", "cpqr", "interp_decomp", "ldl_signed", "solve_lower", "solve_lower_t", "solve_upper",
-    "Factor", "Geometry", "active_after", "apply_inverse", "assemble", "build", "count_levels",
+    "Factor", "Geometry", "active_after", "apply_forward", "apply_inverse", "assemble", "build", "count_levels",
     "energy", "gmres", "pcg",
     "relative_solve_error", "power_norm_error",
 ]

@@ -391,6 +391,33 @@ def apply_inverse(fac: Factor, f: np.ndarray) -> np.ndarray:
     return x
 
 
+def apply_forward(fac: Factor, x: np.ndarray) -> np.ndarray:
+    """F x with F = W^0^{-T} ... W^L^{-T} D W^L^{-1} ... W^0^{-1} (Section 2.4,
+    the product form of F): the inverse of every elementary step of
+    apply_inverse, in the reverse order.  The inverses need the triangular
+    factors themselves (products with L and L^T) where apply_inverse solves
+    with them."""
+    y = np.array(x, dtype=np.float64, copy=True)
+    for lev in fac.levels:                                  # W^l^{-1}, l = 0..L-1
+        for cf in lev.cells:                                # S_I^{-1}
+            y[cf.I] = cf.L.T @ y[cf.I] + cf.X @ y[cf.S]
+        for ff in lev.faces:                                # (Q_F S_F̌)^{-1}
+            y[ff.hat] += ff.T @ y[ff.chk]
+            y[ff.chk] = ff.Lc.T @ y[ff.chk] + ff.Y @ y[ff.hat]
+    z = fac.Lroot.T @ y[fac.root]                           # W^L^{-1}, then D
+    if fac.Sroot is not None:
+        z = fac.Sroot * z
+    y[fac.root] = fac.Lroot @ z                             # W^L^{-T}
+    for lev in reversed(fac.levels):                        # W^l^{-T}, l = L-1..0
+        for ff in reversed(lev.faces):                      # (S_F̌^T Q_F^T)^{-1}
+            y[ff.hat] += ff.Y.T @ y[ff.chk]
+            y[ff.chk] = ff.Lc @ y[ff.chk] + ff.T.T @ y[ff.hat]
+        for cf in reversed(lev.cells):                      # S_I^{-T}
+            y[cf.S] += cf.X.T @ y[cf.I]
+            y[cf.I] = cf.L @ y[cf.I]
+    return y
+
+
 # ---------------------------------------------------------------------------
 # Diagnostics (Section 4, result metrics) and the Krylov driver
 # ---------------------------------------------------------------------------

@@ -21,7 +21,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-Wno-unused-result"]
-SOURCES = ["dense.hip", "build.hip", "solve.hip", "krylov.hip", "plan.cpp", "abi.cpp", "prof.cpp", "mem.cpp"]
+SOURCES = ["dense.hip", "build.hip", "solve.hip", "krylov.hip", "persist.hip", "plan.cpp", "abi.cpp", "prof.cpp", "mem.cpp"]
 
 
 def _compile(src: str) -> str:

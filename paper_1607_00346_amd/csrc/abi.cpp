@@ -2,6 +2,7 @@
 // thread-local error text.  No exception crosses this boundary.
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 
@@ -188,6 +189,15 @@ hif_status hif_apply_noalloc(hif_factor_t F, const double* f, double* u, void* s
   });
 }
 
+hif_status hif_apply_forward(hif_factor_t F, const double* x, double* y, void* stream) {
+  return guarded([&] {
+    HIF_REQUIRE(F != nullptr && F->impl, HIF_EINVAL, "NULL factor");
+    HIF_REQUIRE(x != nullptr && y != nullptr, HIF_EINVAL, "NULL vector");
+    hif::StreamScope scope(as_stream(stream));
+    F->impl->apply_forward(x, y, as_stream(stream));
+  });
+}
+
 hif_status hif_matvec(hif_problem_t A, const double* x, double* y, int32_t nrhs, void* stream) {
   return guarded([&] {
     HIF_REQUIRE(A != nullptr, HIF_EINVAL, "NULL problem");
@@ -294,6 +304,30 @@ hif_status hif_factor_error(hif_problem_t A, hif_factor_t F, const double* x, in
     F->stats.err_norm = nrm;
     if (e_s) *e_s = es;
     if (err_norm) *err_norm = nrm;
+  });
+}
+
+hif_status hif_factor_save(hif_factor_t F, const char* path, void* stream) {
+  return guarded([&] {
+    HIF_REQUIRE(F != nullptr && F->impl && path != nullptr, HIF_EINVAL, "NULL argument");
+    hif::StreamScope scope(as_stream(stream));
+    hif::factor_save(F, path, as_stream(stream));
+  });
+}
+
+hif_status hif_factor_load(const char* path, void* stream, hif_factor_t* out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    HIF_REQUIRE(path != nullptr && out != nullptr, HIF_EINVAL, "NULL argument");
+    hif::StreamScope scope(as_stream(stream));
+    std::unique_ptr<hif_factor_s> F(new hif_factor_s());
+    try {
+      hif::factor_load(path, as_stream(stream), F.get());
+    } catch (...) {
+      (void)hipStreamSynchronize(as_stream(stream));
+      throw;
+    }
+    *out = F.release();
   });
 }
 

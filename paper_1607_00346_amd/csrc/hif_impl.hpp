@@ -35,6 +35,14 @@ struct SkelDesc {
   int64_t kofs, rofs;  // offsets of x_F̂ / x_F̌ in the apply scratch vectors
 };
 
+// One triangular block of the forward apply: M (n x n, column-major, ld) is a
+// stored inverse L^{-1}; its vector segment starts at off in a scratch array.
+struct TrsvDesc {
+  const void* M;
+  int n, ld;
+  int64_t off;
+};
+
 // One matrix of a batched matrix-vector product in the sweeps: A (m x n,
 // column-major, lower triangular if tri), its row-space vector at roff and
 // column-space vector at coff in the scratch arrays.
@@ -80,6 +88,9 @@ struct Level {
   bool gv_L_vec = true;  // every L_I^{-1} starts 16-byte aligned (vector row GEMV)
   DevBuf<GemvDesc> gv_L, gv_S, gv_T, gv_Lc, gv_Y;
   int gv_nS = 0;  // cells with nS > 0 (gv_S entries)
+  // triangular blocks of the forward apply (built on its first use)
+  bool tr_ready = false;
+  DevBuf<TrsvDesc> tr_cells, tr_faces;
   int64_t ksum = 0, rsum = 0;
 };
 
@@ -90,6 +101,8 @@ struct FactorBase {
   virtual ~FactorBase() = default;
   std::shared_ptr<PcgCache> pcg;
   virtual void apply(const double* f, double* u, hipStream_t s) = 0;
+  // u = F f (the product form of F itself), one vector, FP64 in and out.
+  virtual void apply_forward(const double* f, double* u, hipStream_t s) = 0;
   // apply() with its scratch vectors carved out of `scratch` (cap doubles,
   // 256-byte aligned) instead of the factor's own; allocates nothing.
   virtual void apply_scratch(const double* f, double* u, double* scratch, int64_t cap,
@@ -130,6 +143,7 @@ struct FactorImpl : FactorBase {
   // Sweep descriptors and scratch of the apply (idempotent).
   void prepare(hipStream_t s);
   void apply(const double* f, double* u, hipStream_t s) override;
+  void apply_forward(const double* f, double* u, hipStream_t s) override;
   void apply_scratch(const double* f, double* u, double* scratch, int64_t cap,
                      hipStream_t s) override;
   int64_t scratch_doubles() const override;
@@ -192,6 +206,11 @@ struct BuildRequest {
 // differ) with joint launches per level.
 template <typename T>
 void build_factors(const std::vector<BuildRequest>& req, hipStream_t s);
+
+// Factor files: save F (blocks copied to the host, then written), or fill
+// an empty F from a file (plans and layouts rebuilt, blocks uploaded).
+void factor_save(const hif_factor_s* F, const char* path, hipStream_t s);
+void factor_load(const char* path, hipStream_t s, hif_factor_s* F);
 
 // e_s = ||x - F^{-1}A x|| / ||x|| and, for power_iters > 0, the power-method
 // estimate of ||I - F^{-1}A||_2 started at x (NaN for power_iters = 0).

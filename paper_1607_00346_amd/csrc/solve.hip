@@ -754,6 +754,56 @@ __global__ __launch_bounds__(NT) void k_skel_move_b(double* u, int64_t N,
   else *s = (T)u[p];
 }
 
+// ---- forward apply: products with L and L^T from the stored L^{-1} -------
+//
+// One workgroup per block; thread t owns the rows i = t (mod NT) of the
+// block's vector segment, so every entry is read and written by its owner
+// only, and the solved entry of each step reaches the others through LDS.
+
+// v <- M^{-1} v = L v (M = L^{-1} lower triangular): forward substitution.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_trsv_lower(const TrsvDesc* __restrict__ dd, double* v) {
+  __shared__ double yj;
+  const TrsvDesc d = dd[blockIdx.x];
+  const T* M = static_cast<const T*>(d.M);
+  double* x = v + d.off;
+  const int tid = threadIdx.x;
+  for (int j = 0; j < d.n; ++j) {
+    if (tid == j % NT) {
+      const double t = x[j] / (double)M[j + (int64_t)d.ld * j];
+      x[j] = t;
+      yj = t;
+    }
+    __syncthreads();
+    const double y = yj;
+    const T* col = M + (int64_t)d.ld * j;
+    const int i0 = j + 1 + (((tid - (j + 1)) % NT) + NT) % NT;
+    for (int i = i0; i < d.n; i += NT) x[i] -= (double)col[i] * y;
+    __syncthreads();
+  }
+}
+
+// v <- M^{-T} v = L^T v: back substitution with the upper triangular M^T.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_trsv_upper_t(const TrsvDesc* __restrict__ dd, double* v) {
+  __shared__ double yj;
+  const TrsvDesc d = dd[blockIdx.x];
+  const T* M = static_cast<const T*>(d.M);
+  double* x = v + d.off;
+  const int tid = threadIdx.x;
+  for (int j = d.n - 1; j >= 0; --j) {
+    if (tid == j % NT) {
+      const double t = x[j] / (double)M[j + (int64_t)d.ld * j];
+      x[j] = t;
+      yj = t;
+    }
+    __syncthreads();
+    const double y = yj;
+    for (int i = tid; i < j; i += NT) x[i] -= (double)M[j + (int64_t)d.ld * i] * y;
+    __syncthreads();
+  }
+}
+
 // ---- PCG vector kernels --------------------------------------------------
 
 constexpr int kDotBlocks = 1024;
@@ -1153,6 +1203,129 @@ void FactorImpl<T>::sweep(const double* f, double* u, double* xi, double* yv, do
   prof_level() = -1;
 }
 
+// u = F f, F = W^0^{-T} ... W^L^{-T} W^L^{-1} ... W^0^{-1}: every elementary
+// step of apply() inverted, in the reverse order.  The inverses multiply by
+// L_I, L_F̌ and L_Sigma (and their transposes), which the factor holds as
+// explicit inverses: those products are triangular solves with the stored
+// blocks (k_trsv_*), the rest are the sweeps' batched matrix-vector products
+// with the opposite sign.  One workgroup per triangular block and one step
+// per row, so this costs far more than apply(); it is not on the solve path.
+template <typename T>
+void FactorImpl<T>::apply_forward(const double* f, double* u, hipStream_t s) {
+  prepare(s);
+  for (auto& lv : levels) {
+    if (lv.tr_ready) continue;
+    std::vector<TrsvDesc> tc, tf;
+    for (int c = 0; c < lv.plan->ncell; ++c)
+      if (lv.hfd[c].nI > 0) tc.push_back({lv.hfd[c].ptr, lv.hfd[c].nI, lv.hfd[c].ld, lv.hyoff[c]});
+    for (const SkelDesc& d : lv.hsk)
+      tf.push_back({(const T*)lv.skel.get() + d.offL, d.r, d.r, d.rofs});
+    lv.tr_cells.upload(tc, s);
+    lv.tr_faces.upload(tf, s);
+    lv.tr_ready = true;
+  }
+  if (u != f) {
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(N)), dim3(NT), 0, s, f, u, N);
+    HIF_LAUNCH_CHECK();
+  }
+  double* xi = ybuf.get();
+  double* zv = zbuf.get();
+  double* xsv = zbuf.get() + zmax;
+  double* sh = sbuf.get();
+  double* sc = sbuf.get() + kmax;
+  const int nlev = (int)levels.size();
+  auto trsv = [&](const Level<T>& lv, bool faces, bool lower, double* v) {
+    const size_t cnt = faces ? lv.tr_faces.size() : lv.tr_cells.size();
+    if (cnt == 0) return;
+    ProfScope ps("forward_trsv", s);
+    const TrsvDesc* d = faces ? lv.tr_faces.get() : lv.tr_cells.get();
+    if (lower) hipLaunchKernelGGL((k_trsv_lower<T>), dim3((unsigned)cnt), dim3(NT), 0, s, d, v);
+    else hipLaunchKernelGGL((k_trsv_upper_t<T>), dim3((unsigned)cnt), dim3(NT), 0, s, d, v);
+    HIF_LAUNCH_CHECK();
+  };
+  auto gather = [&](const Level<T>& lv, int with_s) {
+    const int gmax = with_s ? lv.maxI + lv.maxS : lv.maxI;
+    dim3 g((unsigned)ceil_div(std::max(1, gmax), NT), (unsigned)lv.plan->ncell);
+    hipLaunchKernelGGL(k_gather_cell, g, dim3(NT), 0, s, (const double*)u, lv.rows.get(),
+                       lv.crow_off.get(), lv.fd.get(), lv.yoff.get(), lv.zoff.get(), xi, xsv,
+                       with_s);
+    HIF_LAUNCH_CHECK();
+  };
+  auto scatter = [&](const Level<T>& lv) {
+    dim3 g((unsigned)ceil_div(std::max(1, lv.maxI), NT), (unsigned)lv.plan->ncell);
+    hipLaunchKernelGGL(k_scatter_I, g, dim3(NT), 0, s, u, lv.rows.get(), lv.crow_off.get(),
+                       lv.fd.get(), lv.yoff.get(), (const double*)xi);
+    HIF_LAUNCH_CHECK();
+  };
+  auto skel_move = [&](const Level<T>& lv, int to_u) {
+    dim3 g((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)lv.hsk.size());
+    hipLaunchKernelGGL(k_skel_move, g, dim3(NT), 0, s, u, lv.skpts.get(), lv.sk.get(), sh, sc,
+                       to_u);
+    HIF_LAUNCH_CHECK();
+  };
+  // W^l^{-1}, l = 0..L-1: cells (x_I <- L_I^T x_I + L_SI^T x_S), then faces
+  // (x_F̂ += T x_F̌; x_F̌ <- L_F̌^T x_F̌ + Y x_F̂)
+  for (int l = 0; l + 1 < nlev; ++l) {
+    Level<T>& lv = levels[l];
+    prof_level() = l;
+    const int nc = lv.plan->ncell;
+    if (nc > 0) {
+      gather(lv, 1);
+      trsv(lv, false, false, xi);
+      if (lv.gv_nS > 0)
+        gemv_launch<T>(true, lv.gv_S.get(), lv.gv_nS, lv.maxS, lv.maxI, xsv, xi, 1.0, 1, s);
+      scatter(lv);
+    }
+    const int ns = (int)lv.hsk.size();
+    if (ns > 0) {
+      skel_move(lv, 0);
+      gemv_launch<T>(false, lv.gv_T.get(), ns, lv.maxk, lv.maxr, sc, sh, 1.0, 1, s);
+      trsv(lv, true, false, sc);
+      gemv_launch<T>(false, lv.gv_Y.get(), ns, lv.maxr, lv.maxk, sh, sc, 1.0, 1, s);
+      skel_move(lv, 1);
+    }
+  }
+  // the root: x <- L_Sigma^T x, then x <- L_Sigma x
+  {
+    Level<T>& lv = levels[nlev - 1];
+    prof_level() = nlev - 1;
+    if (lv.plan->ncell > 0) {
+      gather(lv, 0);
+      trsv(lv, false, false, xi);
+      trsv(lv, false, true, xi);
+      scatter(lv);
+    }
+  }
+  // W^l^{-T}, l = L-1..0: faces (x_F̂ += Y^T x_F̌; x_F̌ <- L_F̌ x_F̌ + T^T x_F̂),
+  // then cells (x_S += L_SI x_I; x_I <- L_I x_I)
+  for (int l = nlev - 2; l >= 0; --l) {
+    Level<T>& lv = levels[l];
+    prof_level() = l;
+    const int ns = (int)lv.hsk.size();
+    if (ns > 0) {
+      skel_move(lv, 0);
+      gemv_launch<T>(true, lv.gv_Y.get(), ns, lv.maxr, lv.maxk, sc, sh, 1.0, 1, s);
+      trsv(lv, true, true, sc);
+      gemv_launch<T>(true, lv.gv_T.get(), ns, lv.maxk, lv.maxr, sh, sc, 1.0, 1, s);
+      skel_move(lv, 1);
+    }
+    const int nc = lv.plan->ncell;
+    if (nc == 0) continue;
+    gather(lv, 0);
+    if (lv.gv_nS > 0 && lv.plan->nface > 0) {
+      gemv_launch<T>(false, lv.gv_S.get(), lv.gv_nS, lv.maxS, lv.maxI, xi, zv, -1.0, 0, s);
+      dim3 gF((unsigned)ceil_div(std::max(1, lv.maxF), NT), (unsigned)lv.plan->nface);
+      hipLaunchKernelGGL(k_face_sub, gF, dim3(NT), 0, s, u, lv.fpts.get(), lv.fpt_off.get(),
+                         lv.fN.get(), lv.fcellA.get(), lv.fcellB.get(), lv.rb_sa.get(),
+                         lv.rb_sb.get(), lv.zoff.get(), (const double*)zv);
+      HIF_LAUNCH_CHECK();
+    }
+    trsv(lv, false, true, xi);
+    scatter(lv);
+  }
+  prof_level() = -1;
+}
+
 // The sweeps of apply() on a block of nb vectors: every matrix-vector product
 // of a level becomes one batched GEMM (MFMA) whose N dimension is the block,
 // so each stored factor word is read once per sweep for the whole block.
@@ -1344,6 +1517,8 @@ template void FactorImpl<double>::prepare(hipStream_t);
 template void FactorImpl<float>::prepare(hipStream_t);
 template void FactorImpl<double>::apply(const double*, double*, hipStream_t);
 template void FactorImpl<float>::apply(const double*, double*, hipStream_t);
+template void FactorImpl<double>::apply_forward(const double*, double*, hipStream_t);
+template void FactorImpl<float>::apply_forward(const double*, double*, hipStream_t);
 template void FactorImpl<double>::apply_scratch(const double*, double*, double*, int64_t,
                                                 hipStream_t);
 template void FactorImpl<float>::apply_scratch(const double*, double*, double*, int64_t,

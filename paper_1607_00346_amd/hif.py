@@ -20,9 +20,10 @@ HIF_MAX_LEVELS = 16
 
 EXPORTED = [
     "hif_problem_create", "hif_build", "hif_build_batched", "hif_apply", "hif_apply_noalloc",
+    "hif_apply_forward",
     "hif_matvec", "hif_pcg", "hif_gmres", "hif_pcg_batched",
     "hif_factor_stats", "hif_factor_ranks", "hif_factor_active", "hif_factor_error",
-    "hif_factor_destroy",
+    "hif_factor_save", "hif_factor_load", "hif_factor_destroy",
     "hif_problem_destroy", "hif_status_string", "hif_last_error", "hif_profile_begin",
     "hif_profile_end", "hif_profile_select", "hif_tune_begin", "hif_tune_end", "hif_release_cached_memory",
 ]
@@ -101,6 +102,7 @@ def lib():
                                         ctypes.POINTER(vp)]
         L.hif_apply.argtypes = [vp, vp, vp, i32, vp]
         L.hif_apply_noalloc.argtypes = [vp, vp, vp, vp]
+        L.hif_apply_forward.argtypes = [vp, vp, vp, vp]
         L.hif_matvec.argtypes = [vp, vp, vp, i32, vp]
         L.hif_pcg.argtypes = [vp, vp, vp, vp, i32, f64, i32, ctypes.POINTER(hif_pcg_info), vp]
         L.hif_gmres.argtypes = [vp, vp, vp, vp, f64, i32, i32, ctypes.POINTER(hif_pcg_info), vp]
@@ -110,6 +112,8 @@ def lib():
         L.hif_factor_stats.argtypes = [vp, ctypes.POINTER(hif_stats)]
         L.hif_factor_ranks.argtypes = [vp, i32, vp, vp, i32, ctypes.POINTER(i32)]
         L.hif_factor_active.argtypes = [vp, i32, vp]
+        L.hif_factor_save.argtypes = [vp, ctypes.c_char_p, vp]
+        L.hif_factor_load.argtypes = [ctypes.c_char_p, vp, ctypes.POINTER(vp)]
         L.hif_factor_error.argtypes = [vp, vp, vp, i32, ctypes.POINTER(f64),
                                        ctypes.POINTER(f64), vp]
         L.hif_factor_destroy.argtypes = [vp]
@@ -125,9 +129,10 @@ def lib():
         L.hif_status_string.restype = ctypes.c_char_p
         L.hif_last_error.restype = ctypes.c_char_p
         for name in ("hif_problem_create", "hif_build", "hif_build_batched", "hif_apply",
-                     "hif_apply_noalloc", "hif_gmres",
+                     "hif_apply_noalloc", "hif_apply_forward", "hif_gmres",
                      "hif_matvec", "hif_pcg", "hif_pcg_batched", "hif_factor_stats",
                      "hif_factor_ranks", "hif_factor_active", "hif_factor_error",
+                     "hif_factor_save", "hif_factor_load",
                      "hif_profile_begin", "hif_profile_end", "hif_profile_select",
                      "hif_tune_begin", "hif_tune_end"):
             getattr(L, name).restype = ctypes.c_int
@@ -195,6 +200,11 @@ def hif_apply_noalloc(F, f, u, stream=None):
     _check(lib().hif_apply_noalloc(F, _dptr(f), _dptr(u), _stream(stream)), "hif_apply_noalloc")
 
 
+def hif_apply_forward(F, x, y, stream=None):
+    """y = F x (one vector): the factorization itself, the product form of F."""
+    _check(lib().hif_apply_forward(F, _dptr(x), _dptr(y), _stream(stream)), "hif_apply_forward")
+
+
 def hif_matvec(A, x, y, nrhs: int = 1, stream=None):
     _check(lib().hif_matvec(A, _dptr(x), _dptr(y), int(nrhs), _stream(stream)), "hif_matvec")
 
@@ -250,6 +260,19 @@ def hif_factor_ranks(F, level: int):
                                   sizes.ctypes.data_as(ctypes.c_void_p), cnt.value,
                                   ctypes.byref(cnt)), "hif_factor_ranks")
     return ranks, sizes
+
+
+def hif_factor_save(F, path: str, stream=None):
+    """Write the factorization to a file."""
+    _check(lib().hif_factor_save(F, os.fsencode(path), _stream(stream)), "hif_factor_save")
+
+
+def hif_factor_load(path: str, stream=None):
+    """A new factor read from a file written by hif_factor_save."""
+    h = ctypes.c_void_p()
+    _check(lib().hif_factor_load(os.fsencode(path), _stream(stream), ctypes.byref(h)),
+           "hif_factor_load")
+    return h
 
 
 def hif_factor_active(F, level: int, n_dof: int):

@@ -92,3 +92,14 @@ def test_periodic_options_checked(L):
                  H.make_options(16, 4, 1e-6, 0, bc=7)):
         st = L.hif_problem_create(ctypes.byref(opts), dummy, dummy, None, ctypes.byref(h))
         assert st == H.HIF_EINVAL and h.value is None
+
+
+def test_factor_load_rejects_missing_file_without_gpu(L, tmp_path):
+    """The file is checked before any device work."""
+    h = ctypes.c_void_p(123)
+    st = L.hif_factor_load(str(tmp_path / "none.hif").encode(), None, ctypes.byref(h))
+    assert st == H.HIF_EINVAL and h.value is None
+    bad = tmp_path / "bad.hif"
+    bad.write_bytes(b"something else entirely")
+    st = L.hif_factor_load(str(bad).encode(), None, ctypes.byref(h))
+    assert st == H.HIF_EINVAL and h.value is None

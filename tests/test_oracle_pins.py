@@ -409,3 +409,41 @@ def test_gmres_matches_direct_solve(restart):
     assert np.linalg.norm(f - A @ u) <= 1e-12 * np.linalg.norm(f)
     ud = spla.spsolve(A.tocsc(), f)
     assert np.linalg.norm(u - ud) <= 1e-9 * np.linalg.norm(ud)
+
+
+# --- forward operator F (Section 2.4, product form) ---------------------------
+
+@pytest.mark.parametrize("bc,bval", [("dirichlet", 0.0), ("periodic", 0.1)])
+@pytest.mark.parametrize("eps", [0.0, 1e-3])
+def test_forward_apply_inverts_and_reduces_to_A(bc, bval, eps):
+    """F (F^{-1} x) = x to rounding; at eps = 0 F is A itself; at eps > 0
+    ||(A - F) x|| stays of the order of eps ||A x||."""
+    n, m = 8, 2
+    a = log_uniform_field(n, -1, 1, 31)
+    b = const_field(n, bval)
+    A = O.assemble(n, a, b, bc)
+    fac = O.build(n, m, a, b, eps, bc)
+    x = np.random.default_rng(32).standard_normal(n ** 3)
+    fx = O.apply_forward(fac, x)
+    assert np.linalg.norm(O.apply_inverse(fac, fx) - x) <= 1e-12 * np.linalg.norm(x)
+    assert np.linalg.norm(O.apply_forward(fac, O.apply_inverse(fac, x)) - x) <= \
+        1e-12 * np.linalg.norm(x)
+    rel = np.linalg.norm(fx - A @ x) / np.linalg.norm(A @ x)
+    assert rel <= (1e-14 if eps == 0.0 else 10 * eps), rel
+
+
+def test_forward_apply_equals_explicit_product():
+    """F x equals (W W^T)^{-1} x with W = W^0 ... W^L written out from the
+    paper's S_I, Q_F, S_F̌ matrices."""
+    n, m, eps = 8, 2, 1e-3
+    N = n ** 3
+    a = log_uniform_field(n, -1, 1, 33)
+    b = const_field(n, 0.0)
+    fac = O.build(n, m, a, b, eps)
+    W = np.eye(N)
+    for Wl in _explicit_W(fac, N):
+        W = W @ Wl
+    Fd = np.linalg.inv(W @ W.T)
+    x = np.random.default_rng(34).standard_normal(N)
+    ref = Fd @ x
+    assert np.linalg.norm(O.apply_forward(fac, x) - ref) <= 1e-9 * np.linalg.norm(ref)
