@@ -303,9 +303,11 @@ hif_status hif_profile_end(hif_kernel_stat* out, int32_t cap, int32_t* count);
 hif_status hif_profile_select(const char* classes);
 
 /* Device memory the library released is kept in a process-wide cache for
- * reuse by later calls (up to 48 GB).  This returns all of it to the device
- * after a device synchronization, e.g. between workloads of very different
- * sizes.  Memory held by live problems and factors is not touched. */
+ * reuse by later calls (up to three quarters of the device's memory; an
+ * allocation that finds the device full empties the cache and retries).
+ * This returns all of it to the device after a device synchronization, e.g.
+ * between workloads of very different sizes.  Memory held by live problems
+ * and factors is not touched. */
 hif_status hif_release_cached_memory(void);
 
 /* Tile autotuning (tune_tiles.py drives it; not needed to factor or solve).

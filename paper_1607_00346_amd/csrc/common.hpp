@@ -50,9 +50,9 @@ MemStats& mem_stats();
 // Device memory with a best-fit cache: a released block is kept for reuse by a
 // later allocation that fits in it with at most a quarter of the request (or
 // 2 MiB) to spare (repeated builds of one problem then allocate nothing new).  The cache holds
-// at most kPoolCap bytes; a release that would overflow it first frees the
-// largest cached blocks (a quarter of the cap at once, after one device
-// synchronization).
+// at most three quarters of the device's memory (at least kPoolCap bytes); a
+// release that would overflow it first frees the largest cached blocks (a
+// quarter of the cap at once, after one device synchronization).
 //
 // Reuse is stream ordered: a block released while a StreamScope for stream s
 // is active on this thread is handed out again, without any synchronization,

@@ -81,6 +81,24 @@ void trim_locked(Pool& P, int64_t target) {
   for (auto& kv : P.free_blocks) kv.second.tag = Tag::kClean;
 }
 
+// The cache's cap: three quarters of the device's memory (at least
+// kPoolCap).  A joint build of many problems frees tens of GB of
+// temporaries and factors between its levels and calls; a cap below that
+// volume made releases trim (a device synchronization and hipFree calls in
+// the middle of a level) and the next level allocate afresh.  An allocation
+// that finds the device full still empties the cache and retries.
+int64_t pool_cap() {
+  static const int64_t cap = [] {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+      (void)hipGetLastError();
+      return kPoolCap;
+    }
+    return std::max<int64_t>(kPoolCap, (int64_t)(total_b / 4 * 3));
+  }();
+  return cap;
+}
+
 }  // namespace
 
 void* pool_alloc(size_t bytes) {
@@ -156,10 +174,11 @@ void pool_free(void* p, size_t bytes) {
     sz = it->second;
     P.live.erase(it);
   }
-  if (P.cached + (int64_t)sz > kPoolCap) {
+  const int64_t cap = pool_cap();
+  if (P.cached + (int64_t)sz > cap) {
     // make room for a quarter of the cache at once, so that a build that
     // overflows it synchronizes once rather than at every release
-    trim_locked(P, P.cached + (int64_t)sz - kPoolCap + kPoolCap / 4);
+    trim_locked(P, P.cached + (int64_t)sz - cap + cap / 4);
   }
   Block b{p, t_stream_set ? Tag::kStream : Tag::kUnknown, t_stream};
   P.free_blocks.emplace(sz, b);
