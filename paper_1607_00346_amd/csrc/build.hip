@@ -23,8 +23,7 @@ template <typename T>
 struct Src {
   Stencil st;
   int has_prev;
-  const int* pface;
-  const int* ploc;
+  const int2* pmap;  // per grid point: (level-(l-1) face, index in it) or (-1, 0)
   const T* panels;
   const int64_t* poff;
   const int* pld;
@@ -47,7 +46,8 @@ template <typename T>
 __device__ __forceinline__ ColLookup<T> col_lookup(const Src<T>& s, int q) {
   ColLookup<T> c;
   c.q = q;
-  c.fq = s.has_prev ? s.pface[q] : -1;
+  const int2 mq = s.has_prev ? s.pmap[q] : make_int2(-1, 0);
+  c.fq = mq.x;
   const int n = s.st.n;
   c.qx = q % n;
   c.qy = (q / n) % n;
@@ -59,7 +59,7 @@ __device__ __forceinline__ ColLookup<T> col_lookup(const Src<T>& s, int q) {
     c.goff[t] = 0;
   }
   if (c.fq >= 0) {
-    c.pcol = s.panels + s.poff[c.fq] + (int64_t)s.pld[c.fq] * s.ploc[q];
+    c.pcol = s.panels + s.poff[c.fq] + (int64_t)s.pld[c.fq] * mq.y;
 #pragma unroll
     for (int t = 0; t < kRowBlocks; ++t) {
       c.gface[t] = s.prb_face[kRowBlocks * c.fq + t];
@@ -73,17 +73,18 @@ __device__ __forceinline__ ColLookup<T> col_lookup(const Src<T>& s, int q) {
 // between two points of level-(l-1) faces lives in the panel of the column
 // point's face (zero if the row point's face is not one of its row blocks),
 // and every entry that involves an edge or corner point is still the stencil
-// value.
+// value.  mp is p's entry of the lookup map, read by the caller from an
+// array laid out like its rows (contiguous, not a gather by p).
 template <typename T>
-__device__ __forceinline__ T row_lookup(const Src<T>& s, const ColLookup<T>& c, int p) {
+__device__ __forceinline__ T row_lookup(const Src<T>& s, const ColLookup<T>& c, int p, int2 mp) {
   if (c.fq >= 0) {
-    const int fp = s.pface[p];
+    const int fp = mp.x;
     if (fp >= 0) {
       int off = -1;
 #pragma unroll
       for (int t = 0; t < kRowBlocks; ++t)
         if (c.gface[t] == fp) off = c.goff[t];
-      return off >= 0 ? c.pcol[off + s.ploc[p]] : T(0);
+      return off >= 0 ? c.pcol[off + mp.y] : T(0);
     }
   }
   const int q = c.q;
@@ -120,8 +121,14 @@ __device__ __forceinline__ int wave_column(int block) {
 // Front of cell c, column j: A_II(i, j) for i >= j into Phi, and zeros above
 // the diagonal (the factorization keeps them, so the inverse's products need
 // no triangular masks).
+// Lookup-map entry i of an array laid out like the rows (none at level 0).
+__device__ __forceinline__ int2 map_at(int has_prev, const int2* __restrict__ m, int64_t i) {
+  return has_prev ? m[i] : make_int2(-1, 0);
+}
+
 template <typename T>
 __global__ __launch_bounds__(NT) void k_gather_front(Src<T> s, const int* __restrict__ rows,
+                                                     const int2* __restrict__ rmap,
                                                      const int64_t* __restrict__ crow_off,
                                                      const FrontDesc* __restrict__ fd) {
   const int c = blockIdx.y;
@@ -129,16 +136,19 @@ __global__ __launch_bounds__(NT) void k_gather_front(Src<T> s, const int* __rest
   const int j = wave_column(blockIdx.x);
   if (j >= f.nI) return;
   const int lane = threadIdx.x & 63;
-  const int* r = rows + crow_off[c];
+  const int64_t o = crow_off[c];
+  const int* r = rows + o;
   const ColLookup<T> cl = col_lookup(s, r[j]);
   T* col = static_cast<T*>(f.ptr) + (int64_t)f.ld * j;
   for (int i = lane; i < j; i += 64) col[i] = T(0);
-  for (int i = j + lane; i < f.nI; i += 64) col[i] = row_lookup(s, cl, r[i]);
+  for (int i = j + lane; i < f.nI; i += 64)
+    col[i] = row_lookup(s, cl, r[i], map_at(s.has_prev, rmap, o + i));
 }
 
 // A_SI of cell c, column j (the j-th interior point): nS x nI, leading dimension nS.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_gather_front_SI(Src<T> s, const int* __restrict__ rows,
+                                                        const int2* __restrict__ rmap,
                                                         const int64_t* __restrict__ crow_off,
                                                         const FrontDesc* __restrict__ fd, T* asi,
                                                         const int64_t* __restrict__ aoff) {
@@ -148,17 +158,20 @@ __global__ __launch_bounds__(NT) void k_gather_front_SI(Src<T> s, const int* __r
   if (j >= f.nI) return;
   const int nS = f.nR - f.nI;
   const int lane = threadIdx.x & 63;
-  const int* r = rows + crow_off[c];
+  const int64_t o = crow_off[c];
+  const int* r = rows + o;
   const ColLookup<T> cl = col_lookup(s, r[j]);
   T* col = asi + aoff[c] + (int64_t)nS * j;
-  for (int i = lane; i < nS; i += 64) col[i] = row_lookup(s, cl, r[f.nI + i]);
+  for (int i = lane; i < nS; i += 64)
+    col[i] = row_lookup(s, cl, r[f.nI + i], map_at(s.has_prev, rmap, o + f.nI + i));
 }
 
 // Panel of face f, column j: Ã^l(rows, F_j) = A^l(rows, F_j) + U_A + U_B, the
 // Schur updates of the two neighbouring cells added in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_gather_panel(
-    Src<T> s, const int* __restrict__ fpts, const int64_t* __restrict__ fpt_off,
+    Src<T> s, const int* __restrict__ fpts, const int2* __restrict__ fmap,
+    const int64_t* __restrict__ fpt_off,
     const int* __restrict__ fN, const int* __restrict__ rb_face, const int* __restrict__ rb_off,
     const int* __restrict__ rb_sa, const int* __restrict__ rb_sb, const int* __restrict__ fcellA,
     const int* __restrict__ fcellB, const T* __restrict__ U, const int64_t* __restrict__ uoff,
@@ -181,9 +194,10 @@ __global__ __launch_bounds__(NT) void k_gather_panel(
     if (g < 0) break;
     const int ro = rb_off[base + t], sa = rb_sa[base + t], sb = rb_sb[base + t];
     const int ng = fN[g];
-    const int* G = fpts + fpt_off[g];
+    const int64_t go = fpt_off[g];
+    const int* G = fpts + go;
     for (int i = lane; i < ng; i += 64) {
-      T v = row_lookup(s, cl, G[i]);
+      T v = row_lookup(s, cl, G[i], map_at(s.has_prev, fmap, go + i));
       if (sa >= 0) v += UA[(sa + i) + (int64_t)ldA * colA];
       if (sb >= 0) v += UB[(sb + i) + (int64_t)ldB * colB];
       col[ro + i] = v;
@@ -317,31 +331,37 @@ __global__ __launch_bounds__(NT) void k_perm_points(const int* __restrict__ fpts
   skpts[o + j] = fpts[o + perm[o + j]];
 }
 
-// Lookup maps for the next level: the face of every face point and its index
-// within the face (-1 for every other point; the fill runs first).
-__global__ __launch_bounds__(NT) void k_fill_int(int* p, int64_t n, int v) {
+// Lookup map for the next level: (face, index within the face) of every face
+// point, (-1, 0) for every other point (the fill runs first).
+__global__ __launch_bounds__(NT) void k_fill_map(int2* p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
-    p[i] = v;
+    p[i] = make_int2(-1, 0);
 }
 
 __global__ __launch_bounds__(NT) void k_face_map(const int* __restrict__ fpts,
                                                  const int64_t* __restrict__ fpt_off,
-                                                 const int* __restrict__ fN, int* pface, int* ploc) {
+                                                 const int* __restrict__ fN, int2* pmap) {
   const int f = blockIdx.y;
   const int j = blockIdx.x * NT + threadIdx.x;
   if (j >= fN[f]) return;
   const int p = fpts[fpt_off[f] + j];
-  pface[p] = f;
-  ploc[p] = j;
+  pmap[p] = make_int2(f, j);
+}
+
+// out[t] = pmap[idx[t]]: the map entries of a row list, laid out like it, so
+// that the gathers read them contiguously instead of gathering by point.
+__global__ __launch_bounds__(NT) void k_map_rows(const int* __restrict__ idx, int64_t n,
+                                                 const int2* __restrict__ pmap, int2* out) {
+  for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT)
+    out[t] = pmap[idx[t]];
 }
 
 template <typename T>
-Src<T> make_src(const hif_problem_s* A, const Level<T>* prev, const int* pface, const int* ploc) {
+Src<T> make_src(const hif_problem_s* A, const Level<T>* prev, const int2* pmap) {
   Src<T> s;
   s.st = A->stencil();
   s.has_prev = prev != nullptr;
-  s.pface = pface;
-  s.ploc = ploc;
+  s.pmap = pmap;
   s.panels = prev ? prev->panel.get() : nullptr;
   s.poff = prev ? prev->panel_off.get() : nullptr;
   s.pld = prev ? prev->panel_ld.get() : nullptr;
@@ -395,8 +415,9 @@ struct Job {
   // 0 for points the ID has left out so far (the candidates of a level are
   // separator points of the level below, so interior points never need it)
   std::vector<uint8_t> active;
-  // face / local index of every level-(l-1) face point, for the A^l lookup
-  DevBuf<int> d_pface, d_ploc;
+  // (face, index in it) of every level-(l-1) face point, for the A^l lookup,
+  // and that map laid out like the level's front rows and face points
+  DevBuf<int2> d_pmap, rmap, fmap;
   // temporaries of the current level
   DevBuf<T> ASI, U, Ahh, Ahc;
   DevBuf<int64_t> d_xoff, d_o11, d_o21, d_ohh, d_ohc;
@@ -464,8 +485,7 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
     }
     J.active.assign((size_t)J.N, 1);
     if (J.L > 0) {
-      J.d_pface.alloc(J.N);
-      J.d_ploc.alloc(J.N);
+      J.d_pmap.alloc(J.N);
     }
     maxL = std::max(maxL, J.L);
   }
@@ -530,7 +550,7 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
       lev.plan = level == 0 ? A->plan0
                             : std::make_shared<const LevelPlan>(plan_level(A->geom[level], J.active));
       const LevelPlan& P = *lev.plan;
-      const Src<T> src = make_src<T>(A, prev, J.d_pface.get(), J.d_ploc.get());
+      const Src<T> src = make_src<T>(A, prev, J.d_pmap.get());
       // index arrays of the plan; level 0's are uploaded once per problem
       auto arr = [&](auto& cached, const auto& host) {
         if (level > 0) return dev_arr(host, s);
@@ -581,15 +601,25 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
       J.d_xoff = to_dev(xoff, s);
       {
         ProfScope ps("gather_front", s);
+        if (prev) {
+          const int64_t nr = (int64_t)P.rows.size();
+          J.rmap.alloc(std::max<int64_t>(nr, 1));
+          hipLaunchKernelGGL(k_map_rows, dim3((unsigned)std::min<int64_t>(ceil_div(nr, NT), 8192)),
+                             dim3(NT), 0, s, lev.rows.get(), nr, (const int2*)J.d_pmap.get(),
+                             J.rmap.get());
+          HIF_LAUNCH_CHECK();
+        }
         dim3 g((unsigned)ceil_div(std::max(1, lev.maxI), kGatherCols), (unsigned)P.ncell);
         hipLaunchKernelGGL((k_gather_front<T>), g, dim3(NT), 0, s, src, lev.rows.get(),
-                           lev.crow_off.get(), lev.fd.get());
+                           (const int2*)J.rmap.get(), lev.crow_off.get(), lev.fd.get());
         HIF_LAUNCH_CHECK();
         if (lev.maxS > 0) {
           hipLaunchKernelGGL((k_gather_front_SI<T>), g, dim3(NT), 0, s, src, lev.rows.get(),
-                             lev.crow_off.get(), lev.fd.get(), J.ASI.get(), J.d_xoff.get());
+                             (const int2*)J.rmap.get(), lev.crow_off.get(), lev.fd.get(),
+                             J.ASI.get(), J.d_xoff.get());
           HIF_LAUNCH_CHECK();
         }
+        J.rmap.release();
       }
       // interior Cholesky and in-place inverse on the top nI x nI block
       for (int c = 0; c < P.ncell; ++c) {
@@ -664,7 +694,7 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
       Level<T>& lev = J.impl->levels[level];
       Level<T>* prev = level > 0 ? &J.impl->levels[level - 1] : nullptr;
       const LevelPlan& P = *lev.plan;
-      const Src<T> src = make_src<T>(A, prev, J.d_pface.get(), J.d_ploc.get());
+      const Src<T> src = make_src<T>(A, prev, J.d_pmap.get());
       auto arr = [&](auto& cached, const auto& host) {
         if (level > 0) return dev_arr(host, s);
         if (!cached.buf) cached = dev_arr(host, s);
@@ -696,15 +726,24 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
         DevBuf<int64_t> d_uoff = to_dev(J.uoff, s);
         DevBuf<int> d_uld = to_dev(J.uld, s);
         ProfScope ps("gather_panel", s);
+        if (prev) {
+          const int64_t nf = (int64_t)P.fpts.size();
+          J.fmap.alloc(std::max<int64_t>(nf, 1));
+          hipLaunchKernelGGL(k_map_rows, dim3((unsigned)std::min<int64_t>(ceil_div(nf, NT), 8192)),
+                             dim3(NT), 0, s, lev.fpts.get(), nf, (const int2*)J.d_pmap.get(),
+                             J.fmap.get());
+          HIF_LAUNCH_CHECK();
+        }
         dim3 g((unsigned)ceil_div(std::max(1, lev.maxF), kGatherCols), (unsigned)P.nface);
         hipLaunchKernelGGL((k_gather_panel<T>), g, dim3(NT), 0, s, src, lev.fpts.get(),
-                           lev.fpt_off.get(), lev.fN.get(), lev.rb_face.get(), lev.rb_off.get(),
-                           lev.rb_sa.get(), lev.rb_sb.get(), lev.fcellA.get(), lev.fcellB.get(),
+                           (const int2*)J.fmap.get(), lev.fpt_off.get(), lev.fN.get(),
+                           lev.rb_face.get(), lev.rb_off.get(), lev.rb_sa.get(), lev.rb_sb.get(), lev.fcellA.get(), lev.fcellB.get(),
                            J.U.get(), d_uoff.get(), d_uld.get(), lev.panel.get(),
                            lev.panel_off.get(), lev.panel_ld.get());
         HIF_LAUNCH_CHECK();
       }
       J.U.release();
+      J.fmap.release();
       if (prev) prev->panel.release();  // A^l has been read for the last time
       for (int f = 0; f < P.nface; ++f) st.face_dofs[level] += P.fN[f];
       lev.hk.assign(P.nface, 0);
@@ -996,13 +1035,13 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
       st.redundant[level] = lev.redundant;
 
       // ---- next level's active set and lookup maps ------------------------
-      hipLaunchKernelGGL(k_fill_int, dim3((unsigned)std::min<int64_t>(ceil_div(J.N, NT), 8192)),
-                         dim3(NT), 0, s, J.d_pface.get(), J.N, -1);
+      hipLaunchKernelGGL(k_fill_map, dim3((unsigned)std::min<int64_t>(ceil_div(J.N, NT), 8192)),
+                         dim3(NT), 0, s, J.d_pmap.get(), J.N);
       HIF_LAUNCH_CHECK();
       if (P.nface > 0) {
         dim3 g((unsigned)ceil_div(std::max(1, lev.maxF), NT), (unsigned)P.nface);
         hipLaunchKernelGGL(k_face_map, g, dim3(NT), 0, s, lev.fpts.get(), lev.fpt_off.get(),
-                           lev.fN.get(), J.d_pface.get(), J.d_ploc.get());
+                           lev.fN.get(), J.d_pmap.get());
         HIF_LAUNCH_CHECK();
       }
       std::vector<int> red;
