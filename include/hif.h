@@ -82,8 +82,11 @@ typedef struct {
                         level l are the planes x_d = w j, j >= 1 (w = leaf 2^l).
                         HIF_PERIODIC (n >= 4): the paper's setting; every plane
                         x_d = w j, j >= 0, below the root is a separator, the
-                        faces on x_d = 0 joining the last and the first cell.
-                        A must be positive definite (periodic: b > 0 somewhere). */
+                        faces on x_d = 0 joining the last and the first cell;
+                        the root is factored as L S L^T (the paper's LDL^T, S =
+                        sign(D), unpivoted), since compression can make it
+                        indefinite along the constant mode.  Cell interiors
+                        and the other factored blocks must be definite.      */
 } hif_options;
 
 typedef struct {      /* result of hif_pcg, hif_pcg_batched and hif_gmres        */

@@ -505,8 +505,11 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
     for (int l = 0; l <= maxL; ++l) {
       if (h_err[2 * l] != kNoErr) {
         const Owner w = own_front[l].at(h_err[2 * l]);
-        throw Error(HIF_ENOTSPD, "non-positive pivot in the interior Cholesky at level " +
-                                     std::to_string(l) + ", cell " + std::to_string(w.index) +
+        const bool ldl = l == jobs[w.job].L && jobs[w.job].A->opts.bc == HIF_PERIODIC;
+        throw Error(HIF_ENOTSPD, (ldl ? std::string("zero pivot in the LDL^T of the root")
+                                      : "non-positive pivot in the interior Cholesky at level " +
+                                            std::to_string(l) + ", cell " +
+                                            std::to_string(w.index)) +
                                      of_problem(w.job));
       }
       if (h_err[2 * l + 1] != kNoErr) {
@@ -540,6 +543,7 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
 
     // ---- fronts: gather, partial Cholesky + inverse (Section 2.2) -------
     std::vector<FrontDesc> tops;
+    std::vector<std::pair<int, FrontDesc>> ldl_roots;  // periodic roots: signed LDL^T
     std::vector<GemmDesc> g_lsi;
     for (int j : here) {
       Job<T>& J = jobs[j];
@@ -621,13 +625,17 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
         }
         J.rmap.release();
       }
-      // interior Cholesky and in-place inverse on the top nI x nI block
+      // interior Cholesky and in-place inverse on the top nI x nI block; the
+      // root of a periodic problem keeps the LDL^T of the paper (Section 2.2):
+      // compression can leave it indefinite along the near-constant mode
+      const bool signed_root = level == J.L && A->opts.bc == HIF_PERIODIC;
       for (int c = 0; c < P.ncell; ++c) {
         FrontDesc t = lev.hfd[c];
         t.nR = t.nI;
         t.id = (int)own_front[level].size();
         own_front[level].push_back({j, c});
-        tops.push_back(t);
+        if (signed_root && t.nI > 0) ldl_roots.push_back({j, t});
+        else tops.push_back(t);
       }
       // L_SI = A_SI L_I^{-T} into the front below L_I^{-1} (L_I^{-T} is upper)
       for (int c = 0; c < P.ncell; ++c) {
@@ -642,6 +650,12 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
       DevBuf<FrontDesc> d_top = to_dev(tops, s);
       front_factor<T>(d_top.get(), tops, d_err.get() + 2 * level, s, true,
                       level == 0 ? kSmallFrontLeaf : kSmallFrontUpper);
+    }
+    for (auto& jr : ldl_roots) {
+      Level<T>& lev = jobs[jr.first].impl->levels[level];
+      lev.sign.alloc(jr.second.nI);
+      DevBuf<FrontDesc> d_root = to_dev(std::vector<FrontDesc>{jr.second}, s);
+      root_ldl<T>(jr.second, d_root.get(), lev.sign.get(), d_err.get() + 2 * level, s);
     }
     run_gemms<T, T>("gemm_lsi", OP_N, OP_T, GF_B_UPPER | GF_TRI_ZEROS, g_lsi, T(1), T(0), s,
                     GC_LSI);

@@ -1107,6 +1107,100 @@ void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
   front_invert<T>(d_fronts, h_fronts, s, upper_zero);
 }
 
+// ---- signed LDL^T of one dense front (the root of a periodic problem) -----
+//
+// A = L S L^T with S = diag(+-1) and L lower triangular with a positive
+// diagonal (the paper's LDL^T with L = L_unit |D|^{1/2}), unpivoted, blocked
+// right-looking in kPanel-column steps: the diagonal block in one workgroup,
+// the panel rows below one per thread, the trailing matrix by the batched GEMM
+// with the sign-scaled panel as one operand.
+
+// Diagonal block A(j0:j0+nb, j0:j0+nb) -> L_jj and its signs, in LDS by one
+// workgroup, column by column.  A zero (or non-finite) pivot sets *err to id
+// and continues with a unit pivot.
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_ldl_diag(T* A, int ld, int j0, int nb, T* sgn,
+                                                   int* err, int id) {
+  __shared__ T a[kPanel][kPanel + 1];  // a[c][r] = A(j0 + r, j0 + c)
+  __shared__ T piv, sg;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb * nb; e += NTHR) {
+    const int c = e / nb, r = e % nb;
+    a[c][r] = r >= c ? A[(j0 + r) + (int64_t)ld * (j0 + c)] : T(0);
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int t = 0; t < nb; ++t) {
+    if (tid == 0) {
+      T d = a[t][t];
+      const bool ok = d != T(0) && isfinite((double)d);
+      bad = bad || !ok;
+      if (!ok) d = T(1);
+      sg = d > T(0) ? T(1) : T(-1);
+      piv = sqrt(d > T(0) ? d : -d);
+      a[t][t] = piv;
+    }
+    __syncthreads();
+    const T den = sg * piv;
+    for (int r = t + 1 + tid; r < nb; r += NTHR) a[t][r] /= den;
+    __syncthreads();
+    // a(r, c) -= L(r, t) s_t L(c, t) for t < c <= r
+    const T st = sg;
+    for (int e = tid; e < nb * nb; e += NTHR) {
+      const int c = e / nb, r = e % nb;
+      if (c > t && r >= c) a[c][r] -= a[t][r] * st * a[t][c];
+    }
+    if (tid == 0) sgn[j0 + t] = st;
+    __syncthreads();
+  }
+  for (int e = tid; e < nb * nb; e += NTHR) {
+    const int c = e / nb, r = e % nb;
+    if (r >= c) A[(j0 + r) + (int64_t)ld * (j0 + c)] = a[c][r];
+  }
+  if (bad) atomicMin(err, id);
+}
+
+// Panel rows below the diagonal block: L(i, j0:j1) = A(i, j0:j1) L_jj^{-T} S_j,
+// one row per thread; W(i - j1, :) = L(i, j0:j1) S_j, the trailing update's
+// left operand (leading dimension ldw).
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_ldl_rows(T* A, int ld, int n, int j0, int nb,
+                                                   const T* __restrict__ sgn, T* W, int ldw) {
+  __shared__ T l[kPanel][kPanel + 1];  // l[c][r] = L_jj(r, c)
+  __shared__ T sj[kPanel];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb * nb; e += NTHR) {
+    const int c = e / nb, r = e % nb;
+    l[c][r] = r >= c ? A[(j0 + r) + (int64_t)ld * (j0 + c)] : T(0);
+  }
+  if (tid < nb) sj[tid] = sgn[j0 + tid];
+  __syncthreads();
+  const int j1 = j0 + nb;
+  const int i = j1 + blockIdx.x * NTHR + tid;
+  if (i >= n) return;
+  T y[kPanel];
+#pragma unroll
+  for (int t = 0; t < kPanel; ++t) y[t] = t < nb ? A[i + (int64_t)ld * (j0 + t)] : T(0);
+  // y L_jj^T = a_i: forward substitution
+#pragma unroll
+  for (int t = 0; t < kPanel; ++t) {
+    if (t < nb) {
+      T v = y[t];
+#pragma unroll
+      for (int u = 0; u < t; ++u) v -= y[u] * l[u][t];
+      y[t] = v / l[t][t];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kPanel; ++t) {
+    if (t < nb) {
+      const T v = y[t] * sj[t];
+      A[i + (int64_t)ld * (j0 + t)] = v;
+      W[(i - j1) + (int64_t)ldw * t] = v * sj[t];
+    }
+  }
+}
+
 // In-place inverse of the lower-triangular L_I of every front, bottom-up over
 // doubling block sizes: with the two diagonal halves already inverted,
 // inv([[A, 0], [B, C]]) = [[A^-1, 0], [-C^-1 B A^-1, C^-1]].
@@ -1239,6 +1333,40 @@ template void gemm_batched<float, float>(int, int, int, const GemmDesc*, int, in
                                          float, hipStream_t, const char*, double, int);
 template void gemm_batched<float, double>(int, int, int, const GemmDesc*, int, int, int, double,
                                           double, hipStream_t, const char*, double, int);
+template <typename T>
+void root_ldl(const FrontDesc& f, const FrontDesc* d_front, T* sgn, int* err, hipStream_t s) {
+  const int n = f.nI, ld = f.ld;
+  T* A = static_cast<T*>(f.ptr);
+  DevBuf<T> W((size_t)std::max(1, n) * kPanel);
+  DevBuf<GemmDesc> dd;
+  for (int j0 = 0; j0 < n; j0 += kPanel) {
+    const int nb = std::min(kPanel, n - j0);
+    const int j1 = j0 + nb, m = n - j1;
+    const double fl = nb * (double)nb * nb / 3.0 + m * (double)nb * nb;
+    {
+      ProfScope ps("ldl_step", s, fl);
+      hipLaunchKernelGGL((k_ldl_diag<T>), dim3(1), dim3(NTHR), 0, s, A, ld, j0, nb, sgn, err,
+                         f.id);
+      if (m > 0)
+        hipLaunchKernelGGL((k_ldl_rows<T>), dim3((unsigned)ceil_div(m, NTHR)), dim3(NTHR), 0, s,
+                           A, ld, n, j0, nb, (const T*)sgn, W.get(), std::max(1, m));
+      HIF_LAUNCH_CHECK();
+    }
+    if (m == 0) break;
+    // A(j1:n, j1:n) -= (L_21 S) L_21^T, lower triangle
+    const std::vector<GemmDesc> g = {{W.get(), A + j1 + (int64_t)ld * j0, A + j1 + (int64_t)ld * j1,
+                                      m, m, nb, std::max(1, m), ld, ld}};
+    dd.upload(g, s);
+    gemm_batched<T, T>(OP_N, OP_T, GF_C_LOWER, dd.get(), 1, m, m, T(-1), T(1), s, "ldl_trailing",
+                       gemm_flops(g[0], GF_C_LOWER));
+  }
+  std::vector<FrontDesc> hf = {f};
+  front_invert<T>(d_front, hf, s, true);
+}
+
+template void root_ldl<double>(const FrontDesc&, const FrontDesc*, double*, int*, hipStream_t);
+template void root_ldl<float>(const FrontDesc&, const FrontDesc*, float*, int*, hipStream_t);
+
 template void front_factor<double>(const FrontDesc*, const std::vector<FrontDesc>&, int*,
                                    hipStream_t, bool, int);
 template void front_factor<float>(const FrontDesc*, const std::vector<FrontDesc>&, int*,

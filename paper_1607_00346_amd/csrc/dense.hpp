@@ -99,6 +99,14 @@ template <typename T>
 void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
                   int* err, hipStream_t s, bool upper_zero, int small_limit);
 
+// Signed LDL^T of one dense front f (nI x nI, no shell rows, strict upper
+// triangle stored as zeros; d_front is f on the device): f <- L^{-1} in place
+// and sgn[0..nI) <- S, where A = L S L^T with S = diag(+-1) and L lower
+// triangular with a positive diagonal (unpivoted; the paper's LDL^T stored as
+// L_unit |D|^{1/2} and sign(D)).  A zero pivot sets *err to f.id.
+template <typename T>
+void root_ldl(const FrontDesc& f, const FrontDesc* d_front, T* sgn, int* err, hipStream_t s);
+
 // Only the in-place inverse of an already factored lower-triangular L_I.
 template <typename T>
 void front_invert(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,

@@ -61,6 +61,7 @@ struct Level {
   std::vector<FrontDesc> hfd;
   DevBuf<FrontDesc> fd;
   DevBuf<T> front;  // per cell [L_I^{-1}; L_SI], (nI+nS) x nI column-major
+  DevBuf<T> sign;   // root of a periodic problem: S of its L S L^T (+-1 per row)
   DevBuf<int64_t> yoff, zoff;  // per cell offsets into the apply scratch vectors
   std::vector<int64_t> hyoff, hzoff;
   int64_t ysum = 0, zsum = 0;
@@ -147,6 +148,9 @@ struct FactorImpl : FactorBase {
   void apply_scratch(const double* f, double* u, double* scratch, int64_t cap,
                      hipStream_t s) override;
   int64_t scratch_doubles() const override;
+  // Multiply the root's rows of ncol vectors (leading dimension ldu) by the
+  // signs of its L S L^T (a no-op unless the root is a periodic problem's).
+  void root_sign(double* u, int64_t ldu, int ncol, hipStream_t s);
   // The single-vector sweeps on the given scratch segments: xi, yv (ymax
   // each), zv, xsv (zmax each), sh (kmax), sc, sc2 (rmax each).
   void sweep(const double* f, double* u, double* xi, double* yv, double* zv, double* xsv,

@@ -5,7 +5,7 @@
 // sizes and redundant points (the ID's outcome), the face points in pivot
 // order, and the numeric arenas of the fronts ([L_I^{-1}; L_SI] per cell)
 // and of the skeletons (T, L_F̌^{-1}, Y per face), in the factor's
-// precision.  Everything else -- the cell/face plans, block layouts and
+// precision, and the signs of a periodic root's L S L^T.  Everything else -- the cell/face plans, block layouts and
 // sweep descriptors -- is a function of the grid, the leaf width, the
 // boundary condition and the redundant points, and is rebuilt on load the
 // way the build lays it out.
@@ -20,7 +20,7 @@ namespace hif {
 namespace {
 
 constexpr char kMagic[8] = {'H', 'I', 'F', 'F', 'A', 'C', 'T', '1'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 
 struct File {
   FILE* f = nullptr;
@@ -85,6 +85,7 @@ void save_impl(const hif_factor_s* F, const FactorImpl<T>& I, File& out, hipStre
     if (l < L) put_dev(out, lv.skpts, s);
     put_dev(out, lv.front, s);
     if (l < L) put_dev(out, lv.skel, s);
+    else put_dev(out, lv.sign, s);  // the signs of a periodic root's L S L^T (else empty)
   }
 }
 
@@ -151,7 +152,13 @@ std::unique_ptr<FactorImpl<T>> load_impl(hif_factor_s* F, File& in, hipStream_t 
     lv.fd.upload(lv.hfd, s);
     lv.yoff.upload(lv.hyoff, s);
     lv.zoff.upload(lv.hzoff, s);
-    if (l == L) break;
+    if (l == L) {
+      std::vector<T> sign = in.get_vec<T>((uint64_t)lv.ysum);
+      HIF_REQUIRE(sign.empty() || (int64_t)sign.size() == lv.ysum, HIF_EINVAL,
+                  "factor file does not match its grid: " + in.path);
+      lv.sign.upload(sign, s);
+      break;
+    }
     // faces: the skeleton layout of the build
     lv.fpts = dev_arr(P.fpts, s);
     lv.fpt_off = dev_arr(P.fpt_off, s);

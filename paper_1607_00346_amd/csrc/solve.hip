@@ -754,6 +754,18 @@ __global__ __launch_bounds__(NT) void k_skel_move_b(double* u, int64_t N,
   else *s = (T)u[p];
 }
 
+// u[rows[i]] *= sign[i] for every column of u (leading dimension ldu): the
+// S = diag(+-1) between the two triangular sweeps of a periodic root.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_root_sign(double* u, int64_t ldu, int ncol,
+                                                  const int* __restrict__ rows,
+                                                  const T* __restrict__ sign, int n) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const double sg = (double)sign[i];
+  for (int c = 0; c < ncol; ++c) u[(int64_t)c * ldu + rows[i]] *= sg;
+}
+
 // ---- forward apply: products with L and L^T from the stored L^{-1} -------
 //
 // One workgroup per block; thread t owns the rows i = t (mod NT) of the
@@ -1043,6 +1055,16 @@ void launch_skel_fused(const Level<T>& lv, int mode, double* u, int down, hipStr
 }
 
 template <typename T>
+void FactorImpl<T>::root_sign(double* u, int64_t ldu, int ncol, hipStream_t s) {
+  const Level<T>& lv = levels.back();
+  if (lv.sign.size() == 0 || lv.plan->ncell == 0) return;
+  const int n = lv.hfd[0].nI;
+  hipLaunchKernelGGL((k_root_sign<T>), dim3((unsigned)ceil_div(std::max(1, n), NT)), dim3(NT), 0,
+                     s, u, ldu, ncol, lv.rows.get(), (const T*)lv.sign.get(), n);
+  HIF_LAUNCH_CHECK();
+}
+
+template <typename T>
 void FactorImpl<T>::apply(const double* f, double* u, hipStream_t s) {
   prepare(s);
   double* sc = sbuf.get() + kmax;
@@ -1151,6 +1173,7 @@ void FactorImpl<T>::sweep(const double* f, double* u, double* xi, double* yv, do
       }
     }
   }
+  root_sign(u, N, 1, s);
   // W^l for l = L..0
   for (int l = nlev - 1; l >= 0; --l) {
     Level<T>& lv = levels[l];
@@ -1285,13 +1308,16 @@ void FactorImpl<T>::apply_forward(const double* f, double* u, hipStream_t s) {
       skel_move(lv, 1);
     }
   }
-  // the root: x <- L_Sigma^T x, then x <- L_Sigma x
+  // the root: x <- L_Sigma^T x, then x <- S x (periodic roots), then x <- L_Sigma x
   {
     Level<T>& lv = levels[nlev - 1];
     prof_level() = nlev - 1;
     if (lv.plan->ncell > 0) {
       gather(lv, 0);
       trsv(lv, false, false, xi);
+      scatter(lv);
+      root_sign(u, N, 1, s);
+      gather(lv, 0);
       trsv(lv, false, true, xi);
       scatter(lv);
     }
@@ -1478,6 +1504,7 @@ void FactorImpl<T>::apply_block(const double* f, double* u, int nrhs, hipStream_
         }
       }
     }
+    root_sign(U, N, nc, s);
     for (int l = nlev - 1; l >= 0; --l) {
       Level<T>& lv = levels[l];
       prof_level() = l;

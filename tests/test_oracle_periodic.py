@@ -86,13 +86,18 @@ def test_ldl_signed_reconstructs_and_keeps_inertia():
 
 def test_periodic_indefinite_root_keeps_ldl():
     """With b = 0.1 on the 1/h^2 stencil the constant mode's eigenvalue (0.1)
-    is far below the compression error at eps = 1e-2 on this grid, so the
-    compressed root is indefinite: the LDL^T root still gives an F^{-1} with
-    which GMRES reaches 1e-12."""
-    n, m = 12, 3
+    is far below the compression error: at 32^3, leaf 8, eps = 1e-3 the
+    compressed root is indefinite (Cholesky fails on it, the LDL^T keeps at
+    least one negative sign), and GMRES with the LDL^T-rooted F^{-1} still
+    reaches 1e-12."""
+    n, m = 32, 8
     a, b = const_field(n, 1.0), const_field(n, 0.1)
     A = O.assemble(n, a, b, "periodic")
-    fac = O.build(n, m, a, b, 1e-2, "periodic")
+    fac = O.build(n, m, a, b, 1e-3, "periodic")
+    assert int(np.sum(fac.Sroot < 0)) >= 1
+    Lm = fac.Lroot * fac.Sroot
+    with pytest.raises(O.NotSPD):
+        O.cholesky(Lm @ fac.Lroot.T)
     f = normal_rhs(n, 24)
     u, its, rel, ok = O.gmres(A, lambda r: O.apply_inverse(fac, r), f, 1e-12, 50, 200)
     assert ok and rel <= 1e-12
@@ -114,3 +119,20 @@ def test_paper_example1_32():
     assert 4.84e-4 / 3 <= es <= 4.84e-4 * 3, es
     _, its, rel, ok = O.gmres(A, lambda r: O.apply_inverse(fac, r), f, 1e-12, 50, 100)
     assert ok and its == 6
+
+
+@pytest.mark.parametrize("n,m", [(8, 8), (16, 4)])
+def test_periodic_negative_b_exact_with_ldl_root(n, m):
+    """b = -10: the periodic operator has one negative eigenvalue (the
+    constant mode's), the cell interiors stay definite, and at eps = 0 the
+    LDL^T root (one negative sign, by Sylvester's law) gives A^{-1} exactly."""
+    a, b = log_uniform_field(n, -1, 1, 5), const_field(n, -10.0)
+    A = O.assemble(n, a, b, "periodic")
+    assert int(np.sum(np.linalg.eigvalsh(A.toarray()) < 0)) == 1
+    fac = O.build(n, m, a, b, 0.0, "periodic")
+    assert int(np.sum(fac.Sroot < 0)) == 1
+    f = normal_rhs(n, 64)
+    x = O.apply_inverse(fac, f)
+    xd = spla.spsolve(A.tocsc(), f)
+    assert np.linalg.norm(x - xd) <= 1e-11 * np.linalg.norm(xd)
+    assert np.linalg.norm(O.apply_forward(fac, x) - f) <= 1e-11 * np.linalg.norm(f)
