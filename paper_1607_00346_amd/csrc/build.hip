@@ -161,7 +161,7 @@ __global__ __launch_bounds__(NT) void k_gather_front_SI(Src<T> s, const int* __r
   const int64_t o = crow_off[c];
   const int* r = rows + o;
   const ColLookup<T> cl = col_lookup(s, r[j]);
-  T* col = asi + aoff[c] + (int64_t)nS * j;
+  T* col = asi + aoff[c] + (int64_t)((nS + 3) / 4 * 4) * j;  // leading dimension pad_ld(nS)
   for (int i = lane; i < nS; i += 64)
     col[i] = row_lookup(s, cl, r[f.nI + i], map_at(s.has_prev, rmap, o + f.nI + i));
 }
@@ -377,10 +377,47 @@ DevBuf<V> to_dev(const std::vector<V>& h, hipStream_t s) {
   return d;
 }
 
+// The batched GEMM kernels give XCD x the x-th eighth of a launch's products
+// (the tiles of one product share its operands in that XCD's L2).  Order a
+// batch of Schur or L_SI products so that the eighths cost the same: products
+// are dealt, largest first, onto the least loaded eighth among those not yet
+// full, and each eighth runs its largest first; the batch is padded with
+// empty products to a multiple of eight.  Only the order changes, never a
+// result.
+std::vector<GemmDesc> balance_xcds(const std::vector<GemmDesc>& h, int flags, int cls) {
+  constexpr int kXcd = 8;
+  const size_t per = (h.size() + kXcd - 1) / kXcd;
+  if (h.size() < 2 * kXcd || per * kXcd > 65535) return h;  // one launch only
+  // only the large products of the cell fronts (reordering the many small
+  // products of the face steps measured slower)
+  if (cls != GC_SYRK && cls != GC_LSI) return h;
+  std::vector<double> cost(per * kXcd, 0.0);
+  for (size_t i = 0; i < h.size(); ++i) cost[i] = gemm_flops(h[i], flags);
+  std::vector<size_t> idx(cost.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  std::vector<std::vector<size_t>> grp(kXcd);
+  std::vector<double> load(kXcd, 0.0);
+  for (size_t i : idx) {
+    int best = -1;
+    for (int g = 0; g < kXcd; ++g)
+      if (grp[g].size() < per && (best < 0 || load[g] < load[best])) best = g;
+    grp[best].push_back(i);
+    load[best] += cost[i];
+  }
+  const GemmDesc empty{nullptr, nullptr, nullptr, 0, 0, 0, 1, 1, 1};
+  std::vector<GemmDesc> out;
+  out.reserve(cost.size());
+  for (auto& g : grp)
+    for (size_t i : g) out.push_back(i < h.size() ? h[i] : empty);
+  return out;
+}
+
 template <typename TIn, typename TC>
-void run_gemms(const char* name, int opa, int opb, int flags, const std::vector<GemmDesc>& h,
+void run_gemms(const char* name, int opa, int opb, int flags, const std::vector<GemmDesc>& h0,
                TC alpha, TC beta, hipStream_t s, int cls = GC_GENERIC) {
-  if (h.empty()) return;
+  if (h0.empty()) return;
+  const std::vector<GemmDesc> h = balance_xcds(h0, flags, cls);
   int mm = 0, mn = 0;
   double fl = 0.0;
   for (auto& d : h) {
@@ -388,10 +425,14 @@ void run_gemms(const char* name, int opa, int opb, int flags, const std::vector<
     mn = std::max(mn, d.n);
     fl += gemm_flops(d, flags);
   }
+  // leading dimensions on the 16-byte grid let the batch take the DMA-fed tile
+  constexpr int V = 16 / (int)sizeof(TIn);
+  bool ld16 = true;
+  for (auto& d : h) ld16 = ld16 && d.lda % V == 0 && d.ldb % V == 0;
   DevBuf<GemmDesc> d;
   d.upload(h, s);
   gemm_batched<TIn, TC>(opa, opb, flags, d.get(), (int)h.size(), mm, mn, alpha, beta, s, name, fl,
-                        cls);
+                        cls, ld16);
 }
 
 double now_s() {
@@ -599,7 +640,7 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
       int64_t xsz = 0;
       for (int c = 0; c < P.ncell; ++c) {
         xoff[c] = xsz;
-        xsz += (int64_t)P.cI[c] * P.cS[c];
+        xsz += (int64_t)P.cI[c] * pad_ld(P.cS[c]);
       }
       J.ASI.alloc(std::max<int64_t>(xsz, 1));
       J.d_xoff = to_dev(xoff, s);
@@ -642,8 +683,8 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
         if (P.cS[c] == 0) continue;
         const FrontDesc& d = lev.hfd[c];
         T* base = static_cast<T*>(d.ptr);
-        g_lsi.push_back({J.ASI.get() + xoff[c], base, base + d.nI, P.cS[c], d.nI, d.nI, P.cS[c],
-                         d.ld, d.ld});
+        g_lsi.push_back({J.ASI.get() + xoff[c], base, base + d.nI, P.cS[c], d.nI, d.nI,
+                         pad_ld(P.cS[c]), d.ld, d.ld});
       }
     }
     if (!tops.empty()) {

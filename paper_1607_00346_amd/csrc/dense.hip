@@ -12,6 +12,7 @@
 #include <sstream>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include "prof.hpp"
 
 namespace hif {
@@ -235,7 +236,9 @@ __device__ __forceinline__ void gemm_tile_t(int flags, const TIn* A, int lda, co
 // symbol for profilers.
 // Workgroups are dealt to the 8 XCDs round-robin; remap the linear block id
 // so that each XCD runs a contiguous range of tiles (neighbouring tiles share
-// A and B panels in that XCD's L2).
+// A and B panels in that XCD's L2).  A batch whose count is a multiple of 8
+// thus gives XCD x its x-th eighth of the products, which the host orders to
+// balance the eighths' costs.
 __device__ __forceinline__ void xcd_remap(unsigned& bx, unsigned& by, unsigned& bz) {
   const unsigned gx = gridDim.x, gy = gridDim.y;
   const unsigned T = gx * gy * gridDim.z;
@@ -259,6 +262,160 @@ __global__ __launch_bounds__(NTHR) void k_gemm_desc(int flags, const GemmDesc* _
   if ((flags & GF_C_LOWER) && m0 + TM - 1 < n0) return;
   gemm_tile_t<TIn, TC, OPA, OPB, TM, TN>(flags, (const TIn*)d.A, d.lda, (const TIn*)d.B, d.ldb,
                                          (TC*)d.C, d.ldc, d.m, d.n, d.k, m0, n0, alpha, beta, sm);
+}
+
+// ---- GEMM tile fed by 16-byte direct-to-LDS loads ------------------------
+//
+// C = alpha A B^T + beta C for an A (m x k) and a B (n x k) whose columns are
+// contiguous (op(A) = A, op(B) = B^T: the Schur SYRK and the L_SI product).
+// Square TS x TS tiles, TS = 32 V with V = 16 / sizeof(T) elements per 16
+// bytes (128 for FP32, 64 for FP64), on four waves in a 2 x 2 arrangement.
+// K runs in chunks of kDmaK through kDmaStages LDS stages that
+// global_load_lds_dwordx4 fills without passing through registers: the next
+// chunk is in flight while one is multiplied, with one barrier per chunk.
+// A stage holds each operand as [k][TS] rows of 512 bytes.  Block x of a
+// wave's V row blocks takes rows V i + x (i = lane % 16), so a lane reads the
+// operands of all V blocks with one 16-byte LDS read, and output row r of
+// block x is row V r + x of the wave's sub-tile (columns likewise).
+// Leading dimensions must be multiples of V.  A pointer off the 16-byte grid
+// shifts the tile grid by its offset: the rows before it belong to the same
+// 16-byte block, are read and never written; rows past m are clamped to the
+// last 16-byte block that holds a valid row, and k past the chunk range to
+// the last valid column (masked to zero before the MFMA).
+constexpr int kDmaK = 16, kDmaStages = 2;
+constexpr int kDmaPerWave = kDmaK / 4;  // DMA instructions per chunk and wave
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// One 16-byte global -> LDS copy per lane: lane l writes bytes [16 l, 16 l + 16)
+// after the wave-uniform LDS address lds.  (A plain device function: inside a
+// kernel template the target builtin would keep the host stub from being
+// emitted.)
+__device__ __forceinline__ void dma16(const void* g, void* lds) {
+  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+
+template <typename T>
+struct DmaSmem {
+  static constexpr int V = 16 / (int)sizeof(T);
+  static constexpr int TS = 32 * V;
+  __align__(16) T op[kDmaStages][2][kDmaK][TS];  // [stage][A, B][k][row]
+};
+
+// Four workgroups per CU (at most 128 VGPRs): four waves per SIMD keep the
+// matrix pipe fed across the per-chunk barriers.
+template <typename T, int CLS>
+__global__ __launch_bounds__(NTHR, 4) void k_gemm_nt(int flags, const GemmDesc* __restrict__ desc,
+                                                     T alpha, T beta) {
+  constexpr int V = DmaSmem<T>::V, TS = DmaSmem<T>::TS;
+  typedef T vec_t __attribute__((ext_vector_type(V)));
+  __shared__ DmaSmem<T> sm;
+  unsigned bx, by, bz;
+  xcd_remap(bx, by, bz);
+  const GemmDesc d = desc[bz];
+  const int offA = (int)(((uintptr_t)d.A / sizeof(T)) % V);
+  const int offB = (int)(((uintptr_t)d.B / sizeof(T)) % V);
+  const int ms = d.m + offA, ns = d.n + offB;  // extents in the shifted grid
+  const int m0s = by * TS, n0s = bx * TS;
+  if (m0s >= ms || n0s >= ns) return;
+  const int m0 = m0s - offA, n0 = n0s - offB;  // C coordinates of the tile corner
+  if ((flags & GF_C_LOWER) && m0 + TS - 1 < n0) return;
+  // triangular operands arrive with their zeros stored: only the K range shrinks
+  int kb = 0, ke = d.k;
+  if (flags & GF_A_LOWER) ke = min(ke, m0 + TS);
+  if (flags & GF_A_UPPER) kb = max(kb, m0);
+  if (flags & GF_B_LOWER) kb = max(kb, n0);
+  if (flags & GF_B_UPPER) ke = min(ke, n0 + TS);
+  const int nchunk = ke > kb ? (ke - kb + kDmaK - 1) / kDmaK : 0;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // This wave's four DMA instructions per chunk: operand (wave >> 1) (A for
+  // waves 0-1, B for 2-3), k rows 8 (wave & 1) + 2 j + (lane >> 5), 16-byte
+  // block lane & 31 of the row.
+  const int opnd = wave >> 1;
+  const T* base = opnd == 0 ? static_cast<const T*>(d.A) - offA : static_cast<const T*>(d.B) - offB;
+  const int ld = opnd == 0 ? d.lda : d.ldb;
+  const int qmax = ((opnd == 0 ? ms : ns) - 1) / V;
+  const int q = min((opnd == 0 ? m0s : n0s) / V + (lane & 31), qmax);
+  const T* src = base + (int64_t)V * q;
+  const int krow0 = (kDmaK / 2) * (wave & 1) + (lane >> 5);
+  auto issue = [&](int c) {
+    const int st = c % kDmaStages;
+    const int t0 = kb + c * kDmaK;
+#pragma unroll
+    for (int j = 0; j < kDmaPerWave; ++j) {
+      const int kr = krow0 + 2 * j;
+      const int kk = min(t0 + kr, ke - 1);
+      dma16(src + (int64_t)ld * kk, &sm.op[st][opnd][(kDmaK / 2) * (wave & 1) + 2 * j][0]);
+    }
+  };
+
+  typename Mfma<T>::acc_t acc[V][V];
+#pragma unroll
+  for (int x = 0; x < V; ++x)
+#pragma unroll
+    for (int y = 0; y < V; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[x][y][v] = T(0);
+
+  const int ra = wm * (TS / 2) + V * (lane & 15);
+  const int rb = wn * (TS / 2) + V * (lane & 15);
+#pragma unroll
+  for (int c = 0; c < kDmaStages - 1; ++c)
+    if (c < nchunk) issue(c);
+  for (int c = 0; c < nchunk; ++c) {
+    // chunk c landed; the later chunks already issued may still fly
+    if (c + kDmaStages - 2 < nchunk)
+      wait_vmcnt<(kDmaStages - 2) * kDmaPerWave>();
+    else
+      wait_vmcnt<0>();
+    asm volatile("s_barrier" ::: "memory");  // every wave's part of chunk c is in LDS
+    // into the stage freed by chunk c - 1
+    if (c + kDmaStages - 1 < nchunk) issue(c + kDmaStages - 1);
+    const int st = c % kDmaStages;
+    const int kvalid = ke - (kb + c * kDmaK);  // k rows of this chunk inside [kb, ke)
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int s4 = 0; s4 < kDmaK / 4; ++s4) {
+      const int kr = 4 * s4 + (lane >> 4);
+      vec_t a = *reinterpret_cast<const vec_t*>(&sm.op[st][0][kr][ra]);
+      vec_t b = *reinterpret_cast<const vec_t*>(&sm.op[st][1][kr][rb]);
+      if (kr >= kvalid) {
+        a = vec_t(T(0));
+        b = vec_t(T(0));
+      }
+#pragma unroll
+      for (int x = 0; x < V; ++x)
+#pragma unroll
+        for (int y = 0; y < V; ++y) acc[x][y] = Mfma<T>::run(a[x], b[y], acc[x][y]);
+    }
+    __builtin_amdgcn_s_setprio(0);
+  }
+
+  T* C = static_cast<T*>(d.C);
+#pragma unroll
+  for (int x = 0; x < V; ++x)
+#pragma unroll
+    for (int y = 0; y < V; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = m0 + wm * (TS / 2) + V * Mfma<T>::row(lane, v) + x;
+        const int gj = n0 + wn * (TS / 2) + V * (lane & 15) + y;
+        if (gi >= 0 && gj >= 0 && gi < d.m && gj < d.n && (!(flags & GF_C_LOWER) || gi >= gj)) {
+          const int64_t idx = gi + (int64_t)d.ldc * gj;
+          T val = alpha * acc[x][y][v];
+          if (beta != T(0)) val += beta * C[idx];
+          C[idx] = val;
+          if ((flags & GF_C_MIRROR) && gi > gj) C[gj + (int64_t)d.ldc * gi] = val;
+        }
+      }
 }
 
 // Trailing update of the blocked front Cholesky with the factored panel
@@ -759,6 +916,21 @@ void launch_gemm(int flags, const GemmDesc* d_desc, int batch, int max_m, int ma
   }
 }
 
+template <typename T, int CLS>
+void launch_gemm_nt(int flags, const GemmDesc* d_desc, int batch, int max_m, int max_n, T alpha,
+                    T beta, hipStream_t s) {
+  constexpr int V = DmaSmem<T>::V, TS = DmaSmem<T>::TS;
+  for (int b0 = 0; b0 < batch; b0 += kMaxGridY) {
+    const int nb = std::min(batch - b0, kMaxGridY);
+    // the shifted grid is up to V - 1 rows (columns) longer
+    dim3 grid((unsigned)ceil_div(max_n + V - 1, TS), (unsigned)ceil_div(max_m + V - 1, TS),
+              (unsigned)nb);
+    hipLaunchKernelGGL((k_gemm_nt<T, CLS>), grid, dim3(NTHR), 0, s, flags, d_desc + b0, alpha,
+                       beta);
+    HIF_LAUNCH_CHECK();
+  }
+}
+
 template <typename TIn, typename TC, int TS>
 void dispatch_gemm(int opa, int opb, int flags, int cls, const GemmDesc* d_desc, int batch,
                    int max_m, int max_n, TC alpha, TC beta, hipStream_t s) {
@@ -863,9 +1035,31 @@ int pick_tile(const TileKey& k, int max_m, int max_n) {
   return (sizeof(TC) == 4 && max_m >= 1024 && max_n >= 1024) ? 128 : 64;
 }
 
+// The DMA tile serves A B^T products whose leading dimensions are multiples of
+// 16 bytes, in one precision, with triangular operands only when their zeros
+// are stored, at the tile size the table picks for it.
+template <typename TIn, typename TC>
+bool use_dma_tile(int ts, int opa, int opb, int flags, bool ld16) {
+  if (!std::is_same<TIn, TC>::value || !ld16 || opa != OP_N || opb != OP_T) return false;
+  if ((flags & (GF_A_LOWER | GF_A_UPPER | GF_B_LOWER | GF_B_UPPER)) && !(flags & GF_TRI_ZEROS))
+    return false;
+  return ts == DmaSmem<TC>::TS;
+}
+
 template <typename TIn, typename TC>
 void launch_tile(int ts, int opa, int opb, int flags, int cls, const GemmDesc* d_desc, int batch,
-                 int max_m, int max_n, TC alpha, TC beta, hipStream_t s) {
+                 int max_m, int max_n, TC alpha, TC beta, hipStream_t s, bool ld16 = false) {
+  if constexpr (std::is_same<TIn, TC>::value) {
+    if (use_dma_tile<TIn, TC>(ts, opa, opb, flags, ld16)) {
+      if (cls == GC_SYRK)
+        launch_gemm_nt<TC, GC_SYRK>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+      else if (cls == GC_LSI)
+        launch_gemm_nt<TC, GC_LSI>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+      else
+        launch_gemm_nt<TC, GC_GENERIC>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+      return;
+    }
+  }
   if (sizeof(TC) == 4 && ts == 128)
     dispatch_gemm<TIn, TC, 128>(opa, opb, flags, cls, d_desc, batch, max_m, max_n, alpha, beta, s);
   else if (ts == 32)
@@ -879,7 +1073,7 @@ void launch_tile(int ts, int opa, int opb, int flags, int cls, const GemmDesc* d
 template <typename TIn, typename TC>
 void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch, int max_m,
                   int max_n, TC alpha, TC beta, hipStream_t s, const char* name, double flops,
-                  int cls) {
+                  int cls, bool ld16) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
   const TileKey key = tile_key<TIn, TC>(opa, opb, flags, max_m, max_n);
   bool tuning;
@@ -916,7 +1110,7 @@ void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch
   }
   ProfScope ps(name, s, flops);
   launch_tile<TIn, TC>(pick_tile<TIn, TC>(key, max_m, max_n), opa, opb, flags, cls, d_desc,
-                       batch, max_m, max_n, alpha, beta, s);
+                       batch, max_m, max_n, alpha, beta, s, ld16);
 }
 
 void tune_begin() {
@@ -978,27 +1172,23 @@ template void transpose_batched<float>(const TransDesc*, int, int, int, hipStrea
 double gemm_flops(const GemmDesc& d, int flags) {
   const double m = d.m, n = d.n, k = d.k;
   if (d.m <= 0 || d.n <= 0 || d.k <= 0) return 0.0;
-  double t = 0.0;
+  // sum over r < rows of min(r + 1, k) and of max(0, k - r), in closed form
+  auto tri_lo = [&](double rows) {
+    const double p = std::min(rows, k);
+    return p * (p + 1) / 2 + (rows - p) * k;
+  };
+  auto tri_up = [&](double rows) {
+    const double p = std::min(rows, k);
+    return p * k - p * (p - 1) / 2;
+  };
   if (flags & GF_C_LOWER) {  // computed outputs: i >= j
     const double nn = std::min(n, m);
     return 2.0 * k * (nn * m - nn * (nn - 1) / 2);
   }
-  if (flags & GF_A_LOWER) {  // row i uses t < min(i+1, k)
-    for (int i = 0; i < d.m; ++i) t += std::min(i + 1, d.k);
-    return 2.0 * n * t;
-  }
-  if (flags & GF_A_UPPER) {  // row i uses t in [i, k)
-    for (int i = 0; i < d.m; ++i) t += std::max(0, d.k - i);
-    return 2.0 * n * t;
-  }
-  if (flags & GF_B_UPPER) {  // column j uses t < min(j+1, k)
-    for (int j = 0; j < d.n; ++j) t += std::min(j + 1, d.k);
-    return 2.0 * m * t;
-  }
-  if (flags & GF_B_LOWER) {  // column j uses t in [j, k)
-    for (int j = 0; j < d.n; ++j) t += std::max(0, d.k - j);
-    return 2.0 * m * t;
-  }
+  if (flags & GF_A_LOWER) return 2.0 * n * tri_lo(m);  // row i uses t < min(i+1, k)
+  if (flags & GF_A_UPPER) return 2.0 * n * tri_up(m);  // row i uses t in [i, k)
+  if (flags & GF_B_UPPER) return 2.0 * m * tri_lo(n);  // column j uses t < min(j+1, k)
+  if (flags & GF_B_LOWER) return 2.0 * m * tri_up(n);  // column j uses t in [j, k)
   return 2.0 * m * n * k;
 }
 
@@ -1328,11 +1518,11 @@ void pivoted_cholesky(double* G, double* L, const int64_t* goff, const int* nF, 
 }
 
 template void gemm_batched<double, double>(int, int, int, const GemmDesc*, int, int, int, double,
-                                           double, hipStream_t, const char*, double, int);
+                                           double, hipStream_t, const char*, double, int, bool);
 template void gemm_batched<float, float>(int, int, int, const GemmDesc*, int, int, int, float,
-                                         float, hipStream_t, const char*, double, int);
+                                         float, hipStream_t, const char*, double, int, bool);
 template void gemm_batched<float, double>(int, int, int, const GemmDesc*, int, int, int, double,
-                                          double, hipStream_t, const char*, double, int);
+                                          double, hipStream_t, const char*, double, int, bool);
 template <typename T>
 void root_ldl(const FrontDesc& f, const FrontDesc* d_front, T* sgn, int* err, hipStream_t s) {
   const int n = f.nI, ld = f.ld;

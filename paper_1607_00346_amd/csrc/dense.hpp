@@ -45,7 +45,7 @@ enum : int { GC_GENERIC = 0, GC_SYRK = 1, GC_LSI = 2, GC_GRAM = 3 };  // kernel 
 template <typename TIn, typename TC>
 void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch, int max_m,
                   int max_n, TC alpha, TC beta, hipStream_t s, const char* name = "gemm",
-                  double flops = 0.0, int cls = GC_GENERIC);
+                  double flops = 0.0, int cls = GC_GENERIC, bool ld16 = false);
 
 // Algorithmic flops of one descriptor under the triangular flags (one flag class).
 double gemm_flops(const GemmDesc& d, int flags);
