@@ -302,7 +302,12 @@ template <typename T>
 struct DmaSmem {
   static constexpr int V = 16 / (int)sizeof(T);
   static constexpr int TS = 32 * V;
-  __align__(16) T op[kDmaStages][2][kDmaK][TS];  // [stage][A, B][k][row]
+  static constexpr int SW = TS / 2;  // rows (and columns) of a wave's sub-tile
+  static constexpr int EC = 32;      // sub-tile columns per epilogue pass
+  union __align__(16) {
+    T op[kDmaStages][2][kDmaK][TS];  // [stage][A, B][k][row]
+    T epi[4][EC][SW + 1];            // [wave][column][row], staged outputs
+  };
 };
 
 // Four workgroups per CU (at most 128 VGPRs): four waves per SIMD keep the
@@ -399,23 +404,54 @@ __global__ __launch_bounds__(NTHR, 4) void k_gemm_nt(int flags, const GemmDesc* 
     __builtin_amdgcn_s_setprio(0);
   }
 
+  // Epilogue through LDS, EC sub-tile columns at a time: each column goes out
+  // with consecutive rows on consecutive lanes, and (GF_C_MIRROR) each
+  // mirrored row with consecutive columns on consecutive lanes, so that the
+  // stores fill whole cache lines.
+  constexpr int SW = DmaSmem<T>::SW, EC = DmaSmem<T>::EC;
+  asm volatile("s_barrier" ::: "memory");  // every wave is done with the stages
+  T(*E)[SW + 1] = sm.epi[wave];
   T* C = static_cast<T*>(d.C);
+  const int rbase = m0 + wm * SW, cbase = n0 + wn * SW;
+  const bool lower = (flags & GF_C_LOWER) != 0, mirror = (flags & GF_C_MIRROR) != 0;
 #pragma unroll
-  for (int x = 0; x < V; ++x)
+  for (int p = 0; p < SW / EC; ++p) {
 #pragma unroll
-    for (int y = 0; y < V; ++y)
+    for (int x = 0; x < V; ++x)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int gi = m0 + wm * (TS / 2) + V * Mfma<T>::row(lane, v) + x;
-        const int gj = n0 + wn * (TS / 2) + V * (lane & 15) + y;
-        if (gi >= 0 && gj >= 0 && gi < d.m && gj < d.n && (!(flags & GF_C_LOWER) || gi >= gj)) {
+      for (int y = 0; y < V; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int cl = V * (lane & 15) + y - EC * p;
+          if (cl >= 0 && cl < EC) E[cl][V * Mfma<T>::row(lane, v) + x] = acc[x][y][v];
+        }
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    constexpr int CPI = 64 / SW;  // columns per store (1 FP32, 2 FP64)
+    {
+      const int rl = lane % SW;
+      const int gi = rbase + rl;
+      for (int j = lane / SW; j < EC; j += CPI) {
+        const int gj = cbase + EC * p + j;
+        if (gi >= 0 && gj >= 0 && gi < d.m && gj < d.n && (!lower || gi >= gj)) {
           const int64_t idx = gi + (int64_t)d.ldc * gj;
-          T val = alpha * acc[x][y][v];
+          T val = alpha * E[j][rl];
           if (beta != T(0)) val += beta * C[idx];
           C[idx] = val;
-          if ((flags & GF_C_MIRROR) && gi > gj) C[gj + (int64_t)d.ldc * gi] = val;
         }
       }
+    }
+    if (mirror) {  // (only with beta = 0: the lower entries are already overwritten)
+      constexpr int RPI = 64 / EC;  // rows per store
+      const int jl = lane % EC;
+      const int gj = cbase + EC * p + jl;
+      for (int r = lane / EC; r < SW; r += RPI) {
+        const int gi = rbase + r;
+        if (gi >= 0 && gj >= 0 && gi < d.m && gj < d.n && gi > gj)
+          C[gj + (int64_t)d.ldc * gi] = alpha * E[jl][r];
+      }
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");  // E is rewritten next
+  }
 }
 
 // Trailing update of the blocked front Cholesky with the factored panel
@@ -1037,10 +1073,12 @@ int pick_tile(const TileKey& k, int max_m, int max_n) {
 
 // The DMA tile serves A B^T products whose leading dimensions are multiples of
 // 16 bytes, in one precision, with triangular operands only when their zeros
-// are stored, at the tile size the table picks for it.
+// are stored and a mirrored output only when it overwrites C, at the tile size
+// the table picks for it.
 template <typename TIn, typename TC>
-bool use_dma_tile(int ts, int opa, int opb, int flags, bool ld16) {
+bool use_dma_tile(int ts, int opa, int opb, int flags, bool ld16, bool beta0) {
   if (!std::is_same<TIn, TC>::value || !ld16 || opa != OP_N || opb != OP_T) return false;
+  if ((flags & GF_C_MIRROR) && !beta0) return false;
   if ((flags & (GF_A_LOWER | GF_A_UPPER | GF_B_LOWER | GF_B_UPPER)) && !(flags & GF_TRI_ZEROS))
     return false;
   return ts == DmaSmem<TC>::TS;
@@ -1050,7 +1088,7 @@ template <typename TIn, typename TC>
 void launch_tile(int ts, int opa, int opb, int flags, int cls, const GemmDesc* d_desc, int batch,
                  int max_m, int max_n, TC alpha, TC beta, hipStream_t s, bool ld16 = false) {
   if constexpr (std::is_same<TIn, TC>::value) {
-    if (use_dma_tile<TIn, TC>(ts, opa, opb, flags, ld16)) {
+    if (use_dma_tile<TIn, TC>(ts, opa, opb, flags, ld16, beta == TC(0))) {
       if (cls == GC_SYRK)
         launch_gemm_nt<TC, GC_SYRK>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
       else if (cls == GC_LSI)
