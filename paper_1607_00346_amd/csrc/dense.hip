@@ -628,16 +628,20 @@ __device__ __forceinline__ void panel_row(T* row, int64_t ld, int nb, const Step
 
 // The same solve without the look-ahead buffers (about a third of the
 // registers); for kernels that rely on other resident workgroups to hide the
-// LDS latency instead.
+// LDS latency instead.  A row that is zero stays zero and is left as it is;
+// returns whether the row was nonzero.
 template <typename T>
-__device__ __forceinline__ void panel_row_light(T* row, int64_t ld, int nb,
+__device__ __forceinline__ bool panel_row_light(T* row, int64_t ld, int nb,
                                                 const StepSmem<T>& ss) {
   T w[kPanel];
+  bool nz = false;
 #pragma unroll
   for (int u = 0; u < kPanel; ++u) {
     const T g = row[ld * min(u, nb - 1)];
     w[u] = u < nb ? g : T(0);
+    nz = nz || w[u] != T(0);
   }
+  if (!nz) return false;
   for (int t = 0; t < nb; ++t) {
     T l[kPanel];
 #pragma unroll
@@ -648,6 +652,7 @@ __device__ __forceinline__ void panel_row_light(T* row, int64_t ld, int nb,
     for (int u = 1; u < kPanel; ++u) w[u - 1] = w[u] - l[u] * x;
     w[kPanel - 1] = T(0);
   }
+  return true;
 }
 
 // One step of the blocked right-looking Cholesky at block column j0, fused.
@@ -686,6 +691,10 @@ __global__ __launch_bounds__(NTHR) void k_front_step(const FrontDesc* __restrict
 // diagonal block, panel rows and trailing update in one launch), for the many
 // small fronts of the lowest level, where per-step launches would leave the
 // chip waiting on latency.  The step buffers and the GEMM tile share LDS.
+// Zero blocks are skipped exactly: a panel row that is zero stays zero, and a
+// trailing tile whose two panel blocks (64 rows) hold no nonzero is left as
+// it is.  The leaf fronts, the stencil on a box in lexicographic order, have
+// a band of at most 64, so each step updates one trailing tile.
 template <typename T>
 __global__ __launch_bounds__(NTHR, 8 / sizeof(T)) void k_front_small(
                                                          const FrontDesc* __restrict__ fd,
@@ -696,6 +705,8 @@ __global__ __launch_bounds__(NTHR, 8 / sizeof(T)) void k_front_small(
   __shared__ __align__(16) char smem[kBytes];
   StepSmem<T>& ss = *reinterpret_cast<StepSmem<T>*>(smem);
   TileSmem<T, 64, 64>& ts = *reinterpret_cast<TileSmem<T, 64, 64>*>(smem);
+  constexpr int kMaxBlk = 16;     // panel blocks tracked (fronts of up to 1024 rows)
+  __shared__ int nzb[kMaxBlk];  // panel block b (rows 64 b ..) holds a nonzero
   const FrontDesc f = fd[blockIdx.x];
   T* base = static_cast<T*>(f.ptr);
   const int tid = threadIdx.x;
@@ -703,21 +714,28 @@ __global__ __launch_bounds__(NTHR, 8 / sizeof(T)) void k_front_small(
   for (int j0 = 0; j0 < f.nI; j0 += kPanel) {
     const int nb = min(kPanel, f.nI - j0);
     const int j1 = j0 + nb;
+    const int m = f.nR - j1, n = f.nI - j1;
+    const bool dense = m > kMaxBlk * 64;
     T* col0 = base + (int64_t)f.ld * j0;
+    if (tid < kMaxBlk) nzb[tid] = 0;  // visible after diag_factor's barriers
     bad_any = diag_factor<T>(col0, f.ld, j0, nb, ss) || bad_any;
     for (int e = tid; e < kPanel * kPanel; e += NTHR) {
       const int c = e >> 6, r = e & 63;
       if (r < nb && c < nb && c <= r) col0[j0 + r + (int64_t)f.ld * c] = ss.Lcol[c][r];
     }
-    for (int i = tid; i < f.nR - j1; i += NTHR) panel_row_light<T>(col0 + j1 + i, f.ld, nb, ss);
-    __syncthreads();  // panel rows visible to the whole workgroup; LDS free
-    const int m = f.nR - j1, n = f.nI - j1;
+    for (int i = tid; i < m; i += NTHR)
+      if (panel_row_light<T>(col0 + j1 + i, f.ld, nb, ss) && !dense) nzb[i >> 6] = 1;
+    __syncthreads();  // panel rows and block flags visible to the workgroup; LDS free
     const T* P = col0 + j1;
-    for (int n0 = 0; n0 < n; n0 += 64)
-      for (int m0 = n0; m0 < m; m0 += 64)
+    for (int n0 = 0; n0 < n; n0 += 64) {
+      if (!dense && !nzb[n0 >> 6]) continue;  // uniform over the workgroup
+      for (int m0 = n0; m0 < m; m0 += 64) {
+        if (!dense && !nzb[m0 >> 6]) continue;
         gemm_tile_t<T, T, OP_N, OP_T, 64, 64>(GF_C_LOWER, P, f.ld, P, f.ld,
                                               base + j1 + (int64_t)f.ld * j1, f.ld, m, n, nb, m0,
                                               n0, T(-1), T(1), ts);
+      }
+    }
     __syncthreads();
   }
   if (bad_any && (tid & 63) == 0) atomicMin(err, f.id);
