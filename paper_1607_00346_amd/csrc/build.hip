@@ -166,6 +166,118 @@ __global__ __launch_bounds__(NT) void k_gather_front_SI(Src<T> s, const int* __r
     col[i] = row_lookup(s, cl, r[f.nI + i], map_at(s.has_prev, rmap, o + f.nI + i));
 }
 
+// L_SI = A_SI L_I^{-T} at the leaf level, where A_SI is the stencil itself: a
+// shell point couples to at most its six grid neighbours, so row i of L_SI is
+// the sum, over the neighbours j of shell point i inside the cell, of
+// A(p_i, q_j) times column j of L_I^{-1} (as a row): the nonzero terms of the
+// dense product (a single one for every shell point of a face), summed in
+// direction order.  Two kernels: the neighbour lists of the shell points,
+// then L_SI by 64 x 64 tiles through LDS (columns of L_I^{-1} read
+// contiguously, columns of L_SI written contiguously).
+constexpr int kLeafIntMax = 1024;
+constexpr int kMaxGridZ = 65535;  // largest z dimension of a launch grid
+
+// Neighbour lists, one workgroup per cell: the cell's interior points
+// (sorted) are staged in LDS and each (shell point, direction) finds its
+// neighbour there by binary search.  Shell row i of cell c (global row
+// zoff[c] + i) gets nb_c = the count and, in direction order, nb_j (interior
+// index) and nb_a (coefficient) in its six slots; a row with no neighbour
+// keeps column 0 with a zero coefficient, so that its first term is always
+// a plain load.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_leaf_nbr(Src<T> s, const int* __restrict__ rows,
+                                                 const int64_t* __restrict__ crow_off,
+                                                 const FrontDesc* __restrict__ fd,
+                                                 const int64_t* __restrict__ zoff, int* nb_c,
+                                                 int* nb_j, T* nb_a) {
+  __shared__ int ri[kLeafIntMax];
+  const FrontDesc f = fd[blockIdx.x];
+  const int nI = f.nI, nS = f.nR - f.nI;
+  if (nS <= 0 || nI <= 0) return;
+  const int* r = rows + crow_off[blockIdx.x];
+  const int64_t z0 = zoff[blockIdx.x];
+  const int n = s.st.n;
+  for (int t = threadIdx.x; t < nI; t += NT) ri[t] = r[t];
+  __syncthreads();
+  for (int i = threadIdx.x; i < nS; i += NT) {
+    const int p = r[nI + i];
+    const int pc[3] = {p % n, (p / n) % n, p / (n * n)};
+    int c = 0;
+    int* jj = nb_j + 6 * (z0 + i);
+    T* aa = nb_a + 6 * (z0 + i);
+    for (int d = 0; d < 6; ++d) {
+      int qc[3] = {pc[0], pc[1], pc[2]};
+      qc[d >> 1] += (d & 1) ? 1 : -1;
+      if (!s.st.periodic && (qc[d >> 1] < 0 || qc[d >> 1] >= n)) continue;
+      qc[d >> 1] = (qc[d >> 1] + n) % n;
+      const int q = (qc[2] * n + qc[1]) * n + qc[0];
+      int lo = 0, hi = nI;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ri[mid] < q) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < nI && ri[lo] == q) {
+        jj[c] = lo;
+        aa[c] = row_lookup(s, col_lookup(s, q), p, make_int2(-1, 0));
+        ++c;
+      }
+    }
+    if (c == 0) {
+      jj[0] = 0;
+      aa[0] = T(0);
+    }
+    nb_c[z0 + i] = c;
+  }
+}
+
+// One 64 x 64 tile (shell rows i0.., interior columns t0..) of one cell's
+// L_SI: lanes read a column of L_I^{-1} along t, the tile is turned in LDS,
+// and lanes write a column of L_SI along i.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_lsi_leaf(const FrontDesc* __restrict__ fd,
+                                                 const int64_t* __restrict__ zoff,
+                                                 const int* __restrict__ nb_c,
+                                                 const int* __restrict__ nb_j,
+                                                 const T* __restrict__ nb_a) {
+  __shared__ T tile[64][65];  // [i][t]
+  const FrontDesc f = fd[blockIdx.z];
+  const int nI = f.nI, nS = f.nR - f.nI;
+  const int t0 = blockIdx.x * 64, i0 = blockIdx.y * 64;
+  if (t0 >= nI || i0 >= nS) return;
+  const int64_t z0 = zoff[blockIdx.z];
+  const T* Linv = static_cast<const T*>(f.ptr);
+  T* C = static_cast<T*>(f.ptr) + nI;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int t = min(t0 + tx, nI - 1);
+  // all list loads, then all column loads, so that their latencies overlap
+  int64_t g[16];
+  int jn[16], cn[16];
+  T a[16], v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int i = min(i0 + ty + 4 * k, nS - 1);
+    g[k] = 6 * (z0 + i);
+    jn[k] = nb_j[g[k]];
+    a[k] = nb_a[g[k]];
+    cn[k] = nb_c[z0 + i];
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = a[k] * Linv[t + (int64_t)f.ld * jn[k]];
+#pragma unroll
+  for (int k = 0; k < 16; ++k)  // shell points with more than one neighbour (edges)
+    for (int e = 1; e < cn[k]; ++e) v[k] += nb_a[g[k] + e] * Linv[t + (int64_t)f.ld * nb_j[g[k] + e]];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) tile[ty + 4 * k][tx] = v[k];
+  __syncthreads();
+  const int i = i0 + tx;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int tt = t0 + ty + 4 * k;
+    if (i < nS && tt < nI) C[i + (int64_t)f.ld * tt] = tile[tx][ty + 4 * k];
+  }
+}
+
 // Panel of face f, column j: Ã^l(rows, F_j) = A^l(rows, F_j) + U_A + U_B, the
 // Schur updates of the two neighbouring cells added in a fixed order.
 template <typename T>
@@ -586,6 +698,7 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
     std::vector<FrontDesc> tops;
     std::vector<std::pair<int, FrontDesc>> ldl_roots;  // periodic roots: signed LDL^T
     std::vector<GemmDesc> g_lsi;
+    std::vector<int> leaf_jobs;  // problems whose leaf L_SI comes from the stencil
     for (int j : here) {
       Job<T>& J = jobs[j];
       const hif_problem_s* A = J.A;
@@ -635,15 +748,20 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
       st.cells[level] = P.ncell;
       st.eliminated[level] = lev.ysum;
       if (P.ncell == 0) continue;
-      // A_SI (nS x nI per cell) until L_SI = A_SI L_I^{-T} is formed
+      // A_SI (nS x nI per cell) until L_SI = A_SI L_I^{-T} is formed; at the
+      // leaf level L_SI comes from the stencil directly (k_lsi_leaf)
+      const bool leaf_lsi = level == 0 && lev.maxS > 0 && lev.maxI <= kLeafIntMax;
+      if (leaf_lsi) leaf_jobs.push_back(j);
       std::vector<int64_t> xoff(P.ncell);
       int64_t xsz = 0;
-      for (int c = 0; c < P.ncell; ++c) {
+      for (int c = 0; c < P.ncell && !leaf_lsi; ++c) {
         xoff[c] = xsz;
         xsz += (int64_t)P.cI[c] * pad_ld(P.cS[c]);
       }
-      J.ASI.alloc(std::max<int64_t>(xsz, 1));
-      J.d_xoff = to_dev(xoff, s);
+      if (!leaf_lsi) {
+        J.ASI.alloc(std::max<int64_t>(xsz, 1));
+        J.d_xoff = to_dev(xoff, s);
+      }
       {
         ProfScope ps("gather_front", s);
         if (prev) {
@@ -658,7 +776,7 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
         hipLaunchKernelGGL((k_gather_front<T>), g, dim3(NT), 0, s, src, lev.rows.get(),
                            (const int2*)J.rmap.get(), lev.crow_off.get(), lev.fd.get());
         HIF_LAUNCH_CHECK();
-        if (lev.maxS > 0) {
+        if (lev.maxS > 0 && !leaf_lsi) {
           hipLaunchKernelGGL((k_gather_front_SI<T>), g, dim3(NT), 0, s, src, lev.rows.get(),
                              (const int2*)J.rmap.get(), lev.crow_off.get(), lev.fd.get(),
                              J.ASI.get(), J.d_xoff.get());
@@ -679,7 +797,7 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
         else tops.push_back(t);
       }
       // L_SI = A_SI L_I^{-T} into the front below L_I^{-1} (L_I^{-T} is upper)
-      for (int c = 0; c < P.ncell; ++c) {
+      for (int c = 0; c < P.ncell && !leaf_lsi; ++c) {
         if (P.cS[c] == 0) continue;
         const FrontDesc& d = lev.hfd[c];
         T* base = static_cast<T*>(d.ptr);
@@ -697,6 +815,25 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
       lev.sign.alloc(jr.second.nI);
       DevBuf<FrontDesc> d_root = to_dev(std::vector<FrontDesc>{jr.second}, s);
       root_ldl<T>(jr.second, d_root.get(), lev.sign.get(), d_err.get() + 2 * level, s);
+    }
+    for (int j : leaf_jobs) {
+      Job<T>& J = jobs[j];
+      const Level<T>& lev = J.impl->levels[level];
+      const int nc = lev.plan->ncell;
+      ProfScope ps("lsi_leaf", s);
+      DevBuf<int> nb_c(std::max<int64_t>(lev.zsum, 1)), nb_j(6 * std::max<int64_t>(lev.zsum, 1));
+      DevBuf<T> nb_a(6 * std::max<int64_t>(lev.zsum, 1));
+      hipLaunchKernelGGL((k_leaf_nbr<T>), dim3((unsigned)nc), dim3(NT), 0, s,
+                         make_src<T>(J.A, nullptr, nullptr), lev.rows.get(), lev.crow_off.get(),
+                         lev.fd.get(), lev.zoff.get(), nb_c.get(), nb_j.get(), nb_a.get());
+      HIF_LAUNCH_CHECK();
+      for (int c0 = 0; c0 < nc; c0 += kMaxGridZ) {
+        dim3 g((unsigned)ceil_div(lev.maxI, 64), (unsigned)ceil_div(lev.maxS, 64),
+               (unsigned)std::min(kMaxGridZ, nc - c0));
+        hipLaunchKernelGGL((k_lsi_leaf<T>), g, dim3(NT), 0, s, lev.fd.get() + c0,
+                           lev.zoff.get() + c0, nb_c.get(), nb_j.get(), nb_a.get());
+        HIF_LAUNCH_CHECK();
+      }
     }
     run_gemms<T, T>("gemm_lsi", OP_N, OP_T, GF_B_UPPER | GF_TRI_ZEROS, g_lsi, T(1), T(0), s,
                     GC_LSI);
