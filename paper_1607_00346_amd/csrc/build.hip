@@ -489,47 +489,14 @@ DevBuf<V> to_dev(const std::vector<V>& h, hipStream_t s) {
   return d;
 }
 
-// The batched GEMM kernels give XCD x the x-th eighth of a launch's products
-// (the tiles of one product share its operands in that XCD's L2).  Order a
-// batch of Schur or L_SI products so that the eighths cost the same: products
-// are dealt, largest first, onto the least loaded eighth among those not yet
-// full, and each eighth runs its largest first; the batch is padded with
-// empty products to a multiple of eight.  Only the order changes, never a
-// result.
-std::vector<GemmDesc> balance_xcds(const std::vector<GemmDesc>& h, int flags, int cls) {
-  constexpr int kXcd = 8;
-  const size_t per = (h.size() + kXcd - 1) / kXcd;
-  if (h.size() < 2 * kXcd || per * kXcd > 65535) return h;  // one launch only
-  // only the large products of the cell fronts (reordering the many small
-  // products of the face steps measured slower)
-  if (cls != GC_SYRK && cls != GC_LSI) return h;
-  std::vector<double> cost(per * kXcd, 0.0);
-  for (size_t i = 0; i < h.size(); ++i) cost[i] = gemm_flops(h[i], flags);
-  std::vector<size_t> idx(cost.size());
-  for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
-  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-  std::vector<std::vector<size_t>> grp(kXcd);
-  std::vector<double> load(kXcd, 0.0);
-  for (size_t i : idx) {
-    int best = -1;
-    for (int g = 0; g < kXcd; ++g)
-      if (grp[g].size() < per && (best < 0 || load[g] < load[best])) best = g;
-    grp[best].push_back(i);
-    load[best] += cost[i];
-  }
-  const GemmDesc empty{nullptr, nullptr, nullptr, 0, 0, 0, 1, 1, 1};
-  std::vector<GemmDesc> out;
-  out.reserve(cost.size());
-  for (auto& g : grp)
-    for (size_t i : g) out.push_back(i < h.size() ? h[i] : empty);
-  return out;
-}
-
 template <typename TIn, typename TC>
 void run_gemms(const char* name, int opa, int opb, int flags, const std::vector<GemmDesc>& h0,
                TC alpha, TC beta, hipStream_t s, int cls = GC_GENERIC) {
   if (h0.empty()) return;
-  const std::vector<GemmDesc> h = balance_xcds(h0, flags, cls);
+  // only the large products of the cell fronts are reordered (reordering the
+  // many small products of the face steps measured slower)
+  const std::vector<GemmDesc> h =
+      cls == GC_SYRK || cls == GC_LSI ? balance_xcds(h0, flags) : h0;
   int mm = 0, mn = 0;
   double fl = 0.0;
   for (auto& d : h) {

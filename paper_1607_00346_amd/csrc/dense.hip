@@ -1,4 +1,5 @@
 // Batched dense kernels for the HIF fronts on gfx950 (CDNA4, wave64).
+#include <algorithm>
 #include <climits>
 #include <cfloat>
 
@@ -1210,6 +1211,39 @@ int tune_end(const char* path) {
   return (int)best.size();
 }
 
+// The batched GEMM kernels give XCD x the x-th eighth of a launch's products
+// (the tiles of one product share its operands in that XCD's L2).  Order a
+// batch so that the eighths cost the same: products
+// are dealt, largest first, onto the least loaded eighth among those not yet
+// full, and each eighth runs its largest first; the batch is padded with
+// empty products to a multiple of eight.  Only the order changes, never a
+// result.
+std::vector<GemmDesc> balance_xcds(const std::vector<GemmDesc>& h, int flags) {
+  constexpr int kXcd = 8;
+  const size_t per = (h.size() + kXcd - 1) / kXcd;
+  if (h.size() < 2 * kXcd || per * kXcd > 65535) return h;  // one launch only
+  std::vector<double> cost(per * kXcd, 0.0);
+  for (size_t i = 0; i < h.size(); ++i) cost[i] = gemm_flops(h[i], flags);
+  std::vector<size_t> idx(cost.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  std::vector<std::vector<size_t>> grp(kXcd);
+  std::vector<double> load(kXcd, 0.0);
+  for (size_t i : idx) {
+    int best = -1;
+    for (int g = 0; g < kXcd; ++g)
+      if (grp[g].size() < per && (best < 0 || load[g] < load[best])) best = g;
+    grp[best].push_back(i);
+    load[best] += cost[i];
+  }
+  const GemmDesc empty{nullptr, nullptr, nullptr, 0, 0, 0, 1, 1, 1};
+  std::vector<GemmDesc> out;
+  out.reserve(cost.size());
+  for (auto& g : grp)
+    for (size_t i : g) out.push_back(i < h.size() ? h[i] : empty);
+  return out;
+}
+
 template <typename T>
 void transpose_batched(const TransDesc* d_desc, int batch, int max_rows, int max_cols,
                        hipStream_t s, const char* name) {
@@ -1348,7 +1382,33 @@ void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
       // always launched: it also puts the factored diagonal blocks in place
       trailing(j0, j0, kPanel, j0 + kPanel, J + kSuper - (j0 + kPanel));
     }
-    if (J + kSuper < maxI) trailing(-1, J, kSuper, J + kSuper, maxI);
+    if (J + kSuper < maxI) {
+      // the rest of every front: one batched product (rank kSuper)
+      std::vector<GemmDesc> gd;
+      double fl = 0.0;
+      int max_m = 0, max_n = 0;
+      for (auto& f : h_fronts) {
+        const int k = std::min(J + kSuper, f.nI) - J;
+        const int c0 = J + kSuper;
+        const int m = f.nR - c0, n = f.nI - c0;
+        if (k <= 0 || m <= 0 || n <= 0) continue;
+        T* base = static_cast<T*>(f.ptr);
+        const T* P = base + c0 + (int64_t)f.ld * J;
+        gd.push_back({P, P, base + c0 + (int64_t)f.ld * c0, m, n, k, f.ld, f.ld, f.ld});
+        fl += gemm_flops(gd.back(), GF_C_LOWER);
+        max_m = std::max(max_m, m);
+        max_n = std::max(max_n, n);
+      }
+      if (!gd.empty()) {
+        gd = balance_xcds(gd, GF_C_LOWER);
+        DevBuf<GemmDesc> dd;
+        dd.upload(gd, s);
+        gemm_batched<T, T>(OP_N, OP_T, GF_C_LOWER, dd.get(), (int)gd.size(), max_m, max_n, T(-1),
+                           T(1), s, "potrf_trailing", fl, GC_GENERIC,
+                           std::all_of(h_fronts.begin(), h_fronts.end(),
+                                       [](const FrontDesc& f) { return f.ld % (16 / (int)sizeof(T)) == 0; }));
+      }
+    }
   }
   front_invert<T>(d_fronts, h_fronts, s, upper_zero);
 }

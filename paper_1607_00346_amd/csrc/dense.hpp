@@ -50,6 +50,11 @@ void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch
 // Algorithmic flops of one descriptor under the triangular flags (one flag class).
 double gemm_flops(const GemmDesc& d, int flags);
 
+// The batch reordered (and padded with empty products) so that the eighths
+// of it that the batched GEMM gives the eight XCDs cost the same; only the
+// order of independent products changes.
+std::vector<GemmDesc> balance_xcds(const std::vector<GemmDesc>& h, int flags);
+
 // Tile autotuning on a real workload: between tune_begin() and tune_end(),
 // every batched GEMM that overwrites its output is run and timed with each
 // candidate tile; tune_end() picks the fastest tile per key (summed device
