@@ -507,7 +507,9 @@ void run_gemms(const char* name, int opa, int opb, int flags, const std::vector<
   // leading dimensions on the 16-byte grid let the batch take the DMA-fed tile
   constexpr int V = 16 / (int)sizeof(TIn);
   bool ld16 = true;
-  for (auto& d : h) ld16 = ld16 && d.lda % V == 0 && d.ldb % V == 0;
+  for (auto& d : h)  // (A^T B: the two operands also share their 16-byte offset)
+    ld16 = ld16 && d.lda % V == 0 && d.ldb % V == 0 &&
+           (opa != OP_T || (uintptr_t)d.A % 16 == (uintptr_t)d.B % 16);
   DevBuf<GemmDesc> d;
   d.upload(h, s);
   gemm_batched<TIn, TC>(opa, opb, flags, d.get(), (int)h.size(), mm, mn, alpha, beta, s, name, fl,

@@ -455,6 +455,167 @@ __global__ __launch_bounds__(NTHR, 4) void k_gemm_nt(int flags, const GemmDesc* 
   }
 }
 
+// ---- A^T B tile fed by 16-byte DMA loads (the ID's Gram) -----------------
+//
+// C = alpha A^T B + beta C accumulated in FP64, for an A (k x m) and a B
+// (k x n) whose columns are contiguous (op(A) = A^T, op(B) = B: the Gram of a
+// face's panel), with FP32 or FP64 values.  64 x 64 tiles on four waves
+// (2 x 2, 32 x 32 each, FP64 MFMA 16x16x4).  K runs in chunks of 128 bytes
+// per column (KC = 32 FP32 or 16 FP64 values) through two LDS stages filled
+// by global_load_lds_dwordx4.  A stage holds each operand as 64 columns of
+// eight 16-byte blocks, their order XOR-swizzled by column so that the 16
+// lanes reading one block of 16 columns hit distinct banks.  A lane's 16-byte
+// read gives E = 16 / sizeof(TIn) consecutive k of its column, used by E MFMA
+// steps: in a chunk, lane group g (lane / 16) supplies k-blocks g and g + 4,
+// the same for both operands, so the MFMA steps run over the chunk's k in a
+// fixed permuted order.  The k grid starts on the 16-byte boundary below the
+// operands (A and B must share their offset from it); values outside [0, k)
+// are masked to zero.
+template <typename TIn>
+struct TnSmem {
+  static constexpr int E = 16 / (int)sizeof(TIn);  // values per 16 bytes
+  static constexpr int KC = 8 * E;                  // k per chunk
+  union __align__(16) {
+    TIn op[2][2][64][KC];   // [stage][A, B][column][k, 16-byte blocks swizzled]
+    double epi[4][32][33];  // [wave][column][row], staged outputs
+  };
+};
+
+template <typename TIn, int CLS>
+__global__ __launch_bounds__(NTHR, 4) void k_gemm_tn(int flags, const GemmDesc* __restrict__ desc,
+                                                     double alpha, double beta) {
+  constexpr int E = TnSmem<TIn>::E, KC = TnSmem<TIn>::KC;
+  typedef TIn vin_t __attribute__((ext_vector_type(E)));
+  __shared__ TnSmem<TIn> sm;
+  unsigned bx, by, bz;
+  xcd_remap(bx, by, bz);
+  const GemmDesc d = desc[bz];
+  const int m0 = by * 64, n0 = bx * 64;
+  if (m0 >= d.m || n0 >= d.n) return;
+  if ((flags & GF_C_LOWER) && m0 + 63 < n0) return;
+  const int off = (int)(((uintptr_t)d.A / sizeof(TIn)) % E);  // (the same for B)
+  const int ks = d.k + off;                                     // k extent, shifted grid
+  const int nchunk = ks > off ? (ks + KC - 1) / KC : 0;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // DMA: wave w loads operand w >> 1, columns 32 (w & 1) + 8 j + lane / 8 of
+  // the tile (j = 0..3); lane % 8 is the block's place in the stage row, which
+  // holds k-block (lane % 8) ^ swz(column)
+  const int opnd = wave >> 1;
+  const TIn* base = static_cast<const TIn*>(opnd == 0 ? d.A : d.B) - off;
+  const int ld = opnd == 0 ? d.lda : d.ldb;
+  const int ncol = opnd == 0 ? d.m : d.n;
+  const int cbeg = opnd == 0 ? m0 : n0;
+  const int qmax = (ks - 1) / E;  // last 16-byte block of a column that holds a value
+  auto swz = [](int col) { return (col >> 1) & 7; };
+  auto issue = [&](int c) {
+    const int st = c & 1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = 32 * (wave & 1) + 8 * j + (lane >> 3);
+      const int gcol = min(cbeg + col, ncol - 1);
+      const int q = min(8 * c + ((lane & 7) ^ swz(col)), qmax);
+      dma16(base + (int64_t)ld * gcol + (int64_t)E * q,
+            &sm.op[st][opnd][32 * (wave & 1) + 8 * j][0]);
+    }
+  };
+
+  Mfma<double>::acc_t acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[x][y][v] = 0.0;
+
+  const int g = lane >> 4;
+  int ca[2], cb[2];  // this lane's columns in the stage rows
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+    ca[x] = wm * 32 + 16 * x + (lane & 15);
+    cb[x] = wn * 32 + 16 * x + (lane & 15);
+  }
+  if (nchunk > 0) issue(0);
+  for (int c = 0; c < nchunk; ++c) {
+    wait_vmcnt<0>();                         // chunk c landed
+    asm volatile("s_barrier" ::: "memory");  // ... for every wave; chunk c - 1 is done
+    if (c + 1 < nchunk) issue(c + 1);        // into the stage chunk c - 1 used
+    const int st = c & 1;
+    const bool edge = (c == 0 && off > 0) || KC * (c + 1) > ks;
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int blk = g + 4 * r;
+      vin_t a[2], b[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        a[x] = *reinterpret_cast<const vin_t*>(&sm.op[st][0][ca[x]][E * (blk ^ swz(ca[x]))]);
+        b[x] = *reinterpret_cast<const vin_t*>(&sm.op[st][1][cb[x]][E * (blk ^ swz(cb[x]))]);
+      }
+      if (edge) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int k = KC * c + E * blk + e;
+          if (k < off || k >= ks) {
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+              a[x][e] = TIn(0);
+              b[x][e] = TIn(0);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            acc[x][y] = Mfma<double>::run((double)a[x][e], (double)b[y][e], acc[x][y]);
+    }
+    __builtin_amdgcn_s_setprio(0);
+  }
+
+  // epilogue through LDS, as in the A B^T tile: columns out with consecutive
+  // rows on consecutive lanes, mirrored rows with consecutive columns
+  asm volatile("s_barrier" ::: "memory");  // every wave is done with the stages
+  double(*Ep)[33] = sm.epi[wave];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Ep[16 * y + (lane & 15)][16 * x + Mfma<double>::row(lane, v)] = acc[x][y][v];
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  double* C = static_cast<double*>(d.C);
+  const int rbase = m0 + wm * 32, cbase = n0 + wn * 32;
+  const bool lower = (flags & GF_C_LOWER) != 0;
+  {
+    const int rl = lane & 31;
+    const int gi = rbase + rl;
+    for (int j = lane >> 5; j < 32; j += 2) {
+      const int gj = cbase + j;
+      if (gi < d.m && gj < d.n && (!lower || gi >= gj)) {
+        const int64_t idx = gi + (int64_t)d.ldc * gj;
+        double val = alpha * Ep[j][rl];
+        if (beta != 0.0) val += beta * C[idx];
+        C[idx] = val;
+      }
+    }
+  }
+  if (flags & GF_C_MIRROR) {  // (only with beta = 0)
+    const int jl = lane & 31;
+    const int gj = cbase + jl;
+    for (int r = lane >> 5; r < 32; r += 2) {
+      const int gi = rbase + r;
+      if (gi < d.m && gj < d.n && gi > gj) C[gj + (int64_t)d.ldc * gi] = alpha * Ep[jl][r];
+    }
+  }
+}
+
 // Trailing update of the blocked front Cholesky with the factored panel
 // columns [p0, p0 + pw): Phi[c0:nR, c0:c0 + cw] -= P[c0:nR] P[c0:c0 + cw]^T
 // (lower part), P = Phi[:, p0:p0 + pw], all ranges clipped to the front, with
@@ -971,6 +1132,18 @@ void launch_gemm(int flags, const GemmDesc* d_desc, int batch, int max_m, int ma
   }
 }
 
+template <typename TIn, int CLS>
+void launch_gemm_tn(int flags, const GemmDesc* d_desc, int batch, int max_m, int max_n,
+                    double alpha, double beta, hipStream_t s) {
+  for (int b0 = 0; b0 < batch; b0 += kMaxGridY) {
+    const int nb = std::min(batch - b0, kMaxGridY);
+    dim3 grid((unsigned)ceil_div(max_n, 64), (unsigned)ceil_div(max_m, 64), (unsigned)nb);
+    hipLaunchKernelGGL((k_gemm_tn<TIn, CLS>), grid, dim3(NTHR), 0, s, flags, d_desc + b0, alpha,
+                       beta);
+    HIF_LAUNCH_CHECK();
+  }
+}
+
 template <typename T, int CLS>
 void launch_gemm_nt(int flags, const GemmDesc* d_desc, int batch, int max_m, int max_n, T alpha,
                     T beta, hipStream_t s) {
@@ -1106,6 +1279,15 @@ bool use_dma_tile(int ts, int opa, int opb, int flags, bool ld16, bool beta0) {
 template <typename TIn, typename TC>
 void launch_tile(int ts, int opa, int opb, int flags, int cls, const GemmDesc* d_desc, int batch,
                  int max_m, int max_n, TC alpha, TC beta, hipStream_t s, bool ld16 = false) {
+  // the Gram: A^T B in FP64 from columns on the 16-byte grid, no operand masks
+  if constexpr (std::is_same<TC, double>::value) {
+    if (cls == GC_GRAM && ld16 && opa == OP_T && opb == OP_N &&
+        !(flags & (GF_A_LOWER | GF_A_UPPER | GF_B_LOWER | GF_B_UPPER)) &&
+        (!(flags & GF_C_MIRROR) || beta == TC(0))) {
+      launch_gemm_tn<TIn, GC_GRAM>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+      return;
+    }
+  }
   if constexpr (std::is_same<TIn, TC>::value) {
     if (use_dma_tile<TIn, TC>(ts, opa, opb, flags, ld16, beta == TC(0))) {
       if (cls == GC_SYRK)
@@ -1142,7 +1324,8 @@ void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch
   // Tuning: a product that overwrites C (beta = 0; no library GEMM with
   // beta = 0 reads C or lets it overlap A or B) is run with every candidate
   // tile and each run timed.  All tile sizes take K in the same chunk order,
-  // so every run writes the same C.
+  // so every run writes the same C (the Gram's DMA tile, whose K order is its
+  // own, runs at every candidate size, as outside tuning).
   if (tuning && beta == TC(0)) {
     std::vector<int> cands = {32, 64};
     if (sizeof(TC) == 4) cands.push_back(128);
@@ -1153,7 +1336,7 @@ void gemm_batched(int opa, int opb, int flags, const GemmDesc* d_desc, int batch
     for (size_t c = 0; c < cands.size(); ++c) {
       HIF_HIP(hipEventRecord(e0, s));
       launch_tile<TIn, TC>(cands[c], opa, opb, flags, cls, d_desc, batch, max_m, max_n, alpha,
-                           beta, s);
+                           beta, s, ld16);
       HIF_HIP(hipEventRecord(e1, s));
       HIF_HIP(hipEventSynchronize(e1));
       HIF_HIP(hipEventElapsedTime(&ms[c], e0, e1));

@@ -1,8 +1,8 @@
 """Tile tuning mode: every output-overwriting GEMM runs with each candidate
 tile.  All tile sizes take K in the same chunk order (chunks start at
-multiples of 16, masked entries are exact zeros), so a factor built while
-tuning must equal one built normally bit for bit, and the tuner must produce
-a table."""
+multiples of 16, masked entries are exact zeros; the Gram's own tile runs
+at every candidate size), so a factor built while tuning must equal one
+built normally bit for bit, and the tuner must produce a table."""
 import numpy as np
 import pytest
 
