@@ -732,7 +732,12 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
         J.d_xoff = to_dev(xoff, s);
       }
       {
-        ProfScope ps("gather_front", s);
+        // algorithmic bytes: the blocks written, and above the leaf level one
+        // source entry (a previous panel's) read per entry
+        double gbytes = 0.0;
+        for (int c = 0; c < P.ncell; ++c)
+          gbytes += (double)P.cI[c] * (P.cI[c] + (leaf_lsi ? 0 : P.cS[c])) * sizeof(T);
+        ProfScope ps("gather_front", s, 0.0, prev ? 2.0 * gbytes : gbytes);
         if (prev) {
           const int64_t nr = (int64_t)P.rows.size();
           J.rmap.alloc(std::max<int64_t>(nr, 1));
@@ -886,7 +891,12 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
       if (P.nface > 0) {
         DevBuf<int64_t> d_uoff = to_dev(J.uoff, s);
         DevBuf<int> d_uld = to_dev(J.uld, s);
-        ProfScope ps("gather_panel", s);
+        // algorithmic bytes: the panels written, the Schur blocks U read once,
+        // and above the leaf level one previous-panel entry per panel entry
+        double ubytes = 0.0;
+        for (int c = 0; c < P.ncell; ++c) ubytes += (double)J.uld[c] * P.cS[c] * sizeof(T);
+        const double pbytes = (double)psz * sizeof(T);
+        ProfScope ps("gather_panel", s, 0.0, pbytes + ubytes + (prev ? pbytes : 0.0));
         if (prev) {
           const int64_t nf = (int64_t)P.fpts.size();
           J.fmap.alloc(std::max<int64_t>(nf, 1));
