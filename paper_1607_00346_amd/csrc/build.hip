@@ -668,6 +668,10 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
     std::vector<std::pair<int, FrontDesc>> ldl_roots;  // periodic roots: signed LDL^T
     std::vector<GemmDesc> g_lsi;
     std::vector<int> leaf_jobs;  // problems whose leaf L_SI comes from the stencil
+    // Lower bandwidth of the leaf fronts: a leaf interior is a box of the grid
+    // in lexicographic order, whose largest neighbour offset (and so the band
+    // of A_II and of its Cholesky factor) is the size of one z-plane of it.
+    int leaf_band = 0;
     for (int j : here) {
       Job<T>& J = jobs[j];
       const hif_problem_s* A = J.A;
@@ -762,6 +766,15 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
       // root of a periodic problem keeps the LDL^T of the paper (Section 2.2):
       // compression can leave it indefinite along the near-constant mode
       const bool signed_root = level == J.L && A->opts.bc == HIF_PERIODIC;
+      if (level == 0) {
+        const int64_t n2 = (int64_t)A->opts.n * A->opts.n;
+        for (int c = 0; c < P.ncell; ++c) {
+          const int* r = P.rows.data() + P.crow_off[c];
+          int w = 0;
+          while (w < P.cI[c] && r[w] / n2 == r[0] / n2) ++w;
+          leaf_band = std::max(leaf_band, w);
+        }
+      }
       for (int c = 0; c < P.ncell; ++c) {
         FrontDesc t = lev.hfd[c];
         t.nR = t.nI;
@@ -782,7 +795,7 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
     if (!tops.empty()) {
       DevBuf<FrontDesc> d_top = to_dev(tops, s);
       front_factor<T>(d_top.get(), tops, d_err.get() + 2 * level, s, true,
-                      level == 0 ? kSmallFrontLeaf : kSmallFrontUpper);
+                      level == 0 ? kSmallFrontLeaf : kSmallFrontUpper, level == 0 ? leaf_band : 0);
     }
     for (auto& jr : ldl_roots) {
       Level<T>& lev = jobs[jr.first].impl->levels[level];

@@ -1467,14 +1467,14 @@ double gemm_flops(const GemmDesc& d, int flags) {
 
 template <typename T>
 void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  int* err, hipStream_t s, bool upper_zero, int small_limit) {
+                  int* err, hipStream_t s, bool upper_zero, int small_limit, int band) {
   const int batch = (int)h_fronts.size();
   if (batch == 0) return;
   if (batch > kMaxGridY) {  // the per-front grid dimension is limited
     for (int b0 = 0; b0 < batch; b0 += kMaxGridY) {
       const int nb = std::min(kMaxGridY, batch - b0);
       std::vector<FrontDesc> sub(h_fronts.begin() + b0, h_fronts.begin() + b0 + nb);
-      front_factor<T>(d_fronts + b0, sub, err, s, upper_zero, small_limit);
+      front_factor<T>(d_fronts + b0, sub, err, s, upper_zero, small_limit, band);
     }
     return;
   }
@@ -1488,8 +1488,8 @@ void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
     DevBuf<FrontDesc> ds, dl;
     ds.upload(small, s);
     dl.upload(large, s);
-    front_factor<T>(ds.get(), small, err, s, upper_zero, small_limit);
-    front_factor<T>(dl.get(), large, err, s, upper_zero, small_limit);
+    front_factor<T>(ds.get(), small, err, s, upper_zero, small_limit, band);
+    front_factor<T>(dl.get(), large, err, s, upper_zero, small_limit, band);
     return;
   }
   int maxI = 0;
@@ -1506,7 +1506,7 @@ void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
                          d_fronts, err);
       HIF_LAUNCH_CHECK();
     }
-    front_invert<T>(d_fronts, h_fronts, s, upper_zero);
+    front_invert<T>(d_fronts, h_fronts, s, upper_zero, band);
     return;
   }
   DevBuf<T> dblk((size_t)batch * kPanel * kPanel);
@@ -1593,7 +1593,7 @@ void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
       }
     }
   }
-  front_invert<T>(d_fronts, h_fronts, s, upper_zero);
+  front_invert<T>(d_fronts, h_fronts, s, upper_zero, band);
 }
 
 // ---- signed LDL^T of one dense front (the root of a periodic problem) -----
@@ -1695,15 +1695,16 @@ __global__ __launch_bounds__(NTHR) void k_ldl_rows(T* A, int ld, int n, int j0, 
 // inv([[A, 0], [B, C]]) = [[A^-1, 0], [-C^-1 B A^-1, C^-1]].
 template <typename T>
 void front_invert(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  hipStream_t s, bool upper_zero) {
+                  hipStream_t s, bool upper_zero, int band) {
   const int zf = upper_zero ? GF_TRI_ZEROS : 0;
+  if (!upper_zero) band = 0;  // (the band shortcut reads stored zeros)
   const int batch = (int)h_fronts.size();
   if (batch == 0) return;
   if (batch > kMaxGridY) {
     for (int b0 = 0; b0 < batch; b0 += kMaxGridY) {
       const int nb = std::min(kMaxGridY, batch - b0);
       std::vector<FrontDesc> sub(h_fronts.begin() + b0, h_fronts.begin() + b0 + nb);
-      front_invert<T>(d_fronts + b0, sub, s, upper_zero);
+      front_invert<T>(d_fronts + b0, sub, s, upper_zero, band);
     }
     return;
   }
@@ -1732,27 +1733,39 @@ void front_invert(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
     int64_t w = 0;
     int mm = 0, mk = 0;
     double f1 = 0.0, f2 = 0.0;
+    // With a band bw < sz, the block B = L(o+sz.., o..o+sz) is nonzero only in
+    // its first rb = min(nc, bw) rows and its last bw columns: W = B A^{-1}
+    // needs those rows and the matching rows k0.. of A^{-1}, and
+    // -C^{-1} W needs the first rb columns of C^{-1}.
+    const bool banded = band > 0 && band < sz;
+    const int k0 = banded ? sz - band : 0;
+    int m1 = 0;
     for (auto& f : h_fronts) {
       T* base = static_cast<T*>(f.ptr);
       for (int o = 0; o + sz < f.nI; o += 2 * sz) {
         const int nc = std::min(sz, f.nI - o - sz);
+        const int rb = banded ? std::min(nc, band) : nc;
         T* Bp = base + (o + sz) + (int64_t)f.ld * o;
         T* Ai = base + o + (int64_t)f.ld * o;
         T* Ci = base + (o + sz) + (int64_t)f.ld * (o + sz);
-        g1.push_back({Bp, Ai, W.get() + w, nc, sz, sz, f.ld, f.ld, nc});
-        g2.push_back({Ci, W.get() + w, Bp, nc, sz, nc, f.ld, nc, f.ld});
-        f1 += gemm_flops(g1.back(), GF_B_LOWER);
+        g1.push_back({Bp + (int64_t)f.ld * k0, Ai + k0, W.get() + w, rb, sz, sz - k0, f.ld, f.ld,
+                      nc});
+        g2.push_back({Ci, W.get() + w, Bp, nc, sz, rb, f.ld, nc, f.ld});
+        f1 += gemm_flops(g1.back(), banded ? 0 : GF_B_LOWER);
         f2 += gemm_flops(g2.back(), GF_A_LOWER);
         w += (int64_t)nc * sz;
         mm = std::max(mm, nc);
+        m1 = std::max(m1, rb);
       }
     }
     (void)mk;
     if (g1.empty()) continue;
     d1.upload(g1, s);
     d2.upload(g2, s);
-    gemm_batched<T, T>(OP_N, OP_N, GF_B_LOWER | zf, d1.get(), (int)g1.size(), mm, sz, T(1), T(0), s,
-                       "trtri_gemm", f1);
+    // (A^{-1} from row k0 on is no longer aligned with its triangle: the band
+    // product drops the mask and multiplies the stored zeros)
+    gemm_batched<T, T>(OP_N, OP_N, (banded ? 0 : GF_B_LOWER) | zf, d1.get(), (int)g1.size(), m1,
+                       sz, T(1), T(0), s, "trtri_gemm", f1);
     gemm_batched<T, T>(OP_N, OP_N, GF_A_LOWER | zf, d2.get(), (int)g2.size(), mm, sz, T(-1), T(0), s,
                        "trtri_gemm", f2);
   }
@@ -1857,12 +1870,12 @@ template void root_ldl<double>(const FrontDesc&, const FrontDesc*, double*, int*
 template void root_ldl<float>(const FrontDesc&, const FrontDesc*, float*, int*, hipStream_t);
 
 template void front_factor<double>(const FrontDesc*, const std::vector<FrontDesc>&, int*,
-                                   hipStream_t, bool, int);
+                                   hipStream_t, bool, int, int);
 template void front_factor<float>(const FrontDesc*, const std::vector<FrontDesc>&, int*,
-                                  hipStream_t, bool, int);
+                                  hipStream_t, bool, int, int);
 template void front_invert<double>(const FrontDesc*, const std::vector<FrontDesc>&, hipStream_t,
-                                   bool);
+                                   bool, int);
 template void front_invert<float>(const FrontDesc*, const std::vector<FrontDesc>&, hipStream_t,
-                                  bool);
+                                  bool, int);
 
 }  // namespace hif

@@ -97,12 +97,15 @@ constexpr int kPanel = 64;  // block width of the blocked factorizations
 // of the leaf level and for the redundant blocks of faces; the few hundred
 // cell fronts of 300-800 columns one level up leave most of the chip idle
 // that way.  The limit depends on the level and the kind of front only, so a
-// front takes the same kernels in a single and in a batched build.
+// front takes the same kernels in a single and in a batched build.  band > 0
+// (with upper_zero): every L_I is known to be zero more than band rows below
+// its diagonal (the leaf fronts), which the inverse uses to shorten its
+// products.
 constexpr int kSmallFrontLeaf = 512, kSmallFrontUpper = 256;
 
 template <typename T>
 void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  int* err, hipStream_t s, bool upper_zero, int small_limit);
+                  int* err, hipStream_t s, bool upper_zero, int small_limit, int band = 0);
 
 // Signed LDL^T of one dense front f (nI x nI, no shell rows, strict upper
 // triangle stored as zeros; d_front is f on the device): f <- L^{-1} in place
@@ -112,10 +115,11 @@ void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
 template <typename T>
 void root_ldl(const FrontDesc& f, const FrontDesc* d_front, T* sgn, int* err, hipStream_t s);
 
-// Only the in-place inverse of an already factored lower-triangular L_I.
+// Only the in-place inverse of an already factored lower-triangular L_I
+// (band as for front_factor).
 template <typename T>
 void front_invert(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  hipStream_t s, bool upper_zero);
+                  hipStream_t s, bool upper_zero, int band = 0);
 
 // Pivoted Cholesky of each symmetric G_b (nF x nF, FP64, offset goff[b], ld
 // ldg[b]), blocked: G is overwritten by its trailing updates.  Writes the
