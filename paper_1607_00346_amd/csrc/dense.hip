@@ -616,72 +616,6 @@ __global__ __launch_bounds__(NTHR, 4) void k_gemm_tn(int flags, const GemmDesc* 
   }
 }
 
-// Trailing update of the blocked front Cholesky with the factored panel
-// columns [p0, p0 + pw): Phi[c0:nR, c0:c0 + cw] -= P[c0:nR] P[c0:c0 + cw]^T
-// (lower part), P = Phi[:, p0:p0 + pw], all ranges clipped to the front, with
-// the panel read in place as both operands.  If j0 >= 0, workgroup (0, 0) of
-// each front first copies the step's factored diagonal block from dblk into
-// place (the step kernel cannot write it: its workgroups read the block
-// unfactored); launched with a (1, 1, batch) grid it does only that.
-template <typename T, int TS>
-__global__ __launch_bounds__(NTHR) void k_front_trailing(const FrontDesc* __restrict__ fd,
-                                                         int j0, int p0, int pw, int c0, int cw,
-                                                         const T* __restrict__ dblk) {
-  __shared__ TileSmem<T, TS, TS> sm;
-  unsigned bx, by, bz;
-  xcd_remap(bx, by, bz);
-  const FrontDesc f = fd[bz];
-  T* base = static_cast<T*>(f.ptr);
-  if (j0 >= 0 && j0 < f.nI && bx == 0 && by == 0) {
-    const int nb = min(kPanel, f.nI - j0);
-    const T* D = dblk + (int64_t)bz * kPanel * kPanel;
-    for (int e = threadIdx.x; e < kPanel * kPanel; e += NTHR) {
-      const int c = e >> 6, r = e & 63;
-      if (r < nb && c < nb && c <= r) base[j0 + r + (int64_t)f.ld * (j0 + c)] = D[e];
-    }
-  }
-  const int k = min(p0 + pw, f.nI) - p0;
-  const int m = f.nR - c0, n = min(c0 + cw, f.nI) - c0;
-  const int m0 = by * TS, n0 = bx * TS;
-  if (k <= 0 || m0 >= m || n0 >= n) return;
-  if (m0 + TS - 1 < n0) return;
-  const T* P = base + c0 + (int64_t)f.ld * p0;
-  gemm_tile_t<T, T, OP_N, OP_T, TS, TS>(GF_C_LOWER, P, f.ld, P, f.ld,
-                                        base + c0 + (int64_t)f.ld * c0, f.ld, m, n, k, m0, n0,
-                                        T(-1), T(1), sm);
-}
-
-// Forward substitution of one row against a factored block, steps [tb, te):
-// w[u] holds column t + u of the row (a window of W columns that shifts by one
-// per step, so every register index is static), Lsh[t][u] = L(t + u, t).
-// Each step's column of L is read from LDS one step ahead, into two register
-// buffers used in turn, so its latency hides behind the previous step.
-template <typename T, int W>
-__device__ __forceinline__ void window_solve(T (&w)[kPanel], const T (*Lsh)[kPanel],
-                                             const T* rd, T* row, int64_t ld, int tb, int te) {
-  T la[W], lb[W];
-  auto fetch = [&](T (&d)[W], int t) {
-#pragma unroll
-    for (int u = 0; u < W; ++u) d[u] = Lsh[t][u];
-  };
-  auto step = [&](const T (&l)[W], int t) {
-    const T x = w[0] * rd[t];
-    row[ld * t] = x;
-#pragma unroll
-    for (int u = 1; u < W; ++u) w[u - 1] = w[u] - l[u] * x;
-    w[W - 1] = T(0);
-  };
-  if (tb >= te) return;
-  fetch(la, tb);
-  for (int t = tb; t < te; t += 2) {
-    if (t + 1 < te) fetch(lb, t + 1);
-    step(la, t);
-    if (t + 1 >= te) break;
-    if (t + 2 < te) fetch(la, t + 2);
-    step(lb, t + 1);
-  }
-}
-
 // Value of v in lane l of the wave (l uniform).
 template <typename T>
 __device__ __forceinline__ T read_lane(T v, int l) {
@@ -699,10 +633,13 @@ __device__ __forceinline__ T read_lane(T v, int l) {
 // shifted to start at their diagonal, Lsh[t][u] = L_jj(t + u, t) (zero past
 // the block); rd[t] = 1 / L_jj(t, t).
 template <typename T>
-struct StepSmem {
+struct DiagSmem {
   __align__(16) T Lcol[kPanel][kPanel];
-  __align__(16) T Lsh[kPanel][kPanel];
   T rd[kPanel];
+};
+template <typename T>
+struct StepSmem : DiagSmem<T> {
+  __align__(16) T Lsh[kPanel][kPanel];
 };
 
 // Cholesky of the diagonal block A(j0:j0+nb, j0:j0+nb) held in the column
@@ -711,11 +648,12 @@ struct StepSmem {
 // wave owning column t forms L(:, t) and publishes it through LDS, then every
 // wave updates its later columns.  Ends with a barrier.  Returns, per thread,
 // whether its wave met a non-positive pivot (replaced by 1 to continue).
-template <typename T>
-__device__ __forceinline__ bool diag_factor(const T* col0, int64_t ld, int j0, int nb,
-                                            StepSmem<T>& ss) {
+template <typename T, typename S>
+__device__ __forceinline__ bool diag_factor(const T* col0, int64_t ld, int j0, int nb, S& ss) {
+  constexpr bool kShift = std::is_same<S, StepSmem<T>>::value;  // also fill Lsh
   const int tid = threadIdx.x;
-  for (int e = tid; e < kPanel * kPanel; e += NTHR) (&ss.Lsh[0][0])[e] = T(0);
+  if constexpr (kShift)
+    for (int e = tid; e < kPanel * kPanel; e += NTHR) (&ss.Lsh[0][0])[e] = T(0);
   const int lane = tid & 63;
   const int q = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
   const int rl = min(lane, nb - 1);
@@ -748,7 +686,8 @@ __device__ __forceinline__ bool diag_factor(const T* col0, int64_t ld, int j0, i
           const T lit = lane > t ? w[v] * r : (lane == t ? ltt : T(0));
           w[v] = lit;
           ss.Lcol[t][lane] = lit;
-          if (lane >= t) ss.Lsh[t][lane - t] = lit;
+          if constexpr (kShift)
+            if (lane >= t) ss.Lsh[t][lane - t] = lit;
         }
         __syncthreads();
         if (q >= qt) {
@@ -772,26 +711,10 @@ __device__ __forceinline__ bool diag_factor(const T* col0, int64_t ld, int j0, i
   return bad;
 }
 
-// One panel row below the factored diagonal block: x L_jj^T = p in place
-// (row points at column j0 of the row, leading dimension ld).
-template <typename T>
-__device__ __forceinline__ void panel_row(T* row, int64_t ld, int nb, const StepSmem<T>& ss) {
-  T w[kPanel];
-#pragma unroll
-  for (int u = 0; u < kPanel; ++u) {
-    const T g = row[ld * min(u, nb - 1)];
-    w[u] = u < nb ? g : T(0);
-  }
-  // first half on the full window, then on its lower half
-  const int tm = min(nb, kPanel / 2);
-  window_solve<T, kPanel>(w, ss.Lsh, ss.rd, row, ld, 0, tm);
-  window_solve<T, kPanel / 2>(w, ss.Lsh, ss.rd, row, ld, tm, nb);
-}
-
-// The same solve without the look-ahead buffers (about a third of the
-// registers); for kernels that rely on other resident workgroups to hide the
-// LDS latency instead.  A row that is zero stays zero and is left as it is;
-// returns whether the row was nonzero.
+// One panel row below the factored diagonal block: x L_jj^T = p in place (row
+// points at column j0 of the row, leading dimension ld), by forward
+// substitution.  A row that is zero stays zero and is left as it is; returns
+// whether the row was nonzero.
 template <typename T>
 __device__ __forceinline__ bool panel_row_light(T* row, int64_t ld, int nb,
                                                 const StepSmem<T>& ss) {
@@ -817,36 +740,93 @@ __device__ __forceinline__ bool panel_row_light(T* row, int64_t ld, int nb,
   return true;
 }
 
-// One step of the blocked right-looking Cholesky at block column j0, fused.
-// Every workgroup factors the diagonal block L_jj itself (the redundant work
-// across workgroups costs less than a launch and a round trip through memory)
-// and workgroup 0 stores it to dblk (64 x 64, column-major; the trailing
-// kernel puts it in place).  Then each thread solves one panel row below the
-// block by forward substitution.
+// Diagonal block of the blocked right-looking Cholesky at block column j0,
+// by one workgroup: L_jj by diag_factor, then its inverse by wave 0 (lane c
+// forms column c, right-looking, the columns of L_jj read as LDS broadcasts),
+// written over the block (strict upper part zero).  The panel kernel then
+// forms the rows below as P L_jj^{-T}, and the inverse of L_I starts from
+// these inverted diagonal blocks.
 template <typename T>
-__global__ __launch_bounds__(NTHR) void k_front_step(const FrontDesc* __restrict__ fd,
-                                                     int j0, T* __restrict__ dblk, int* err) {
-  __shared__ StepSmem<T> ss;
-  const FrontDesc f = fd[blockIdx.y];
+__device__ __forceinline__ void diag_step(T* col0, int64_t ld, int j0, int nb, DiagSmem<T>& ss,
+                                          int* err, int id) {
+  const int tid = threadIdx.x;
+  const bool bad = diag_factor<T>(col0, ld, j0, nb, ss);
+  if (bad && (tid & 63) == 0) atomicMin(err, id);
+  if (tid >= 64) return;
+  const int lane = tid;
+  T x[kPanel];  // column `lane` of the inverse, from e_lane (identity past nb)
+#pragma unroll
+  for (int i = 0; i < kPanel; ++i) x[i] = i == lane ? T(1) : T(0);
+#pragma unroll
+  for (int t = 0; t < kPanel; ++t) {
+    if (t < nb) {
+      x[t] *= ss.rd[t];
+#pragma unroll
+      for (int u = t + 1; u < kPanel; ++u) x[u] -= ss.Lcol[t][u] * x[t];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // column `lane` of the block: rows lane.. of the inverse, zeros above
+  T* dst = col0 + j0 + ld * lane;
+  if (lane < nb) {
+#pragma unroll
+    for (int i = 0; i < kPanel; ++i)
+      if (i < nb) dst[i] = i >= lane ? x[i] : T(0);
+  }
+}
+
+// The diagonal step of every front, one workgroup each.
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_front_diag(const FrontDesc* __restrict__ fd, int j0,
+                                                     int* err) {
+  __shared__ DiagSmem<T> ss;
+  const FrontDesc f = fd[blockIdx.x];
+  if (j0 >= f.nI) return;
+  diag_step<T>(static_cast<T*>(f.ptr) + (int64_t)f.ld * j0, f.ld, j0, min(kPanel, f.nI - j0), ss,
+               err, f.id);
+}
+
+// Trailing update of the blocked front Cholesky with the factored panel
+// columns [p0, p0 + pw): Phi[c0:nR, c0:c0 + cw] -= P[c0:nR] P[c0:c0 + cw]^T
+// (lower part), P = Phi[:, p0:p0 + pw], all ranges clipped to the front, with
+// the panel read in place as both operands.
+template <typename T, int TS>
+__global__ __launch_bounds__(NTHR) void k_front_trailing(const FrontDesc* __restrict__ fd,
+                                                         int p0, int pw, int c0, int cw) {
+  __shared__ TileSmem<T, TS, TS> sm;
+  unsigned bx, by, bz;
+  xcd_remap(bx, by, bz);
+  const FrontDesc f = fd[bz];
+  T* base = static_cast<T*>(f.ptr);
+  const int k = min(p0 + pw, f.nI) - p0;
+  const int m = f.nR - c0, n = min(c0 + cw, f.nI) - c0;
+  const int m0 = by * TS, n0 = bx * TS;
+  if (k <= 0 || m0 >= m || n0 >= n) return;
+  if (m0 + TS - 1 < n0) return;
+  const T* P = base + c0 + (int64_t)f.ld * p0;
+  gemm_tile_t<T, T, OP_N, OP_T, TS, TS>(GF_C_LOWER, P, f.ld, P, f.ld,
+                                        base + c0 + (int64_t)f.ld * c0, f.ld, m, n, k, m0, n0,
+                                        T(-1), T(1), sm);
+}
+
+// Panel rows below the diagonal block at j0, 64 rows per workgroup: P <- P
+// L_jj^{-T} in place, one GEMM tile (the rows are read in full before any is
+// written; the diagonal block holds L_jj^{-1}).
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_front_panel(const FrontDesc* __restrict__ fd, int j0) {
+  __shared__ TileSmem<T, 64, 64> sm;
+  unsigned bx, by, bz;
+  xcd_remap(bx, by, bz);
+  const FrontDesc f = fd[by];
   if (j0 >= f.nI) return;
   const int nb = min(kPanel, f.nI - j0);
   const int j1 = j0 + nb;
   const int m = f.nR - j1;
-  const int r0 = blockIdx.x * NTHR;
-  if (blockIdx.x > 0 && r0 >= m) return;
-  T* col0 = static_cast<T*>(f.ptr) + (int64_t)f.ld * j0;  // column j0 of the front
-  const int tid = threadIdx.x;
-  const bool bad = diag_factor<T>(col0, f.ld, j0, nb, ss);
-  if (blockIdx.x == 0) {
-    if (bad && (tid & 63) == 0) atomicMin(err, f.id);
-    T* D = dblk + (int64_t)blockIdx.y * kPanel * kPanel;
-    for (int e = tid; e < kPanel * kPanel; e += NTHR) {
-      const int c = e >> 6, r = e & 63;
-      D[e] = (r >= c && c < nb) ? ss.Lcol[c][r] : T(0);
-    }
-  }
-  const int i = r0 + tid;
-  if (i < m) panel_row<T>(col0 + j1 + i, f.ld, nb, ss);
+  const int m0 = bx * 64;
+  if (m0 >= m) return;
+  T* col0 = static_cast<T*>(f.ptr) + (int64_t)f.ld * j0;
+  gemm_tile_t<T, T, OP_N, OP_T, 64, 64>(GF_B_UPPER | GF_TRI_ZEROS, col0 + j1, f.ld, col0 + j0,
+                                        f.ld, col0 + j1, f.ld, m, nb, nb, m0, 0, T(1), T(0), sm);
 }
 
 // The whole blocked Cholesky of one small front per workgroup (every step's
@@ -1506,13 +1486,11 @@ void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
                          d_fronts, err);
       HIF_LAUNCH_CHECK();
     }
-    front_invert<T>(d_fronts, h_fronts, s, upper_zero, band);
+    front_invert<T>(d_fronts, h_fronts, s, upper_zero, band, false);
     return;
   }
-  DevBuf<T> dblk((size_t)batch * kPanel * kPanel);
-  // Trailing update of panel columns [p0, p0 + pw) into [c0, c0 + cw) (j0 >= 0:
-  // also put step j0's diagonal blocks in place).
-  auto trailing = [&](int j0, int p0, int pw, int c0, int cw) {
+  // Trailing update of panel columns [p0, p0 + pw) into [c0, c0 + cw).
+  auto trailing = [&](int p0, int pw, int c0, int cw) {
     int max_m = 0, max_n = 0;
     double fl = 0.0;
     for (auto& f : h_fronts) {
@@ -1523,18 +1501,17 @@ void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
       max_n = std::max(max_n, n);
       fl += 2.0 * k * ((double)n * m - (double)n * (n - 1) / 2);
     }
-    if (j0 < 0 && max_n == 0) return;
+    if (max_n == 0) return;
     ProfScope ps("potrf_trailing", s, fl);
-    const T* D = dblk.get();
     if (sizeof(T) == 4 && max_n >= 1024) {
       dim3 gt((unsigned)ceil_div(max_n, 128), (unsigned)ceil_div(max_m, 128), (unsigned)batch);
-      hipLaunchKernelGGL((k_front_trailing<T, 128>), gt, dim3(NTHR), 0, s, d_fronts, j0, p0,
-                         pw, c0, cw, D);
+      hipLaunchKernelGGL((k_front_trailing<T, 128>), gt, dim3(NTHR), 0, s, d_fronts, p0, pw, c0,
+                         cw);
     } else {
       dim3 gt((unsigned)std::max<int64_t>(1, ceil_div(max_n, 64)),
               (unsigned)std::max<int64_t>(1, ceil_div(max_m, 64)), (unsigned)batch);
-      hipLaunchKernelGGL((k_front_trailing<T, 64>), gt, dim3(NTHR), 0, s, d_fronts, j0, p0,
-                         pw, c0, cw, D);
+      hipLaunchKernelGGL((k_front_trailing<T, 64>), gt, dim3(NTHR), 0, s, d_fronts, p0, pw, c0,
+                         cw);
     }
     HIF_LAUNCH_CHECK();
   };
@@ -1542,28 +1519,36 @@ void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
   // columns up to the super-panel's end; the rest of the trailing matrix is
   // updated once per super-panel with all of its columns (rank kSuper), which
   // reads and writes the trailing matrix kSuper / kPanel times less often.
+  // A step: the diagonal block factored and inverted once per front, the
+  // panel rows below formed as P L_jj^{-T} (a product, 64 rows a workgroup),
+  // then the trailing update inside the super-panel.
   constexpr int kSuper = 4 * kPanel;
   for (int J = 0; J < maxI; J += kSuper) {
     const int Je = std::min(J + kSuper, maxI);
     for (int j0 = J; j0 < Je; j0 += kPanel) {
       int max_m = 0;
-      double fl_step = 0.0;
+      double fl_diag = 0.0, fl_panel = 0.0;
       for (auto& f : h_fronts) {
         if (f.nI <= j0) continue;
         const int nb = std::min(kPanel, f.nI - j0);
         const double m = f.nR - j0 - nb;
         max_m = std::max(max_m, (int)m);
-        fl_step += nb * (double)nb * nb / 3.0 + m * nb * (double)nb;
+        fl_diag += 2.0 * nb * (double)nb * nb / 3.0;  // L_jj and its inverse
+        fl_panel += m * nb * (double)(nb + 1);
       }
       {
-        ProfScope ps("potrf_step", s, fl_step);
-        dim3 g((unsigned)std::max<int64_t>(1, ceil_div(max_m, NTHR)), (unsigned)batch);
-        hipLaunchKernelGGL((k_front_step<T>), g, dim3(NTHR), 0, s, d_fronts, j0, dblk.get(),
-                           err);
+        ProfScope ps("potrf_diag", s, fl_diag);
+        hipLaunchKernelGGL((k_front_diag<T>), dim3((unsigned)batch), dim3(NTHR), 0, s, d_fronts,
+                           j0, err);
         HIF_LAUNCH_CHECK();
       }
-      // always launched: it also puts the factored diagonal blocks in place
-      trailing(j0, j0, kPanel, j0 + kPanel, J + kSuper - (j0 + kPanel));
+      if (max_m > 0) {
+        ProfScope ps("potrf_panel", s, fl_panel);
+        dim3 g((unsigned)ceil_div(max_m, 64), (unsigned)batch);
+        hipLaunchKernelGGL((k_front_panel<T>), g, dim3(NTHR), 0, s, d_fronts, j0);
+        HIF_LAUNCH_CHECK();
+      }
+      trailing(j0, kPanel, j0 + kPanel, J + kSuper - (j0 + kPanel));
     }
     if (J + kSuper < maxI) {
       // the rest of every front: one batched product (rank kSuper)
@@ -1593,7 +1578,7 @@ void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
       }
     }
   }
-  front_invert<T>(d_fronts, h_fronts, s, upper_zero, band);
+  front_invert<T>(d_fronts, h_fronts, s, upper_zero, band, true);
 }
 
 // ---- signed LDL^T of one dense front (the root of a periodic problem) -----
@@ -1695,7 +1680,7 @@ __global__ __launch_bounds__(NTHR) void k_ldl_rows(T* A, int ld, int n, int j0, 
 // inv([[A, 0], [B, C]]) = [[A^-1, 0], [-C^-1 B A^-1, C^-1]].
 template <typename T>
 void front_invert(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  hipStream_t s, bool upper_zero, int band) {
+                  hipStream_t s, bool upper_zero, int band, bool diag_done) {
   const int zf = upper_zero ? GF_TRI_ZEROS : 0;
   if (!upper_zero) band = 0;  // (the band shortcut reads stored zeros)
   const int batch = (int)h_fronts.size();
@@ -1704,13 +1689,13 @@ void front_invert(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
     for (int b0 = 0; b0 < batch; b0 += kMaxGridY) {
       const int nb = std::min(kMaxGridY, batch - b0);
       std::vector<FrontDesc> sub(h_fronts.begin() + b0, h_fronts.begin() + b0 + nb);
-      front_invert<T>(d_fronts + b0, sub, s, upper_zero, band);
+      front_invert<T>(d_fronts + b0, sub, s, upper_zero, band, diag_done);
     }
     return;
   }
   int maxI = 0;
   for (auto& f : h_fronts) maxI = std::max(maxI, f.nI);
-  {
+  if (!diag_done) {
     ProfScope ps("trtri_diag", s);
     dim3 g((unsigned)ceil_div(maxI, kPanel), (unsigned)batch);
     hipLaunchKernelGGL((k_diag_inv<T>), g, dim3(64), 0, s, d_fronts);
@@ -1874,8 +1859,8 @@ template void front_factor<double>(const FrontDesc*, const std::vector<FrontDesc
 template void front_factor<float>(const FrontDesc*, const std::vector<FrontDesc>&, int*,
                                   hipStream_t, bool, int, int);
 template void front_invert<double>(const FrontDesc*, const std::vector<FrontDesc>&, hipStream_t,
-                                   bool, int);
+                                   bool, int, bool);
 template void front_invert<float>(const FrontDesc*, const std::vector<FrontDesc>&, hipStream_t,
-                                  bool, int);
+                                  bool, int, bool);
 
 }  // namespace hif

@@ -116,10 +116,11 @@ template <typename T>
 void root_ldl(const FrontDesc& f, const FrontDesc* d_front, T* sgn, int* err, hipStream_t s);
 
 // Only the in-place inverse of an already factored lower-triangular L_I
-// (band as for front_factor).
+// (band as for front_factor; diag_done: its 64 x 64 diagonal blocks already
+// hold their inverses).
 template <typename T>
 void front_invert(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
-                  hipStream_t s, bool upper_zero, int band = 0);
+                  hipStream_t s, bool upper_zero, int band = 0, bool diag_done = false);
 
 // Pivoted Cholesky of each symmetric G_b (nF x nF, FP64, offset goff[b], ld
 // ldg[b]), blocked: G is overwritten by its trailing updates.  Writes the
