@@ -113,6 +113,7 @@ __device__ __forceinline__ T row_lookup(const Src<T>& s, const ColLookup<T>& c, 
 // column's lookup state is then wave-uniform (scalar registers) and columns
 // of a few dozen rows still keep most lanes busy.
 constexpr int kGatherCols = NT / 64;
+constexpr int kGatherUnroll = 4;  // rows per lane whose loads are issued together
 
 __device__ __forceinline__ int wave_column(int block) {
   return block * kGatherCols + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -141,8 +142,23 @@ __global__ __launch_bounds__(NT) void k_gather_front(Src<T> s, const int* __rest
   const ColLookup<T> cl = col_lookup(s, r[j]);
   T* col = static_cast<T*>(f.ptr) + (int64_t)f.ld * j;
   for (int i = lane; i < j; i += 64) col[i] = T(0);
-  for (int i = j + lane; i < f.nI; i += 64)
-    col[i] = row_lookup(s, cl, r[i], map_at(s.has_prev, rmap, o + i));
+  // kGatherUnroll rows per lane at a time: all lookups' loads before any store
+  for (int i0 = j + lane; i0 < f.nI; i0 += 64 * kGatherUnroll) {
+    int p[kGatherUnroll];
+    int2 mp[kGatherUnroll];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      const int i = min(i0 + 64 * u, f.nI - 1);
+      p[u] = r[i];
+      mp[u] = map_at(s.has_prev, rmap, o + i);
+    }
+    T v[kGatherUnroll];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) v[u] = row_lookup(s, cl, p[u], mp[u]);
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u)
+      if (i0 + 64 * u < f.nI) col[i0 + 64 * u] = v[u];
+  }
 }
 
 // A_SI of cell c, column j (the j-th interior point): nS x nI, leading dimension nS.
@@ -162,8 +178,22 @@ __global__ __launch_bounds__(NT) void k_gather_front_SI(Src<T> s, const int* __r
   const int* r = rows + o;
   const ColLookup<T> cl = col_lookup(s, r[j]);
   T* col = asi + aoff[c] + (int64_t)((nS + 3) / 4 * 4) * j;  // leading dimension pad_ld(nS)
-  for (int i = lane; i < nS; i += 64)
-    col[i] = row_lookup(s, cl, r[f.nI + i], map_at(s.has_prev, rmap, o + f.nI + i));
+  for (int i0 = lane; i0 < nS; i0 += 64 * kGatherUnroll) {
+    int p[kGatherUnroll];
+    int2 mp[kGatherUnroll];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      const int i = min(i0 + 64 * u, nS - 1);
+      p[u] = r[f.nI + i];
+      mp[u] = map_at(s.has_prev, rmap, o + f.nI + i);
+    }
+    T v[kGatherUnroll];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) v[u] = row_lookup(s, cl, p[u], mp[u]);
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u)
+      if (i0 + 64 * u < nS) col[i0 + 64 * u] = v[u];
+  }
 }
 
 // L_SI = A_SI L_I^{-T} at the leaf level, where A_SI is the stencil itself: a
