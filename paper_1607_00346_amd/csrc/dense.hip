@@ -269,22 +269,21 @@ __global__ __launch_bounds__(NTHR) void k_gemm_desc(int flags, const GemmDesc* _
 //
 // C = alpha A B^T + beta C for an A (m x k) and a B (n x k) whose columns are
 // contiguous (op(A) = A, op(B) = B^T: the Schur SYRK and the L_SI product).
-// Square TS x TS tiles, TS = 32 V with V = 16 / sizeof(T) elements per 16
-// bytes (128 for FP32, 64 for FP64), on four waves in a 2 x 2 arrangement.
-// K runs in chunks of kDmaK through kDmaStages LDS stages that
+// Square TS x TS tiles (TS = 128 or 64 for FP32, 64 for FP64) on four waves in
+// a 2 x 2 arrangement, each wave FM = TS / 32 blocks of 16 rows by FM blocks of
+// 16 columns.  K runs in chunks of kDmaK through kDmaStages LDS stages that
 // global_load_lds_dwordx4 fills without passing through registers: the next
 // chunk is in flight while one is multiplied, with one barrier per chunk.
-// A stage holds each operand as [k][TS] rows of 512 bytes.  Block x of a
-// wave's V row blocks takes rows V i + x (i = lane % 16), so a lane reads the
-// operands of all V blocks with one 16-byte LDS read, and output row r of
-// block x is row V r + x of the wave's sub-tile (columns likewise).
-// Leading dimensions must be multiples of V.  A pointer off the 16-byte grid
-// shifts the tile grid by its offset: the rows before it belong to the same
-// 16-byte block, are read and never written; rows past m are clamped to the
-// last 16-byte block that holds a valid row, and k past the chunk range to
-// the last valid column (masked to zero before the MFMA).
+// A stage holds each operand as [k][TS] rows.  Block x of a wave's FM row
+// blocks takes rows FM i + x (i = lane % 16), so a lane reads the operands of
+// all FM blocks with one LDS read of FM consecutive values, and output row r
+// of block x is row FM r + x of the wave's sub-tile (columns likewise).
+// Leading dimensions must be multiples of V = 16 / sizeof(T).  A pointer off
+// the 16-byte grid shifts the tile grid by its offset: the rows before it
+// belong to the same 16-byte block, are read and never written; rows past m
+// are clamped to the last 16-byte block that holds a valid row, and k past
+// the chunk range to the last valid column (masked to zero before the MFMA).
 constexpr int kDmaK = 16, kDmaStages = 2;
-constexpr int kDmaPerWave = kDmaK / 4;  // DMA instructions per chunk and wave
 
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
@@ -299,10 +298,13 @@ __device__ __forceinline__ void dma16(const void* g, void* lds) {
   __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
 }
 
-template <typename T>
+template <typename T, int TS>
 struct DmaSmem {
-  static constexpr int V = 16 / (int)sizeof(T);
-  static constexpr int TS = 32 * V;
+  static constexpr int V = 16 / (int)sizeof(T);         // values per 16 bytes
+  static constexpr int FM = TS / 32;                    // row blocks per wave
+  static constexpr int LPR = TS * (int)sizeof(T) / 16;  // DMA lanes per k row
+  static constexpr int KPI = 64 / LPR;                  // k rows per DMA instruction
+  static constexpr int IPW = kDmaK / KPI / 2;           // DMA instructions per chunk and wave
   static constexpr int SW = TS / 2;  // rows (and columns) of a wave's sub-tile
   static constexpr int EC = 32;      // sub-tile columns per epilogue pass
   union __align__(16) {
@@ -313,12 +315,13 @@ struct DmaSmem {
 
 // Four workgroups per CU (at most 128 VGPRs): four waves per SIMD keep the
 // matrix pipe fed across the per-chunk barriers.
-template <typename T, int CLS>
+template <typename T, int TS, int CLS>
 __global__ __launch_bounds__(NTHR, 4) void k_gemm_nt(int flags, const GemmDesc* __restrict__ desc,
                                                      T alpha, T beta) {
-  constexpr int V = DmaSmem<T>::V, TS = DmaSmem<T>::TS;
-  typedef T vec_t __attribute__((ext_vector_type(V)));
-  __shared__ DmaSmem<T> sm;
+  using S = DmaSmem<T, TS>;
+  constexpr int V = S::V, FM = S::FM, LPR = S::LPR, KPI = S::KPI, IPW = S::IPW;
+  typedef T vec_t __attribute__((ext_vector_type(FM)));
+  __shared__ S sm;
   unsigned bx, by, bz;
   xcd_remap(bx, by, bz);
   const GemmDesc d = desc[bz];
@@ -342,44 +345,44 @@ __global__ __launch_bounds__(NTHR, 4) void k_gemm_nt(int flags, const GemmDesc* 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 1, wn = wave & 1;
 
-  // This wave's four DMA instructions per chunk: operand (wave >> 1) (A for
-  // waves 0-1, B for 2-3), k rows 8 (wave & 1) + 2 j + (lane >> 5), 16-byte
-  // block lane & 31 of the row.
+  // This wave's IPW DMA instructions per chunk: operand (wave >> 1) (A for
+  // waves 0-1, B for 2-3), the half (wave & 1) of the chunk's k rows, KPI k
+  // rows an instruction, 16-byte block lane % LPR of the row.
   const int opnd = wave >> 1;
   const T* base = opnd == 0 ? static_cast<const T*>(d.A) - offA : static_cast<const T*>(d.B) - offB;
   const int ld = opnd == 0 ? d.lda : d.ldb;
   const int qmax = ((opnd == 0 ? ms : ns) - 1) / V;
-  const int q = min((opnd == 0 ? m0s : n0s) / V + (lane & 31), qmax);
+  const int q = min((opnd == 0 ? m0s : n0s) / V + lane % LPR, qmax);
   const T* src = base + (int64_t)V * q;
-  const int krow0 = (kDmaK / 2) * (wave & 1) + (lane >> 5);
+  const int krow0 = (kDmaK / 2) * (wave & 1) + lane / LPR;
   auto issue = [&](int c) {
     const int st = c % kDmaStages;
     const int t0 = kb + c * kDmaK;
 #pragma unroll
-    for (int j = 0; j < kDmaPerWave; ++j) {
-      const int kr = krow0 + 2 * j;
+    for (int j = 0; j < IPW; ++j) {
+      const int kr = krow0 + KPI * j;
       const int kk = min(t0 + kr, ke - 1);
-      dma16(src + (int64_t)ld * kk, &sm.op[st][opnd][(kDmaK / 2) * (wave & 1) + 2 * j][0]);
+      dma16(src + (int64_t)ld * kk, &sm.op[st][opnd][(kDmaK / 2) * (wave & 1) + KPI * j][0]);
     }
   };
 
-  typename Mfma<T>::acc_t acc[V][V];
+  typename Mfma<T>::acc_t acc[FM][FM];
 #pragma unroll
-  for (int x = 0; x < V; ++x)
+  for (int x = 0; x < FM; ++x)
 #pragma unroll
-    for (int y = 0; y < V; ++y)
+    for (int y = 0; y < FM; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[x][y][v] = T(0);
 
-  const int ra = wm * (TS / 2) + V * (lane & 15);
-  const int rb = wn * (TS / 2) + V * (lane & 15);
+  const int ra = wm * (TS / 2) + FM * (lane & 15);
+  const int rb = wn * (TS / 2) + FM * (lane & 15);
 #pragma unroll
   for (int c = 0; c < kDmaStages - 1; ++c)
     if (c < nchunk) issue(c);
   for (int c = 0; c < nchunk; ++c) {
     // chunk c landed; the later chunks already issued may still fly
     if (c + kDmaStages - 2 < nchunk)
-      wait_vmcnt<(kDmaStages - 2) * kDmaPerWave>();
+      wait_vmcnt<(kDmaStages - 2) * IPW>();
     else
       wait_vmcnt<0>();
     asm volatile("s_barrier" ::: "memory");  // every wave's part of chunk c is in LDS
@@ -398,9 +401,9 @@ __global__ __launch_bounds__(NTHR, 4) void k_gemm_nt(int flags, const GemmDesc* 
         b = vec_t(T(0));
       }
 #pragma unroll
-      for (int x = 0; x < V; ++x)
+      for (int x = 0; x < FM; ++x)
 #pragma unroll
-        for (int y = 0; y < V; ++y) acc[x][y] = Mfma<T>::run(a[x], b[y], acc[x][y]);
+        for (int y = 0; y < FM; ++y) acc[x][y] = Mfma<T>::run(a[x], b[y], acc[x][y]);
     }
     __builtin_amdgcn_s_setprio(0);
   }
@@ -409,7 +412,7 @@ __global__ __launch_bounds__(NTHR, 4) void k_gemm_nt(int flags, const GemmDesc* 
   // with consecutive rows on consecutive lanes, and (GF_C_MIRROR) each
   // mirrored row with consecutive columns on consecutive lanes, so that the
   // stores fill whole cache lines.
-  constexpr int SW = DmaSmem<T>::SW, EC = DmaSmem<T>::EC;
+  constexpr int SW = S::SW, EC = S::EC;
   asm volatile("s_barrier" ::: "memory");  // every wave is done with the stages
   T(*E)[SW + 1] = sm.epi[wave];
   T* C = static_cast<T*>(d.C);
@@ -418,16 +421,16 @@ __global__ __launch_bounds__(NTHR, 4) void k_gemm_nt(int flags, const GemmDesc* 
 #pragma unroll
   for (int p = 0; p < SW / EC; ++p) {
 #pragma unroll
-    for (int x = 0; x < V; ++x)
+    for (int x = 0; x < FM; ++x)
 #pragma unroll
-      for (int y = 0; y < V; ++y)
+      for (int y = 0; y < FM; ++y)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int cl = V * (lane & 15) + y - EC * p;
-          if (cl >= 0 && cl < EC) E[cl][V * Mfma<T>::row(lane, v) + x] = acc[x][y][v];
+          const int cl = FM * (lane & 15) + y - EC * p;
+          if (cl >= 0 && cl < EC) E[cl][FM * Mfma<T>::row(lane, v) + x] = acc[x][y][v];
         }
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    constexpr int CPI = 64 / SW;  // columns per store (1 FP32, 2 FP64)
+    constexpr int CPI = 64 / SW;  // columns per store (1 or 2)
     {
       const int rl = lane % SW;
       const int gi = rbase + rl;
@@ -1124,16 +1127,16 @@ void launch_gemm_tn(int flags, const GemmDesc* d_desc, int batch, int max_m, int
   }
 }
 
-template <typename T, int CLS>
+template <typename T, int TS, int CLS>
 void launch_gemm_nt(int flags, const GemmDesc* d_desc, int batch, int max_m, int max_n, T alpha,
                     T beta, hipStream_t s) {
-  constexpr int V = DmaSmem<T>::V, TS = DmaSmem<T>::TS;
+  constexpr int V = DmaSmem<T, TS>::V;
   for (int b0 = 0; b0 < batch; b0 += kMaxGridY) {
     const int nb = std::min(batch - b0, kMaxGridY);
     // the shifted grid is up to V - 1 rows (columns) longer
     dim3 grid((unsigned)ceil_div(max_n + V - 1, TS), (unsigned)ceil_div(max_m + V - 1, TS),
               (unsigned)nb);
-    hipLaunchKernelGGL((k_gemm_nt<T, CLS>), grid, dim3(NTHR), 0, s, flags, d_desc + b0, alpha,
+    hipLaunchKernelGGL((k_gemm_nt<T, TS, CLS>), grid, dim3(NTHR), 0, s, flags, d_desc + b0, alpha,
                        beta);
     HIF_LAUNCH_CHECK();
   }
@@ -1253,7 +1256,7 @@ bool use_dma_tile(int ts, int opa, int opb, int flags, bool ld16, bool beta0) {
   if ((flags & GF_C_MIRROR) && !beta0) return false;
   if ((flags & (GF_A_LOWER | GF_A_UPPER | GF_B_LOWER | GF_B_UPPER)) && !(flags & GF_TRI_ZEROS))
     return false;
-  return ts == DmaSmem<TC>::TS;
+  return ts == 64 || (sizeof(TC) == 4 && ts == 128);
 }
 
 template <typename TIn, typename TC>
@@ -1270,12 +1273,21 @@ void launch_tile(int ts, int opa, int opb, int flags, int cls, const GemmDesc* d
   }
   if constexpr (std::is_same<TIn, TC>::value) {
     if (use_dma_tile<TIn, TC>(ts, opa, opb, flags, ld16, beta == TC(0))) {
-      if (cls == GC_SYRK)
-        launch_gemm_nt<TC, GC_SYRK>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
-      else if (cls == GC_LSI)
-        launch_gemm_nt<TC, GC_LSI>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
-      else
-        launch_gemm_nt<TC, GC_GENERIC>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+      auto go = [&](auto tsc) {
+        constexpr int TSC = decltype(tsc)::value;
+        if (cls == GC_SYRK)
+          launch_gemm_nt<TC, TSC, GC_SYRK>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+        else if (cls == GC_LSI)
+          launch_gemm_nt<TC, TSC, GC_LSI>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+        else
+          launch_gemm_nt<TC, TSC, GC_GENERIC>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+      };
+      if constexpr (sizeof(TC) == 4) {
+        if (ts == 128) go(std::integral_constant<int, 128>());
+        else go(std::integral_constant<int, 64>());
+      } else {
+        go(std::integral_constant<int, 64>());
+      }
       return;
     }
   }
