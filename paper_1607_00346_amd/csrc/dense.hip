@@ -644,15 +644,23 @@ template <typename T>
 struct StepSmem : DiagSmem<T> {
   __align__(16) T Lsh[kPanel][kPanel];
 };
+// ... with the inverse staged row by row, X[i][c] = L_jj^{-1}(i, c) (rows
+// padded so that a column read down the lanes meets distinct banks)
+template <typename T>
+struct DiagInvSmem : DiagSmem<T> {
+  T X[kPanel][kPanel + 1];
+};
 
 // Cholesky of the diagonal block A(j0:j0+nb, j0:j0+nb) held in the column
 // block col0 (leading dimension ld) into LDS, by the four waves of the
 // workgroup: lane = row, wave q holds columns 16q .. 16q + 15; at step t the
 // wave owning column t forms L(:, t) and publishes it through LDS, then every
-// wave updates its later columns.  Ends with a barrier.  Returns, per thread,
+// wave updates its later columns.  One barrier per column, but few registers:
+// the form for the leaf fronts, whose many workgroups per CU hide the
+// barriers.  Ends with a barrier.  Returns, per thread,
 // whether its wave met a non-positive pivot (replaced by 1 to continue).
 template <typename T, typename S>
-__device__ __forceinline__ bool diag_factor(const T* col0, int64_t ld, int j0, int nb, S& ss) {
+__device__ __forceinline__ bool diag_factor_col(const T* col0, int64_t ld, int j0, int nb, S& ss) {
   constexpr bool kShift = std::is_same<S, StepSmem<T>>::value;  // also fill Lsh
   const int tid = threadIdx.x;
   if constexpr (kShift)
@@ -714,6 +722,78 @@ __device__ __forceinline__ bool diag_factor(const T* col0, int64_t ld, int j0, i
   return bad;
 }
 
+// The same Cholesky with four barriers instead of 64, for the latency-bound
+// diagonal steps of the large fronts (one workgroup per front).  Blocked by
+// wave: the wave owning columns 16k .. 16k + 15 factors them in its registers
+// (the entries L(16k + u, t) that a column update needs are read across lanes,
+// no barrier), publishes them through LDS, and every later wave then takes
+// their rank-16 update; four barriers per block instead of one per column.
+// A block narrower than 64 is padded with the identity: its own entries then
+// receive only the same fused multiply-adds, in the same order, as in the
+// column-by-column right-looking form (the padding contributes exact zeros of
+// negative sign, which change no value).  Ends with a barrier; returns as
+// diag_factor_col.
+template <typename T>
+__device__ __forceinline__ bool diag_factor_blk(const T* col0, int64_t ld, int j0, int nb,
+                                                DiagSmem<T>& ss) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int q = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
+  const int rl = min(lane, nb - 1);
+  T w[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int c = 16 * q + v;
+    const T g = col0[ld * min(c, nb - 1) + j0 + rl];
+    w[v] = (lane < nb && c < nb) ? (c <= lane ? g : T(0)) : (c == lane ? T(1) : T(0));
+  }
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (q == k) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int t = 16 * k + v;
+        {
+          T d = read_lane(w[v], t);
+          bad = bad || !(d > T(0));
+          d = d > T(0) ? d : T(1);
+          T ltt, r;
+          if constexpr (sizeof(T) == 4) {
+            r = __builtin_amdgcn_rsqf(d);  // 1 ulp; shortens the serial chain
+            ltt = d * r;
+          } else {
+            ltt = sqrt(d);
+            r = T(1) / ltt;
+          }
+          const T lit = lane > t ? w[v] * r : (lane == t ? ltt : T(0));
+          w[v] = lit;
+#pragma unroll
+          for (int u = v + 1; u < 16; ++u) w[u] -= lit * read_lane(lit, 16 * k + u);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int t = 16 * k + v;
+        ss.Lcol[t][lane] = w[v];
+      }
+    }
+    __syncthreads();
+    if (q > k) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int t = 16 * k + v;
+        const T li = ss.Lcol[t][lane];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) w[u] -= li * ss.Lcol[t][16 * q + u];
+      }
+    }
+  }
+  if (tid < kPanel) ss.rd[tid] = T(1) / ss.Lcol[tid][tid];
+  __syncthreads();
+  return bad;
+}
+
 // One panel row below the factored diagonal block: x L_jj^T = p in place (row
 // points at column j0 of the row, leading dimension ld), by forward
 // substitution.  A row that is zero stays zero and is left as it is; returns
@@ -744,37 +824,55 @@ __device__ __forceinline__ bool panel_row_light(T* row, int64_t ld, int nb,
 }
 
 // Diagonal block of the blocked right-looking Cholesky at block column j0,
-// by one workgroup: L_jj by diag_factor, then its inverse by wave 0 (lane c
-// forms column c, right-looking, the columns of L_jj read as LDS broadcasts),
-// written over the block (strict upper part zero).  The panel kernel then
-// forms the rows below as P L_jj^{-T}, and the inverse of L_I starts from
-// these inverted diagonal blocks.
+// by one workgroup: L_jj by diag_factor_blk, then its inverse X by the four waves,
+// lane = column of X and wave p = its rows 16p .. 16p + 15.  Row block p takes
+// the contributions of the row blocks above it as they are published, then
+// solves its own 16 rows (the same operations, in the same order, as the
+// column-by-column forward substitution).  The inverse is written over the
+// block (strict upper part zero) from LDS, with rows on lanes.  The panel
+// kernel then forms the rows below as P L_jj^{-T}, and the inverse of L_I
+// starts from these inverted diagonal blocks.  (Past nb the block is the
+// identity, as diag_factor_blk pads it.)
 template <typename T>
-__device__ __forceinline__ void diag_step(T* col0, int64_t ld, int j0, int nb, DiagSmem<T>& ss,
-                                          int* err, int id) {
-  const int tid = threadIdx.x;
-  const bool bad = diag_factor<T>(col0, ld, j0, nb, ss);
-  if (bad && (tid & 63) == 0) atomicMin(err, id);
-  if (tid >= 64) return;
-  const int lane = tid;
-  T x[kPanel];  // column `lane` of the inverse, from e_lane (identity past nb)
+__device__ __forceinline__ void diag_step(T* col0, int64_t ld, int j0, int nb,
+                                          DiagInvSmem<T>& ss, int* err, int id) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int p = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool bad = diag_factor_blk<T>(col0, ld, j0, nb, ss);
+  if (bad && lane == 0) atomicMin(err, id);
+  T x[16];  // rows 16p .. 16p + 15 of column `lane`, from the identity
 #pragma unroll
-  for (int i = 0; i < kPanel; ++i) x[i] = i == lane ? T(1) : T(0);
+  for (int i = 0; i < 16; ++i) x[i] = 16 * p + i == lane ? T(1) : T(0);
 #pragma unroll
-  for (int t = 0; t < kPanel; ++t) {
-    if (t < nb) {
-      x[t] *= ss.rd[t];
+  for (int k = 0; k < 4; ++k) {
+    if (p == k) {
 #pragma unroll
-      for (int u = t + 1; u < kPanel; ++u) x[u] -= ss.Lcol[t][u] * x[t];
+      for (int s = 0; s < 16; ++s) {
+        const int t = 16 * k + s;
+        x[s] *= ss.rd[t];
+#pragma unroll
+        for (int i = s + 1; i < 16; ++i) x[i] -= ss.Lcol[t][16 * k + i] * x[s];
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) ss.X[16 * k + i][lane] = x[i];
     }
-    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+    if (p > k) {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const int t = 16 * k + s;
+        const T xt = ss.X[t][lane];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) x[i] -= ss.Lcol[t][16 * p + i] * xt;
+      }
+    }
   }
-  // column `lane` of the block: rows lane.. of the inverse, zeros above
-  T* dst = col0 + j0 + ld * lane;
   if (lane < nb) {
 #pragma unroll
-    for (int i = 0; i < kPanel; ++i)
-      if (i < nb) dst[i] = i >= lane ? x[i] : T(0);
+    for (int v = 0; v < 16; ++v) {
+      const int c = 16 * p + v;
+      if (c < nb) col0[j0 + lane + ld * c] = lane >= c ? ss.X[lane][c] : T(0);
+    }
   }
 }
 
@@ -782,11 +880,12 @@ __device__ __forceinline__ void diag_step(T* col0, int64_t ld, int j0, int nb, D
 template <typename T>
 __global__ __launch_bounds__(NTHR) void k_front_diag(const FrontDesc* __restrict__ fd, int j0,
                                                      int* err) {
-  __shared__ DiagSmem<T> ss;
+  __shared__ DiagInvSmem<T> ss;
   const FrontDesc f = fd[blockIdx.x];
   if (j0 >= f.nI) return;
-  diag_step<T>(static_cast<T*>(f.ptr) + (int64_t)f.ld * j0, f.ld, j0, min(kPanel, f.nI - j0), ss,
-               err, f.id);
+  const int nb = min(kPanel, f.nI - j0);
+  T* col0 = static_cast<T*>(f.ptr) + (int64_t)f.ld * j0;
+  diag_step<T>(col0, f.ld, j0, nb, ss, err, f.id);
 }
 
 // Trailing update of the blocked front Cholesky with the factored panel
@@ -862,8 +961,8 @@ __global__ __launch_bounds__(NTHR, 8 / sizeof(T)) void k_front_small(
     const int m = f.nR - j1, n = f.nI - j1;
     const bool dense = m > kMaxBlk * 64;
     T* col0 = base + (int64_t)f.ld * j0;
-    if (tid < kMaxBlk) nzb[tid] = 0;  // visible after diag_factor's barriers
-    bad_any = diag_factor<T>(col0, f.ld, j0, nb, ss) || bad_any;
+    if (tid < kMaxBlk) nzb[tid] = 0;  // visible after diag_factor_col's barriers
+    bad_any = diag_factor_col<T>(col0, f.ld, j0, nb, ss) || bad_any;
     for (int e = tid; e < kPanel * kPanel; e += NTHR) {
       const int c = e >> 6, r = e & 63;
       if (r < nb && c < nb && c <= r) col0[j0 + r + (int64_t)f.ld * c] = ss.Lcol[c][r];
