@@ -458,6 +458,184 @@ __global__ __launch_bounds__(NTHR, 4) void k_gemm_nt(int flags, const GemmDesc* 
   }
 }
 
+// LDS of the DMA-fed A B tile (both column-major, B's columns contiguous in
+// k): A as in the A B^T tile, [k][row]; B by 16-byte blocks of k, block kb of
+// column n at slot BPC n + (kb ^ swz(n)), so that the 16 lanes that read one k
+// of columns n = i + 16 y (i = 0 .. 15) meet distinct banks.
+template <typename T, int TS>
+struct NnSmem {
+  static constexpr int V = 16 / (int)sizeof(T);         // values per 16 bytes
+  static constexpr int FM = TS / 32;                    // row (column) blocks per wave
+  static constexpr int LPR = TS * (int)sizeof(T) / 16;  // A: DMA lanes per k row
+  static constexpr int KPI = 64 / LPR;                  // A: k rows per DMA instruction
+  static constexpr int IPW = kDmaK / KPI / 2;           // A: DMA instructions per chunk and wave
+  static constexpr int BPC = kDmaK / V;                 // B: 16-byte blocks per column and chunk
+  static constexpr int BIW = TS * BPC / 64 / 2;         // B: DMA instructions per chunk and wave
+  static constexpr int SWS = BPC == 4 ? 2 : 1;          // B: swizzle shift (slots per bank row)
+  static constexpr int SW = TS / 2;
+  static constexpr int EC = 32;
+  struct Ops {
+    T a[kDmaStages][kDmaK][TS];
+    T b[kDmaStages][TS * kDmaK];
+  };
+  union __align__(16) {
+    Ops op;
+    T epi[4][EC][SW + 1];
+  };
+  static __device__ __forceinline__ int swz(int n) { return (n >> SWS) & (BPC - 1); }
+};
+
+// C = alpha A B + beta C on DMA-fed TS x TS tiles: the A B^T tile's pipeline
+// (K in 16-wide chunks through two LDS stages, one barrier per chunk, A rows
+// on the shifted grid), with B taken by 16-byte k blocks of its columns (B on
+// the 16-byte grid).  Lane i of a 16-lane group multiplies rows FM i + x of A
+// by columns i + 16 y of B; the K order is that of the other tiles.
+template <typename T, int TS>
+__global__ __launch_bounds__(NTHR, 4) void k_gemm_nn(int flags, const GemmDesc* __restrict__ desc,
+                                                     T alpha, T beta) {
+  using S = NnSmem<T, TS>;
+  constexpr int V = S::V, FM = S::FM, LPR = S::LPR, KPI = S::KPI, IPW = S::IPW;
+  constexpr int BPC = S::BPC, BIW = S::BIW;
+  static_assert(IPW == BIW, "both operand halves take the same DMA count");
+  typedef T vec_t __attribute__((ext_vector_type(FM)));
+  __shared__ S sm;
+  unsigned bx, by, bz;
+  xcd_remap(bx, by, bz);
+  const GemmDesc d = desc[bz];
+  const int offA = (int)(((uintptr_t)d.A / sizeof(T)) % V);
+  const int ms = d.m + offA;  // rows in the shifted grid
+  const int m0s = by * TS, n0 = bx * TS;
+  if (m0s >= ms || n0 >= d.n) return;
+  const int m0 = m0s - offA;
+  if ((flags & GF_C_LOWER) && m0 + TS - 1 < n0) return;
+  int kb = 0, ke = d.k;  // (kb stays on the 16-byte grid: no A-upper mask here)
+  if (flags & GF_A_LOWER) ke = min(ke, m0 + TS);
+  if (flags & GF_B_LOWER) kb = max(kb, n0);
+  if (flags & GF_B_UPPER) ke = min(ke, n0 + TS);
+  const int nchunk = ke > kb ? (ke - kb + kDmaK - 1) / kDmaK : 0;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  const int half = wave & 1;
+
+  // waves 0-1: A, as in the A B^T tile; waves 2-3: B, slots 64 I + lane of
+  // instruction I = BIW half + j
+  const bool opa = wave < 2;
+  const T* baseA = static_cast<const T*>(d.A) - offA;
+  const int qa = min(m0s / V + lane % LPR, (ms - 1) / V);
+  const T* srcA = baseA + (int64_t)V * qa;
+  const int krow0 = (kDmaK / 2) * half + lane / LPR;
+  const T* B = static_cast<const T*>(d.B);
+  const int kqmax = ((ke - 1) / V) * V;  // start of the last 16-byte k block holding a value
+  auto issue = [&](int c) {
+    const int st = c % kDmaStages;
+    const int t0 = kb + c * kDmaK;
+    if (opa) {
+#pragma unroll
+      for (int j = 0; j < IPW; ++j) {
+        const int kr = krow0 + KPI * j;
+        const int kk = min(t0 + kr, ke - 1);
+        dma16(srcA + (int64_t)d.lda * kk, &sm.op.a[st][(kDmaK / 2) * half + KPI * j][0]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < BIW; ++j) {
+        const int I = BIW * half + j;
+        const int slot = 64 * I + lane;
+        const int n = slot / BPC;
+        const int blk = (slot % BPC) ^ S::swz(n);
+        const int gn = min(n0 + n, d.n - 1);
+        const int gk = min(t0 + V * blk, kqmax);
+        dma16(B + (int64_t)d.ldb * gn + gk, &sm.op.b[st][64 * V * I]);
+      }
+    }
+  };
+
+  typename Mfma<T>::acc_t acc[FM][FM];
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int y = 0; y < FM; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[x][y][v] = T(0);
+
+  const int ra = wm * (TS / 2) + FM * (lane & 15);
+  const int cb = wn * (TS / 2) + (lane & 15);  // columns cb + 16 y
+#pragma unroll
+  for (int c = 0; c < kDmaStages - 1; ++c)
+    if (c < nchunk) issue(c);
+  for (int c = 0; c < nchunk; ++c) {
+    if (c + kDmaStages - 2 < nchunk)
+      wait_vmcnt<(kDmaStages - 2) * IPW>();
+    else
+      wait_vmcnt<0>();
+    asm volatile("s_barrier" ::: "memory");  // every wave's part of chunk c is in LDS
+    if (c + kDmaStages - 1 < nchunk) issue(c + kDmaStages - 1);
+    const int st = c % kDmaStages;
+    const int kvalid = ke - (kb + c * kDmaK);
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int s4 = 0; s4 < kDmaK / 4; ++s4) {
+      const int kr = 4 * s4 + (lane >> 4);
+      vec_t a = *reinterpret_cast<const vec_t*>(&sm.op.a[st][kr][ra]);
+      T b[FM];
+#pragma unroll
+      for (int y = 0; y < FM; ++y) {
+        const int n = cb + 16 * y;
+        b[y] = sm.op.b[st][V * (BPC * n + ((kr / V) ^ S::swz(n))) + kr % V];
+      }
+      if (kr >= kvalid) {
+        a = vec_t(T(0));
+#pragma unroll
+        for (int y = 0; y < FM; ++y) b[y] = T(0);
+      }
+#pragma unroll
+      for (int x = 0; x < FM; ++x)
+#pragma unroll
+        for (int y = 0; y < FM; ++y) acc[x][y] = Mfma<T>::run(a[x], b[y], acc[x][y]);
+    }
+    __builtin_amdgcn_s_setprio(0);
+  }
+
+  // epilogue through LDS as in the A B^T tile (columns cb + 16 y here)
+  constexpr int SW = S::SW, EC = S::EC;
+  asm volatile("s_barrier" ::: "memory");
+  T(*E)[SW + 1] = sm.epi[wave];
+  T* C = static_cast<T*>(d.C);
+  const int rbase = m0 + wm * SW, cbase = n0 + wn * SW;
+  const bool lower = (flags & GF_C_LOWER) != 0;
+#pragma unroll
+  for (int p = 0; p < SW / EC; ++p) {
+#pragma unroll
+    for (int x = 0; x < FM; ++x)
+#pragma unroll
+      for (int y = 0; y < FM; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int cl = (lane & 15) + 16 * y - EC * p;
+          if (cl >= 0 && cl < EC) E[cl][FM * Mfma<T>::row(lane, v) + x] = acc[x][y][v];
+        }
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    constexpr int CPI = 64 / SW;
+    {
+      const int rl = lane % SW;
+      const int gi = rbase + rl;
+      for (int j = lane / SW; j < EC; j += CPI) {
+        const int gj = cbase + EC * p + j;
+        if (gi >= 0 && gi < d.m && gj < d.n && (!lower || gi >= gj)) {
+          const int64_t idx = gi + (int64_t)d.ldc * gj;
+          T val = alpha * E[j][rl];
+          if (beta != T(0)) val += beta * C[idx];
+          C[idx] = val;
+        }
+      }
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  }
+}
+
 // ---- A^T B tile fed by 16-byte DMA loads (the ID's Gram) -----------------
 //
 // C = alpha A^T B + beta C accumulated in FP64, for an A (k x m) and a B
@@ -1241,6 +1419,18 @@ void launch_gemm_nt(int flags, const GemmDesc* d_desc, int batch, int max_m, int
   }
 }
 
+template <typename T, int TS>
+void launch_gemm_nn(int flags, const GemmDesc* d_desc, int batch, int max_m, int max_n, T alpha,
+                    T beta, hipStream_t s) {
+  constexpr int V = NnSmem<T, TS>::V;
+  for (int b0 = 0; b0 < batch; b0 += kMaxGridY) {
+    const int nb = std::min(batch - b0, kMaxGridY);
+    dim3 grid((unsigned)ceil_div(max_n, TS), (unsigned)ceil_div(max_m + V - 1, TS), (unsigned)nb);
+    hipLaunchKernelGGL((k_gemm_nn<T, TS>), grid, dim3(NTHR), 0, s, flags, d_desc + b0, alpha, beta);
+    HIF_LAUNCH_CHECK();
+  }
+}
+
 template <typename TIn, typename TC, int TS>
 void dispatch_gemm(int opa, int opb, int flags, int cls, const GemmDesc* d_desc, int batch,
                    int max_m, int max_n, TC alpha, TC beta, hipStream_t s) {
@@ -1349,6 +1539,15 @@ int pick_tile(const TileKey& k, int max_m, int max_n) {
 // 16 bytes, in one precision, with triangular operands only when their zeros
 // are stored and a mirrored output only when it overwrites C, at the tile size
 // the table picks for it.
+// ... and A B products (no mirror, no A-upper mask), B on the 16-byte grid.
+template <typename TIn, typename TC>
+bool use_dma_nn(int ts, int opa, int opb, int flags, bool ld16) {
+  if (!std::is_same<TIn, TC>::value || !ld16 || opa != OP_N || opb != OP_N) return false;
+  if (flags & (GF_C_MIRROR | GF_A_UPPER)) return false;
+  if ((flags & (GF_A_LOWER | GF_B_LOWER | GF_B_UPPER)) && !(flags & GF_TRI_ZEROS)) return false;
+  return ts == 64 || (sizeof(TC) == 4 && ts == 128);
+}
+
 template <typename TIn, typename TC>
 bool use_dma_tile(int ts, int opa, int opb, int flags, bool ld16, bool beta0) {
   if (!std::is_same<TIn, TC>::value || !ld16 || opa != OP_N || opb != OP_T) return false;
@@ -1386,6 +1585,17 @@ void launch_tile(int ts, int opa, int opb, int flags, int cls, const GemmDesc* d
         else go(std::integral_constant<int, 64>());
       } else {
         go(std::integral_constant<int, 64>());
+      }
+      return;
+    }
+    if (use_dma_nn<TIn, TC>(ts, opa, opb, flags, ld16)) {
+      if constexpr (sizeof(TC) == 4) {
+        if (ts == 128)
+          launch_gemm_nn<TC, 128>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+        else
+          launch_gemm_nn<TC, 64>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
+      } else {
+        launch_gemm_nn<TC, 64>(flags, d_desc, batch, max_m, max_n, alpha, beta, s);
       }
       return;
     }
@@ -1812,11 +2022,13 @@ void front_invert(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
     hipLaunchKernelGGL((k_diag_inv<T>), g, dim3(64), 0, s, d_fronts);
     HIF_LAUNCH_CHECK();
   }
+  // W blocks with their leading dimension on the 16-byte grid (a DMA-fed B)
+  auto wld = [](int nc) { return (nc + 3) & ~3; };
   int64_t wmax = 0;
   for (int sz = kPanel; sz < maxI; sz *= 2) {
     int64_t w = 0;
     for (auto& f : h_fronts)
-      for (int o = 0; o + sz < f.nI; o += 2 * sz) w += (int64_t)std::min(sz, f.nI - o - sz) * sz;
+      for (int o = 0; o + sz < f.nI; o += 2 * sz) w += (int64_t)wld(std::min(sz, f.nI - o - sz)) * sz;
     wmax = std::max(wmax, w);
   }
   if (wmax == 0) return;
@@ -1844,12 +2056,13 @@ void front_invert(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
         T* Bp = base + (o + sz) + (int64_t)f.ld * o;
         T* Ai = base + o + (int64_t)f.ld * o;
         T* Ci = base + (o + sz) + (int64_t)f.ld * (o + sz);
+        const int lw = wld(nc);
         g1.push_back({Bp + (int64_t)f.ld * k0, Ai + k0, W.get() + w, rb, sz, sz - k0, f.ld, f.ld,
-                      nc});
-        g2.push_back({Ci, W.get() + w, Bp, nc, sz, rb, f.ld, nc, f.ld});
+                      lw});
+        g2.push_back({Ci, W.get() + w, Bp, nc, sz, rb, f.ld, lw, f.ld});
         f1 += gemm_flops(g1.back(), banded ? 0 : GF_B_LOWER);
         f2 += gemm_flops(g2.back(), GF_A_LOWER);
-        w += (int64_t)nc * sz;
+        w += (int64_t)lw * sz;
         mm = std::max(mm, nc);
         m1 = std::max(m1, rb);
       }
@@ -1860,10 +2073,17 @@ void front_invert(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
     d2.upload(g2, s);
     // (A^{-1} from row k0 on is no longer aligned with its triangle: the band
     // product drops the mask and multiplies the stored zeros)
+    // a DMA-fed B needs its columns on the 16-byte grid (A's rows may be shifted)
+    constexpr int V = 16 / (int)sizeof(T);
+    auto grid16 = [&](const std::vector<GemmDesc>& g) {
+      for (const GemmDesc& e : g)
+        if (e.lda % V || e.ldb % V || ((uintptr_t)e.B % 16)) return false;
+      return true;
+    };
     gemm_batched<T, T>(OP_N, OP_N, (banded ? 0 : GF_B_LOWER) | zf, d1.get(), (int)g1.size(), m1,
-                       sz, T(1), T(0), s, "trtri_gemm", f1);
+                       sz, T(1), T(0), s, "trtri_gemm", f1, GC_GENERIC, grid16(g1));
     gemm_batched<T, T>(OP_N, OP_N, GF_A_LOWER | zf, d2.get(), (int)g2.size(), mm, sz, T(-1), T(0), s,
-                       "trtri_gemm", f2);
+                       "trtri_gemm", f2, GC_GENERIC, grid16(g2));
   }
 }
 
