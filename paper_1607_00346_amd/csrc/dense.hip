@@ -1280,9 +1280,19 @@ __global__ __launch_bounds__(NTP) void k_pchol_panel(
     }
     if (lane == 0) { rv[wave] = bv; ri[wave] = bi; }
     __syncthreads();
+    if (wave == 0) {  // the waves' candidates, reduced across lanes (a total order: any tree)
+      if (NTP > 64) {
+        bv = lane < NTP / 64 ? rv[lane] : -DBL_MAX;
+        bi = lane < NTP / 64 ? ri[lane] : INT_MAX;
+#pragma unroll
+        for (int off = NTP / 128; off > 0; off >>= 1) {
+          const double ov = __shfl_xor(bv, off);
+          const int oi = __shfl_xor(bi, off);
+          if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+      }
+    }
     if (tid == 0) {
-      for (int w = 1; w < NTP / 64; ++w)
-        if (rv[w] > bv || (rv[w] == bv && ri[w] < bi)) { bv = rv[w]; bi = ri[w]; }
       if (j == 0) s_r11 = bv;
       const int stop = (j == 0) ? !(bv > 0.0) : !(bv > eps * eps * s_r11);
       s_stop = stop;
@@ -1300,6 +1310,8 @@ __global__ __launch_bounds__(NTP) void k_pchol_panel(
     const int p = s_p;
     const double ljj = sqrt(s_dp);
     const int np = j - j0;
+    // this thread's first entry of column p, in flight with the pivot row's load
+    const double g0 = tid < nF ? Gb[tid + (int64_t)ld * p] : 0.0;
     if (tid < np) lp[tid] = Lb[p + (int64_t)ld * (j0 + tid)];
     __syncthreads();
     for (int a = tid; a < nF; a += NTP) {
@@ -1308,7 +1320,7 @@ __global__ __launch_bounds__(NTP) void k_pchol_panel(
       else if (piv[a]) v = 0.0;
       else {
         const double* la = Lb + a + (int64_t)ld * j0;
-        double s0 = Gb[a + (int64_t)ld * p], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        double s0 = a == tid ? g0 : Gb[a + (int64_t)ld * p], s1 = 0.0, s2 = 0.0, s3 = 0.0;
         int t = 0;
         for (; t + 4 <= np; t += 4) {
           s0 -= la[(int64_t)ld * t] * lp[t];
