@@ -471,7 +471,7 @@ struct NnSmem {
   static constexpr int IPW = kDmaK / KPI / 2;           // A: DMA instructions per chunk and wave
   static constexpr int BPC = kDmaK / V;                 // B: 16-byte blocks per column and chunk
   static constexpr int BIW = TS * BPC / 64 / 2;         // B: DMA instructions per chunk and wave
-  static constexpr int SWS = BPC == 4 ? 2 : 1;          // B: swizzle shift (slots per bank row)
+  static constexpr int SWS = BPC == 4 ? 2 : 1;          // B: log2 columns per 256 bytes of banks
   static constexpr int SW = TS / 2;
   static constexpr int EC = 32;
   struct Ops {
@@ -905,7 +905,7 @@ __device__ __forceinline__ bool diag_factor_col(const T* col0, int64_t ld, int j
 // wave: the wave owning columns 16k .. 16k + 15 factors them in its registers
 // (the entries L(16k + u, t) that a column update needs are read across lanes,
 // no barrier), publishes them through LDS, and every later wave then takes
-// their rank-16 update; four barriers per block instead of one per column.
+// their rank-16 update: one barrier per 16 columns instead of one per column.
 // A block narrower than 64 is padded with the identity: its own entries then
 // receive only the same fused multiply-adds, in the same order, as in the
 // column-by-column right-looking form (the padding contributes exact zeros of
@@ -932,23 +932,21 @@ __device__ __forceinline__ bool diag_factor_blk(const T* col0, int64_t ld, int j
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int t = 16 * k + v;
-        {
-          T d = read_lane(w[v], t);
-          bad = bad || !(d > T(0));
-          d = d > T(0) ? d : T(1);
-          T ltt, r;
-          if constexpr (sizeof(T) == 4) {
-            r = __builtin_amdgcn_rsqf(d);  // 1 ulp; shortens the serial chain
-            ltt = d * r;
-          } else {
-            ltt = sqrt(d);
-            r = T(1) / ltt;
-          }
-          const T lit = lane > t ? w[v] * r : (lane == t ? ltt : T(0));
-          w[v] = lit;
-#pragma unroll
-          for (int u = v + 1; u < 16; ++u) w[u] -= lit * read_lane(lit, 16 * k + u);
+        T d = read_lane(w[v], t);
+        bad = bad || !(d > T(0));
+        d = d > T(0) ? d : T(1);
+        T ltt, r;
+        if constexpr (sizeof(T) == 4) {
+          r = __builtin_amdgcn_rsqf(d);  // 1 ulp; shortens the serial chain
+          ltt = d * r;
+        } else {
+          ltt = sqrt(d);
+          r = T(1) / ltt;
         }
+        const T lit = lane > t ? w[v] * r : (lane == t ? ltt : T(0));
+        w[v] = lit;
+#pragma unroll
+        for (int u = v + 1; u < 16; ++u) w[u] -= lit * read_lane(lit, 16 * k + u);
       }
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
