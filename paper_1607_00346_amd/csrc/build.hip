@@ -309,7 +309,12 @@ __global__ __launch_bounds__(NT) void k_lsi_leaf(const FrontDesc* __restrict__ f
 }
 
 // Panel of face f, column j: Ã^l(rows, F_j) = A^l(rows, F_j) + U_A + U_B, the
-// Schur updates of the two neighbouring cells added in a fixed order.
+// Schur updates of the two neighbouring cells added in a fixed order.  The
+// panel's row blocks (the face and the other faces of both cells) are
+// contiguous in the column, so the rows run as one range: lane t < 11 reads
+// the descriptors of block t, which every lane then holds in scalar
+// registers, and each lane takes kGatherUnroll rows at a time, finding a
+// row's block by comparison, with all their loads issued before any store.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_gather_panel(
     Src<T> s, const int* __restrict__ fpts, const int2* __restrict__ fmap,
@@ -331,18 +336,64 @@ __global__ __launch_bounds__(NT) void k_gather_panel(
   const T* UB = U + uoff[B];
   const int ldA = uld[A], ldB = uld[B];
   T* col = panels + poff[f] + (int64_t)pld[f] * j;
+  // block descriptors: lane t holds block t (used blocks form a prefix)
+  int lg = -1, lro = 0, lsa = -1, lsb = -1, lgo = 0, lng = 0;
+  if (lane < kRowBlocks) {
+    lg = rb_face[base + lane];
+    if (lg >= 0) {
+      lro = rb_off[base + lane];
+      lsa = rb_sa[base + lane];
+      lsb = rb_sb[base + lane];
+      lgo = (int)fpt_off[lg];
+      lng = fN[lg];
+    }
+  }
+  int ro[kRowBlocks], go[kRowBlocks], sa[kRowBlocks], sb[kRowBlocks];
+  int nb = 0;
+#pragma unroll
   for (int t = 0; t < kRowBlocks; ++t) {
-    const int g = rb_face[base + t];
-    if (g < 0) break;
-    const int ro = rb_off[base + t], sa = rb_sa[base + t], sb = rb_sb[base + t];
-    const int ng = fN[g];
-    const int64_t go = fpt_off[g];
-    const int* G = fpts + go;
-    for (int i = lane; i < ng; i += 64) {
-      T v = row_lookup(s, cl, G[i], map_at(s.has_prev, fmap, go + i));
-      if (sa >= 0) v += UA[(sa + i) + (int64_t)ldA * colA];
-      if (sb >= 0) v += UB[(sb + i) + (int64_t)ldB * colB];
-      col[ro + i] = v;
+    ro[t] = __builtin_amdgcn_readlane(lro, t);
+    go[t] = __builtin_amdgcn_readlane(lgo, t);
+    sa[t] = __builtin_amdgcn_readlane(lsa, t);
+    sb[t] = __builtin_amdgcn_readlane(lsb, t);
+    nb += __builtin_amdgcn_readlane(lg, t) >= 0 ? 1 : 0;
+  }
+  if (nb == 0) return;
+  int nrow = 0;  // rows of the panel: the end of the last block
+#pragma unroll
+  for (int t = 0; t < kRowBlocks; ++t)
+    if (t == nb - 1) nrow = ro[t] + __builtin_amdgcn_readlane(lng, t);
+  for (int r0 = lane; r0 < nrow; r0 += 64 * kGatherUnroll) {
+    int p[kGatherUnroll];
+    int2 mp[kGatherUnroll];
+    T ua[kGatherUnroll], ub[kGatherUnroll];
+    bool ha[kGatherUnroll], hb[kGatherUnroll];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      const int r = min(r0 + 64 * u, nrow - 1);
+      int bro = ro[0], bgo = go[0], bsa = sa[0], bsb = sb[0];
+#pragma unroll
+      for (int t = 1; t < kRowBlocks; ++t)
+        if (t < nb && r >= ro[t]) {
+          bro = ro[t];
+          bgo = go[t];
+          bsa = sa[t];
+          bsb = sb[t];
+        }
+      const int i = r - bro;
+      p[u] = fpts[bgo + i];
+      mp[u] = map_at(s.has_prev, fmap, (int64_t)bgo + i);
+      ha[u] = bsa >= 0;
+      hb[u] = bsb >= 0;
+      ua[u] = ha[u] ? UA[(bsa + i) + (int64_t)ldA * colA] : T(0);
+      ub[u] = hb[u] ? UB[(bsb + i) + (int64_t)ldB * colB] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      T v = row_lookup(s, cl, p[u], mp[u]);
+      if (ha[u]) v += ua[u];
+      if (hb[u]) v += ub[u];
+      if (r0 + 64 * u < nrow) col[r0 + 64 * u] = v;
     }
   }
 }

@@ -718,6 +718,22 @@ __global__ __launch_bounds__(NTHR, 4) void k_gemm_tn(int flags, const GemmDesc* 
     ca[x] = wm * 32 + 16 * x + (lane & 15);
     cb[x] = wn * 32 + 16 * x + (lane & 15);
   }
+  // The 16 x 16 output blocks of this wave that hold a stored entry: inside
+  // C and, for a lower C, not wholly above the diagonal.  The others take no
+  // MFMA (a face whose width lies just past a multiple of 64 leaves most of
+  // its last tile row empty); a live block's sums are formed in the same
+  // order either way.  (Wave-uniform: the branches are scalar.)
+  bool live[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int r0 = m0 + wm * 32 + 16 * x, c0 = n0 + wn * 32 + 16 * y;
+      live[x][y] = r0 < d.m && c0 < d.n && (!(flags & GF_C_LOWER) || r0 + 15 >= c0);
+    }
+  // (FP64 operands keep every block: measured slower with the skips)
+  const bool all_live =
+      sizeof(TIn) == 8 || (live[0][0] && live[0][1] && live[1][0] && live[1][1]);
   if (nchunk > 0) issue(0);
   for (int c = 0; c < nchunk; ++c) {
     wait_vmcnt<0>();                         // chunk c landed
@@ -748,13 +764,32 @@ __global__ __launch_bounds__(NTHR, 4) void k_gemm_tn(int flags, const GemmDesc* 
           }
         }
       }
+      if (all_live) {
 #pragma unroll
-      for (int e = 0; e < E; ++e)
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+              acc[x][y] = Mfma<double>::run((double)a[x][e], (double)b[y][e], acc[x][y]);
+      } else {
+        double da[2][E], db[2][E];  // widened first: no VALU result feeds an MFMA directly
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            da[x][e] = (double)a[x][e];
+            db[x][e] = (double)b[x][e];
+          }
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
           for (int y = 0; y < 2; ++y)
-            acc[x][y] = Mfma<double>::run((double)a[x][e], (double)b[y][e], acc[x][y]);
+            if (live[x][y]) {
+#pragma unroll
+              for (int e = 0; e < E; ++e) acc[x][y] = Mfma<double>::run(da[x][e], db[y][e], acc[x][y]);
+            }
+      }
     }
     __builtin_amdgcn_s_setprio(0);
   }
@@ -1369,6 +1404,22 @@ __global__ __launch_bounds__(NTHR) void k_transpose(const TransDesc* __restrict_
 }
 
 // Rank and the tail of the permutation: unpivoted indices ascending.
+// Faces whose rank is already settled (kst >= 0) need no further update of
+// their Gram: their descriptors of the coming update get m = n = k = 0, so
+// that every tile of the batched product returns at once.  (What the update
+// would write there is never read: the ID takes only the first k pivot
+// columns of L, and the panel kernel returns for a finished face.)
+__global__ __launch_bounds__(NTHR) void k_pchol_drop_done(GemmDesc* __restrict__ desc,
+                                                          const int* __restrict__ bidx,
+                                                          const int* __restrict__ kst, int cnt) {
+  const int i = blockIdx.x * NTHR + threadIdx.x;
+  if (i < cnt && kst[bidx[i]] >= 0) {
+    desc[i].m = 0;
+    desc[i].n = 0;
+    desc[i].k = 0;
+  }
+}
+
 __global__ __launch_bounds__(64) void k_pchol_tail(const int* __restrict__ nFa,
                                                    const int64_t* __restrict__ poff,
                                                    int* __restrict__ perm,
@@ -2110,7 +2161,9 @@ void pivoted_cholesky(double* G, double* L, const int64_t* goff, const int* nF, 
   DevBuf<int> pivbuf(std::max<int64_t>(tot, 1)), kst(batch);
   HIF_HIP(hipMemsetAsync(kst.get(), 0xff, sizeof(int) * batch, s));  // -1: running
   std::vector<GemmDesc> gd;
+  std::vector<int> gb;  // face of each update descriptor
   DevBuf<GemmDesc> dd;
+  DevBuf<int> db;
   for (int j0 = 0; j0 < maxF; j0 += kPivPanel) {
     {
       ProfScope ps("pivoted_cholesky", s);
@@ -2135,6 +2188,7 @@ void pivoted_cholesky(double* G, double* L, const int64_t* goff, const int* nF, 
     if (j0 + kPivPanel >= maxF) break;
     // G -= L_p L_p^T with the panel's columns L_p (lower part computed, both written)
     gd.clear();
+    gb.clear();
     int mm = 0;
     double fl = 0.0;
     for (int b = 0; b < batch; ++b) {
@@ -2142,11 +2196,17 @@ void pivoted_cholesky(double* G, double* L, const int64_t* goff, const int* nF, 
       const int kk = std::min(kPivPanel, h_nF[b] - j0);
       double* Lp = L + h_goff[b] + (int64_t)h_ldg[b] * j0;
       gd.push_back({Lp, Lp, G + h_goff[b], h_nF[b], h_nF[b], kk, h_ldg[b], h_ldg[b], h_ldg[b]});
+      gb.push_back(b);
       mm = std::max(mm, h_nF[b]);
       fl += gemm_flops(gd.back(), GF_C_LOWER);
     }
     if (gd.empty()) continue;
     dd.upload(gd, s);
+    db.upload(gb, s);
+    hipLaunchKernelGGL(k_pchol_drop_done, dim3((unsigned)ceil_div((int)gd.size(), NTHR)),
+                       dim3(NTHR), 0, s, dd.get(), (const int*)db.get(), (const int*)kst.get(),
+                       (int)gd.size());
+    HIF_LAUNCH_CHECK();
     gemm_batched<double, double>(OP_N, OP_T, GF_C_LOWER | GF_C_MIRROR, dd.get(), (int)gd.size(),
                                  mm, mm, -1.0, 1.0, s, "pivchol_update", fl);
   }
