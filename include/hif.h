@@ -58,7 +58,7 @@ typedef enum {
   HIF_ENOMEM = -2,   /* device allocation failed                                   */
   HIF_ENOTSPD = -3,  /* a Cholesky pivot was not positive (level/front in message) */
   HIF_ENOCONV = -4,  /* PCG reached maxit; u holds the last iterate                */
-  HIF_EDEVICE = -5   /* any other HIP runtime error                                */
+  HIF_EDEVICE = -5   /* any other HIP runtime error, or a failed internal check    */
 } hif_status;
 
 enum { HIF_FP64 = 0, HIF_MIXED = 1 };  /* factor precision                        */

@@ -420,7 +420,7 @@ const char* hif_status_string(hif_status s) {
     case HIF_ENOMEM: return "HIF_ENOMEM: out of device memory";
     case HIF_ENOTSPD: return "HIF_ENOTSPD: matrix not positive definite";
     case HIF_ENOCONV: return "HIF_ENOCONV: PCG did not converge";
-    case HIF_EDEVICE: return "HIF_EDEVICE: device runtime error";
+    case HIF_EDEVICE: return "HIF_EDEVICE: device runtime error or failed internal check";
   }
   return "unknown hif_status";
 }

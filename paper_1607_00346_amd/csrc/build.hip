@@ -1146,6 +1146,16 @@ void build_factors(const std::vector<BuildRequest>& req, hipStream_t s) {
                      2 * rr * rr * kk + 2 * rr * rr * rr / 3 + rr * rr * kk + 2 * kk * kk * rr;
         }
         const int nsk = (int)lev.hsk.size();
+        // every block and vector range a descriptor names lies inside the arena
+        // it indexes (the skeleton kernels and the apply sweeps trust them)
+        for (const SkelDesc& d : lev.hsk)
+          HIF_REQUIRE(d.face >= 0 && d.face < P.nface && d.k >= 0 && d.r > 0 &&
+                          d.k + d.r == P.fN[d.face] && d.pts_off == P.fpt_off[d.face] &&
+                          d.offT >= 0 && d.offL == d.offT + (int64_t)d.k * d.r &&
+                          d.offY == d.offL + (int64_t)d.r * d.r &&
+                          d.offY + (int64_t)d.r * d.k <= ssz && d.kofs >= 0 &&
+                          d.kofs + d.k <= lev.ksum && d.rofs >= 0 && d.rofs + d.r <= lev.rsum,
+                      HIF_EDEVICE, "internal error: a skeleton descriptor leaves its arenas");
         J.ssz = ssz;
         lev.sk = to_dev(lev.hsk, s);
         lev.skel.alloc(std::max<int64_t>(ssz, 1));
