@@ -1122,12 +1122,13 @@ __global__ __launch_bounds__(NTHR) void k_front_trailing(const FrontDesc* __rest
                                         T(-1), T(1), sm);
 }
 
-// Panel rows below the diagonal block at j0, 64 rows per workgroup: P <- P
-// L_jj^{-T} in place, one GEMM tile (the rows are read in full before any is
-// written; the diagonal block holds L_jj^{-1}).
-template <typename T>
+// Panel rows below the diagonal block at j0, TM rows per workgroup: P <- P
+// L_jj^{-T} in place, one TM x 64 GEMM tile over all of the block's columns
+// (the rows are read in full before any is written; the diagonal block holds
+// L_jj^{-1}).
+template <typename T, int TM>
 __global__ __launch_bounds__(NTHR) void k_front_panel(const FrontDesc* __restrict__ fd, int j0) {
-  __shared__ TileSmem<T, 64, 64> sm;
+  __shared__ TileSmem<T, TM, 64> sm;
   unsigned bx, by, bz;
   xcd_remap(bx, by, bz);
   const FrontDesc f = fd[by];
@@ -1135,10 +1136,10 @@ __global__ __launch_bounds__(NTHR) void k_front_panel(const FrontDesc* __restric
   const int nb = min(kPanel, f.nI - j0);
   const int j1 = j0 + nb;
   const int m = f.nR - j1;
-  const int m0 = bx * 64;
+  const int m0 = bx * TM;
   if (m0 >= m) return;
   T* col0 = static_cast<T*>(f.ptr) + (int64_t)f.ld * j0;
-  gemm_tile_t<T, T, OP_N, OP_T, 64, 64>(GF_B_UPPER | GF_TRI_ZEROS, col0 + j1, f.ld, col0 + j0,
+  gemm_tile_t<T, T, OP_N, OP_T, TM, 64>(GF_B_UPPER | GF_TRI_ZEROS, col0 + j1, f.ld, col0 + j0,
                                         f.ld, col0 + j1, f.ld, m, nb, nb, m0, 0, T(1), T(0), sm);
 }
 
@@ -1827,6 +1828,10 @@ double gemm_flops(const GemmDesc& d, int flags) {
   return 2.0 * m * n * k;
 }
 
+// Below this many 64-wide tiles a step's panel and trailing launches take
+// 32-wide tiles (every tile size sums K in the same order: same results).
+constexpr int64_t kFewTiles = 1024;
+
 template <typename T>
 void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fronts,
                   int* err, hipStream_t s, bool upper_zero, int small_limit, int band) {
@@ -1885,9 +1890,14 @@ void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
     }
     if (max_n == 0) return;
     ProfScope ps("potrf_trailing", s, fl);
+    const int64_t nwg64 = ceil_div(max_n, 64) * ceil_div(max_m, 64) * (int64_t)batch;
     if (sizeof(T) == 4 && max_n >= 1024) {
       dim3 gt((unsigned)ceil_div(max_n, 128), (unsigned)ceil_div(max_m, 128), (unsigned)batch);
       hipLaunchKernelGGL((k_front_trailing<T, 128>), gt, dim3(NTHR), 0, s, d_fronts, p0, pw, c0,
+                         cw);
+    } else if (nwg64 < kFewTiles) {  // few fronts (the root): 32-wide tiles, four times the workgroups
+      dim3 gt((unsigned)ceil_div(max_n, 32), (unsigned)ceil_div(max_m, 32), (unsigned)batch);
+      hipLaunchKernelGGL((k_front_trailing<T, 32>), gt, dim3(NTHR), 0, s, d_fronts, p0, pw, c0,
                          cw);
     } else {
       dim3 gt((unsigned)std::max<int64_t>(1, ceil_div(max_n, 64)),
@@ -1926,8 +1936,13 @@ void front_factor(const FrontDesc* d_fronts, const std::vector<FrontDesc>& h_fro
       }
       if (max_m > 0) {
         ProfScope ps("potrf_panel", s, fl_panel);
-        dim3 g((unsigned)ceil_div(max_m, 64), (unsigned)batch);
-        hipLaunchKernelGGL((k_front_panel<T>), g, dim3(NTHR), 0, s, d_fronts, j0);
+        if (ceil_div(max_m, 64) * batch < kFewTiles) {
+          dim3 g((unsigned)ceil_div(max_m, 32), (unsigned)batch);
+          hipLaunchKernelGGL((k_front_panel<T, 32>), g, dim3(NTHR), 0, s, d_fronts, j0);
+        } else {
+          dim3 g((unsigned)ceil_div(max_m, 64), (unsigned)batch);
+          hipLaunchKernelGGL((k_front_panel<T, 64>), g, dim3(NTHR), 0, s, d_fronts, j0);
+        }
         HIF_LAUNCH_CHECK();
       }
       trailing(j0, kPanel, j0 + kPanel, J + kSuper - (j0 + kPanel));
