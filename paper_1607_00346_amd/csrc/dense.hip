@@ -1404,7 +1404,6 @@ __global__ __launch_bounds__(NTHR) void k_transpose(const TransDesc* __restrict_
   }
 }
 
-// Rank and the tail of the permutation: unpivoted indices ascending.
 // Faces whose rank is already settled (kst >= 0) need no further update of
 // their Gram: their descriptors of the coming update get m = n = k = 0, so
 // that every tile of the batched product returns at once.  (What the update
@@ -1421,6 +1420,7 @@ __global__ __launch_bounds__(NTHR) void k_pchol_drop_done(GemmDesc* __restrict__
   }
 }
 
+// Rank and the tail of the permutation: unpivoted indices ascending.
 __global__ __launch_bounds__(64) void k_pchol_tail(const int* __restrict__ nFa,
                                                    const int64_t* __restrict__ poff,
                                                    int* __restrict__ perm,
