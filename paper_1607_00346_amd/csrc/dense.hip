@@ -1152,7 +1152,7 @@ __global__ __launch_bounds__(NTHR) void k_front_panel(const FrontDesc* __restric
 // it is.  The leaf fronts, the stencil on a box in lexicographic order, have
 // a band of at most 64, so each step updates one trailing tile.
 template <typename T>
-__global__ __launch_bounds__(NTHR, 8 / sizeof(T)) void k_front_small(
+__global__ __launch_bounds__(NTHR, 16 / sizeof(T)) void k_front_small(
                                                          const FrontDesc* __restrict__ fd,
                                                          int* err) {
   constexpr size_t kBytes = sizeof(StepSmem<T>) > sizeof(TileSmem<T, 64, 64>)
