@@ -192,44 +192,55 @@ LevelPlan plan_level(const LevelGeom& G, const std::vector<uint8_t>& active) {
   P.root = G.root;
   P.ncell = G.ncell;
   P.nface = G.nface;
-  // active face points
+  // active face points.  The compactions here write every candidate and
+  // advance past the active ones only: no branch on the irregular mask.
   P.fN.assign(P.nface, 0);
   P.fpt_off.assign(P.nface + 1, 0);
-  P.fpts.clear();
-  P.fpts.reserve(G.cand_F.size());
+  P.fpts.resize(G.cand_F.size());
+  int64_t nf = 0;
   for (int f = 0; f < P.nface; ++f) {
     for (int64_t t = G.cand_F_off[f]; t < G.cand_F_off[f + 1]; ++t) {
       const int p = G.cand_F[t];
-      if (active[p]) P.fpts.push_back(p);
+      P.fpts[nf] = p;
+      nf += active[p] != 0;
     }
-    P.fpt_off[f + 1] = (int64_t)P.fpts.size();
+    P.fpt_off[f + 1] = nf;
     P.fN[f] = (int)(P.fpt_off[f + 1] - P.fpt_off[f]);
   }
+  P.fpts.resize(nf);
   // cells: I then S
   P.cface = G.cface;
   P.cface_off.assign((size_t)P.ncell * 6, -1);
   P.cI.assign(P.ncell, 0);
   P.cS.assign(P.ncell, 0);
   P.crow_off.assign(P.ncell + 1, 0);
-  P.rows.clear();
-  P.rows.reserve(G.cand_I.size() + 6 * P.fpts.size());
+  // a cell's rows: its active interior, then the points of its up to six faces
+  int64_t cap = (int64_t)G.cand_I.size();
+  for (size_t q = 0; q < P.cface.size(); ++q)
+    if (P.cface[q] >= 0) cap += P.fN[P.cface[q]];
+  P.rows.resize(cap);
+  int64_t nr = 0;
   for (int c = 0; c < P.ncell; ++c) {
     for (int64_t t = G.cand_I_off[c]; t < G.cand_I_off[c + 1]; ++t) {
       const int p = G.cand_I[t];
-      if (active[p]) P.rows.push_back(p);
+      P.rows[nr] = p;
+      nr += active[p] != 0;
     }
-    P.cI[c] = (int)((int64_t)P.rows.size() - P.crow_off[c]);
+    P.cI[c] = (int)(nr - P.crow_off[c]);
     int off = 0;
     for (int s = 0; s < 6; ++s) {
       const int f = P.cface[(size_t)c * 6 + s];
       if (f < 0) continue;
       P.cface_off[(size_t)c * 6 + s] = off;
-      P.rows.insert(P.rows.end(), P.fpts.begin() + P.fpt_off[f], P.fpts.begin() + P.fpt_off[f + 1]);
+      std::copy(P.fpts.begin() + P.fpt_off[f], P.fpts.begin() + P.fpt_off[f + 1],
+                P.rows.begin() + nr);
+      nr += P.fN[f];
       off += P.fN[f];
     }
     P.cS[c] = off;
-    P.crow_off[c + 1] = (int64_t)P.rows.size();
+    P.crow_off[c + 1] = nr;
   }
+  P.rows.resize(nr);
   // panel row blocks
   P.fcellA = G.fcellA;
   P.fcellB = G.fcellB;
